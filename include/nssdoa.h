@@ -1,0 +1,213 @@
+/*
+ * nssdoa.h -- C ABI of the MI355X noise-subspace narrowband DOA library (libnssdoa.so).
+ *
+ * The library estimates directions of arrival with the four noise-subspace methods of
+ * Eray & Temizel, "Performance Analysis of Noise Subspace-based Narrowband Direction-of-Arrival
+ * (DOA) Estimation Algorithms on CPU and GPU" (arXiv 2007.14135): PHD, MUSIC, EV and MN.
+ * Per frame of complex snapshots it runs the common code structure of Table 2 on the GPU:
+ *   Step-1  sample covariance R = X X^H / N                              (Eq. 3)
+ *   Step-2  Hermitian eigendecomposition, eigenvalues descending         (Table 2, Step-2)
+ *   Step-3/4 noise-subspace selection; the Step-4 matrix C is kept in
+ *           factored form C = B B^H                                      (Table 3)
+ *   Step-5  pseudo-spectrum P(theta) = 1 / (a^H C a) = 1 / ||B^H a||^2
+ *           over a uniform azimuth grid, steering vectors of Eq. 2       (Table 2, Step-5)
+ *   Step-6  peak search and selection of the D strongest peaks           (Table 2, Step-6)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns nssdoa_status; NSSDOA_OK (0) on success.  No C++ exception crosses the
+ *   ABI.  nssdoa_last_error() returns a message describing the last failure on this thread.
+ * - Argument errors are detected on the host, synchronously, before any device work, and
+ *   return NSSDOA_EINVAL.  Problems that depend on the data (non-finite input, a degenerate
+ *   noise subspace, fewer peaks than sources) never fail a call: they set per-frame status bits.
+ * - "host" pointers are ordinary CPU memory; "device" pointers are GPU memory of the current
+ *   HIP device (for example the data_ptr() of a torch tensor on that device).
+ * - The caller owns every buffer it passes and the stream.  The library never frees caller
+ *   memory.  Plans and batches own only their internal device tables and free them on destroy.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Device work is
+ *   enqueued on it and the call returns; results are valid once the stream has been
+ *   synchronised.  Two calls that share a workspace or an output buffer must not overlap.
+ * - Directions are azimuth angles in degrees, measured from +y toward +x in the horizontal plane
+ *   (phi = 90 deg in Eq. 2).  Element positions are in wavelengths.
+ */
+#ifndef NSSDOA_H
+#define NSSDOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NSSDOA_OK = 0,
+    NSSDOA_EINVAL = 1,        /* invalid argument (checked on the host before device work)  */
+    NSSDOA_EUNSUPPORTED = 2,  /* valid request this build does not implement                */
+    NSSDOA_ENOMEM = 3,        /* a device or host allocation of the library failed          */
+    NSSDOA_EDEVICE = 4,       /* a HIP runtime call failed (no device, launch failure, ...) */
+    NSSDOA_ESTATE = 5         /* object used in a state that does not allow the call        */
+} nssdoa_status;
+
+/* Table 3: the four noise-subspace methods.  Their Step-4 matrices factor as C = B B^H with
+ * PHD  B = e_min (eigenvector of the smallest eigenvalue), K = 1 column;
+ * MUSIC B = E_n (eigenvectors D+1..M), K = M - D columns;
+ * EV   B = E_n diag(lambda_n^(-1/2)), K = M - D columns;
+ * MN   B = P_n e_1 / (e_1^H P_n e_1) with P_n = E_n E_n^H, K = 1 column. */
+typedef enum { NSSDOA_PHD = 0, NSSDOA_MUSIC = 1, NSSDOA_EV = 2, NSSDOA_MN = 3 } nssdoa_alg;
+
+/* Arithmetic of the spectrum scan (Step-5).  The covariance is always accumulated in FP64, and
+ * the eigensolve, noise-subspace matrices and peak refinement are always FP64.
+ * C128: complex128 snapshots, FP64 scan, double spectrum.
+ * C64 : complex64 snapshots, FP32 scan on the matrix cores with FP32 accumulation; points whose
+ *       ||B^H a||^2 is below lowq_tau * ||B||_F^2 are re-evaluated in FP64; float spectrum. */
+typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 } nssdoa_prec;
+
+/* Per-frame status bits written to status[] by nssdoa_estimate. */
+#define NSSDOA_ST_NONFINITE_INPUT   0x1u  /* R has a NaN/Inf entry; no peaks, spectrum is NaN      */
+#define NSSDOA_ST_EVD_NOT_CONVERGED 0x2u  /* Jacobi stopped at max_sweeps above tolerance          */
+#define NSSDOA_ST_DEGENERATE        0x4u  /* EV: a noise eigenvalue <= 0; MN: (P_n)_11 <= 1e-300   */
+#define NSSDOA_ST_FEWER_PEAKS       0x8u  /* fewer than D local maxima; unused slots idx = -1      */
+#define NSSDOA_ST_PEAK_OVERFLOW     0x10u /* more local maxima than the candidate buffer holds     */
+
+/* An array geometry: M elements at host positions pos_wl[3*m + {0,1,2}] = (x, y, z) in
+ * wavelengths (Eq. 2).  The plan copies the positions; the caller may free them afterwards. */
+typedef struct {
+    int32_t M;            /* number of elements, 2 <= M <= 64 and M a multiple of 8 for C64   */
+    int32_t reserved;     /* must be 0                                                         */
+    const double* pos_wl; /* host, 3*M doubles                                                 */
+} nssdoa_array;
+
+/* A uniform azimuth scan grid (the AngleSer of Table 2, Step-5): theta_l = start_deg +
+ * l * step_deg for l = 0..L-1, each computed from l in FP64.  circular != 0 makes the first and
+ * last points neighbours for the peak search (a full 360 deg grid); otherwise neither end can be
+ * a peak. */
+typedef struct {
+    double start_deg;
+    double step_deg;      /* > 0                                                               */
+    int32_t L;            /* >= 3                                                              */
+    int32_t circular;
+} nssdoa_grid;
+
+/* One frame of snapshots.  X_N of Eq. 3 is M x N with one column per snapshot; it is stored
+ * element-major: snapshot n of element m is complex element x_off + m * ldx + n of the X buffer
+ * (complex64 or complex128 interleaved re, im).  spec_off is the element offset of this frame's
+ * L spectrum values in the spectrum buffer (ignored when no spectrum buffer is passed). */
+typedef struct {
+    int32_t array_id;     /* index into the plan's arrays                                      */
+    int32_t grid_id;      /* index into the plan's grids                                       */
+    int32_t N;            /* snapshots, >= 1                                                   */
+    int32_t D;            /* sources, 1 <= D < M                                               */
+    int64_t x_off;        /* >= 0                                                              */
+    int64_t ldx;          /* >= N                                                              */
+    int64_t spec_off;     /* >= 0                                                              */
+} nssdoa_frame;
+
+/* One selected peak (Table 2, Step-6): grid index, its angle and the FP64 spectrum value. */
+typedef struct {
+    int32_t idx;          /* grid index, or -1 for an unused slot                              */
+    int32_t reserved;
+    double angle_deg;     /* start + idx * step, NaN for an unused slot                        */
+    double value;         /* P at idx evaluated in FP64, NaN for an unused slot                */
+} nssdoa_peak;
+
+/* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */
+typedef struct {
+    double jacobi_tol;        /* stop when |r_pq| <= tol * sqrt(r_pp r_qq) for all p<q; 1e-15  */
+    int32_t max_sweeps;       /* Jacobi sweep limit, >= 1; 30                                  */
+    int32_t refine_halfwidth; /* FP64 re-evaluation window around each candidate peak, 1..16; 4 */
+    double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 2e-3 */
+    int32_t extra_candidates; /* local maxima kept beyond D for the FP64 re-pick, 0..16; 4     */
+    int32_t reserved;         /* must be 0                                                     */
+} nssdoa_options;
+
+typedef struct nssdoa_plan_s* nssdoa_plan;
+typedef struct nssdoa_batch_s* nssdoa_batch;
+
+/* Intermediate results a caller (or a test) may read from the workspace after nssdoa_estimate. */
+typedef enum {
+    NSSDOA_WS_COV = 0,     /* R, M x M complex128, row-major, full Hermitian                    */
+    NSSDOA_WS_EVALS = 1,   /* lambda, M doubles, descending                                     */
+    NSSDOA_WS_EVECS = 2,   /* U, M x M complex128, row-major, column k pairs with lambda_k      */
+    NSSDOA_WS_B = 3,       /* B, M x K complex128, column-major (column k contiguous)            */
+    NSSDOA_WS_QREF = 4,    /* ||B||_F^2, one double                                             */
+    NSSDOA_WS_SPECTRUM = 5 /* the internal spectrum (used when no spectrum buffer is passed)    */
+} nssdoa_ws_item;
+
+/* Stages of nssdoa_estimate, for nssdoa_stage_time. */
+typedef enum {
+    NSSDOA_STAGE_COVARIANCE = 0, /* Step-1                                                     */
+    NSSDOA_STAGE_EIGEN = 1,      /* Step-2..4: covariance reduction, Jacobi, B                 */
+    NSSDOA_STAGE_SCAN = 2,       /* Step-5                                                     */
+    NSSDOA_STAGE_PEAKS = 3,      /* low-Q FP64 re-evaluation and Step-6                        */
+    NSSDOA_STAGE_COUNT = 4
+} nssdoa_stage;
+
+/* Create a plan holding array geometries and scan grids (host work only, no device call).
+ * arrays[n_arrays] and grids[n_grids] are host arrays, copied.  options may be NULL.
+ * EINVAL: NULL plan/arrays/grids, n_arrays or n_grids < 1, M < 2 or M > 64, L < 3,
+ * step <= 0 or non-finite, non-finite positions, an option out of its stated range. */
+nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, int32_t n_arrays,
+                                 const nssdoa_grid* grids, int32_t n_grids,
+                                 const nssdoa_options* options);
+
+/* Free a plan.  Every batch created from it must have been destroyed first (ESTATE otherwise).
+ * NULL is accepted and ignored. */
+nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan);
+
+/* Validate a set of frames for one algorithm and scan precision, group the frames that share an
+ * array and a grid, and upload the schedule to the current device (the batch owns it).
+ * frames[n_frames] is a host array, copied.  max_D is the peak slots per frame in the outputs.
+ * EINVAL: NULL pointers, n_frames < 1, unknown array/grid ids, N < 1, D < 1, D >= M, D > max_D,
+ * ldx < N, negative offsets, max_D > 64; for C64 the array's M must be 8, 16, 32 or 64.
+ * EUNSUPPORTED: BF16/F16.  EDEVICE/ENOMEM: device upload failed. */
+nssdoa_status nssdoa_batch_create(nssdoa_batch* batch, nssdoa_plan plan, nssdoa_alg alg,
+                                  nssdoa_prec prec, const nssdoa_frame* frames, int32_t n_frames,
+                                  int32_t max_D);
+
+/* Free a batch (waits for nothing: the caller must not destroy a batch whose work is in flight).
+ * NULL is accepted and ignored. */
+nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch);
+
+/* Bytes of device workspace nssdoa_estimate needs for this batch. */
+nssdoa_status nssdoa_workspace_size(nssdoa_batch batch, size_t* bytes);
+
+/* Byte offset, inside the workspace, of `item` for frame `frame` (see nssdoa_ws_item). */
+nssdoa_status nssdoa_workspace_offset(nssdoa_batch batch, nssdoa_ws_item item, int32_t frame,
+                                      size_t* offset);
+
+/* Run Steps 1-6 for every frame of the batch on `stream`.
+ *   X         device, complex64 (C64) or complex128 (C128) snapshots addressed by the frames
+ *   x_elems   complex elements in X; every frame must satisfy x_off + (M-1)*ldx + N <= x_elems
+ *   spectrum  device, float (C64) or double (C128); frame f's L values at frames[f].spec_off.
+ *             May be NULL: the spectrum then lives in the workspace only.
+ *   spectrum_elems  elements in spectrum; every frame must satisfy spec_off + L <= spectrum_elems
+ *             (ignored when spectrum is NULL)
+ *   peaks     device, n_frames * max_D entries, best first per frame
+ *   npeaks    device, n_frames int32: number of valid peaks per frame (<= D)
+ *   status    device, n_frames uint32: NSSDOA_ST_* bits
+ *   workspace device, at least nssdoa_workspace_size bytes, 256-byte aligned; its contents on
+ *             entry do not matter
+ * EINVAL: NULL X/peaks/npeaks/status/workspace, a frame outside X or the spectrum, workspace
+ * too small or not 256-byte aligned. */
+nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                              size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                              uint32_t* status, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/* Per-stage device timing.  While enabled, nssdoa_estimate records HIP events around each stage
+ * on its stream; nssdoa_stage_time waits for them and returns the summed milliseconds and the
+ * number of launches of `stage` since timing was (re)enabled. */
+nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable);
+nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* total_ms,
+                                int64_t* launches);
+
+/* Static description of a status code, and the last failure message on this thread. */
+const char* nssdoa_status_string(nssdoa_status status);
+const char* nssdoa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSSDOA_H */

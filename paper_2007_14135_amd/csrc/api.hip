@@ -1,0 +1,580 @@
+// Host side of libnssdoa: argument validation, batch scheduling, workspace layout and the
+// launch sequence of nssdoa_estimate.  See include/nssdoa.h for the contract of every call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "nssdoa.h"
+#include "internal.h"
+
+using namespace nssdoa;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nssdoa_status fail(nssdoa_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+nssdoa_status fail(nssdoa_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+nssdoa_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? NSSDOA_ENOMEM : NSSDOA_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+constexpr int kChunkRows = 384;      // rows of stacked B per scan work item (12 tiles)
+constexpr int kCovTargetItems = 2048;
+
+}  // namespace
+
+struct nssdoa_plan_s {
+    std::vector<int32_t> M;
+    std::vector<std::vector<double>> pos;
+    std::vector<nssdoa_grid> grids;
+    nssdoa_options opt;
+    int live_batches = 0;
+};
+
+struct StageEvents {
+    int stage;
+    hipEvent_t a, b;
+};
+
+struct nssdoa_batch_s {
+    nssdoa_plan plan = nullptr;
+    nssdoa_alg alg;
+    nssdoa_prec prec;
+    int32_t n_frames = 0, max_D = 0, max_M = 0;
+    std::vector<FrameDev> frames;
+    std::vector<GroupDev> groups;
+    std::vector<CovItem> cov_items;
+    std::vector<ScanItem> scan_items;           // sorted by group M
+    std::vector<std::pair<int, std::pair<int, int>>> scan_ranges;   // M -> [begin, end)
+    std::vector<PointItem> point_items;
+    std::vector<int32_t> blk;
+    std::vector<double> pos;
+    std::vector<int32_t> peak_list;             // frames grouped by M bucket
+    std::vector<std::pair<int, std::pair<int, int>>> peak_ranges;   // bucket M -> [begin, end)
+    size_t ws_bytes = 0;
+    size_t spec_elem = 4;
+    size_t x_extent = 0;       // complex elements of X the frames address
+    size_t spec_extent = 0;    // elements of the caller's spectrum the frames address
+    // device copies
+    char* dev = nullptr;
+    FrameDev* d_frames = nullptr;
+    GroupDev* d_groups = nullptr;
+    CovItem* d_cov = nullptr;
+    ScanItem* d_scan = nullptr;
+    PointItem* d_points = nullptr;
+    int32_t* d_blk = nullptr;
+    double* d_pos = nullptr;
+    int32_t* d_plist = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<StageEvents> pending;
+    double stage_ms[NSSDOA_STAGE_COUNT] = {0, 0, 0, 0};
+    int64_t stage_n[NSSDOA_STAGE_COUNT] = {0, 0, 0, 0};
+};
+
+extern "C" {
+
+const char* nssdoa_status_string(nssdoa_status s) {
+    switch (s) {
+        case NSSDOA_OK: return "ok";
+        case NSSDOA_EINVAL: return "invalid argument";
+        case NSSDOA_EUNSUPPORTED: return "unsupported";
+        case NSSDOA_ENOMEM: return "out of memory";
+        case NSSDOA_EDEVICE: return "device error";
+        case NSSDOA_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* nssdoa_last_error(void) { return g_last_error.c_str(); }
+
+nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, int32_t n_arrays,
+                                 const nssdoa_grid* grids, int32_t n_grids,
+                                 const nssdoa_options* options) {
+    if (!plan) return fail(NSSDOA_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!arrays || n_arrays < 1) return fail(NSSDOA_EINVAL, "need at least one array");
+    if (!grids || n_grids < 1) return fail(NSSDOA_EINVAL, "need at least one grid");
+    nssdoa_options opt;
+    opt.jacobi_tol = 1e-15;
+    opt.max_sweeps = 30;
+    opt.refine_halfwidth = 4;
+    opt.lowq_tau = 2e-3;
+    opt.extra_candidates = 4;
+    opt.reserved = 0;
+    if (options) {
+        opt = *options;
+        if (!(opt.jacobi_tol > 0.0 && opt.jacobi_tol < 1.0))
+            return fail(NSSDOA_EINVAL, "jacobi_tol must be in (0, 1)");
+        if (opt.max_sweeps < 1 || opt.max_sweeps > 1000)
+            return fail(NSSDOA_EINVAL, "max_sweeps must be in [1, 1000]");
+        if (opt.refine_halfwidth < 1 || opt.refine_halfwidth > 16)
+            return fail(NSSDOA_EINVAL, "refine_halfwidth must be in [1, 16]");
+        if (!(opt.lowq_tau >= 0.0) || !isfinite(opt.lowq_tau))
+            return fail(NSSDOA_EINVAL, "lowq_tau must be finite and >= 0");
+        if (opt.extra_candidates < 0 || opt.extra_candidates > 16)
+            return fail(NSSDOA_EINVAL, "extra_candidates must be in [0, 16]");
+        if (opt.reserved != 0) return fail(NSSDOA_EINVAL, "options.reserved must be 0");
+    }
+    auto* p = new (std::nothrow) nssdoa_plan_s();
+    if (!p) return fail(NSSDOA_ENOMEM, "host allocation failed");
+    for (int a = 0; a < n_arrays; ++a) {
+        const nssdoa_array& ar = arrays[a];
+        if (ar.M < 2 || ar.M > 64) {
+            delete p;
+            return fail(NSSDOA_EINVAL, "array %d: M=%d outside [2, 64]", a, ar.M);
+        }
+        if (!ar.pos_wl || ar.reserved != 0) {
+            delete p;
+            return fail(NSSDOA_EINVAL, "array %d: NULL positions or nonzero reserved", a);
+        }
+        std::vector<double> v(ar.pos_wl, ar.pos_wl + 3 * ar.M);
+        for (double x : v)
+            if (!isfinite(x)) {
+                delete p;
+                return fail(NSSDOA_EINVAL, "array %d: non-finite position", a);
+            }
+        p->M.push_back(ar.M);
+        p->pos.push_back(std::move(v));
+    }
+    for (int g = 0; g < n_grids; ++g) {
+        const nssdoa_grid& gr = grids[g];
+        if (gr.L < 3) {
+            delete p;
+            return fail(NSSDOA_EINVAL, "grid %d: L=%d < 3", g, gr.L);
+        }
+        if (!(gr.step_deg > 0.0) || !isfinite(gr.step_deg) || !isfinite(gr.start_deg)) {
+            delete p;
+            return fail(NSSDOA_EINVAL, "grid %d: step must be finite and > 0", g);
+        }
+        p->grids.push_back(gr);
+    }
+    p->opt = opt;
+    *plan = p;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan) {
+    if (!plan) return NSSDOA_OK;
+    if (plan->live_batches > 0)
+        return fail(NSSDOA_ESTATE, "plan still has %d live batches", plan->live_batches);
+    delete plan;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch) {
+    if (!batch) return NSSDOA_OK;
+    for (auto& e : batch->pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (batch->dev) (void)hipFree(batch->dev);
+    if (batch->plan) batch->plan->live_batches--;
+    delete batch;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_alg alg,
+                                  nssdoa_prec prec, const nssdoa_frame* frames, int32_t n_frames,
+                                  int32_t max_D) {
+    if (!out) return fail(NSSDOA_EINVAL, "batch is NULL");
+    *out = nullptr;
+    if (!plan) return fail(NSSDOA_EINVAL, "plan is NULL");
+    if (!frames || n_frames < 1) return fail(NSSDOA_EINVAL, "need at least one frame");
+    if (alg < NSSDOA_PHD || alg > NSSDOA_MN) return fail(NSSDOA_EINVAL, "unknown algorithm %d", (int)alg);
+    if (prec < NSSDOA_C128 || prec > NSSDOA_F16) return fail(NSSDOA_EINVAL, "unknown precision %d", (int)prec);
+    if (max_D < 1 || max_D > 64) return fail(NSSDOA_EINVAL, "max_D=%d outside [1, 64]", max_D);
+    if (prec == NSSDOA_BF16 || prec == NSSDOA_F16)
+        return fail(NSSDOA_EUNSUPPORTED, "BF16/F16 scans are not built in this library");
+    const int n_arr = (int)plan->M.size(), n_grid = (int)plan->grids.size();
+    for (int f = 0; f < n_frames; ++f) {
+        const nssdoa_frame& fr = frames[f];
+        if (fr.array_id < 0 || fr.array_id >= n_arr)
+            return fail(NSSDOA_EINVAL, "frame %d: unknown array_id %d", f, fr.array_id);
+        if (fr.grid_id < 0 || fr.grid_id >= n_grid)
+            return fail(NSSDOA_EINVAL, "frame %d: unknown grid_id %d", f, fr.grid_id);
+        const int M = plan->M[fr.array_id];
+        if (fr.N < 1) return fail(NSSDOA_EINVAL, "frame %d: N=%d < 1", f, fr.N);
+        if (fr.D < 1 || fr.D >= M) return fail(NSSDOA_EINVAL, "frame %d: D=%d outside [1, M-1] (M=%d)", f, fr.D, M);
+        if (fr.D > max_D) return fail(NSSDOA_EINVAL, "frame %d: D=%d > max_D=%d", f, fr.D, max_D);
+        if (fr.ldx < fr.N) return fail(NSSDOA_EINVAL, "frame %d: ldx < N", f);
+        if (fr.x_off < 0 || fr.spec_off < 0) return fail(NSSDOA_EINVAL, "frame %d: negative offset", f);
+        if (prec == NSSDOA_C64 && (M % 8 != 0 || M > 64))
+            return fail(NSSDOA_EINVAL, "frame %d: the FP32 scan needs M in {8, 16, 32, 64} (M=%d)", f, M);
+    }
+
+    auto* b = new (std::nothrow) nssdoa_batch_s();
+    if (!b) return fail(NSSDOA_ENOMEM, "host allocation failed");
+    b->plan = plan;
+    b->alg = alg;
+    b->prec = prec;
+    b->n_frames = n_frames;
+    b->max_D = max_D;
+    b->spec_elem = prec == NSSDOA_C128 ? sizeof(double) : sizeof(float);
+
+    // positions table (one copy per array)
+    std::vector<int> pos_off(n_arr);
+    for (int a = 0; a < n_arr; ++a) {
+        pos_off[a] = (int)b->pos.size();
+        b->pos.insert(b->pos.end(), plan->pos[a].begin(), plan->pos[a].end());
+    }
+
+    // groups: frames sharing (array, grid), in order of first appearance
+    std::map<std::pair<int, int>, int> gid;
+    std::vector<std::vector<int>> gframes;
+    b->frames.resize(n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        const nssdoa_frame& in = frames[f];
+        auto key = std::make_pair(in.array_id, in.grid_id);
+        auto it = gid.find(key);
+        int g;
+        if (it == gid.end()) {
+            g = (int)b->groups.size();
+            gid[key] = g;
+            GroupDev gd;
+            memset(&gd, 0, sizeof(gd));
+            const nssdoa_grid& gr = plan->grids[in.grid_id];
+            gd.M = plan->M[in.array_id];
+            gd.L = gr.L;
+            gd.pos_off = pos_off[in.array_id];
+            gd.grid_start = gr.start_deg;
+            gd.grid_step = gr.step_deg;
+            b->groups.push_back(gd);
+            gframes.emplace_back();
+        } else {
+            g = it->second;
+        }
+        gframes[g].push_back(f);
+        FrameDev& fd = b->frames[f];
+        memset(&fd, 0, sizeof(fd));
+        const nssdoa_grid& gr = plan->grids[in.grid_id];
+        fd.M = plan->M[in.array_id];
+        fd.N = in.N;
+        fd.D = in.D;
+        fd.K = (alg == NSSDOA_MUSIC || alg == NSSDOA_EV) ? fd.M - in.D : 1;
+        fd.group = g;
+        fd.x_off = in.x_off;
+        fd.ldx = in.ldx;
+        fd.spec_off_user = in.spec_off;
+        fd.grid_start = gr.start_deg;
+        fd.grid_step = gr.step_deg;
+        fd.L = gr.L;
+        fd.circular = gr.circular ? 1 : 0;
+        fd.pos_off = pos_off[in.array_id];
+        fd.alg = (int32_t)alg;
+        b->max_M = std::max(b->max_M, fd.M);
+        b->x_extent = std::max(b->x_extent, (size_t)(in.x_off + (int64_t)(fd.M - 1) * in.ldx + in.N));
+        b->spec_extent = std::max(b->spec_extent, (size_t)(in.spec_off + gr.L));
+    }
+
+    // covariance chunks over snapshots
+    const int S_target = std::max(1, (kCovTargetItems + n_frames - 1) / n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDev& fd = b->frames[f];
+        const int S = std::max(1, std::min(S_target, fd.N / 256));
+        const int len = (fd.N + S - 1) / S;
+        int c = 0;
+        for (int n0 = 0; n0 < fd.N; n0 += len, ++c) b->cov_items.push_back({f, c, n0, std::min(fd.N, n0 + len)});
+        fd.n_chunks = c;
+    }
+
+    // workspace: per-frame regions, then per-group packed B tiles, then the spectrum
+    size_t off = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        FrameDev& fd = b->frames[f];
+        const size_t MM = (size_t)fd.M * fd.M;
+        fd.ws_partial = (int64_t)off; off = align_up(off + (size_t)fd.n_chunks * MM * 16);
+        fd.ws_R = (int64_t)off;       off = align_up(off + MM * 16);
+        fd.ws_evals = (int64_t)off;   off = align_up(off + (size_t)fd.M * 8);
+        fd.ws_evecs = (int64_t)off;   off = align_up(off + MM * 16);
+        fd.ws_B = (int64_t)off;       off = align_up(off + (size_t)fd.M * fd.K * 16);
+        fd.ws_qref = (int64_t)off;    off = align_up(off + 8);
+    }
+    if (prec == NSSDOA_C64) {
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            GroupDev& gd = b->groups[g];
+            int row = 0, chunk_start = 0, chunk_frames = 0;
+            std::vector<std::pair<int, int>> chunks;
+            int last_f = -1;
+            for (int f : gframes[g]) {
+                FrameDev& fd = b->frames[f];
+                const int rows = round_up(2 * fd.K, 8);
+                if (chunk_frames > 0 && (row - chunk_start) + rows > kChunkRows) {
+                    const int end = round_up(row, 32);
+                    b->frames[last_f].emb_rows += end - row;   // the last frame zero-fills the tail
+                    chunks.push_back({chunk_start / 32, end / 32});
+                    row = chunk_start = end;
+                    chunk_frames = 0;
+                }
+                fd.emb_row0 = row;
+                fd.emb_rows = rows;
+                row += rows;
+                ++chunk_frames;
+                last_f = f;
+            }
+            const int end = round_up(row, 32);
+            b->frames[last_f].emb_rows += end - row;
+            chunks.push_back({chunk_start / 32, end / 32});
+            gd.n_tiles = end / 32;
+            gd.blk_off = (int)b->blk.size();
+            b->blk.resize(b->blk.size() + (size_t)gd.n_tiles * 4, -1);
+            for (int f : gframes[g]) {
+                const FrameDev& fd = b->frames[f];
+                for (int r = fd.emb_row0; r < fd.emb_row0 + round_up(2 * fd.K, 8); r += 8)
+                    b->blk[gd.blk_off + r / 8] = f;
+            }
+            gd.ws_emb = (int64_t)off;
+            off = align_up(off + (size_t)gd.n_tiles * 64 * gd.M * sizeof(float));
+            const int n_at = (gd.L + kScanAnglesPerWG - 1) / kScanAnglesPerWG;
+            for (auto& ch : chunks)
+                for (int at = 0; at < n_at; ++at)
+                    b->scan_items.push_back({(int)g, at, ch.first, ch.second});
+        }
+        std::stable_sort(b->scan_items.begin(), b->scan_items.end(),
+                         [&](const ScanItem& x, const ScanItem& y) { return b->groups[x.group].M < b->groups[y.group].M; });
+        for (size_t i = 0; i < b->scan_items.size();) {
+            const int M = b->groups[b->scan_items[i].group].M;
+            size_t j = i;
+            while (j < b->scan_items.size() && b->groups[b->scan_items[j].group].M == M) ++j;
+            b->scan_ranges.push_back({M, {(int)i, (int)j}});
+            i = j;
+        }
+    } else {
+        for (int f = 0; f < n_frames; ++f)
+            for (int l0 = 0; l0 < b->frames[f].L; l0 += 256) b->point_items.push_back({f, l0});
+    }
+    for (int f = 0; f < n_frames; ++f) {
+        b->frames[f].spec_off_ws = (int64_t)((off - 0) / b->spec_elem);
+        off += (size_t)b->frames[f].L * b->spec_elem;
+    }
+    off = align_up(off);
+    b->ws_bytes = off;
+    // the internal spectrum offsets above are relative to the workspace base in elements
+    // (the region is aligned to the element size because every earlier region is 256-aligned)
+
+    // peak frame lists by M bucket
+    for (int mb : {8, 16, 32, 64}) {
+        const int begin = (int)b->peak_list.size();
+        for (int f = 0; f < n_frames; ++f) {
+            const int M = b->frames[f].M;
+            const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
+            if (bucket == mb) b->peak_list.push_back(f);
+        }
+        if ((int)b->peak_list.size() > begin) b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
+    }
+
+    // upload the schedule
+    size_t o_frames = 0;
+    size_t o_groups = align_up(o_frames + b->frames.size() * sizeof(FrameDev));
+    size_t o_cov = align_up(o_groups + b->groups.size() * sizeof(GroupDev));
+    size_t o_scan = align_up(o_cov + b->cov_items.size() * sizeof(CovItem));
+    size_t o_pts = align_up(o_scan + b->scan_items.size() * sizeof(ScanItem));
+    size_t o_blk = align_up(o_pts + b->point_items.size() * sizeof(PointItem));
+    size_t o_pos = align_up(o_blk + b->blk.size() * sizeof(int32_t));
+    size_t o_pl = align_up(o_pos + b->pos.size() * sizeof(double));
+    size_t total = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
+    std::vector<char> host(total, 0);
+    auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(host.data() + o, src, n); };
+    put(o_frames, b->frames.data(), b->frames.size() * sizeof(FrameDev));
+    put(o_groups, b->groups.data(), b->groups.size() * sizeof(GroupDev));
+    put(o_cov, b->cov_items.data(), b->cov_items.size() * sizeof(CovItem));
+    put(o_scan, b->scan_items.data(), b->scan_items.size() * sizeof(ScanItem));
+    put(o_pts, b->point_items.data(), b->point_items.size() * sizeof(PointItem));
+    put(o_blk, b->blk.data(), b->blk.size() * sizeof(int32_t));
+    put(o_pos, b->pos.data(), b->pos.size() * sizeof(double));
+    put(o_pl, b->peak_list.data(), b->peak_list.size() * sizeof(int32_t));
+    hipError_t e = hipMalloc((void**)&b->dev, total);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "hipMalloc(batch tables)");
+    }
+    e = hipMemcpy(b->dev, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->dev);
+        delete b;
+        return hip_fail(e, "hipMemcpy(batch tables)");
+    }
+    b->d_frames = reinterpret_cast<FrameDev*>(b->dev + o_frames);
+    b->d_groups = reinterpret_cast<GroupDev*>(b->dev + o_groups);
+    b->d_cov = reinterpret_cast<CovItem*>(b->dev + o_cov);
+    b->d_scan = reinterpret_cast<ScanItem*>(b->dev + o_scan);
+    b->d_points = reinterpret_cast<PointItem*>(b->dev + o_pts);
+    b->d_blk = reinterpret_cast<int32_t*>(b->dev + o_blk);
+    b->d_pos = reinterpret_cast<double*>(b->dev + o_pos);
+    b->d_plist = reinterpret_cast<int32_t*>(b->dev + o_pl);
+    plan->live_batches++;
+    *out = b;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_workspace_size(nssdoa_batch batch, size_t* bytes) {
+    if (!batch || !bytes) return fail(NSSDOA_EINVAL, "NULL argument");
+    *bytes = batch->ws_bytes;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_workspace_offset(nssdoa_batch batch, nssdoa_ws_item item, int32_t frame,
+                                      size_t* offset) {
+    if (!batch || !offset) return fail(NSSDOA_EINVAL, "NULL argument");
+    if (frame < 0 || frame >= batch->n_frames) return fail(NSSDOA_EINVAL, "frame %d out of range", frame);
+    const FrameDev& fd = batch->frames[frame];
+    switch (item) {
+        case NSSDOA_WS_COV: *offset = (size_t)fd.ws_R; break;
+        case NSSDOA_WS_EVALS: *offset = (size_t)fd.ws_evals; break;
+        case NSSDOA_WS_EVECS: *offset = (size_t)fd.ws_evecs; break;
+        case NSSDOA_WS_B: *offset = (size_t)fd.ws_B; break;
+        case NSSDOA_WS_QREF: *offset = (size_t)fd.ws_qref; break;
+        case NSSDOA_WS_SPECTRUM: *offset = (size_t)fd.spec_off_ws * batch->spec_elem; break;
+        default: return fail(NSSDOA_EINVAL, "unknown workspace item %d", (int)item);
+    }
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable) {
+    if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
+    for (auto& e : batch->pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    batch->pending.clear();
+    for (int s = 0; s < NSSDOA_STAGE_COUNT; ++s) {
+        batch->stage_ms[s] = 0.0;
+        batch->stage_n[s] = 0;
+    }
+    batch->timing = enable != 0;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* total_ms,
+                                int64_t* launches) {
+    if (!batch || !total_ms || !launches) return fail(NSSDOA_EINVAL, "NULL argument");
+    if (stage < 0 || stage >= NSSDOA_STAGE_COUNT) return fail(NSSDOA_EINVAL, "unknown stage %d", (int)stage);
+    for (auto& e : batch->pending) {
+        hipError_t err = hipEventSynchronize(e.b);
+        if (err != hipSuccess) return hip_fail(err, "hipEventSynchronize");
+        float ms = 0.0f;
+        err = hipEventElapsedTime(&ms, e.a, e.b);
+        if (err != hipSuccess) return hip_fail(err, "hipEventElapsedTime");
+        batch->stage_ms[e.stage] += ms;
+        batch->stage_n[e.stage] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    batch->pending.clear();
+    *total_ms = batch->stage_ms[stage];
+    *launches = batch->stage_n[stage];
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                              size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                              uint32_t* status, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+    if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
+    if (!X || !peaks || !npeaks || !status || !workspace)
+        return fail(NSSDOA_EINVAL, "NULL X, peaks, npeaks, status or workspace");
+    if (x_elems < batch->x_extent)
+        return fail(NSSDOA_EINVAL, "X holds %zu complex elements, the frames address %zu", x_elems,
+                    batch->x_extent);
+    if (spectrum && spectrum_elems < batch->spec_extent)
+        return fail(NSSDOA_EINVAL, "spectrum holds %zu elements, the frames address %zu",
+                    spectrum_elems, batch->spec_extent);
+    if (workspace_bytes < batch->ws_bytes)
+        return fail(NSSDOA_EINVAL, "workspace of %zu bytes < required %zu", workspace_bytes, batch->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(NSSDOA_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    const int use_user = spectrum != nullptr;
+    void* spec = use_user ? spectrum : static_cast<void*>(ws);
+    const bool c128 = batch->prec == NSSDOA_C128;
+    const nssdoa_options& opt = batch->plan->opt;
+
+    hipEvent_t ev0 = nullptr;
+    auto stage_begin = [&]() -> nssdoa_status {
+        if (!batch->timing) return NSSDOA_OK;
+        hipError_t e = hipEventCreate(&ev0);
+        if (e == hipSuccess) e = hipEventRecord(ev0, s);
+        return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "hipEventRecord");
+    };
+    auto stage_end = [&](int stage) -> nssdoa_status {
+        if (!batch->timing) return NSSDOA_OK;
+        hipEvent_t ev1;
+        hipError_t e = hipEventCreate(&ev1);
+        if (e == hipSuccess) e = hipEventRecord(ev1, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        batch->pending.push_back({stage, ev0, ev1});
+        return NSSDOA_OK;
+    };
+    nssdoa_status st;
+    hipError_t e;
+
+    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    e = launch_cov(c128, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, s);
+    if (e != hipSuccess) return hip_fail(e, "covariance launch");
+    if ((st = stage_end(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
+
+    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    EvdParams ep;
+    ep.tol = opt.jacobi_tol;
+    ep.max_sweeps = opt.max_sweeps;
+    ep.write_emb = c128 ? 0 : 1;
+    e = launch_evd(batch->d_frames, batch->n_frames, batch->max_M, ep, batch->d_groups, ws, status, s);
+    if (e != hipSuccess) return hip_fail(e, "eigen launch");
+    if ((st = stage_end(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
+
+    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    if (c128) {
+        e = launch_scan_f64(batch->d_points, (int)batch->point_items.size(), batch->max_M, batch->d_frames,
+                            batch->d_pos, ws, static_cast<double*>(spec), use_user, s);
+        if (e != hipSuccess) return hip_fail(e, "FP64 scan launch");
+    } else {
+        for (auto& r : batch->scan_ranges) {
+            e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
+                                batch->d_groups, batch->d_frames, batch->d_blk, batch->d_pos, ws,
+                                static_cast<float*>(spec), use_user, s);
+            if (e != hipSuccess) return hip_fail(e, "FP32 scan launch");
+        }
+    }
+    if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
+
+    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    PeakParams pp;
+    pp.lowq_tau = opt.lowq_tau;
+    pp.halfwidth = opt.refine_halfwidth;
+    pp.extra = opt.extra_candidates;
+    pp.max_D = batch->max_D;
+    pp.refine_lowq = c128 ? 0 : 1;
+    pp.use_user_spec = use_user;
+    pp.pad = 0;
+    for (auto& r : batch->peak_ranges) {
+        e = launch_peaks(c128, r.first, batch->d_plist + r.second.first, r.second.second - r.second.first,
+                         batch->d_frames, batch->d_pos, ws, spec, pp, peaks, npeaks, status, s);
+        if (e != hipSuccess) return hip_fail(e, "peak launch");
+    }
+    if ((st = stage_end(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;
+    return NSSDOA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernels and the host side of libnssdoa.
+// Device descriptors are plain structs uploaded once per batch; every kernel reads them with
+// uniform (scalar) loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nssdoa {
+
+constexpr double kDeg2Rad = 0.017453292519943295;   // pi / 180, the same constant numpy uses
+constexpr int kScanWaves = 4;                       // waves per scan workgroup
+constexpr int kScanAnglesPerWave = 64;              // two 32-angle MFMA column tiles
+constexpr int kScanAnglesPerWG = kScanWaves * kScanAnglesPerWave;
+constexpr int kCandCap = 2048;                      // local maxima buffered per frame
+constexpr int kMaxK = 64;
+
+enum Alg : int32_t { kPHD = 0, kMUSIC = 1, kEV = 2, kMN = 3 };
+
+// Per-frame descriptor.  Byte offsets (ws_*) are relative to the workspace base.
+struct FrameDev {
+    int32_t M, N, D, K;         // K = columns of B (M - D for MUSIC/EV, 1 for PHD/MN)
+    int32_t group;              // index of the (array, grid) group
+    int32_t n_chunks;           // covariance partial sums
+    int32_t emb_row0;           // first row of this frame in its group's packed FP32 B tiles
+    int32_t emb_rows;           // rows reserved there (>= 2K, multiple of 8)
+    int64_t x_off, ldx;         // snapshot addressing, complex elements
+    int64_t spec_off_user;      // element offset in the caller's spectrum buffer
+    int64_t spec_off_ws;        // element offset in the workspace spectrum
+    int64_t ws_partial;         // n_chunks * M*M complex128 partial covariances
+    int64_t ws_R;               // M*M complex128
+    int64_t ws_evals;           // M double
+    int64_t ws_evecs;           // M*M complex128
+    int64_t ws_B;               // M*K complex128, column-major
+    int64_t ws_qref;            // 1 double
+    double grid_start, grid_step;
+    int32_t L, circular;
+    int32_t pos_off;            // offset (doubles) of this frame's 3*M positions
+    int32_t alg;
+};
+
+// Frames that share an array geometry and a scan grid: their spectra are one GEMM.
+struct GroupDev {
+    int32_t M, L;
+    int32_t pos_off, n_tiles;   // packed FP32 B tiles of 32 rows
+    double grid_start, grid_step;
+    int64_t ws_emb;             // byte offset of n_tiles * 64 lanes * M floats
+    int32_t blk_off;            // offset of this group's 8-row-block -> frame table
+    int32_t pad;
+};
+
+struct CovItem { int32_t frame, chunk, n0, n1; };
+struct ScanItem { int32_t group, angle_tile, t0, t1; };       // t1 exclusive, whole frames
+struct PointItem { int32_t frame, l0; };                      // FP64 scan: 256 angles
+
+struct EvdParams {
+    double tol;
+    int32_t max_sweeps;
+    int32_t write_emb;          // 1: write the FP32 packed B tiles (C64 scan)
+};
+
+struct PeakParams {
+    double lowq_tau;            // FP32 spectra: FP64 re-evaluation below tau * qref
+    int32_t halfwidth;          // FP64 window around each candidate
+    int32_t extra;              // candidates beyond D
+    int32_t max_D;              // peak slots per frame
+    int32_t refine_lowq;        // 1 for FP32 spectra
+    int32_t use_user_spec;      // spectrum lives in the caller's buffer
+    int32_t pad;
+};
+
+// Scan angle theta_l = start + l * step with the product and the sum rounded separately
+// (contraction into one fused multiply-add is switched off here).
+__device__ inline double grid_angle(double start, double step, int l) {
+#pragma clang fp contract(off)
+    const double prod = step * (double)l;
+    return start + prod;
+}
+
+// ||B^H a(theta)||^2 in FP64 for one direction (Eq. 2 with phi = 90 deg, Table 3 Step-4 in
+// factored form).  B is M x K complex128, column-major.  The phase in cycles is reduced to
+// [-1/2, 1/2] before the sine and cosine so that its rounding does not grow with the aperture.
+template <int MB>
+__device__ inline double q64_eval(const double* __restrict__ pos, int M, int K,
+                                  const double2* __restrict__ B, double theta_deg) {
+    double sth, cth;
+    sincos(theta_deg * kDeg2Rad, &sth, &cth);
+    double ar[MB], ai[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        ar[m] = 0.0;
+        ai[m] = 0.0;
+        if (m < M) {
+            double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
+            double r = c - rint(c);
+            sincospi(2.0 * r, &ai[m], &ar[m]);
+        }
+    }
+    double Q = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double2* bk = B + (size_t)k * M;
+        double yr = 0.0, yi = 0.0;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (m < M) {
+                double2 b = bk[m];
+                // conj(b) * a = (br ar + bi ai) + j (br ai - bi ar)
+                yr += b.x * ar[m] + b.y * ai[m];
+                yi += b.x * ai[m] - b.y * ar[m];
+            }
+        }
+        Q += yr * yr + yi * yi;
+    }
+    return Q;
+}
+
+// Host-side launchers (defined next to their kernels).
+hipError_t launch_cov(bool c128, const CovItem* items, int n_items, const FrameDev* frames,
+                      const void* X, char* ws, hipStream_t s);
+hipError_t launch_evd(const FrameDev* frames, int n_frames, int max_M, const EvdParams& p,
+                      const GroupDev* groups, char* ws, uint32_t* status, hipStream_t s);
+hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
+                           const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                           const char* ws, float* spec, int use_user_spec, hipStream_t s);
+hipError_t launch_scan_f64(const PointItem* items, int n_items, int max_M,
+                           const FrameDev* frames, const double* pos, const char* ws,
+                           double* spec, int use_user_spec, hipStream_t s);
+hipError_t launch_peaks(bool f64, int max_M, const int32_t* frame_list, int n_frames,
+                        const FrameDev* frames, const double* pos, const char* ws, void* spec,
+                        const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
+                        hipStream_t s);
+
+}  // namespace nssdoa

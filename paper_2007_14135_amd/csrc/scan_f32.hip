@@ -1,0 +1,158 @@
+// Step-5 (Table 2): pseudo-spectrum scan P(theta_l) = 1 / ||B^H a(theta_l)||^2 in FP32 on the
+// matrix cores, for every frame of a group that shares one array geometry and one grid.
+//
+// Real embedding: with a = ar + j ai and a column b of B,
+//   Re(b^H a) = br.ar + bi.ai,   Im(b^H a) = -bi.ar + br.ai,
+// so the complex contraction becomes the real product T = Bemb (rows) x S (columns) with inner
+// dimension 2M, Bemb holding two rows (re-row, im-row) per column of B and S the embedded
+// steering vectors (ar; ai).  Frames of a group are stacked along the rows; each frame owns a
+// multiple of 8 rows (zero padded), so every 8-row block belongs to exactly one frame and
+// Q_f(l) = sum of T^2 over the frame's rows.
+//
+// MFMA mapping (v_mfma_f32_32x32x2f32, D[i][j] += A[i][k] B[k][j], i, j < 32, k < 2):
+//   A operand = Bemb rows (lane h*32+i holds row i, inner 2s+h), B operand = steering
+//   (lane h*32+j holds angle j, inner 2s+h), s = 0..M-1 covers the 2M inner values.
+//   The accumulator register r of lane h*32+j holds row 8*(r/4) + 4h + r%4 of angle j, so the
+//   sum of squares of registers 4g..4g+3 is the half of 8-row block g held by this lane; the
+//   other half is in lane j + 32(1-h) and is added once per frame at the write.
+// Each wave owns 64 angles (two 32-angle column tiles sharing every A operand); a workgroup of
+// four waves owns 256 angles and one chunk of whole frames.  Steering values are generated once
+// per work item: the phase in cycles is formed and reduced to [-1/2, 1/2] in FP64, then
+// sincospi runs in FP32.
+#include <float.h>
+
+#include "internal.h"
+
+namespace nssdoa {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int M>
+__device__ inline void steering_regs(const double* __restrict__ p, double th, int h, float* st) {
+    double sth, cth;
+    sincos(th * kDeg2Rad, &sth, &cth);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+        const int m = 2 * j + h;
+        const double c = p[3 * m] * sth + p[3 * m + 1] * cth;   // cycles, phi = 90 deg
+        const double r = c - rint(c);
+        float s, co;
+        sincospif((float)(2.0 * r), &s, &co);
+        st[j] = co;            // inner index 2j+h < M      : Re a_m
+        st[j + M / 2] = s;     // inner index M+2j+h >= M   : Im a_m
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restrict__ items,
+                                                       const GroupDev* __restrict__ groups,
+                                                       const FrameDev* __restrict__ frames,
+                                                       const int32_t* __restrict__ blkframe,
+                                                       const double* __restrict__ pos,
+                                                       const char* __restrict__ ws,
+                                                       float* __restrict__ spec, int use_user) {
+    const ScanItem it = items[blockIdx.x];
+    const GroupDev& g = groups[it.group];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const int base = it.angle_tile * kScanAnglesPerWG + wave * kScanAnglesPerWave;
+
+    float st0[M], st1[M];
+    {
+        const double* p = pos + g.pos_off;
+        const int j = lane & 31;
+        steering_regs<M>(p, grid_angle(g.grid_start, g.grid_step, base + j), h, st0);
+        steering_regs<M>(p, grid_angle(g.grid_start, g.grid_step, base + 32 + j), h, st1);
+    }
+
+    const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
+    const int4* blk4 = reinterpret_cast<const int4*>(blkframe + g.blk_off);
+    float q0 = 0.0f, q1 = 0.0f;
+    int cur = -1;
+
+    auto flush = [&](int f) {
+        const float t0 = q0 + __shfl_xor(q0, 32);
+        const float t1 = q1 + __shfl_xor(q1, 32);
+        const float v = (lane < 32) ? t0 : t1;
+        const int l = base + lane;          // col tile lane/32, angle lane%32
+        if (l < g.L) {
+            const FrameDev& fd = frames[f];
+            float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
+            out[l] = 1.0f / fmaxf(v, FLT_MIN);
+        }
+    };
+
+    float b[M];
+    if (it.t0 < it.t1) {
+        const float4* src = reinterpret_cast<const float4*>(emb + (size_t)it.t0 * 64 * M);
+#pragma unroll
+        for (int v = 0; v < M / 4; ++v) {
+            const float4 x = src[v];
+            b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
+        }
+    }
+    for (int t = it.t0; t < it.t1; ++t) {
+        float bn[M];
+        if (t + 1 < it.t1) {
+            const float4* src = reinterpret_cast<const float4*>(emb + (size_t)(t + 1) * 64 * M);
+#pragma unroll
+            for (int v = 0; v < M / 4; ++v) {
+                const float4 x = src[v];
+                bn[4 * v] = x.x; bn[4 * v + 1] = x.y; bn[4 * v + 2] = x.z; bn[4 * v + 3] = x.w;
+            }
+        }
+        floatx16 a0 = {0.0f}, a1 = {0.0f};
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st0[s], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st1[s], a1, 0, 0, 0);
+        }
+        const int4 fb = blk4[t];
+        const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+            const int f = fbk[gq];
+            if (f != cur) {
+                if (cur >= 0) flush(cur);
+                cur = f;
+                q0 = 0.0f;
+                q1 = 0.0f;
+            }
+            q0 += a0[4 * gq] * a0[4 * gq] + a0[4 * gq + 1] * a0[4 * gq + 1] +
+                  a0[4 * gq + 2] * a0[4 * gq + 2] + a0[4 * gq + 3] * a0[4 * gq + 3];
+            q1 += a1[4 * gq] * a1[4 * gq] + a1[4 * gq + 1] * a1[4 * gq + 1] +
+                  a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
+        }
+#pragma unroll
+        for (int s = 0; s < M; ++s) b[s] = bn[s];
+    }
+    if (cur >= 0) flush(cur);
+}
+
+template <int M>
+hipError_t launch_m(const ScanItem* items, int n_items, const GroupDev* groups,
+                    const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                    const char* ws, float* spec, int use_user, hipStream_t s) {
+    hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
+                       blkframe, pos, ws, spec, use_user);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
+                           const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                           const char* ws, float* spec, int use_user, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (M) {
+        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
+        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
+        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
+        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nssdoa
