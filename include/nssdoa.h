@@ -159,7 +159,9 @@ nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan);
  * array and a grid, and upload the schedule to the current device (the batch owns it).
  * frames[n_frames] is a host array, copied.  max_D is the peak slots per frame in the outputs.
  * EINVAL: NULL pointers, n_frames < 1, unknown array/grid ids, N < 1, D < 1, D >= M, D > max_D,
- * ldx < N, negative offsets, max_D > 64; for C64 the array's M must be 8, 16, 32 or 64.
+ * ldx < N, negative offsets, max_D > 64, a grid longer than 4096 * floor(4096 / (D +
+ * extra_candidates)) points (the peak candidate capacity); for C64 the array's M must be 8, 16,
+ * 32 or 64.
  * EUNSUPPORTED: BF16/F16.  EDEVICE/ENOMEM: device upload failed. */
 nssdoa_status nssdoa_batch_create(nssdoa_batch* batch, nssdoa_plan plan, nssdoa_alg alg,
                                   nssdoa_prec prec, const nssdoa_frame* frames, int32_t n_frames,

@@ -70,8 +70,10 @@ struct nssdoa_batch_s {
     std::vector<PointItem> point_items;
     std::vector<int32_t> blk;
     std::vector<double> pos;
-    std::vector<int32_t> peak_list;             // frames grouped by M bucket
+    std::vector<int32_t> peak_list;             // frames grouped by M bucket (8, 16, 32, 64)
     std::vector<std::pair<int, std::pair<int, int>>> peak_ranges;   // bucket M -> [begin, end)
+    std::vector<PointItem> refine_items;        // (frame, chunk start), grouped like peak_list
+    std::vector<std::pair<int, int>> refine_ranges;                 // per bucket [begin, end)
     size_t ws_bytes = 0;
     size_t spec_elem = 4;
     size_t x_extent = 0;       // complex elements of X the frames address
@@ -86,6 +88,8 @@ struct nssdoa_batch_s {
     int32_t* d_blk = nullptr;
     double* d_pos = nullptr;
     int32_t* d_plist = nullptr;
+    PointItem* d_refine = nullptr;
+    double2* d_cis = nullptr;
     // timing
     bool timing = false;
     std::vector<StageEvents> pending;
@@ -220,6 +224,14 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         if (fr.D > max_D) return fail(NSSDOA_EINVAL, "frame %d: D=%d > max_D=%d", f, fr.D, max_D);
         if (fr.ldx < fr.N) return fail(NSSDOA_EINVAL, "frame %d: ldx < N", f);
         if (fr.x_off < 0 || fr.spec_off < 0) return fail(NSSDOA_EINVAL, "frame %d: negative offset", f);
+        {
+            const int64_t L = plan->grids[fr.grid_id].L;
+            const int64_t slots = (L + kRefineChunk - 1) / kRefineChunk * (fr.D + plan->opt.extra_candidates);
+            if (slots > kSelCap)
+                return fail(NSSDOA_EINVAL, "frame %d: grid of %lld points with D + extra_candidates = %d "
+                            "exceeds the peak candidate capacity (%d slots of %d-point chunks)", f,
+                            (long long)L, fr.D + plan->opt.extra_candidates, kSelCap, kRefineChunk);
+        }
         if (prec == NSSDOA_C64 && (M % 8 != 0 || M > 64))
             return fail(NSSDOA_EINVAL, "frame %d: the FP32 scan needs M in {8, 16, 32, 64} (M=%d)", f, M);
     }
@@ -310,6 +322,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.ws_evecs = (int64_t)off;   off = align_up(off + MM * 16);
         fd.ws_B = (int64_t)off;       off = align_up(off + (size_t)fd.M * fd.K * 16);
         fd.ws_qref = (int64_t)off;    off = align_up(off + 8);
+        const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk;
+        fd.ws_cand = (int64_t)off;    off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
     }
     if (prec == NSSDOA_C64) {
         for (size_t g = 0; g < b->groups.size(); ++g) {
@@ -373,15 +387,21 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     // the internal spectrum offsets above are relative to the workspace base in elements
     // (the region is aligned to the element size because every earlier region is 256-aligned)
 
-    // peak frame lists by M bucket
+    // frame lists and refine work items by M bucket
     for (int mb : {8, 16, 32, 64}) {
         const int begin = (int)b->peak_list.size();
+        const int ibegin = (int)b->refine_items.size();
         for (int f = 0; f < n_frames; ++f) {
             const int M = b->frames[f].M;
             const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
-            if (bucket == mb) b->peak_list.push_back(f);
+            if (bucket != mb) continue;
+            b->peak_list.push_back(f);
+            for (int l0 = 0; l0 < b->frames[f].L; l0 += kRefineChunk) b->refine_items.push_back({f, l0});
         }
-        if ((int)b->peak_list.size() > begin) b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
+        if ((int)b->peak_list.size() > begin) {
+            b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
+            b->refine_ranges.push_back({ibegin, (int)b->refine_items.size()});
+        }
     }
 
     // upload the schedule
@@ -393,7 +413,9 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     size_t o_blk = align_up(o_pts + b->point_items.size() * sizeof(PointItem));
     size_t o_pos = align_up(o_blk + b->blk.size() * sizeof(int32_t));
     size_t o_pl = align_up(o_pos + b->pos.size() * sizeof(double));
-    size_t total = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
+    size_t o_ri = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
+    size_t o_cis = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
+    size_t total = align_up(o_cis + kCisTable * sizeof(double2));
     std::vector<char> host(total, 0);
     auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(host.data() + o, src, n); };
     put(o_frames, b->frames.data(), b->frames.size() * sizeof(FrameDev));
@@ -404,6 +426,17 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     put(o_blk, b->blk.data(), b->blk.size() * sizeof(int32_t));
     put(o_pos, b->pos.data(), b->pos.size() * sizeof(double));
     put(o_pl, b->peak_list.data(), b->peak_list.size() * sizeof(int32_t));
+    put(o_ri, b->refine_items.data(), b->refine_items.size() * sizeof(PointItem));
+    {
+        // exp(j 2 pi k / 256), k = -128..128, from extended-precision host sin/cos
+        std::vector<double2> cis(kCisTable);
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int k = -128; k <= 128; ++k) {
+            const long double a = pi * (long double)k / 128.0L;
+            cis[k + 128] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+        put(o_cis, cis.data(), cis.size() * sizeof(double2));
+    }
     hipError_t e = hipMalloc((void**)&b->dev, total);
     if (e != hipSuccess) {
         delete b;
@@ -423,6 +456,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->d_blk = reinterpret_cast<int32_t*>(b->dev + o_blk);
     b->d_pos = reinterpret_cast<double*>(b->dev + o_pos);
     b->d_plist = reinterpret_cast<int32_t*>(b->dev + o_pl);
+    b->d_refine = reinterpret_cast<PointItem*>(b->dev + o_ri);
+    b->d_cis = reinterpret_cast<double2*>(b->dev + o_cis);
     plan->live_batches++;
     *out = b;
     return NSSDOA_OK;
@@ -540,14 +575,17 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     ep.tol = opt.jacobi_tol;
     ep.max_sweeps = opt.max_sweeps;
     ep.write_emb = c128 ? 0 : 1;
-    e = launch_evd(batch->d_frames, batch->n_frames, batch->max_M, ep, batch->d_groups, ws, status, s);
-    if (e != hipSuccess) return hip_fail(e, "eigen launch");
+    for (auto& r : batch->peak_ranges) {
+        e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
+                       batch->d_frames, batch->d_groups, ws, status, s);
+        if (e != hipSuccess) return hip_fail(e, "eigen launch");
+    }
     if ((st = stage_end(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
 
     if ((st = stage_begin()) != NSSDOA_OK) return st;
     if (c128) {
         e = launch_scan_f64(batch->d_points, (int)batch->point_items.size(), batch->max_M, batch->d_frames,
-                            batch->d_pos, ws, static_cast<double*>(spec), use_user, s);
+                            batch->d_pos, batch->d_cis, ws, static_cast<double*>(spec), use_user, s);
         if (e != hipSuccess) return hip_fail(e, "FP64 scan launch");
     } else {
         for (auto& r : batch->scan_ranges) {
@@ -568,9 +606,12 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     pp.refine_lowq = c128 ? 0 : 1;
     pp.use_user_spec = use_user;
     pp.pad = 0;
-    for (auto& r : batch->peak_ranges) {
-        e = launch_peaks(c128, r.first, batch->d_plist + r.second.first, r.second.second - r.second.first,
-                         batch->d_frames, batch->d_pos, ws, spec, pp, peaks, npeaks, status, s);
+    for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
+        const auto& r = batch->peak_ranges[i];
+        const auto& ri = batch->refine_ranges[i];
+        e = launch_peaks(c128, r.first, batch->d_refine + ri.first, ri.second - ri.first,
+                         batch->d_plist + r.second.first, r.second.second - r.second.first,
+                         batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
         if (e != hipSuccess) return hip_fail(e, "peak launch");
     }
     if ((st = stage_end(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;

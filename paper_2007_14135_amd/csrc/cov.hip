@@ -60,16 +60,34 @@ __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
 
     const TIn* xf = X + fr.x_off;
+    // Tiles are staged through registers: the next tile's loads are in flight while the current
+    // tile is being accumulated.  Thread tid stages elements e = tid + u * 256 (m = e / NT).
+    constexpr int kPer = kTileElems / kThreads;
+    int em[kPer], en[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * kThreads;
+        em[u] = e / NT;
+        en[u] = e - em[u] * NT;
+    }
+    double2 pre[kPer];
+    auto fetch = [&](int nb) {
+        const int cnt = min(NT, it.n1 - nb);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            pre[u] = make_double2(0.0, 0.0);
+            if (em[u] < M && en[u] < cnt) pre[u] = load_c<TIn>(xf + (size_t)em[u] * fr.ldx + nb + en[u]);
+        }
+    };
+    fetch(it.n0);
     for (int nb = it.n0; nb < it.n1; nb += NT) {
         const int cnt = min(NT, it.n1 - nb);
         __syncthreads();
-        for (int e = tid; e < M4 * NT; e += kThreads) {
-            const int m = e / NT, n = e - m * NT;
-            double2 v = make_double2(0.0, 0.0);
-            if (m < M && n < cnt) v = load_c<TIn>(xf + (size_t)m * fr.ldx + nb + n);
-            xs[e] = v;
-        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (em[u] < M4) xs[tid + u * kThreads] = pre[u];
         __syncthreads();
+        if (nb + NT < it.n1) fetch(nb + NT);
         if (active) {
             for (int n = g; n < cnt; n += G) {
                 double2 xi[4], xj[4];

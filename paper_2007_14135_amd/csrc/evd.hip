@@ -13,6 +13,8 @@
 // scan) as the packed real-embedded FP32 operand tiles of the scan kernel.
 #include <float.h>
 
+#include <algorithm>
+
 #include "nssdoa.h"
 #include "internal.h"
 
@@ -29,66 +31,134 @@ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x +
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// Block-wide reductions: butterfly inside each wave, then one LDS pass over the wave results.
 __device__ inline double block_max(double v, double* red) {
-    const int tid = threadIdx.x, bd = blockDim.x;
-    red[tid] = v;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) red[wid] = v;
     __syncthreads();
-    for (int s = bd >> 1; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-        __syncthreads();
-    }
     double r = red[0];
+    for (int w = 1; w < nw; ++w) r = fmax(r, red[w]);
     __syncthreads();
     return r;
 }
 
 __device__ inline double block_sum(double v, double* red) {
-    const int tid = threadIdx.x, bd = blockDim.x;
-    red[tid] = v;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) red[wid] = v;
     __syncthreads();
-    for (int s = bd >> 1; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
     double r = red[0];
+    for (int w = 1; w < nw; ++w) r += red[w];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ frames, EvdParams prm,
-                                                  const GroupDev* __restrict__ groups,
-                                                  char* __restrict__ ws,
-                                                  uint32_t* __restrict__ status) {
+// FP64 reciprocal square root and reciprocal: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rsq64(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    r = fma(0.5 * r, fma(-x, r * r, 1.0), r);
+    r = fma(0.5 * r, fma(-x, r * r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+struct Rot {
+    int p, q;
+    double c, s, t;   // t = tan * |r_pq|, the shift of the two diagonal entries
+    double2 e;        // exp(-j arg r_pq)
+};
+
+// Pivot pair k of round-robin step `step` and its rotation, from the current matrix A.
+// Position 0 holds index 0, position i >= 1 holds ((i - 1 + step) mod (Mp - 1)) + 1, and pair k
+// joins positions k and Mp-1-k.  The rotation first removes the phase of r_pq, then applies
+// [[c, s], [-s, c]] with t = sgn(theta) / (|theta| + sqrt(theta^2 + 1)),
+// theta = (r_qq - r_pp) / (2 |r_pq|); it is the identity when |r_pq| is below threshold.
+__device__ __forceinline__ Rot rotation(const double2* __restrict__ A, int ld, int M, int Mp, int step,
+                                        int k, double tol2, double floor2) {
+    const int n1 = Mp - 1;                       // 0 <= k - 1 + step < 2 (Mp - 1): no division
+    int xa = k - 1 + step;
+    xa -= (xa >= n1) ? n1 : 0;
+    const int ia = (k == 0) ? 0 : xa + 1;
+    int xb = n1 - k - 1 + step;
+    xb -= (xb >= n1) ? n1 : 0;
+    const int ib = xb + 1;
+    Rot r;
+    r.p = min(ia, ib);
+    r.q = max(ia, ib);
+    r.c = 1.0;
+    r.s = 0.0;
+    r.t = 0.0;
+    r.e = make_double2(1.0, 0.0);
+    if (r.q < M) {
+        const double2 apq = A[r.p * ld + r.q];
+        const double app = A[r.p * ld + r.p].x, aqq = A[r.q * ld + r.q].x;
+        const double ab2 = apq.x * apq.x + apq.y * apq.y;
+        if (ab2 > tol2 * fmax(fabs(app * aqq), floor2) && ab2 > 0.0) {
+            const double rab = rsq64(ab2);
+            r.e = make_double2(apq.x * rab, -apq.y * rab);
+            const double th = 0.5 * (aqq - app) * rab;
+            const double h = fma(th, th, 1.0);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) * rcp64(fabs(th) + h * rsq64(h));
+            r.c = rsq64(fma(t, t, 1.0));
+            r.s = t * r.c;
+            r.t = t * (ab2 * rab);
+        }
+    }
+    return r;
+}
+
+constexpr int kMaxTasksPerThread = 3;
+
+template <bool DB>
+__global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ flist,
+                                                   const FrameDev* __restrict__ frames, EvdParams prm,
+                                                   const GroupDev* __restrict__ groups,
+                                                   char* __restrict__ ws,
+                                                   uint32_t* __restrict__ status) {
     extern __shared__ double2 lds[];
-    __shared__ int pr[kMaxPairs], qr[kMaxPairs], perm[64];
-    __shared__ double rc[kMaxPairs], rs[kMaxPairs], rt[kMaxPairs];
-    __shared__ double2 re[kMaxPairs];
-    __shared__ double red[256];
+    __shared__ int perm[64];
+    __shared__ double red[32];
+    __shared__ double lam[64];
     __shared__ int bad;
 
-    const FrameDev& fr = frames[blockIdx.x];
+    const int fidx = flist[blockIdx.x];
+    const FrameDev& fr = frames[fidx];
     const int tid = threadIdx.x, bd = blockDim.x;
     const int M = fr.M, Mp = M + (M & 1), ld = Mp + 1, np = Mp / 2;
     double2* A = lds;
     double2* V = lds + Mp * ld;
+    double2* A2 = DB ? lds + 2 * Mp * ld : lds;   // second copy of A when double buffered
 
     if (tid == 0) bad = 0;
     __syncthreads();
 
-    // Step-1 completion: R = (sum of chunk partials) / N, Hermitian by construction.
+    // Step-1 completion: R = (sum of chunk partials, in chunk order) / N, Hermitian by construction.
     const double2* part = reinterpret_cast<const double2*>(ws + fr.ws_partial);
     double2* Rout = reinterpret_cast<double2*>(ws + fr.ws_R);
     const double dN = (double)fr.N;
+    const int nch = fr.n_chunks;
     for (int e = tid; e < Mp * Mp; e += bd) {
         const int i = e / Mp, j = e - i * Mp;
         V[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
         if (i < M && j < M) {
             if (i <= j) {
                 double2 s = make_double2(0.0, 0.0);
-                for (int c = 0; c < fr.n_chunks; ++c) {
-                    double2 v = part[(size_t)c * M * M + i * M + j];
-                    s.x += v.x;
-                    s.y += v.y;
+                for (int c0 = 0; c0 < nch; c0 += 8) {
+                    double2 v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        v[u] = (c0 + u < nch) ? part[(size_t)(c0 + u) * M * M + i * M + j] : make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        s.x += v[u].x;
+                        s.y += v[u].y;
+                    }
                 }
                 s.x = s.x / dN;
                 s.y = (i == j) ? 0.0 : s.y / dN;
@@ -110,7 +180,7 @@ __global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ f
     double2* evecs = reinterpret_cast<double2*>(ws + fr.ws_evecs);
     double2* Bout = reinterpret_cast<double2*>(ws + fr.ws_B);
     double* qref = reinterpret_cast<double*>(ws + fr.ws_qref);
-    double2* Bs = A;   // B is staged over A once the eigenpairs are extracted
+    double2* Bs = lds;   // B is staged over the first copy of A once the eigenpairs are read
 
     if (bad) {
         st |= NSSDOA_ST_NONFINITE_INPUT;
@@ -129,101 +199,115 @@ __global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ f
         for (int e = tid; e < M; e += bd) tr += fabs(A[e * ld + e].x);
         tr = block_sum(tr, red);
         const double floor2 = (1e-2 * tr) * (1e-2 * tr);
+        const int nA = np * np, nT = nA + Mp * np;
+        // task coordinates of this thread, fixed for the whole solve: an A task is a 2x2 block
+        // (pair k, pair l), a V task is (row i, pair l)
+        int tk[kMaxTasksPerThread], tl[kMaxTasksPerThread];
+#pragma unroll
+        for (int u = 0; u < kMaxTasksPerThread; ++u) {
+            const int task = tid + u * bd;
+            if (task < nA) {
+                tk[u] = task / np;
+                tl[u] = task - tk[u] * np;
+            } else {
+                const int t2 = task - nA;
+                tk[u] = t2 / np;
+                tl[u] = t2 - tk[u] * np;
+            }
+        }
         bool converged = false;
         for (int sweep = 0; sweep <= prm.max_sweeps; ++sweep) {
-            // relative off-diagonal size: max |r_pq|^2 / max(r_pp r_qq, floor^2)
-            double mx = 0.0;
-            for (int e = tid; e < M * M; e += bd) {
-                const int i = e / M, j = e - i * M;
-                if (i < j) {
+            int above = 0;
+            for (int i = 0; i < M; ++i) {
+                for (int j = i + 1 + tid; j < M; j += bd) {
                     const double2 a = A[i * ld + j];
-                    const double den = fmax(fabs(A[i * ld + i].x * A[j * ld + j].x), floor2);
                     const double num = a.x * a.x + a.y * a.y;
-                    const double r = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
-                    mx = fmax(mx, r);
+                    above |= num > tol2 * fmax(fabs(A[i * ld + i].x * A[j * ld + j].x), floor2);
                 }
             }
-            mx = block_max(mx, red);
-            if (mx <= tol2) {
+            if (!__syncthreads_or(above)) {
                 converged = true;
                 break;
             }
             if (sweep == prm.max_sweeps) break;
             for (int step = 0; step < Mp - 1; ++step) {
-                if (tid < np) {
-                    // round-robin: position 0 holds index 0, position i >= 1 holds
-                    // ((i - 1 + step) mod (Mp - 1)) + 1; pair k joins positions k and Mp-1-k.
-                    const int k = tid;
-                    const int ia = (k == 0) ? 0 : ((k - 1 + step) % (Mp - 1)) + 1;
-                    const int kb = Mp - 1 - k;
-                    const int ib = ((kb - 1 + step) % (Mp - 1)) + 1;
-                    const int p = min(ia, ib), q = max(ia, ib);
-                    pr[k] = p;
-                    qr[k] = q;
-                    double c = 1.0, s = 0.0, t = 0.0;
-                    double2 e = make_double2(1.0, 0.0);
-                    if (q < M) {
-                        const double2 apq = A[p * ld + q];
-                        const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
-                        const double ab = hypot(apq.x, apq.y);
-                        if (ab > prm.tol * sqrt(fmax(fabs(app * aqq), floor2)) && ab > 0.0) {
-                            e = make_double2(apq.x / ab, -apq.y / ab);     // exp(-j arg r_pq)
-                            const double th = (aqq - app) / (2.0 * ab);
-                            t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                            c = 1.0 / sqrt(1.0 + t * t);
-                            s = t * c;
-                            t = t * ab;
-                        }
-                    }
-                    rc[k] = c;
-                    rs[k] = s;
-                    rt[k] = t;
-                    re[k] = e;
-                }
-                __syncthreads();
-                const int nA = np * np, nV = Mp * np;
-                for (int task = tid; task < nA + nV; task += bd) {
+                // every thread derives the rotations its tasks need from the current A, reads
+                // its blocks, and (after a barrier when A is updated in place) writes them
+                Rot rk[kMaxTasksPerThread], rl[kMaxTasksPerThread];
+                double2 b[kMaxTasksPerThread][4];
+#pragma unroll
+                for (int u = 0; u < kMaxTasksPerThread; ++u) {
+                    const int task = tid + u * bd;
+                    if (task >= nT) break;
                     if (task < nA) {
-                        const int k = task / np, l = task - k * np;
-                        const int p1 = pr[k], q1 = qr[k];
+                        const int k = tk[u], l = tl[u];
+                        rk[u] = rotation(A, ld, M, Mp, step, k, tol2, floor2);
+                        rl[u] = (l == k) ? rk[u] : rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        b[u][0] = A[rk[u].p * ld + rl[u].p];
+                        b[u][1] = A[rk[u].p * ld + rl[u].q];
+                        b[u][2] = A[rk[u].q * ld + rl[u].p];
+                        b[u][3] = A[rk[u].q * ld + rl[u].q];
+                    } else {
+                        const int i = tk[u], l = tl[u];
+                        rl[u] = rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        rk[u].p = i;
+                        b[u][0] = V[i * ld + rl[u].p];
+                        b[u][1] = V[i * ld + rl[u].q];
+                    }
+                }
+                if (!DB) __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kMaxTasksPerThread; ++u) {
+                    const int task = tid + u * bd;
+                    if (task >= nT) break;
+                    if (task < nA) {
+                        const int k = tk[u], l = tl[u];
+                        const Rot& r1 = rk[u];
+                        const Rot& r2 = rl[u];
+                        double2 o11, o12, o21, o22;
                         if (k == l) {
-                            if (rs[k] != 0.0) {
-                                A[p1 * ld + p1] = make_double2(A[p1 * ld + p1].x - rt[k], 0.0);
-                                A[q1 * ld + q1] = make_double2(A[q1 * ld + q1].x + rt[k], 0.0);
-                                A[p1 * ld + q1] = make_double2(0.0, 0.0);
-                                A[q1 * ld + p1] = make_double2(0.0, 0.0);
+                            // diagonal block: the rotation annihilates r_pq exactly
+                            o11 = make_double2(b[u][0].x - r1.t, 0.0);
+                            o22 = make_double2(b[u][3].x + r1.t, 0.0);
+                            o12 = make_double2(0.0, 0.0);
+                            o21 = o12;
+                            if (r1.s == 0.0) {
+                                o11 = b[u][0];
+                                o12 = b[u][1];
+                                o21 = b[u][2];
+                                o22 = b[u][3];
                             }
                         } else {
-                            const int p2 = pr[l], q2 = qr[l];
-                            const double c1 = rc[k], s1 = rs[k], c2 = rc[l], s2 = rs[l];
-                            const double2 e1 = re[k], e2 = re[l];
-                            const double2 b11 = A[p1 * ld + p2], b12 = A[p1 * ld + q2];
-                            const double2 b21 = A[q1 * ld + p2], b22 = A[q1 * ld + q2];
-                            // right: B J_l, J = [[c, s], [-s e, c e]]
-                            const double2 se2 = cscale(s2, e2), ce2 = cscale(c2, e2);
-                            const double2 r11 = csub(cscale(c2, b11), cmul(b12, se2));
-                            const double2 r12 = cadd(cscale(s2, b11), cmul(b12, ce2));
-                            const double2 r21 = csub(cscale(c2, b21), cmul(b22, se2));
-                            const double2 r22 = cadd(cscale(s2, b21), cmul(b22, ce2));
-                            // left: J_k^H (B J_l), J^H = [[c, -s conj(e)], [s, c conj(e)]]
-                            const double2 se1 = cscale(s1, cconj(e1)), ce1 = cscale(c1, cconj(e1));
-                            A[p1 * ld + p2] = csub(cscale(c1, r11), cmul(se1, r21));
-                            A[p1 * ld + q2] = csub(cscale(c1, r12), cmul(se1, r22));
-                            A[q1 * ld + p2] = cadd(cscale(s1, r11), cmul(ce1, r21));
-                            A[q1 * ld + q2] = cadd(cscale(s1, r12), cmul(ce1, r22));
+                            // right: B J_l with J = [[c, s], [-s e, c e]]
+                            const double2 se2 = cscale(r2.s, r2.e), ce2 = cscale(r2.c, r2.e);
+                            const double2 x11 = csub(cscale(r2.c, b[u][0]), cmul(b[u][1], se2));
+                            const double2 x12 = cadd(cscale(r2.s, b[u][0]), cmul(b[u][1], ce2));
+                            const double2 x21 = csub(cscale(r2.c, b[u][2]), cmul(b[u][3], se2));
+                            const double2 x22 = cadd(cscale(r2.s, b[u][2]), cmul(b[u][3], ce2));
+                            // left: J_k^H (B J_l) with J^H = [[c, -s conj(e)], [s, c conj(e)]]
+                            const double2 se1 = cscale(r1.s, cconj(r1.e)), ce1 = cscale(r1.c, cconj(r1.e));
+                            o11 = csub(cscale(r1.c, x11), cmul(se1, x21));
+                            o12 = csub(cscale(r1.c, x12), cmul(se1, x22));
+                            o21 = cadd(cscale(r1.s, x11), cmul(ce1, x21));
+                            o22 = cadd(cscale(r1.s, x12), cmul(ce1, x22));
                         }
+                        A2[r1.p * ld + r2.p] = o11;
+                        A2[r1.p * ld + r2.q] = o12;
+                        A2[r1.q * ld + r2.p] = o21;
+                        A2[r1.q * ld + r2.q] = o22;
                     } else {
-                        const int t2 = task - nA;
-                        const int i = t2 / np, l = t2 - i * np;
-                        const int p = pr[l], q = qr[l];
-                        const double c = rc[l], s = rs[l];
-                        const double2 e = re[l];
-                        const double2 v1 = V[i * ld + p], v2 = V[i * ld + q];
-                        V[i * ld + p] = csub(cscale(c, v1), cmul(v2, cscale(s, e)));
-                        V[i * ld + q] = cadd(cscale(s, v1), cmul(v2, cscale(c, e)));
+                        const Rot& r = rl[u];
+                        const int i = rk[u].p;
+                        V[i * ld + r.p] = csub(cscale(r.c, b[u][0]), cmul(b[u][1], cscale(r.s, r.e)));
+                        V[i * ld + r.q] = cadd(cscale(r.s, b[u][0]), cmul(b[u][1], cscale(r.c, r.e)));
                     }
                 }
                 __syncthreads();
+                if (DB) {
+                    double2* t = A;
+                    A = A2;
+                    A2 = t;
+                }
             }
         }
         if (!converged) st |= NSSDOA_ST_EVD_NOT_CONVERGED;
@@ -248,7 +332,7 @@ __global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ f
         double lam_k = 0.0;
         if (tid < M) lam_k = A[perm[tid] * ld + perm[tid]].x;
         __syncthreads();
-        if (tid < M) red[tid] = lam_k;
+        if (tid < M) lam[tid] = lam_k;
         __syncthreads();
 
         // Table 3, Step-3/4: B with C = B B^H
@@ -257,12 +341,12 @@ __global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ f
                 const int k = e / M, m = e - k * M;
                 double2 v = V[m * ld + perm[fr.D + k]];
                 if (fr.alg == kEV) {
-                    const double l = red[fr.D + k];
+                    const double l = lam[fr.D + k];
                     v = cscale(l > 0.0 ? 1.0 / sqrt(l) : 0.0, v);
                 }
                 Bs[e] = v;
             }
-            if (fr.alg == kEV && red[M - 1] <= 0.0) st |= NSSDOA_ST_DEGENERATE;
+            if (fr.alg == kEV && lam[M - 1] <= 0.0) st |= NSSDOA_ST_DEGENERATE;
         } else if (fr.alg == kPHD) {
             for (int m = tid; m < M; m += bd) Bs[m] = V[m * ld + perm[M - 1]];
         } else {   // MN: d = P_n e_1 / (P_n)_11 with P_n = E_n E_n^H
@@ -313,23 +397,34 @@ __global__ __launch_bounds__(256) void evd_kernel(const FrameDev* __restrict__ f
             emb[((size_t)tile * 64 + h * 32 + i) * M + s] = v;
         }
     }
-    if (tid == 0) status[blockIdx.x] = st;
+    if (tid == 0) status[fidx] = st;
 }
 
 }  // namespace
 
-hipError_t launch_evd(const FrameDev* frames, int n_frames, int max_M, const EvdParams& p,
-                      const GroupDev* groups, char* ws, uint32_t* status, hipStream_t s) {
+hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
+                      const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
+                      hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
     const int Mp = max_M + (max_M & 1);
-    const size_t lds = (size_t)2 * Mp * (Mp + 1) * sizeof(double2);
-    const int threads = max_M <= 16 ? 64 : 256;
+    // one thread per 2x2 block update and per V row-pair update of a step: 3 Mp^2 / 4 tasks,
+    // at most kMaxTasksPerThread per thread
+    const int tasks = 3 * Mp * Mp / 4;
+    const int threads = std::min(1024, std::max(64, (tasks + 63) / 64 * 64));
+    if (tasks > threads * kMaxTasksPerThread) return hipErrorInvalidValue;
+    const bool db = Mp <= 32;     // a second copy of A fits in LDS: one barrier per step
+    const size_t lds = (size_t)(db ? 3 : 2) * Mp * (Mp + 1) * sizeof(double2);
+    const void* fn = db ? (const void*)evd_kernel<true> : (const void*)evd_kernel<false>;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)evd_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(evd_kernel, dim3(n_frames), dim3(threads), lds, s, frames, p, groups, ws, status);
+    if (db)
+        hipLaunchKernelGGL(evd_kernel<true>, dim3(n_frames), dim3(threads), lds, s, frame_list, frames, p,
+                           groups, ws, status);
+    else
+        hipLaunchKernelGGL(evd_kernel<false>, dim3(n_frames), dim3(threads), lds, s, frame_list, frames, p,
+                           groups, ws, status);
     return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@ constexpr double kDeg2Rad = 0.017453292519943295;   // pi / 180, the same consta
 constexpr int kScanWaves = 4;                       // waves per scan workgroup
 constexpr int kScanAnglesPerWave = 64;              // two 32-angle MFMA column tiles
 constexpr int kScanAnglesPerWG = kScanWaves * kScanAnglesPerWave;
-constexpr int kCandCap = 2048;                      // local maxima buffered per frame
-constexpr int kMaxK = 64;
+constexpr int kRefineChunk = 4096;                  // grid points per refine/local-maximum workgroup
+constexpr int kSelCap = 4096;                       // chunk candidates gathered per frame
 
 enum Alg : int32_t { kPHD = 0, kMUSIC = 1, kEV = 2, kMN = 3 };
 
@@ -33,6 +33,7 @@ struct FrameDev {
     int64_t ws_evecs;           // M*M complex128
     int64_t ws_B;               // M*K complex128, column-major
     int64_t ws_qref;            // 1 double
+    int64_t ws_cand;            // ceil(L / kRefineChunk) * (D + extra) candidate slots of 16 bytes
     double grid_start, grid_step;
     int32_t L, circular;
     int32_t pos_off;            // offset (doubles) of this frame's 3*M positions
@@ -77,12 +78,34 @@ __device__ inline double grid_angle(double start, double step, int l) {
     return start + prod;
 }
 
+constexpr int kCisTable = 257;   // exp(j 2 pi k / 256) for k = -128..128
+
+// exp(j 2 pi r) in FP64 for |r| <= 1/2: r = k/256 + d with |d| <= 1/512; exp(j 2 pi k/256) comes
+// from a correctly rounded table and exp(j 2 pi d) from its Taylor series to degree 9
+// (|2 pi d| <= pi/256, truncation below 1e-25).
+__device__ __forceinline__ double2 cis2pi(double r, const double2* __restrict__ cis) {
+    const double kd = rint(r * 256.0);
+    const double x = fma(kd, -1.0 / 256.0, r) * 6.283185307179586;
+    const double x2 = x * x;
+    double c = fma(x2, 1.0 / 40320.0, -1.0 / 720.0);
+    c = fma(c, x2, 1.0 / 24.0);
+    c = fma(c, x2, -0.5);
+    c = fma(c, x2, 1.0);
+    double s = fma(x2, 1.0 / 362880.0, -1.0 / 5040.0);
+    s = fma(s, x2, 1.0 / 120.0);
+    s = fma(s, x2, -1.0 / 6.0);
+    s = fma(s * x2, x, x);
+    const double2 t = cis[(int)kd + 128];
+    return make_double2(t.x * c - t.y * s, fma(t.x, s, t.y * c));
+}
+
 // ||B^H a(theta)||^2 in FP64 for one direction (Eq. 2 with phi = 90 deg, Table 3 Step-4 in
 // factored form).  B is M x K complex128, column-major.  The phase in cycles is reduced to
-// [-1/2, 1/2] before the sine and cosine so that its rounding does not grow with the aperture.
+// [-1/2, 1/2] before exp(j 2 pi .) so that its rounding does not grow with the aperture.
 template <int MB>
-__device__ inline double q64_eval(const double* __restrict__ pos, int M, int K,
-                                  const double2* __restrict__ B, double theta_deg) {
+__device__ __forceinline__ double q64_eval(const double* __restrict__ pos, int M, int K,
+                                           const double2* __restrict__ B, double theta_deg,
+                                           const double2* __restrict__ cis) {
     double sth, cth;
     sincos(theta_deg * kDeg2Rad, &sth, &cth);
     double ar[MB], ai[MB];
@@ -91,22 +114,39 @@ __device__ inline double q64_eval(const double* __restrict__ pos, int M, int K,
         ar[m] = 0.0;
         ai[m] = 0.0;
         if (m < M) {
-            double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
-            double r = c - rint(c);
-            sincospi(2.0 * r, &ai[m], &ar[m]);
+            const double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
+            const double2 a = cis2pi(c - rint(c), cis);
+            ar[m] = a.x;
+            ai[m] = a.y;
         }
     }
     double Q = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double2* bk = B + (size_t)k * M;
+    int k = 0;
+    for (; k + 4 <= K; k += 4) {
+        double yr[4] = {0.0, 0.0, 0.0, 0.0}, yi[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            if (m < M) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double2 b = B[(size_t)(k + u) * M + m];
+                    // conj(b) * a = (br ar + bi ai) + j (br ai - bi ar)
+                    yr[u] = fma(b.x, ar[m], fma(b.y, ai[m], yr[u]));
+                    yi[u] = fma(b.x, ai[m], fma(-b.y, ar[m], yi[u]));
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Q += yr[u] * yr[u] + yi[u] * yi[u];
+    }
+    for (; k < K; ++k) {
         double yr = 0.0, yi = 0.0;
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
             if (m < M) {
-                double2 b = bk[m];
-                // conj(b) * a = (br ar + bi ai) + j (br ai - bi ar)
-                yr += b.x * ar[m] + b.y * ai[m];
-                yi += b.x * ai[m] - b.y * ar[m];
+                const double2 b = B[(size_t)k * M + m];
+                yr = fma(b.x, ar[m], fma(b.y, ai[m], yr));
+                yi = fma(b.x, ai[m], fma(-b.y, ar[m], yi));
             }
         }
         Q += yr * yr + yi * yi;
@@ -117,16 +157,18 @@ __device__ inline double q64_eval(const double* __restrict__ pos, int M, int K,
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_cov(bool c128, const CovItem* items, int n_items, const FrameDev* frames,
                       const void* X, char* ws, hipStream_t s);
-hipError_t launch_evd(const FrameDev* frames, int n_frames, int max_M, const EvdParams& p,
-                      const GroupDev* groups, char* ws, uint32_t* status, hipStream_t s);
+hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
+                      const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
+                      hipStream_t s);
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const double* pos,
                            const char* ws, float* spec, int use_user_spec, hipStream_t s);
 hipError_t launch_scan_f64(const PointItem* items, int n_items, int max_M,
-                           const FrameDev* frames, const double* pos, const char* ws,
-                           double* spec, int use_user_spec, hipStream_t s);
-hipError_t launch_peaks(bool f64, int max_M, const int32_t* frame_list, int n_frames,
-                        const FrameDev* frames, const double* pos, const char* ws, void* spec,
+                           const FrameDev* frames, const double* pos, const double2* cis,
+                           const char* ws, double* spec, int use_user_spec, hipStream_t s);
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items,
+                        const int32_t* frame_list, int n_frames, const FrameDev* frames,
+                        const double* pos, const double2* cis, char* ws, void* spec,
                         const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
                         hipStream_t s);
 

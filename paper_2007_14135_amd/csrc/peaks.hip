@@ -1,17 +1,22 @@
 // Step-6 (Table 2): peak search and selection, preceded for FP32 spectra by the FP64
 // re-evaluation of low-Q points.
 //
-// One workgroup per frame:
-//  1. FP32 spectra: every point with P >= 1 / (tau * ||B||_F^2), i.e. Q below tau times its
-//     typical size, is recomputed in FP64 and written back (these are the spectrum peaks, where
-//     FP32 rounding is largest relative to Q).
-//  2. Local maxima over the spectrum: P[l] > P[l-1] and the run of values equal to P[l] ends
-//     in a strictly smaller value; the run is reported at its first index.  Grid ends are not
-//     peaks unless the grid is circular.  Candidates go to an LDS list.
-//  3. The D + extra best candidates by (value desc, index asc) are kept.
-//  4. Each kept candidate's window of +-halfwidth points is evaluated in FP64.
-//  5. Local maxima of the FP64 windows are ranked by (FP64 value desc, index asc) and the first
-//     D are written.  Slots beyond the number found get idx = -1 and NaN.
+// refine_kernel, one workgroup per (frame, chunk of 4096 grid points):
+//  1. loads the chunk plus a halo of 16 points on each side into LDS; for FP32 spectra every
+//     point with P >= 1 / (tau ||B||_F^2), i.e. ||B^H a||^2 below tau times its typical size,
+//     is recomputed in FP64 (halo points are recomputed identically by both neighbours, and only
+//     the owner writes the value back);
+//  2. finds the local maxima of its own points: P[l] > P[l-1] and the run of values equal to
+//     P[l] ends in a strictly smaller value (the run is reported at its first index); grid ends
+//     are not peaks unless the grid is circular;
+//  3. writes its best D + extra maxima by (value desc, index asc) to the chunk's reserved slots,
+//     unused slots get index -1.  Slots are per chunk, so no atomics cross workgroups and the
+//     result does not depend on scheduling.
+// select_kernel, one workgroup per frame:
+//  4. ranks the chunk candidates and keeps the best D + extra;
+//  5. evaluates a window of +-halfwidth points around each in FP64;
+//  6. ranks the distinct FP64 local maxima of the windows by (value desc, index asc) and writes
+//     the first D; slots beyond the number found get idx = -1 and NaN.
 #include <float.h>
 
 #include "nssdoa.h"
@@ -20,46 +25,193 @@
 namespace nssdoa {
 namespace {
 
-constexpr int kMaxSel = 96;      // D + extra <= 64 + 16 < 96
+constexpr int kHalo = 16;
+constexpr int kLocalCap = kRefineChunk / 2;
+constexpr int kMaxSel = 96;      // D + extra <= 63 + 16 < 96
 constexpr int kMaxWin = 33;      // 2 * 16 + 1
-constexpr int kMaxFinal = 512;
+constexpr int kMaxFinal = 1024;
+
+struct Cand {
+    double v;
+    int32_t idx;
+    int32_t pad;
+};
+
+__device__ inline double qnan() { return __longlong_as_double(0x7ff8000000000000LL); }
 
 template <int MB, typename TS>
-__global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ flist,
-                                                    const FrameDev* __restrict__ frames,
-                                                    const double* __restrict__ pos,
-                                                    const char* __restrict__ ws,
-                                                    TS* __restrict__ spec, PeakParams prm,
-                                                    nssdoa_peak* __restrict__ peaks,
-                                                    int32_t* __restrict__ npeaks,
-                                                    uint32_t* __restrict__ status) {
-    __shared__ double cval[kCandCap];
-    __shared__ int cidx[kCandCap];
+__global__ __launch_bounds__(256) void refine_kernel(const PointItem* __restrict__ items,
+                                                     const FrameDev* __restrict__ frames,
+                                                     const double* __restrict__ pos,
+                                                     const double2* __restrict__ cis,
+                                                     char* __restrict__ ws, TS* __restrict__ spec,
+                                                     PeakParams prm,
+                                                     const uint32_t* __restrict__ status) {
+    __shared__ double v[kRefineChunk + 2 * kHalo];
+    __shared__ int rlist[kRefineChunk + 2 * kHalo];
+    __shared__ double lval[kLocalCap];
+    __shared__ int lidx[kLocalCap];
+    __shared__ int lcount, rcount;
+
+    const PointItem it = items[blockIdx.x];
+    const int f = it.frame;
+    const FrameDev& fr = frames[f];
+    const int tid = threadIdx.x;
+    const int L = fr.L, l0 = it.l0;
+    const int nown = min(kRefineChunk, L - l0);
+    const int span = nown + 2 * kHalo;
+    const bool circ = fr.circular != 0;
+    const int C = fr.D + prm.extra;
+    TS* P = spec + (prm.use_user_spec ? fr.spec_off_user : fr.spec_off_ws);
+    Cand* slots = reinterpret_cast<Cand*>(ws + fr.ws_cand) + (size_t)(l0 / kRefineChunk) * C;
+
+    if (status[f] & NSSDOA_ST_NONFINITE_INPUT) {
+        for (int o = tid; o < nown; o += blockDim.x) P[l0 + o] = (TS)qnan();
+        for (int s = tid; s < C; s += blockDim.x) {
+            slots[s].v = qnan();
+            slots[s].idx = -1;
+        }
+        return;
+    }
+
+    double pthr = INFINITY;
+    if (prm.refine_lowq) pthr = 1.0 / (prm.lowq_tau * *reinterpret_cast<const double*>(ws + fr.ws_qref));
+    const double* ps = pos + fr.pos_off;
+    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
+    if (tid == 0) {
+        lcount = 0;
+        rcount = 0;
+    }
+    // load the chunk and its halo; points beyond a non-circular grid end hold NaN, which
+    // compares false both ways
+    {
+        // every load of this thread is issued before the first LDS store
+        constexpr int kPer = (kRefineChunk + 2 * kHalo + 255) / 256;
+        double xs[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * 256;
+            const int l = l0 - kHalo + e;
+            double x = qnan();
+            if (e < span) {
+                if (l >= 0 && l < L) x = (double)P[l];
+                else if (circ) x = (double)P[((l % L) + L) % L];
+            }
+            xs[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * 256;
+            if (e < span) v[e] = xs[u];
+        }
+    }
+    __syncthreads();
+    if (prm.refine_lowq) {
+        // list the low-Q points, then re-evaluate them in FP64 one per thread
+        for (int e = tid; e < span; e += blockDim.x) {
+            const double x = v[e];
+            if (x == x && !(x < pthr)) rlist[atomicAdd(&rcount, 1)] = e;
+        }
+        __syncthreads();
+        const int nr = rcount;
+        for (int i = tid; i < nr; i += blockDim.x) {
+            const int e = rlist[i];
+            int l = l0 - kHalo + e;
+            if (l < 0 || l >= L) l = ((l % L) + L) % L;
+            const double Q = q64_eval<MB>(ps, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis);
+            const double x = 1.0 / fmax(Q, (double)FLT_MIN);
+            v[e] = x;
+            if (e >= kHalo && e < kHalo + nown) P[l] = (TS)x;
+        }
+        __syncthreads();
+    }
+
+    for (int o = tid; o < nown; o += blockDim.x) {
+        const int l = l0 + o;
+        if (!circ && (l == 0 || l == L - 1)) continue;
+        const int e = o + kHalo;
+        const double x = v[e];
+        if (!(x > v[e - 1])) continue;
+        int r = e + 1;
+        while (r < span && v[r] == x) ++r;
+        bool peak = false;
+        if (r < span) {
+            peak = v[r] < x;
+        } else {
+            // the run of equal values is longer than the halo: follow it in the stored spectrum
+            int rl = l0 - kHalo + r, steps = 0;
+            for (;;) {
+                if (rl >= L) {
+                    if (!circ) break;
+                    rl -= L;
+                }
+                const double y = (double)P[rl];
+                if (y != x) {
+                    peak = y < x;
+                    break;
+                }
+                if (++steps >= L) break;
+                ++rl;
+            }
+        }
+        if (peak) {
+            const int slot = atomicAdd(&lcount, 1);
+            if (slot < kLocalCap) {
+                lval[slot] = x;
+                lidx[slot] = l;
+            }
+        }
+    }
+    __syncthreads();
+    const int n = min(lcount, kLocalCap);
+    for (int i = tid; i < n; i += blockDim.x) {
+        const double vi = lval[i];
+        const int li = lidx[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += (lval[j] > vi) || (lval[j] == vi && lidx[j] < li);
+        if (rank < C) {
+            slots[rank].v = vi;
+            slots[rank].idx = li;
+        }
+    }
+    for (int s = n + tid; s < C; s += blockDim.x) {
+        slots[s].v = qnan();
+        slots[s].idx = -1;
+    }
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__ flist,
+                                                     const FrameDev* __restrict__ frames,
+                                                     const double* __restrict__ pos,
+                                                     const double2* __restrict__ cis,
+                                                     const char* __restrict__ ws, PeakParams prm,
+                                                     nssdoa_peak* __restrict__ peaks,
+                                                     int32_t* __restrict__ npeaks,
+                                                     uint32_t* __restrict__ status) {
+    __shared__ double cval[kSelCap];
+    __shared__ int cidx[kSelCap];
     __shared__ int sel[kMaxSel];
     __shared__ double win[kMaxSel * kMaxWin];
     __shared__ double fval[kMaxFinal];
     __shared__ int fidx[kMaxFinal];
-    __shared__ int ccount, fcount;
+    __shared__ int rankpos[kMaxSel];
+    __shared__ int ccount, fcount, nuniq;
 
     const int f = flist[blockIdx.x];
     const FrameDev& fr = frames[f];
     const int tid = threadIdx.x;
-    const int L = fr.L, D = fr.D, M = fr.M, K = fr.K;
+    const int L = fr.L, D = fr.D;
     const bool circ = fr.circular != 0;
-    TS* P = spec + (prm.use_user_spec ? fr.spec_off_user : fr.spec_off_ws);
-    const double* ps = pos + fr.pos_off;
-    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     nssdoa_peak* out = peaks + (size_t)f * prm.max_D;
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
     uint32_t st = status[f];
 
     if (st & NSSDOA_ST_NONFINITE_INPUT) {
-        for (int l = tid; l < L; l += blockDim.x) P[l] = (TS)nan;
         for (int r = tid; r < prm.max_D; r += blockDim.x) {
             out[r].idx = -1;
             out[r].reserved = 0;
-            out[r].angle_deg = nan;
-            out[r].value = nan;
+            out[r].angle_deg = qnan();
+            out[r].value = qnan();
         }
         if (tid == 0) {
             npeaks[f] = 0;
@@ -68,89 +220,52 @@ __global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ 
         return;
     }
 
-    // 1. FP64 re-evaluation of low-Q points of an FP32 spectrum
-    if (prm.refine_lowq) {
-        const double qref = *reinterpret_cast<const double*>(ws + fr.ws_qref);
-        const double pthr = 1.0 / (prm.lowq_tau * qref);
-        for (int l = tid; l < L; l += blockDim.x) {
-            const double v = (double)P[l];
-            if (!(v < pthr)) {
-                const double Q = q64_eval<MB>(ps, M, K, B, grid_angle(fr.grid_start, fr.grid_step, l));
-                P[l] = (TS)(1.0 / fmax(Q, (double)FLT_MIN));
-            }
-        }
-    }
+    // 4. gather the chunk candidates and keep the best C
+    const int Cc = D + prm.extra;
+    const int total = ((L + kRefineChunk - 1) / kRefineChunk) * Cc;
+    const Cand* slots = reinterpret_cast<const Cand*>(ws + fr.ws_cand);
     if (tid == 0) {
         ccount = 0;
         fcount = 0;
+        nuniq = 0;
     }
     __syncthreads();
-
-    // 2. local maxima with the plateau rule
-    for (int l = tid; l < L; l += blockDim.x) {
-        if (!circ && (l == 0 || l == L - 1)) continue;
-        const double v = (double)P[l];
-        const double vl = (double)P[l == 0 ? L - 1 : l - 1];
-        if (!(v > vl)) continue;
-        int r = l + 1, steps = 0;
-        bool peak = false;
-        for (;;) {
-            int rr = r;
-            if (rr >= L) {
-                if (!circ) break;          // the run reaches the last point: not a peak
-                rr -= L;
-            }
-            const double vr = (double)P[rr];
-            if (vr != v) {
-                peak = vr < v;
-                break;
-            }
-            if (++steps >= L) break;
-            ++r;
-        }
-        if (peak) {
-            const int slot = atomicAdd(&ccount, 1);
-            if (slot < kCandCap) {
-                cval[slot] = v;
-                cidx[slot] = l;
-            }
+    for (int i = tid; i < total; i += blockDim.x) {
+        const Cand c = slots[i];
+        if (c.idx >= 0) {
+            const int s = atomicAdd(&ccount, 1);
+            cval[s] = c.v;
+            cidx[s] = c.idx;
         }
     }
     __syncthreads();
-
-    // 3. keep the best C candidates
-    const int nc = min(ccount, kCandCap);
-    if (ccount > kCandCap) st |= NSSDOA_ST_PEAK_OVERFLOW;
-    const int C = min(nc, D + prm.extra);
+    const int nc = ccount;
+    const int C = min(nc, Cc);
     for (int i = tid; i < nc; i += blockDim.x) {
         const double vi = cval[i];
         const int li = cidx[i];
         int rank = 0;
-        for (int j = 0; j < nc; ++j) {
-            const double vj = cval[j];
-            rank += (vj > vi) || (vj == vi && cidx[j] < li);
-        }
+        for (int j = 0; j < nc; ++j) rank += (cval[j] > vi) || (cval[j] == vi && cidx[j] < li);
         if (rank < C) sel[rank] = li;
     }
     __syncthreads();
 
-    // 4. FP64 windows
+    // 5. FP64 windows around the kept candidates
+    const double* ps = pos + fr.pos_off;
+    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     const int w = prm.halfwidth, W = 2 * w + 1;
     for (int e = tid; e < C * W; e += blockDim.x) {
         const int c = e / W, o = e - c * W;
         int l = sel[c] + o - w;
-        double v = nan;
-        if (circ) {
-            l = ((l % L) + L) % L;
-            v = 1.0 / fmax(q64_eval<MB>(ps, M, K, B, grid_angle(fr.grid_start, fr.grid_step, l)), 1e-300);
-        } else if (l >= 0 && l < L) {
-            v = 1.0 / fmax(q64_eval<MB>(ps, M, K, B, grid_angle(fr.grid_start, fr.grid_step, l)), 1e-300);
-        }
-        win[c * kMaxWin + o] = v;
+        double x = qnan();
+        if (circ) l = ((l % L) + L) % L;
+        if (circ || (l >= 0 && l < L))
+            x = 1.0 / fmax(q64_eval<MB>(ps, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis), 1e-300);
+        win[c * kMaxWin + o] = x;
     }
     __syncthreads();
 
-    // 5. FP64 local maxima inside the windows (interior points with both neighbours known)
+    // 6. FP64 local maxima inside the windows (interior points: both neighbours known)
     for (int e = tid; e < C * W; e += blockDim.x) {
         const int c = e / W, o = e - c * W;
         if (o == 0 || o == W - 1) continue;
@@ -158,26 +273,20 @@ __global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ 
         if (circ) l = ((l % L) + L) % L;
         else if (l <= 0 || l >= L - 1) continue;
         const double* wv = win + c * kMaxWin;
-        const double v = wv[o];
-        if (!(v > wv[o - 1])) continue;
+        const double x = wv[o];
+        if (!(x > wv[o - 1])) continue;
         int r = o + 1;
-        while (r < W && wv[r] == v) ++r;
-        if (r < W && wv[r] < v) {
-            const int slot = atomicAdd(&fcount, 1);
-            if (slot < kMaxFinal) {
-                fval[slot] = v;
-                fidx[slot] = l;
+        while (r < W && wv[r] == x) ++r;
+        if (r < W && wv[r] < x) {
+            const int s = atomicAdd(&fcount, 1);
+            if (s < kMaxFinal) {
+                fval[s] = x;
+                fidx[s] = l;
             }
         }
     }
     __syncthreads();
-
-    // 6. rank the distinct FP64 peaks and write the first D
     const int nf = min(fcount, kMaxFinal);
-    __shared__ int nuniq;
-    __shared__ int rankpos[kMaxSel];
-    if (tid == 0) nuniq = 0;
-    __syncthreads();
     for (int i = tid; i < nf; i += blockDim.x) {
         const int li = fidx[i];
         bool dup = false;
@@ -191,8 +300,7 @@ __global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ 
             bool djdup = false;
             for (int k = 0; k < j; ++k) djdup |= (fidx[k] == lj);
             if (djdup) continue;
-            const double vj = fval[j];
-            rank += (vj > vi) || (vj == vi && lj < li);
+            rank += (fval[j] > vi) || (fval[j] == vi && lj < li);
         }
         if (rank < D) rankpos[rank] = i;
     }
@@ -208,8 +316,8 @@ __global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ 
         } else {
             out[r].idx = -1;
             out[r].reserved = 0;
-            out[r].angle_deg = nan;
-            out[r].value = nan;
+            out[r].angle_deg = qnan();
+            out[r].value = qnan();
         }
     }
     if (tid == 0) {
@@ -219,32 +327,42 @@ __global__ __launch_bounds__(256) void peaks_kernel(const int32_t* __restrict__ 
     }
 }
 
-template <typename TS>
-hipError_t launch_t(int max_M, const int32_t* flist, int n, const FrameDev* frames, const double* pos,
-                    const char* ws, TS* spec, const PeakParams& p, nssdoa_peak* peaks,
-                    int32_t* npeaks, uint32_t* status, hipStream_t s) {
-    if (max_M <= 8)
-        hipLaunchKernelGGL((peaks_kernel<8, TS>), dim3(n), dim3(256), 0, s, flist, frames, pos, ws, spec, p, peaks, npeaks, status);
-    else if (max_M <= 16)
-        hipLaunchKernelGGL((peaks_kernel<16, TS>), dim3(n), dim3(256), 0, s, flist, frames, pos, ws, spec, p, peaks, npeaks, status);
-    else if (max_M <= 32)
-        hipLaunchKernelGGL((peaks_kernel<32, TS>), dim3(n), dim3(256), 0, s, flist, frames, pos, ws, spec, p, peaks, npeaks, status);
-    else
-        hipLaunchKernelGGL((peaks_kernel<64, TS>), dim3(n), dim3(256), 0, s, flist, frames, pos, ws, spec, p, peaks, npeaks, status);
+template <int MB>
+hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_t* flist, int n_frames,
+                     const FrameDev* frames, const double* pos, const double2* cis, char* ws, void* spec,
+                     const PeakParams& p, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                     hipStream_t s) {
+    if (n_items > 0) {
+        if (f64)
+            hipLaunchKernelGGL((refine_kernel<MB, double>), dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws,
+                               static_cast<double*>(spec), p, status);
+        else
+            hipLaunchKernelGGL((refine_kernel<MB, float>), dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws,
+                               static_cast<float*>(spec), p, status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_frames > 0)
+        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), 0, s, flist, frames, pos, cis, ws, p, peaks,
+                           npeaks, status);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_peaks(bool f64, int max_M, const int32_t* frame_list, int n_frames,
-                        const FrameDev* frames, const double* pos, const char* ws, void* spec,
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items,
+                        const int32_t* frame_list, int n_frames, const FrameDev* frames,
+                        const double* pos, const double2* cis, char* ws, void* spec,
                         const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
                         hipStream_t s) {
-    if (n_frames <= 0) return hipSuccess;
     nssdoa_peak* pk = static_cast<nssdoa_peak*>(peaks);
-    if (f64)
-        return launch_t<double>(max_M, frame_list, n_frames, frames, pos, ws, static_cast<double*>(spec), p, pk, npeaks, status, s);
-    return launch_t<float>(max_M, frame_list, n_frames, frames, pos, ws, static_cast<float*>(spec), p, pk, npeaks, status, s);
+    switch (bucket_M) {
+        case 8: return launch_mb<8>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        case 16: return launch_mb<16>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        case 32: return launch_mb<32>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        case 64: return launch_mb<64>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace nssdoa

@@ -10,6 +10,7 @@ template <int MB>
 __global__ __launch_bounds__(256) void scan_f64_kernel(const PointItem* __restrict__ items,
                                                        const FrameDev* __restrict__ frames,
                                                        const double* __restrict__ pos,
+                                                       const double2* __restrict__ cis,
                                                        const char* __restrict__ ws,
                                                        double* __restrict__ spec, int use_user) {
     const PointItem it = items[blockIdx.x];
@@ -18,7 +19,7 @@ __global__ __launch_bounds__(256) void scan_f64_kernel(const PointItem* __restri
     if (l >= fr.L) return;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
-                                  grid_angle(fr.grid_start, fr.grid_step, l));
+                                  grid_angle(fr.grid_start, fr.grid_step, l), cis);
     double* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
     out[l] = 1.0 / fmax(Q, 1e-300);
 }
@@ -26,17 +27,17 @@ __global__ __launch_bounds__(256) void scan_f64_kernel(const PointItem* __restri
 }  // namespace
 
 hipError_t launch_scan_f64(const PointItem* items, int n_items, int max_M,
-                           const FrameDev* frames, const double* pos, const char* ws,
-                           double* spec, int use_user, hipStream_t s) {
+                           const FrameDev* frames, const double* pos, const double2* cis,
+                           const char* ws, double* spec, int use_user, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (max_M <= 8)
-        hipLaunchKernelGGL(scan_f64_kernel<8>, dim3(n_items), dim3(256), 0, s, items, frames, pos, ws, spec, use_user);
+        hipLaunchKernelGGL(scan_f64_kernel<8>, dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws, spec, use_user);
     else if (max_M <= 16)
-        hipLaunchKernelGGL(scan_f64_kernel<16>, dim3(n_items), dim3(256), 0, s, items, frames, pos, ws, spec, use_user);
+        hipLaunchKernelGGL(scan_f64_kernel<16>, dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws, spec, use_user);
     else if (max_M <= 32)
-        hipLaunchKernelGGL(scan_f64_kernel<32>, dim3(n_items), dim3(256), 0, s, items, frames, pos, ws, spec, use_user);
+        hipLaunchKernelGGL(scan_f64_kernel<32>, dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws, spec, use_user);
     else
-        hipLaunchKernelGGL(scan_f64_kernel<64>, dim3(n_items), dim3(256), 0, s, items, frames, pos, ws, spec, use_user);
+        hipLaunchKernelGGL(scan_f64_kernel<64>, dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws, spec, use_user);
     return hipGetLastError();
 }
 
