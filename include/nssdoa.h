@@ -59,8 +59,12 @@ typedef enum { NSSDOA_PHD = 0, NSSDOA_MUSIC = 1, NSSDOA_EV = 2, NSSDOA_MN = 3 } 
 /* Arithmetic of the spectrum scan (Step-5).  The covariance is always accumulated in FP64, and
  * the eigensolve, noise-subspace matrices and peak refinement are always FP64.
  * C128: complex128 snapshots, FP64 scan, double spectrum.
- * C64 : complex64 snapshots, FP32 scan on the matrix cores with FP32 accumulation; points whose
- *       ||B^H a||^2 is below lowq_tau * ||B||_F^2 are re-evaluated in FP64; float spectrum. */
+ * C64 : complex64 snapshots, FP32 scan on the matrix cores with FP32 accumulation; float
+ *       spectrum.
+ * BF16, F16: complex64 snapshots, scan operands rounded to bfloat16 / IEEE half on the matrix
+ *       cores with FP32 accumulation; float spectrum.
+ * For C64, BF16 and F16 every point whose scanned ||B^H a||^2 is below lowq_tau * ||B||_F^2 (the
+ * neighbourhoods of the spectrum peaks) is re-evaluated in FP64 before the peak search. */
 typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 } nssdoa_prec;
 
 /* Per-frame status bits written to status[] by nssdoa_estimate. */
@@ -73,7 +77,7 @@ typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 
 /* An array geometry: M elements at host positions pos_wl[3*m + {0,1,2}] = (x, y, z) in
  * wavelengths (Eq. 2).  The plan copies the positions; the caller may free them afterwards. */
 typedef struct {
-    int32_t M;            /* number of elements, 2 <= M <= 64 and M a multiple of 8 for C64   */
+    int32_t M;            /* elements, 2 <= M <= 64; 8, 16, 32 or 64 for the C64/BF16/F16 scans */
     int32_t reserved;     /* must be 0                                                         */
     const double* pos_wl; /* host, 3*M doubles                                                 */
 } nssdoa_array;
@@ -160,9 +164,9 @@ nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan);
  * frames[n_frames] is a host array, copied.  max_D is the peak slots per frame in the outputs.
  * EINVAL: NULL pointers, n_frames < 1, unknown array/grid ids, N < 1, D < 1, D >= M, D > max_D,
  * ldx < N, negative offsets, max_D > 64, a grid longer than 4096 * floor(4096 / (D +
- * extra_candidates)) points (the peak candidate capacity); for C64 the array's M must be 8, 16,
- * 32 or 64.
- * EUNSUPPORTED: BF16/F16.  EDEVICE/ENOMEM: device upload failed. */
+ * extra_candidates)) points (the peak candidate capacity); for C64, BF16 and F16 the array's M
+ * must be 8, 16, 32 or 64.
+ * EDEVICE/ENOMEM: device upload failed. */
 nssdoa_status nssdoa_batch_create(nssdoa_batch* batch, nssdoa_plan plan, nssdoa_alg alg,
                                   nssdoa_prec prec, const nssdoa_frame* frames, int32_t n_frames,
                                   int32_t max_D);

@@ -1,0 +1,127 @@
+"""FP64 oracle of the learned proposal stage: covariance features, MLP forward/backward, BCE
+loss, Adam, angle-bin labels and proposal windows.
+
+TEST INFRASTRUCTURE (see the package docstring).  The paper has no learned component; this
+stage is the proposal network of the batched build: a 272 -> 512 -> 512 -> 180 multilayer
+perceptron maps the normalised upper triangle of R (Eq. 3) to a 1-degree azimuth heatmap, and
+the fine scan of Table 2 Step-5 runs only in windows around its best bins.  Readings (not in the
+paper, stated here): ReLU hidden units, sigmoid outputs trained with binary cross-entropy on
+multi-hot bin labels, bin b covering [-90 + b, -89 + b) degrees, features R * M / trace(R)
+upper triangle i <= j row-major with (re, im) interleaved, He-uniform initial weights, zero
+biases, Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+SIZES = (272, 512, 512, 180)
+N_BINS = 180
+
+
+def features(R: np.ndarray) -> np.ndarray:
+    """272 features of a 16x16 covariance: R scaled by M / trace(R), upper triangle i <= j in
+    row-major order, real and imaginary parts interleaved."""
+    R = np.asarray(R, dtype=np.complex128)
+    M = R.shape[0]
+    Rn = R * (M / np.real(np.trace(R)))
+    iu, ju = np.triu_indices(M)
+    v = Rn[iu, ju]
+    out = np.empty(2 * len(v), dtype=np.float64)
+    out[0::2] = v.real
+    out[1::2] = v.imag
+    return out
+
+
+def init_params(seed: int, sizes=SIZES):
+    """He-uniform weights W_l (out x in) ~ U(-sqrt(6/in), sqrt(6/in)), zero biases, from PCG64."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(int(seed))))
+    params = []
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / fin)
+        params.append((rng.uniform(-lim, lim, size=(fout, fin)), np.zeros(fout)))
+    return params
+
+
+def forward(params, X: np.ndarray):
+    """Logits z (batch x 180) and the hidden activations, FP64.  ReLU after layers 1 and 2."""
+    X = np.asarray(X, dtype=np.float64)
+    acts = [X]
+    h = X
+    for li, (W, b) in enumerate(params):
+        z = h @ W.T + b
+        if li < len(params) - 1:
+            h = np.maximum(z, 0.0)
+            acts.append(h)
+        else:
+            h = z
+    return h, acts
+
+
+def bce_with_logits(z: np.ndarray, y: np.ndarray) -> float:
+    """Mean over batch and outputs of  max(z,0) - z y + log(1 + exp(-|z|))."""
+    z = np.asarray(z, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return float(np.mean(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def backward(params, X: np.ndarray, y: np.ndarray):
+    """Loss and gradients (dW, db) of bce_with_logits(forward(X)) by the chain rule."""
+    z, acts = forward(params, X)
+    n = z.size
+    sig = 1.0 / (1.0 + np.exp(-z))
+    delta = (sig - np.asarray(y, dtype=np.float64)) / n        # dL/dz
+    grads = [None] * len(params)
+    for li in range(len(params) - 1, -1, -1):
+        W, b = params[li]
+        a = acts[li]
+        grads[li] = (delta.T @ a, delta.sum(axis=0))
+        if li > 0:
+            delta = (delta @ W) * (acts[li] > 0.0)
+    return bce_with_logits(z, y), grads
+
+
+def adam_step(params, grads, m, v, t: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (t counts from 1); returns new params, m, v."""
+    newp, newm, newv = [], [], []
+    for (W, b), (gW, gb), (mW, mb), (vW, vb) in zip(params, grads, m, v):
+        out = []
+        for p, g, mm, vv in ((W, gW, mW, vW), (b, gb, mb, vb)):
+            mm = b1 * mm + (1.0 - b1) * g
+            vv = b2 * vv + (1.0 - b2) * g * g
+            mhat = mm / (1.0 - b1 ** t)
+            vhat = vv / (1.0 - b2 ** t)
+            out.append((p - lr * mhat / (np.sqrt(vhat) + eps), mm, vv))
+        newp.append((out[0][0], out[1][0]))
+        newm.append((out[0][1], out[1][1]))
+        newv.append((out[0][2], out[1][2]))
+    return newp, newm, newv
+
+
+def bin_labels(angles_deg, n_bins: int = N_BINS) -> np.ndarray:
+    """Multi-hot labels: bin b = floor(theta + 90), clipped to [0, n_bins - 1]."""
+    y = np.zeros(n_bins, dtype=np.float64)
+    for a in np.atleast_1d(angles_deg):
+        y[int(np.clip(np.floor(float(a) + 90.0), 0, n_bins - 1))] = 1.0
+    return y
+
+
+def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid_start: float,
+                     grid_step: float, L: int):
+    """Index ranges [l0, l1) of the global grid covered by +-half_window around the centres of the
+    topk best bins (ties to the lower bin), merged where they overlap, ascending."""
+    order = sorted(range(len(scores)), key=lambda b: (-float(scores[b]), b))[:topk]
+    rng = []
+    for b in order:
+        c = -89.5 + b
+        l0 = int(np.ceil((c - half_window_deg - grid_start) / grid_step - 1e-9))
+        l1 = int(np.floor((c + half_window_deg - grid_start) / grid_step + 1e-9)) + 1
+        rng.append((max(0, l0), min(L, l1)))
+    rng.sort()
+    merged = []
+    for a, b in rng:
+        if merged and a <= merged[-1][1]:
+            merged[-1] = (merged[-1][0], max(merged[-1][1], b))
+        else:
+            merged.append((a, b))
+    return merged

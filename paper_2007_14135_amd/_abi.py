@@ -76,11 +76,13 @@ _SIGNATURES = {
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
+def load(path: str = None) -> ctypes.CDLL:
     """Load libnssdoa.so (once) and declare its prototypes; raises if it has not been built."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError("libnssdoa.so is not built (%s); run __graft_entry__.build() first" % path)
     lib = ctypes.CDLL(path)

@@ -39,7 +39,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
-constexpr int kChunkRows = 384;      // rows of stacked B per scan work item (12 tiles)
+constexpr int kChunkRows = 384;      // rows of stacked B per FP32 scan work item (12 tiles)
+constexpr int kChunkRowsLP = 4096;   // rows per 16-bit scan work item (128 tiles)
 constexpr int kCovTargetItems = 2048;
 
 }  // namespace
@@ -74,6 +75,8 @@ struct nssdoa_batch_s {
     std::vector<std::pair<int, std::pair<int, int>>> peak_ranges;   // bucket M -> [begin, end)
     std::vector<PointItem> refine_items;        // (frame, chunk start), grouped like peak_list
     std::vector<std::pair<int, int>> refine_ranges;                 // per bucket [begin, end)
+    std::vector<PointItem> lowq_items;          // (frame, first list entry) slices of 256
+    std::vector<std::pair<int, int>> lowq_ranges;                   // per bucket [begin, end)
     size_t ws_bytes = 0;
     size_t spec_elem = 4;
     size_t x_extent = 0;       // complex elements of X the frames address
@@ -90,6 +93,7 @@ struct nssdoa_batch_s {
     int32_t* d_plist = nullptr;
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
+    PointItem* d_lowq = nullptr;
     // timing
     bool timing = false;
     std::vector<StageEvents> pending;
@@ -209,8 +213,6 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     if (alg < NSSDOA_PHD || alg > NSSDOA_MN) return fail(NSSDOA_EINVAL, "unknown algorithm %d", (int)alg);
     if (prec < NSSDOA_C128 || prec > NSSDOA_F16) return fail(NSSDOA_EINVAL, "unknown precision %d", (int)prec);
     if (max_D < 1 || max_D > 64) return fail(NSSDOA_EINVAL, "max_D=%d outside [1, 64]", max_D);
-    if (prec == NSSDOA_BF16 || prec == NSSDOA_F16)
-        return fail(NSSDOA_EUNSUPPORTED, "BF16/F16 scans are not built in this library");
     const int n_arr = (int)plan->M.size(), n_grid = (int)plan->grids.size();
     for (int f = 0; f < n_frames; ++f) {
         const nssdoa_frame& fr = frames[f];
@@ -232,8 +234,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
                             "exceeds the peak candidate capacity (%d slots of %d-point chunks)", f,
                             (long long)L, fr.D + plan->opt.extra_candidates, kSelCap, kRefineChunk);
         }
-        if (prec == NSSDOA_C64 && (M % 8 != 0 || M > 64))
-            return fail(NSSDOA_EINVAL, "frame %d: the FP32 scan needs M in {8, 16, 32, 64} (M=%d)", f, M);
+        if (prec != NSSDOA_C128 && M != 8 && M != 16 && M != 32 && M != 64)
+            return fail(NSSDOA_EINVAL, "frame %d: the matrix-core scans need M in {8, 16, 32, 64} (M=%d)", f, M);
     }
 
     auto* b = new (std::nothrow) nssdoa_batch_s();
@@ -324,8 +326,20 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.ws_qref = (int64_t)off;    off = align_up(off + 8);
         const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk;
         fd.ws_cand = (int64_t)off;    off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
+        if (prec != NSSDOA_C128) {
+            // low-Q list: room for an eighth of the grid (at least 256 points); a frame with more
+            // low-Q points re-evaluates them in its local-maximum pass instead
+            fd.lowq_cap = round_up(std::max(256, fd.L / 8), 256);
+            fd.ws_lowq = (int64_t)off;  off = align_up(off + (size_t)(fd.lowq_cap + 1) * 4);
+        }
     }
-    if (prec == NSSDOA_C64) {
+    if (prec != NSSDOA_C128) {
+        const bool lp = prec != NSSDOA_C64;
+        // rows of stacked B per scan work item: the 16-bit scans form their steering operands
+        // per work item at a cost comparable to 64 tiles of their MFMA work, so they take
+        // longer chunks
+        const int chunk_rows = lp ? kChunkRowsLP : kChunkRows;
+        const size_t emb_elem = lp ? 2 : sizeof(float);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             GroupDev& gd = b->groups[g];
             int row = 0, chunk_start = 0, chunk_frames = 0;
@@ -334,7 +348,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             for (int f : gframes[g]) {
                 FrameDev& fd = b->frames[f];
                 const int rows = round_up(2 * fd.K, 8);
-                if (chunk_frames > 0 && (row - chunk_start) + rows > kChunkRows) {
+                if (chunk_frames > 0 && (row - chunk_start) + rows > chunk_rows) {
                     const int end = round_up(row, 32);
                     b->frames[last_f].emb_rows += end - row;   // the last frame zero-fills the tail
                     chunks.push_back({chunk_start / 32, end / 32});
@@ -359,7 +373,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
                     b->blk[gd.blk_off + r / 8] = f;
             }
             gd.ws_emb = (int64_t)off;
-            off = align_up(off + (size_t)gd.n_tiles * 64 * gd.M * sizeof(float));
+            off = align_up(off + (size_t)gd.n_tiles * 64 * gd.M * emb_elem);
             const int n_at = (gd.L + kScanAnglesPerWG - 1) / kScanAnglesPerWG;
             for (auto& ch : chunks)
                 for (int at = 0; at < n_at; ++at)
@@ -391,16 +405,19 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     for (int mb : {8, 16, 32, 64}) {
         const int begin = (int)b->peak_list.size();
         const int ibegin = (int)b->refine_items.size();
+        const int lbegin = (int)b->lowq_items.size();
         for (int f = 0; f < n_frames; ++f) {
             const int M = b->frames[f].M;
             const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
             if (bucket != mb) continue;
             b->peak_list.push_back(f);
             for (int l0 = 0; l0 < b->frames[f].L; l0 += kRefineChunk) b->refine_items.push_back({f, l0});
+            for (int i0 = 0; i0 < b->frames[f].lowq_cap; i0 += 256) b->lowq_items.push_back({f, i0});
         }
         if ((int)b->peak_list.size() > begin) {
             b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
             b->refine_ranges.push_back({ibegin, (int)b->refine_items.size()});
+            b->lowq_ranges.push_back({lbegin, (int)b->lowq_items.size()});
         }
     }
 
@@ -414,7 +431,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     size_t o_pos = align_up(o_blk + b->blk.size() * sizeof(int32_t));
     size_t o_pl = align_up(o_pos + b->pos.size() * sizeof(double));
     size_t o_ri = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
-    size_t o_cis = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
+    size_t o_lq = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
+    size_t o_cis = align_up(o_lq + b->lowq_items.size() * sizeof(PointItem));
     size_t total = align_up(o_cis + kCisTable * sizeof(double2));
     std::vector<char> host(total, 0);
     auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(host.data() + o, src, n); };
@@ -427,6 +445,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     put(o_pos, b->pos.data(), b->pos.size() * sizeof(double));
     put(o_pl, b->peak_list.data(), b->peak_list.size() * sizeof(int32_t));
     put(o_ri, b->refine_items.data(), b->refine_items.size() * sizeof(PointItem));
+    put(o_lq, b->lowq_items.data(), b->lowq_items.size() * sizeof(PointItem));
     {
         // exp(j 2 pi k / 256), k = -128..128, from extended-precision host sin/cos
         std::vector<double2> cis(kCisTable);
@@ -458,6 +477,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->d_plist = reinterpret_cast<int32_t*>(b->dev + o_pl);
     b->d_refine = reinterpret_cast<PointItem*>(b->dev + o_ri);
     b->d_cis = reinterpret_cast<double2*>(b->dev + o_cis);
+    b->d_lowq = reinterpret_cast<PointItem*>(b->dev + o_lq);
     plan->live_batches++;
     *out = b;
     return NSSDOA_OK;
@@ -566,7 +586,7 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     hipError_t e;
 
     if ((st = stage_begin()) != NSSDOA_OK) return st;
-    e = launch_cov(c128, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, s);
+    e = launch_cov(c128, batch->max_M, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, s);
     if (e != hipSuccess) return hip_fail(e, "covariance launch");
     if ((st = stage_end(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
 
@@ -574,7 +594,7 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     EvdParams ep;
     ep.tol = opt.jacobi_tol;
     ep.max_sweeps = opt.max_sweeps;
-    ep.write_emb = c128 ? 0 : 1;
+    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? 1 : batch->prec == NSSDOA_BF16 ? 2 : 3;
     for (auto& r : batch->peak_ranges) {
         e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
                        batch->d_frames, batch->d_groups, ws, status, s);
@@ -589,10 +609,16 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
         if (e != hipSuccess) return hip_fail(e, "FP64 scan launch");
     } else {
         for (auto& r : batch->scan_ranges) {
-            e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
-                                batch->d_groups, batch->d_frames, batch->d_blk, batch->d_pos, ws,
-                                static_cast<float*>(spec), use_user, s);
-            if (e != hipSuccess) return hip_fail(e, "FP32 scan launch");
+            if (batch->prec == NSSDOA_C64)
+                e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
+                                    batch->d_groups, batch->d_frames, batch->d_blk, batch->d_pos, ws,
+                                    static_cast<float*>(spec), use_user, (float)opt.lowq_tau, s);
+            else
+                e = launch_scan_lp(batch->prec == NSSDOA_F16, r.first, batch->d_scan + r.second.first,
+                                   r.second.second - r.second.first, batch->d_groups, batch->d_frames,
+                                   batch->d_blk, batch->d_pos, ws, static_cast<float*>(spec), use_user,
+                                   (float)opt.lowq_tau, s);
+            if (e != hipSuccess) return hip_fail(e, "scan launch");
         }
     }
     if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
@@ -609,7 +635,9 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
         const auto& r = batch->peak_ranges[i];
         const auto& ri = batch->refine_ranges[i];
-        e = launch_peaks(c128, r.first, batch->d_refine + ri.first, ri.second - ri.first,
+        const auto& rq = batch->lowq_ranges[i];
+        e = launch_peaks(c128, r.first, batch->d_lowq + rq.first, rq.second - rq.first,
+                         batch->d_refine + ri.first, ri.second - ri.first,
                          batch->d_plist + r.second.first, r.second.second - r.second.first,
                          batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
         if (e != hipSuccess) return hip_fail(e, "peak launch");

@@ -1,6 +1,17 @@
 // Step-1 (Eq. 3): partial sample covariances  sum_n x_i[n] conj(x_j[n])  over snapshot chunks.
 //
-// One workgroup per (frame, snapshot chunk).  The chunk is staged through LDS in tiles of
+// Two kernels compute the same partial sums; both accumulate in FP64.  For complex64 input
+// every product of two FP32 values is exact in FP64, so the only rounding is the accumulation.
+//
+// cov_mfma_kernel (M <= 32): the real-embedded Gram on the FP64 matrix cores.  With
+// Y = [Re X; Im X], Re R = Xr Xr^T + Xi Xi^T and Im R = Xi Xr^T - (Xi Xr^T)^T, so per 16-row
+// block pair three 16x16x4 products are accumulated.  Lane l holds element l%16 of snapshot
+// group l/16: that one register is both the A operand (A[i][k], i = l%16, k = l/16) and the
+// B operand (B[k][j], j = l%16) of v_mfma_f64_16x16x4f64, whose result register r of lane l is
+// D[l/16 + 4r][l%16].  Each wave owns every fourth 16-snapshot block of the chunk and prefetches
+// the next block while the matrix cores run; the four waves are reduced in LDS in fixed order.
+//
+// cov_kernel (any M): the chunk is staged through LDS in tiles of
 // 1024 complex values converted to FP64; each thread owns a 4x4 block of the upper block
 // triangle of R for a strided subset of the tile's snapshots and accumulates in FP64.  For
 // complex64 input every product of two FP32 values is exact in FP64, so the only rounding is
@@ -32,7 +43,7 @@ __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict
                                                        const FrameDev* __restrict__ frames,
                                                        const TIn* __restrict__ X,
                                                        char* __restrict__ ws) {
-    __shared__ double2 xs[kTileElems];
+    __shared__ double2 xs[kTileElems + 64];     // rows padded by one element (bank conflicts)
     __shared__ double2 red[kThreads];
 
     const CovItem it = items[blockIdx.x];
@@ -85,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kPer; ++u)
-            if (em[u] < M4) xs[tid + u * kThreads] = pre[u];
+            if (em[u] < M4) xs[em[u] * (NT + 1) + en[u]] = pre[u];
         __syncthreads();
         if (nb + NT < it.n1) fetch(nb + NT);
         if (active) {
@@ -93,8 +104,8 @@ __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict
                 double2 xi[4], xj[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    xi[a] = xs[(4 * ti + a) * NT + n];
-                    xj[a] = xs[(4 * tj + a) * NT + n];
+                    xi[a] = xs[(4 * ti + a) * (NT + 1) + n];
+                    xj[a] = xs[(4 * tj + a) * (NT + 1) + n];
                 }
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
@@ -132,11 +143,131 @@ __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict
         }
 }
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename TIn, int RB>   // RB = 16-row blocks (M <= 16 RB)
+__global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict__ items,
+                                                       const FrameDev* __restrict__ frames,
+                                                       const TIn* __restrict__ X,
+                                                       char* __restrict__ ws) {
+    constexpr int NP = RB * (RB + 1) / 2;          // symmetric block pairs (I <= J)
+    constexpr int NX = RB * RB;                    // all block pairs of Xi Xr^T
+    __shared__ double sre[4][RB * 16][RB * 16 + 1];
+    __shared__ double sim[4][RB * 16][RB * 16 + 1];
+
+    const CovItem it = items[blockIdx.x];
+    const FrameDev& fr = frames[it.frame];
+    const int M = fr.M;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mi = lane & 15, q = lane >> 4;       // element in a row block, snapshot group
+
+    doublex4 drr[NP], dii[NP], dir[NX];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) { drr[t] = doublex4{0, 0, 0, 0}; dii[t] = doublex4{0, 0, 0, 0}; }
+#pragma unroll
+    for (int t = 0; t < NX; ++t) dir[t] = doublex4{0, 0, 0, 0};
+
+    const TIn* xf = X + fr.x_off;
+    // per row block b: this lane's element row and whether it exists
+    const TIn* rowp[RB];
+    bool rowok[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        const int m = b * 16 + mi;
+        rowok[b] = m < M;
+        rowp[b] = xf + (size_t)(rowok[b] ? m : 0) * fr.ldx;
+    }
+    double2 cur[RB][4], nxt[RB][4];
+    auto fetch = [&](int n, double2 (&dst)[RB][4]) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int nn = n + 4 * q + u;
+                dst[b][u] = (rowok[b] && nn < it.n1) ? load_c<TIn>(rowp[b] + nn) : make_double2(0.0, 0.0);
+            }
+    };
+    int n = it.n0 + 16 * wave;
+    if (n < it.n1) fetch(n, cur);
+    for (; n < it.n1; n += 64) {
+        if (n + 64 < it.n1) fetch(n + 64, nxt);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < RB; ++I)
+#pragma unroll
+                for (int J = I; J < RB; ++J, ++t) {
+                    drr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].x, cur[J][u].x, drr[t], 0, 0, 0);
+                    dii[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].y, cur[J][u].y, dii[t], 0, 0, 0);
+                }
+#pragma unroll
+            for (int I = 0; I < RB; ++I)
+#pragma unroll
+                for (int J = 0; J < RB; ++J)
+                    dir[I * RB + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].y, cur[J][u].x, dir[I * RB + J], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cur[b][u] = nxt[b][u];
+    }
+
+    // scatter this wave's sums to LDS: Re R over I <= J, Xi Xr^T over all block pairs
+    {
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = I; J < RB; ++J, ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sre[wave][I * 16 + q + 4 * r][J * 16 + mi] = drr[t][r] + dii[t][r];
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sim[wave][I * 16 + q + 4 * r][J * 16 + mi] = dir[I * RB + J][r];
+    }
+    __syncthreads();
+    double2* out = reinterpret_cast<double2*>(ws + fr.ws_partial) + (size_t)it.chunk * M * M;
+    for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+        const int i = e / M, j = e - i * M;
+        if (i > j) continue;
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            re += sre[w][i][j];
+            im += sim[w][i][j] - sim[w][j][i];   // Im R_ij = sum xi_i xr_j - xr_i xi_j
+        }
+        out[i * M + j] = make_double2(re, im);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_cov(bool c128, const CovItem* items, int n_items, const FrameDev* frames,
+hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
                       const void* X, char* ws, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (max_M <= 32) {
+        if (c128) {
+            if (max_M <= 16)
+                hipLaunchKernelGGL((cov_mfma_kernel<double2, 1>), dim3(n_items), dim3(256), 0, s, items, frames,
+                                   static_cast<const double2*>(X), ws);
+            else
+                hipLaunchKernelGGL((cov_mfma_kernel<double2, 2>), dim3(n_items), dim3(256), 0, s, items, frames,
+                                   static_cast<const double2*>(X), ws);
+        } else {
+            if (max_M <= 16)
+                hipLaunchKernelGGL((cov_mfma_kernel<float2, 1>), dim3(n_items), dim3(256), 0, s, items, frames,
+                                   static_cast<const float2*>(X), ws);
+            else
+                hipLaunchKernelGGL((cov_mfma_kernel<float2, 2>), dim3(n_items), dim3(256), 0, s, items, frames,
+                                   static_cast<const float2*>(X), ws);
+        }
+        return hipGetLastError();
+    }
     if (c128)
         hipLaunchKernelGGL(cov_kernel<double2>, dim3(n_items), dim3(kThreads), 0, s, items, frames,
                            static_cast<const double2*>(X), ws);

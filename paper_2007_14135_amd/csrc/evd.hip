@@ -114,9 +114,10 @@ __device__ __forceinline__ Rot rotation(const double2* __restrict__ A, int ld, i
 }
 
 constexpr int kMaxTasksPerThread = 3;
+constexpr int kMaxPairChecks = 2;   // off-diagonal pairs checked per thread and sweep
 
 template <bool DB>
-__global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ flist,
+__global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __restrict__ flist,
                                                    const FrameDev* __restrict__ frames, EvdParams prm,
                                                    const GroupDev* __restrict__ groups,
                                                    char* __restrict__ ws,
@@ -135,7 +136,10 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
     double2* V = lds + Mp * ld;
     double2* A2 = DB ? lds + 2 * Mp * ld : lds;   // second copy of A when double buffered
 
-    if (tid == 0) bad = 0;
+    if (tid == 0) {
+        bad = 0;
+        if (prm.write_emb) *reinterpret_cast<int*>(ws + fr.ws_lowq) = 0;   // low-Q list of the scan
+    }
     __syncthreads();
 
     // Step-1 completion: R = (sum of chunk partials, in chunk order) / N, Hermitian by construction.
@@ -215,11 +219,23 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
                 tl[u] = t2 - tk[u] * np;
             }
         }
+        // off-diagonal pairs (i < j) checked by this thread each sweep, indices fixed up front
+        const int npairs = M * (M - 1) / 2;
+        int ci[kMaxPairChecks], cj[kMaxPairChecks];
+#pragma unroll
+        for (int u = 0; u < kMaxPairChecks; ++u) {
+            int t = tid + u * bd, i = 0;
+            while (t >= M - 1 - i && i < M - 1) { t -= M - 1 - i; ++i; }
+            ci[u] = i;
+            cj[u] = i + 1 + t;
+        }
         bool converged = false;
         for (int sweep = 0; sweep <= prm.max_sweeps; ++sweep) {
             int above = 0;
-            for (int i = 0; i < M; ++i) {
-                for (int j = i + 1 + tid; j < M; j += bd) {
+#pragma unroll
+            for (int v = 0; v < kMaxPairChecks; ++v) {
+                if (tid + v * bd < npairs) {
+                    const int i = ci[v], j = cj[v];
                     const double2 a = A[i * ld + j];
                     const double num = a.x * a.x + a.y * a.y;
                     above |= num > tol2 * fmax(fabs(A[i * ld + i].x * A[j * ld + j].x), floor2);
@@ -231,59 +247,38 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
             }
             if (sweep == prm.max_sweeps) break;
             for (int step = 0; step < Mp - 1; ++step) {
-                // every thread derives the rotations its tasks need from the current A, reads
-                // its blocks, and (after a barrier when A is updated in place) writes them
-                Rot rk[kMaxTasksPerThread], rl[kMaxTasksPerThread];
-                double2 b[kMaxTasksPerThread][4];
+                // Each task derives the rotations it needs from the current A, reads its block and
+                // computes the new values.  Double buffered: written at once to the other copy.
+                // In place: kept in registers until every thread has read, then written.
+                double2 keep[kMaxTasksPerThread][4];
+                int kp[kMaxTasksPerThread][4];
 #pragma unroll
                 for (int u = 0; u < kMaxTasksPerThread; ++u) {
                     const int task = tid + u * bd;
-                    if (task >= nT) break;
                     if (task < nA) {
                         const int k = tk[u], l = tl[u];
-                        rk[u] = rotation(A, ld, M, Mp, step, k, tol2, floor2);
-                        rl[u] = (l == k) ? rk[u] : rotation(A, ld, M, Mp, step, l, tol2, floor2);
-                        b[u][0] = A[rk[u].p * ld + rl[u].p];
-                        b[u][1] = A[rk[u].p * ld + rl[u].q];
-                        b[u][2] = A[rk[u].q * ld + rl[u].p];
-                        b[u][3] = A[rk[u].q * ld + rl[u].q];
-                    } else {
-                        const int i = tk[u], l = tl[u];
-                        rl[u] = rotation(A, ld, M, Mp, step, l, tol2, floor2);
-                        rk[u].p = i;
-                        b[u][0] = V[i * ld + rl[u].p];
-                        b[u][1] = V[i * ld + rl[u].q];
-                    }
-                }
-                if (!DB) __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kMaxTasksPerThread; ++u) {
-                    const int task = tid + u * bd;
-                    if (task >= nT) break;
-                    if (task < nA) {
-                        const int k = tk[u], l = tl[u];
-                        const Rot& r1 = rk[u];
-                        const Rot& r2 = rl[u];
+                        const Rot r1 = rotation(A, ld, M, Mp, step, k, tol2, floor2);
+                        const Rot r2 = (l == k) ? r1 : rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        const double2 b11 = A[r1.p * ld + r2.p], b12 = A[r1.p * ld + r2.q];
+                        const double2 b21 = A[r1.q * ld + r2.p], b22 = A[r1.q * ld + r2.q];
                         double2 o11, o12, o21, o22;
                         if (k == l) {
                             // diagonal block: the rotation annihilates r_pq exactly
-                            o11 = make_double2(b[u][0].x - r1.t, 0.0);
-                            o22 = make_double2(b[u][3].x + r1.t, 0.0);
-                            o12 = make_double2(0.0, 0.0);
-                            o21 = o12;
                             if (r1.s == 0.0) {
-                                o11 = b[u][0];
-                                o12 = b[u][1];
-                                o21 = b[u][2];
-                                o22 = b[u][3];
+                                o11 = b11; o12 = b12; o21 = b21; o22 = b22;
+                            } else {
+                                o11 = make_double2(b11.x - r1.t, 0.0);
+                                o22 = make_double2(b22.x + r1.t, 0.0);
+                                o12 = make_double2(0.0, 0.0);
+                                o21 = o12;
                             }
                         } else {
                             // right: B J_l with J = [[c, s], [-s e, c e]]
                             const double2 se2 = cscale(r2.s, r2.e), ce2 = cscale(r2.c, r2.e);
-                            const double2 x11 = csub(cscale(r2.c, b[u][0]), cmul(b[u][1], se2));
-                            const double2 x12 = cadd(cscale(r2.s, b[u][0]), cmul(b[u][1], ce2));
-                            const double2 x21 = csub(cscale(r2.c, b[u][2]), cmul(b[u][3], se2));
-                            const double2 x22 = cadd(cscale(r2.s, b[u][2]), cmul(b[u][3], ce2));
+                            const double2 x11 = csub(cscale(r2.c, b11), cmul(b12, se2));
+                            const double2 x12 = cadd(cscale(r2.s, b11), cmul(b12, ce2));
+                            const double2 x21 = csub(cscale(r2.c, b21), cmul(b22, se2));
+                            const double2 x22 = cadd(cscale(r2.s, b21), cmul(b22, ce2));
                             // left: J_k^H (B J_l) with J^H = [[c, -s conj(e)], [s, c conj(e)]]
                             const double2 se1 = cscale(r1.s, cconj(r1.e)), ce1 = cscale(r1.c, cconj(r1.e));
                             o11 = csub(cscale(r1.c, x11), cmul(se1, x21));
@@ -291,15 +286,33 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
                             o21 = cadd(cscale(r1.s, x11), cmul(ce1, x21));
                             o22 = cadd(cscale(r1.s, x12), cmul(ce1, x22));
                         }
-                        A2[r1.p * ld + r2.p] = o11;
-                        A2[r1.p * ld + r2.q] = o12;
-                        A2[r1.q * ld + r2.p] = o21;
-                        A2[r1.q * ld + r2.q] = o22;
-                    } else {
-                        const Rot& r = rl[u];
-                        const int i = rk[u].p;
-                        V[i * ld + r.p] = csub(cscale(r.c, b[u][0]), cmul(b[u][1], cscale(r.s, r.e)));
-                        V[i * ld + r.q] = cadd(cscale(r.s, b[u][0]), cmul(b[u][1], cscale(r.c, r.e)));
+                        if (DB) {
+                            A2[r1.p * ld + r2.p] = o11;
+                            A2[r1.p * ld + r2.q] = o12;
+                            A2[r1.q * ld + r2.p] = o21;
+                            A2[r1.q * ld + r2.q] = o22;
+                        } else {
+                            keep[u][0] = o11; keep[u][1] = o12; keep[u][2] = o21; keep[u][3] = o22;
+                            kp[u][0] = r1.p * ld + r2.p; kp[u][1] = r1.p * ld + r2.q;
+                            kp[u][2] = r1.q * ld + r2.p; kp[u][3] = r1.q * ld + r2.q;
+                        }
+                    } else if (task < nT) {
+                        // V <- V J_l on row i: no other task touches these two entries this step
+                        const int i = tk[u], l = tl[u];
+                        const Rot r = rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        const double2 v1 = V[i * ld + r.p], v2 = V[i * ld + r.q];
+                        V[i * ld + r.p] = csub(cscale(r.c, v1), cmul(v2, cscale(r.s, r.e)));
+                        V[i * ld + r.q] = cadd(cscale(r.s, v1), cmul(v2, cscale(r.c, r.e)));
+                    }
+                }
+                if (!DB) {
+                    __syncthreads();
+#pragma unroll
+                    for (int u = 0; u < kMaxTasksPerThread; ++u) {
+                        if (tid + u * bd < nA) {
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) A[kp[u][w]] = keep[u][w];
+                        }
                     }
                 }
                 __syncthreads();
@@ -376,12 +389,13 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
     for (int e = tid; e < M * K; e += bd) Bout[e] = Bs[e];
 
     if (prm.write_emb) {
-        // Real embedding of B for the FP32 scan: column k gives two rows over the inner index
+        // Real embedding of B for the scan: column k gives two rows over the inner index
         // kk in [0, 2M):  re-row (Re b, Im b) and im-row (-Im b, Re b), so that the row dot the
-        // embedded steering (Re a, Im a) is Re(b^H a) and Im(b^H a).  Rows are packed per
-        // 32-row tile as [64 lanes][M floats]: lane h*32+i holds inner kk = 2s+h of row i.
+        // embedded steering (Re a, Im a) is Re(b^H a) and Im(b^H a).  Rows are packed per 32-row
+        // tile as [64 lanes][M values], in the operand order of the scan's MFMA:
+        //   FP32 (32x32x2):        lane h*32+i holds inner kk = 2s + h of row i at position s;
+        //   BF16/FP16 (32x32x16):  lane h*32+i holds inner kk = 16s + 8h + t at position 8s + t.
         const GroupDev& g = groups[fr.group];
-        float* emb = reinterpret_cast<float*>(ws + g.ws_emb);
         const int rows = fr.emb_rows, inner = 2 * M;
         for (int e = tid; e < rows * inner; e += bd) {
             const int rl = e / inner, kk = e - rl * inner;
@@ -393,8 +407,16 @@ __global__ __launch_bounds__(1024) void evd_kernel(const int32_t* __restrict__ f
                 else v = (float)(kk < M ? -b.y : b.x);
             }
             const int r = fr.emb_row0 + rl;
-            const int tile = r >> 5, i = r & 31, h = kk & 1, s = kk >> 1;
-            emb[((size_t)tile * 64 + h * 32 + i) * M + s] = v;
+            const int tile = r >> 5, i = r & 31;
+            if (prm.write_emb == 1) {
+                const int h = kk & 1, s2 = kk >> 1;
+                reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * 64 + h * 32 + i) * M + s2] = v;
+            } else {
+                const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
+                const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;
+                if (prm.write_emb == 2) reinterpret_cast<__bf16*>(ws + g.ws_emb)[o] = (__bf16)v;
+                else reinterpret_cast<_Float16*>(ws + g.ws_emb)[o] = (_Float16)v;
+            }
         }
     }
     if (tid == 0) status[fidx] = st;
@@ -410,9 +432,10 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
     // one thread per 2x2 block update and per V row-pair update of a step: 3 Mp^2 / 4 tasks,
     // at most kMaxTasksPerThread per thread
     const int tasks = 3 * Mp * Mp / 4;
-    const int threads = std::min(1024, std::max(64, (tasks + 63) / 64 * 64));
-    if (tasks > threads * kMaxTasksPerThread) return hipErrorInvalidValue;
     const bool db = Mp <= 32;     // a second copy of A fits in LDS: one barrier per step
+    const int threads = std::min(db ? 256 : 1024, std::max(64, (tasks + 63) / 64 * 64));
+    if (tasks > threads * kMaxTasksPerThread) return hipErrorInvalidValue;
+    if (max_M * (max_M - 1) / 2 > threads * kMaxPairChecks) return hipErrorInvalidValue;
     const size_t lds = (size_t)(db ? 3 : 2) * Mp * (Mp + 1) * sizeof(double2);
     const void* fn = db ? (const void*)evd_kernel<true> : (const void*)evd_kernel<false>;
     if (lds > 65536) {

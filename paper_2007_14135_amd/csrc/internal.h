@@ -34,10 +34,13 @@ struct FrameDev {
     int64_t ws_B;               // M*K complex128, column-major
     int64_t ws_qref;            // 1 double
     int64_t ws_cand;            // ceil(L / kRefineChunk) * (D + extra) candidate slots of 16 bytes
+    int64_t ws_lowq;            // int32 count, then lowq_cap int32 grid indices with low FP32 Q
     double grid_start, grid_step;
     int32_t L, circular;
     int32_t pos_off;            // offset (doubles) of this frame's 3*M positions
     int32_t alg;
+    int32_t lowq_cap;           // capacity of the low-Q list (a multiple of 256)
+    int32_t pad2;
 };
 
 // Frames that share an array geometry and a scan grid: their spectra are one GEMM.
@@ -57,7 +60,7 @@ struct PointItem { int32_t frame, l0; };                      // FP64 scan: 256 
 struct EvdParams {
     double tol;
     int32_t max_sweeps;
-    int32_t write_emb;          // 1: write the FP32 packed B tiles (C64 scan)
+    int32_t write_emb;          // packed B tiles for the scan: 0 none, 1 FP32, 2 BF16, 3 FP16
 };
 
 struct PeakParams {
@@ -154,22 +157,67 @@ __device__ __forceinline__ double q64_eval(const double* __restrict__ pos, int M
     return Q;
 }
 
+// The same quantity evaluated by a group of 16 lanes of one wave (lanes 16g..16g+15 share one
+// direction): lane j forms a_m for m = j, j+16, ... into LDS (`a` holds 4 * MB entries per wave),
+// then forms y_k = b_k^H a for k = j, j+16, ..., and the 16 partial sums of |y_k|^2 are added
+// with a butterfly.  Every lane of the wave must call it; the result is in all 16 lanes.
+template <int MB>
+__device__ __forceinline__ double q64_group(const double* __restrict__ pos, int M, int K,
+                                            const double2* __restrict__ B, double theta_deg,
+                                            const double2* __restrict__ cis, double2* a) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    double sth, cth;
+    sincos(theta_deg * kDeg2Rad, &sth, &cth);
+    for (int m = j; m < M; m += 16) {
+        const double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
+        a[g * MB + m] = cis2pi(c - rint(c), cis);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double q = 0.0;
+    for (int k = j; k < K; k += 16) {
+        const double2* bk = B + (size_t)k * M;
+        double yr = 0.0, yi = 0.0;
+#pragma unroll 8
+        for (int m = 0; m < M; ++m) {
+            const double2 b = bk[m];
+            const double2 am = a[g * MB + m];
+            yr = fma(b.x, am.x, fma(b.y, am.y, yr));
+            yi = fma(b.x, am.y, fma(-b.y, am.x, yi));
+        }
+        q += yr * yr + yi * yi;
+    }
+    q += __shfl_xor(q, 8, 16);
+    q += __shfl_xor(q, 4, 16);
+    q += __shfl_xor(q, 2, 16);
+    q += __shfl_xor(q, 1, 16);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();   // `a` may be reused by the caller's next call
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return q;
+}
+
 // Host-side launchers (defined next to their kernels).
-hipError_t launch_cov(bool c128, const CovItem* items, int n_items, const FrameDev* frames,
+hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
                       const void* X, char* ws, hipStream_t s);
 hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s);
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const double* pos,
-                           const char* ws, float* spec, int use_user_spec, hipStream_t s);
+                           char* ws, float* spec, int use_user_spec, float lowq_tau,
+                           hipStream_t s);
+hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
+                          const FrameDev* frames, const int32_t* blkframe, const double* pos, char* ws,
+                          float* spec, int use_user, float lowq_tau, hipStream_t s);
 hipError_t launch_scan_f64(const PointItem* items, int n_items, int max_M,
                            const FrameDev* frames, const double* pos, const double2* cis,
                            const char* ws, double* spec, int use_user_spec, hipStream_t s);
-hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items,
-                        const int32_t* frame_list, int n_frames, const FrameDev* frames,
-                        const double* pos, const double2* cis, char* ws, void* spec,
-                        const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
-                        hipStream_t s);
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* lowq_items, int n_lowq_items,
+                        const PointItem* items, int n_items, const int32_t* frame_list,
+                        int n_frames, const FrameDev* frames, const double* pos,
+                        const double2* cis, char* ws, void* spec, const PeakParams& p,
+                        void* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s);
 
 }  // namespace nssdoa

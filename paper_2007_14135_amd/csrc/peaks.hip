@@ -1,11 +1,14 @@
 // Step-6 (Table 2): peak search and selection, preceded for FP32 spectra by the FP64
 // re-evaluation of low-Q points.
 //
-// refine_kernel, one workgroup per (frame, chunk of 4096 grid points):
-//  1. loads the chunk plus a halo of 16 points on each side into LDS; for FP32 spectra every
-//     point with P >= 1 / (tau ||B||_F^2), i.e. ||B^H a||^2 below tau times its typical size,
-//     is recomputed in FP64 (halo points are recomputed identically by both neighbours, and only
-//     the owner writes the value back);
+// lowq_kernel: the scan appends, per frame, every grid point whose FP32 ||B^H a||^2 is below
+//  tau ||B||_F^2 (the spectrum peaks, where FP32 rounding is largest relative to Q); one thread
+//  per listed point recomputes it in FP64 and writes the rounded value back.  Work items are
+//  256-entry slices of the lists, so the FP64 work is spread over the whole GPU whatever the
+//  per-frame counts are.
+// localmax_kernel, one workgroup per (frame, chunk of 4096 grid points):
+//  1. loads the chunk plus a halo of 16 points on each side into LDS (a frame whose list
+//     overflowed re-evaluates its low-Q points here instead);
 //  2. finds the local maxima of its own points: P[l] > P[l-1] and the run of values equal to
 //     P[l] ends in a strictly smaller value (the run is reported at its first index); grid ends
 //     are not peaks unless the grid is circular;
@@ -14,7 +17,7 @@
 //     result does not depend on scheduling.
 // select_kernel, one workgroup per frame:
 //  4. ranks the chunk candidates and keeps the best D + extra;
-//  5. evaluates a window of +-halfwidth points around each in FP64;
+//  5. evaluates a window of +-halfwidth points around each in FP64 (16 lanes per point);
 //  6. ranks the distinct FP64 local maxima of the windows by (value desc, index asc) and writes
 //     the first D; slots beyond the number found get idx = -1 and NaN.
 #include <float.h>
@@ -39,8 +42,28 @@ struct Cand {
 
 __device__ inline double qnan() { return __longlong_as_double(0x7ff8000000000000LL); }
 
+template <int MB>
+__global__ __launch_bounds__(256) void lowq_kernel(const PointItem* __restrict__ items,
+                                                   const FrameDev* __restrict__ frames,
+                                                   const double* __restrict__ pos,
+                                                   const double2* __restrict__ cis,
+                                                   const char* __restrict__ ws, float* __restrict__ spec,
+                                                   int use_user, const uint32_t* __restrict__ status) {
+    const PointItem it = items[blockIdx.x];
+    const FrameDev& fr = frames[it.frame];
+    const int* list = reinterpret_cast<const int*>(ws + fr.ws_lowq);
+    const int n = min(list[0], fr.lowq_cap);
+    const int i = it.l0 + (int)threadIdx.x;
+    if (i >= n || (status[it.frame] & NSSDOA_ST_NONFINITE_INPUT)) return;
+    const int l = list[1 + i];
+    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
+    const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis);
+    float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+    P[l] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
+}
+
 template <int MB, typename TS>
-__global__ __launch_bounds__(256) void refine_kernel(const PointItem* __restrict__ items,
+__global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restrict__ items,
                                                      const FrameDev* __restrict__ frames,
                                                      const double* __restrict__ pos,
                                                      const double2* __restrict__ cis,
@@ -74,8 +97,10 @@ __global__ __launch_bounds__(256) void refine_kernel(const PointItem* __restrict
         return;
     }
 
+    // FP32 spectra were re-evaluated by lowq_kernel unless the frame's list overflowed
+    const bool overflow = prm.refine_lowq && *reinterpret_cast<const int*>(ws + fr.ws_lowq) > fr.lowq_cap;
     double pthr = INFINITY;
-    if (prm.refine_lowq) pthr = 1.0 / (prm.lowq_tau * *reinterpret_cast<const double*>(ws + fr.ws_qref));
+    if (overflow) pthr = 1.0 / (prm.lowq_tau * *reinterpret_cast<const double*>(ws + fr.ws_qref));
     const double* ps = pos + fr.pos_off;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     if (tid == 0) {
@@ -106,7 +131,7 @@ __global__ __launch_bounds__(256) void refine_kernel(const PointItem* __restrict
         }
     }
     __syncthreads();
-    if (prm.refine_lowq) {
+    if (overflow) {
         // list the low-Q points, then re-evaluate them in FP64 one per thread
         for (int e = tid; e < span; e += blockDim.x) {
             const double x = v[e];
@@ -197,6 +222,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     __shared__ int fidx[kMaxFinal];
     __shared__ int rankpos[kMaxSel];
     __shared__ int ccount, fcount, nuniq;
+    __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
 
     const int f = flist[blockIdx.x];
     const FrameDev& fr = frames[f];
@@ -254,14 +280,21 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     const double* ps = pos + fr.pos_off;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     const int w = prm.halfwidth, W = 2 * w + 1;
-    for (int e = tid; e < C * W; e += blockDim.x) {
-        const int c = e / W, o = e - c * W;
-        int l = sel[c] + o - w;
-        double x = qnan();
-        if (circ) l = ((l % L) + L) % L;
-        if (circ || (l >= 0 && l < L))
-            x = 1.0 / fmax(q64_eval<MB>(ps, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis), 1e-300);
-        win[c * kMaxWin + o] = x;
+    {
+        // 16 lanes per window point: 16 points per pass of the 256-thread workgroup
+        const int grp = tid >> 4, j = tid & 15;
+        double2* a = asteer + (tid >> 6) * 4 * MB;
+        for (int e0 = 0; e0 < C * W; e0 += 16) {
+            const int e = e0 + grp;
+            const bool valid = e < C * W;
+            const int c = valid ? e / W : 0, o = valid ? e - c * W : 0;
+            int l = valid ? sel[c] + o - w : 0;
+            if (circ) l = ((l % L) + L) % L;
+            const bool inside = valid && (circ || (l >= 0 && l < L));
+            const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
+                                           grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
+            if (valid && j == 0) win[c * kMaxWin + o] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
+        }
     }
     __syncthreads();
 
@@ -328,41 +361,52 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
 }
 
 template <int MB>
-hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_t* flist, int n_frames,
-                     const FrameDev* frames, const double* pos, const double2* cis, char* ws, void* spec,
-                     const PeakParams& p, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
-                     hipStream_t s) {
+hipError_t launch_mb(bool f64, const PointItem* lowq_items, int n_lowq, const PointItem* items, int n_items,
+                     const int32_t* flist, int n_frames, const FrameDev* frames, const double* pos,
+                     const double2* cis, char* ws, void* spec, const PeakParams& p, nssdoa_peak* peaks,
+                     int32_t* npeaks, uint32_t* status, hipStream_t s) {
+    if (!f64 && p.refine_lowq && n_lowq > 0) {
+        hipLaunchKernelGGL((lowq_kernel<MB>), dim3(n_lowq), dim3(256), 0, s, lowq_items, frames, pos, cis, ws,
+                           static_cast<float*>(spec), p.use_user_spec, status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (n_items > 0) {
         if (f64)
-            hipLaunchKernelGGL((refine_kernel<MB, double>), dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws,
-                               static_cast<double*>(spec), p, status);
+            hipLaunchKernelGGL((localmax_kernel<MB, double>), dim3(n_items), dim3(256), 0, s, items, frames, pos,
+                               cis, ws, static_cast<double*>(spec), p, status);
         else
-            hipLaunchKernelGGL((refine_kernel<MB, float>), dim3(n_items), dim3(256), 0, s, items, frames, pos, cis, ws,
-                               static_cast<float*>(spec), p, status);
+            hipLaunchKernelGGL((localmax_kernel<MB, float>), dim3(n_items), dim3(256), 0, s, items, frames, pos,
+                               cis, ws, static_cast<float*>(spec), p, status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_frames > 0)
-        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), 0, s, flist, frames, pos, cis, ws, p, peaks,
-                           npeaks, status);
+        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), 0, s, flist, frames, pos, cis, ws, p,
+                           peaks, npeaks, status);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items,
-                        const int32_t* frame_list, int n_frames, const FrameDev* frames,
-                        const double* pos, const double2* cis, char* ws, void* spec,
-                        const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
-                        hipStream_t s) {
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* lowq_items, int n_lowq_items,
+                        const PointItem* items, int n_items, const int32_t* frame_list,
+                        int n_frames, const FrameDev* frames, const double* pos,
+                        const double2* cis, char* ws, void* spec, const PeakParams& p,
+                        void* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s) {
     nssdoa_peak* pk = static_cast<nssdoa_peak*>(peaks);
+#define NSSDOA_PEAKS_CASE(MB)                                                                       \
+    case MB:                                                                                     \
+        return launch_mb<MB>(f64, lowq_items, n_lowq_items, items, n_items, frame_list, n_frames,   \
+                             frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
     switch (bucket_M) {
-        case 8: return launch_mb<8>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
-        case 16: return launch_mb<16>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
-        case 32: return launch_mb<32>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
-        case 64: return launch_mb<64>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        NSSDOA_PEAKS_CASE(8)
+        NSSDOA_PEAKS_CASE(16)
+        NSSDOA_PEAKS_CASE(32)
+        NSSDOA_PEAKS_CASE(64)
         default: return hipErrorInvalidValue;
     }
+#undef NSSDOA_PEAKS_CASE
 }
 
 }  // namespace nssdoa

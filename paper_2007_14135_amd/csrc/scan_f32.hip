@@ -50,8 +50,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
                                                        const FrameDev* __restrict__ frames,
                                                        const int32_t* __restrict__ blkframe,
                                                        const double* __restrict__ pos,
-                                                       const char* __restrict__ ws,
-                                                       float* __restrict__ spec, int use_user) {
+                                                       char* __restrict__ ws,
+                                                       float* __restrict__ spec, int use_user,
+                                                       float lowq_tau) {
     const ScanItem it = items[blockIdx.x];
     const GroupDev& g = groups[it.group];
     const int lane = threadIdx.x & 63;
@@ -77,10 +78,18 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         const float t1 = q1 + __shfl_xor(q1, 32);
         const float v = (lane < 32) ? t0 : t1;
         const int l = base + lane;          // col tile lane/32, angle lane%32
+        const FrameDev& fd = frames[f];
         if (l < g.L) {
-            const FrameDev& fd = frames[f];
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
+            // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
+            // re-evaluation (entries beyond the capacity are only counted)
+            const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
+            if (v < thr) {
+                int* cnt = reinterpret_cast<int*>(ws + fd.ws_lowq);
+                const int slot = atomicAdd(cnt, 1);
+                if (slot < fd.lowq_cap) cnt[1 + slot] = l;
+            }
         }
     };
 
@@ -134,9 +143,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 template <int M>
 hipError_t launch_m(const ScanItem* items, int n_items, const GroupDev* groups,
                     const FrameDev* frames, const int32_t* blkframe, const double* pos,
-                    const char* ws, float* spec, int use_user, hipStream_t s) {
+                    char* ws, float* spec, int use_user, float tau, hipStream_t s) {
     hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
-                       blkframe, pos, ws, spec, use_user);
+                       blkframe, pos, ws, spec, use_user, tau);
     return hipGetLastError();
 }
 
@@ -144,13 +153,13 @@ hipError_t launch_m(const ScanItem* items, int n_items, const GroupDev* groups,
 
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const double* pos,
-                           const char* ws, float* spec, int use_user, hipStream_t s) {
+                           char* ws, float* spec, int use_user, float tau, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (M) {
-        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
-        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
-        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
-        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, s);
+        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
+        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
+        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
+        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
         default: return hipErrorInvalidValue;
     }
 }

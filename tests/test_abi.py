@@ -85,11 +85,12 @@ def test_batch_rejects_invalid(frame, alg, prec, max_D, msg):
     assert e.value.status == _abi.EINVAL, msg
 
 
-def test_batch_reduced_precision_is_reported_unsupported():
-    plan = nd.Plan([_ula(8)], [(-90, 0.1, 1800)])
+@pytest.mark.parametrize("prec", ["c64", "bf16", "f16"])
+def test_matrix_core_scans_need_supported_M(prec):
+    plan = nd.Plan([_ula(12)], [(-90, 0.1, 1800)])
     with pytest.raises(nd.NssdoaError) as e:
-        nd.Batch(plan, "music", "bf16", [(0, 0, 1024, 2, 0, 1024, 0)], 4)
-    assert e.value.status in (_abi.EUNSUPPORTED, _abi.EDEVICE)
+        nd.Batch(plan, "music", prec, [(0, 0, 1024, 2, 0, 1024, 0)], 4)
+    assert e.value.status == _abi.EINVAL
 
 
 def test_null_handles_rejected():

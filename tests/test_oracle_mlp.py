@@ -1,0 +1,99 @@
+"""Pins for the learned-proposal oracle: gradients by central differences, closed forms of the
+loss and of Adam's first step, feature invariances, bin labels and window arithmetic."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _small(seed=3):
+    rng = np.random.default_rng(seed)
+    params = mlp.init_params(seed, sizes=(7, 6, 5, 4))
+    # nonzero biases so that every term of the gradient is exercised
+    params = [(W, rng.normal(0, 0.1, size=b.shape)) for W, b in params]
+    X = rng.normal(size=(5, 7))
+    y = (rng.uniform(size=(5, 4)) < 0.3).astype(float)
+    return params, X, y
+
+
+def test_gradients_match_central_differences():
+    params, X, y = _small()
+    loss, grads = mlp.backward(params, X, y)
+    h = 1e-6
+    for li in range(3):
+        for which in (0, 1):
+            P = params[li][which]
+            G = grads[li][which]
+            it = np.nditer(P, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = P[idx]
+                P[idx] = old + h
+                lp = mlp.bce_with_logits(mlp.forward(params, X)[0], y)
+                P[idx] = old - h
+                lm = mlp.bce_with_logits(mlp.forward(params, X)[0], y)
+                P[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - G[idx]) <= 1e-7 * max(1.0, abs(fd)) + 1e-9, (li, which, idx, fd, G[idx])
+
+
+def test_bce_closed_forms():
+    assert abs(mlp.bce_with_logits(np.zeros((2, 3)), np.ones((2, 3))) - np.log(2.0)) < 1e-15
+    assert mlp.bce_with_logits(np.array([[40.0]]), np.array([[1.0]])) < 1e-17
+    assert abs(mlp.bce_with_logits(np.array([[40.0]]), np.array([[0.0]])) - 40.0) < 1e-12
+    # symmetry: L(z, y) = L(-z, 1 - y)
+    z = np.array([[0.3, -2.0, 5.0]])
+    y = np.array([[1.0, 0.0, 1.0]])
+    assert abs(mlp.bce_with_logits(z, y) - mlp.bce_with_logits(-z, 1 - y)) < 1e-15
+
+
+def test_adam_first_step_closed_form():
+    params, X, y = _small()
+    _, grads = mlp.backward(params, X, y)
+    m = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    v = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    lr = 1e-3
+    newp, _, _ = mlp.adam_step(params, grads, m, v, 1, lr)
+    for (W, b), (W2, b2), (gW, gb) in zip(params, newp, grads):
+        # bias-corrected first step: delta = -lr * g / (|g| + eps)
+        assert np.allclose(W2 - W, -lr * gW / (np.abs(gW) + 1e-8), rtol=1e-12, atol=1e-18)
+        assert np.allclose(b2 - b, -lr * gb / (np.abs(gb) + 1e-8), rtol=1e-12, atol=1e-18)
+
+
+def test_features_layout_and_invariance():
+    rng = np.random.default_rng(0)
+    Z = rng.normal(size=(16, 40)) + 1j * rng.normal(size=(16, 40))
+    R = Z @ Z.conj().T / 40
+    f = mlp.features(R)
+    assert f.shape == (272,)
+    assert np.allclose(mlp.features(3.7 * R), f, rtol=1e-14, atol=1e-15)
+    # diagonal entries sit at the start of each row of the upper triangle; their imaginary parts are 0
+    pos, diag_re = 0, []
+    for i in range(16):
+        assert abs(f[2 * pos + 1]) < 1e-14
+        diag_re.append(f[2 * pos])
+        pos += 16 - i
+    assert abs(sum(diag_re) - 16.0) < 1e-12          # trace of M R / trace(R)
+    # first row: element (0, 1) follows (0, 0)
+    Rn = R * 16 / np.trace(R).real
+    assert np.isclose(f[2], Rn[0, 1].real) and np.isclose(f[3], Rn[0, 1].imag)
+
+
+def test_bin_labels():
+    y = mlp.bin_labels([-90.0, -0.5, 0.0, 89.999])
+    assert y.sum() == 4 and y[0] == y[89] == y[90] == y[179] == 1
+    assert mlp.bin_labels([90.0])[179] == 1          # clipped
+
+
+def test_proposal_windows_arithmetic():
+    s = np.zeros(180)
+    s[90] = 0.9                                       # bin 90 = [0, 1) deg, centre 0.5
+    w = mlp.proposal_windows(s, 1, 1.0, -90.0, 0.001, 180000)
+    assert w == [(89500, 91501)]                      # -0.5 .. 1.5 deg inclusive: 2001 points
+    s[91] = 0.8
+    w = mlp.proposal_windows(s, 2, 1.0, -90.0, 0.001, 180000)
+    assert w == [(89500, 92501)]                      # overlapping windows merge
+    s[0] = 0.95                                       # centre -89.5: clipped at the grid start
+    w = mlp.proposal_windows(s, 3, 1.0, -90.0, 0.001, 180000)
+    assert w[0] == (0, 1501)
