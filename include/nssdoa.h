@@ -73,6 +73,8 @@ typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 
 #define NSSDOA_ST_DEGENERATE        0x4u  /* EV: a noise eigenvalue <= 0; MN: (P_n)_11 <= 1e-300   */
 #define NSSDOA_ST_FEWER_PEAKS       0x8u  /* fewer than D local maxima; unused slots idx = -1      */
 #define NSSDOA_ST_PEAK_OVERFLOW     0x10u /* more local maxima than the candidate buffer holds     */
+#define NSSDOA_ST_FALLBACK_USED     0x20u /* windowed estimation scanned the whole grid (best score
+                                             below the threshold); informational                */
 
 /* An array geometry: M elements at host positions pos_wl[3*m + {0,1,2}] = (x, y, z) in
  * wavelengths (Eq. 2).  The plan copies the positions; the caller may free them afterwards. */
@@ -144,7 +146,8 @@ typedef enum {
     NSSDOA_STAGE_EIGEN = 1,      /* Step-2..4: covariance reduction, Jacobi, B                 */
     NSSDOA_STAGE_SCAN = 2,       /* Step-5                                                     */
     NSSDOA_STAGE_PEAKS = 3,      /* low-Q FP64 re-evaluation and Step-6                        */
-    NSSDOA_STAGE_COUNT = 4
+    NSSDOA_STAGE_PROPOSAL = 4,   /* windowed estimation: features, network, windows            */
+    NSSDOA_STAGE_COUNT = 5
 } nssdoa_stage;
 
 /* Create a plan holding array geometries and scan grids (host work only, no device call).
@@ -207,6 +210,99 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
 nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable);
 nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* total_ms,
                                 int64_t* launches);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned proposal network (not part of the paper's method: a batched front end that restricts
+ * the Table 2 Step-5 scan to windows).  A 3-layer perceptron in -> width -> width -> out with
+ * ReLU hidden units maps covariance features to per-bin logits; its GEMMs round operands to
+ * bfloat16 and accumulate in FP32 on the matrix cores.  Parameters are FP32 (master copy) with
+ * Adam moments; all of it lives in device memory owned by the nssdoa_mlp object.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct nssdoa_mlp_s* nssdoa_mlp;
+
+/* Allocate a network with zero parameters and zero Adam state; max_batch bounds the rows of
+ * forward and training calls (activation buffers are sized for it).
+ * EINVAL: NULL mlp, a size outside [1, 65536], max_batch outside [1, 2^20]. */
+nssdoa_status nssdoa_mlp_create(nssdoa_mlp* mlp, int32_t in, int32_t width, int32_t out, int32_t max_batch);
+nssdoa_status nssdoa_mlp_destroy(nssdoa_mlp mlp);
+
+/* Number of parameters: width*in + width + width*width + width + out*width + out, stored in the
+ * order W1 (width x in, row-major), b1, W2, b2, W3 (out x width), b3. */
+nssdoa_status nssdoa_mlp_param_count(nssdoa_mlp mlp, size_t* count);
+
+/* Checkpoint blob (host memory): eight int32 header words (magic, version, in, width, out, Adam
+ * step, 0, 0) followed by the FP32 parameters, first moments and second moments, each in the
+ * parameter order above.  save with blob == NULL returns the size in *bytes; otherwise *bytes
+ * must be at least that size and receives it.  load requires the exact size and a matching
+ * header.  Both synchronise the device.  Initial weights are loaded this way (the caller draws
+ * them). */
+nssdoa_status nssdoa_mlp_save(nssdoa_mlp mlp, void* blob, size_t* bytes);
+nssdoa_status nssdoa_mlp_load(nssdoa_mlp mlp, const void* blob, size_t bytes);
+
+/* Logits of `batch` feature rows: feats device [batch][in] FP32, logits device [batch][out]. */
+nssdoa_status nssdoa_mlp_forward(nssdoa_mlp mlp, const float* feats, int32_t batch, float* logits,
+                                 void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the mean binary
+ * cross-entropy with logits between the network output and `targets` (device [batch][out], 0/1).
+ * loss: device, one float, receives the loss before the update.  EINVAL: NULL pointers, batch
+ * outside [1, max_batch], lr outside [0, 1e3). */
+nssdoa_status nssdoa_mlp_train_step(nssdoa_mlp mlp, const float* feats, const float* targets,
+                                    int32_t batch, float lr, float* loss, void* stream);
+
+/* Host copy of the gradients of the last training step (count = nssdoa_mlp_param_count). */
+nssdoa_status nssdoa_mlp_gradients(nssdoa_mlp mlp, float* host, size_t count);
+
+/* ---------------------------------------------------------------------------------------------
+ * Windowed estimation: Steps 1-4 for every frame as in nssdoa_estimate, then the Step-5 scan and
+ * the Step-6 peak search only inside angle windows proposed from per-bin scores.
+ *
+ * Bins: n_bins bins of width w = 180 / n_bins deg; bin b covers [-90 + b w, -90 + (b+1) w) and its
+ * centre is c_b = -90 + (b + 1/2) w.  Per frame the topk best scores (ties to the lower bin; NaN
+ * never chosen) give windows [c_b - half_window_deg, c_b + half_window_deg], snapped inward to the
+ * frame's grid: grid indices ceil((c_b - hw - start) / step - 1e-9) .. floor((c_b + hw - start) /
+ * step + 1e-9), clipped to [0, L), each operation rounded in FP64; overlapping or touching windows
+ * merge.  If the frame's best score is below the threshold (or NaN) the frame falls back to one
+ * window over its whole grid and gets NSSDOA_ST_FALLBACK_USED.  Windows never wrap around a
+ * circular grid.
+ * Within the windows everything is as in nssdoa_estimate (FP32 scan, FP64 re-evaluation of
+ * low-Q points, FP64 re-pick around the candidates) except that spectrum values outside every
+ * window are unknown: the first and last points of a window are never peaks, and a peak's
+ * neighbours and plateau must lie inside its window.  Spectrum values outside the windows are
+ * not written; a frame with NSSDOA_ST_NONFINITE_INPUT gets no windows and no spectrum values.
+ *
+ * Requirements beyond nssdoa_estimate (EUNSUPPORTED otherwise): the batch was created with
+ * NSSDOA_C64, and all its frames have the same M.  EINVAL: topk outside [1, 16], n_bins outside
+ * [1, 256], half_window_deg outside (0, 180], a NaN threshold, a frame whose grid of L points
+ * gives (ceil(L / 4096) + topk) * (D + extra_candidates) > 4096 candidate slots, a workspace
+ * smaller than nssdoa_windowed_workspace_size.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Bytes of device workspace windowed estimation needs for this batch: with mlp == NULL for
+ * nssdoa_estimate_windowed, with the network for nssdoa_estimate_learned. */
+nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes);
+
+/* Windowed estimation with caller scores: scores is device [n_frames][n_bins] float, row f for
+ * frame f; a frame falls back to the full grid when its best score < score_threshold.  The other
+ * arguments are those of nssdoa_estimate. */
+nssdoa_status nssdoa_estimate_windowed(nssdoa_batch batch, const void* X, size_t x_elems, const float* scores,
+                                       int32_t n_bins, int32_t topk, double half_window_deg,
+                                       float score_threshold, void* spectrum, size_t spectrum_elems,
+                                       nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Windowed estimation with the learned proposal: per frame the features (upper triangle i <= j
+ * of R * M / trace(R), row-major, real and imaginary parts interleaved: M (M + 1) values, which
+ * must equal the network's input size) go through the network; its outputs are the bin logits
+ * (n_bins = the network's output size).  A frame falls back to the full grid when
+ * sigmoid(best logit) < fallback_score, i.e. best logit < log(p / (1 - p)); fallback_score in
+ * [0, 1] (0: never, 1: always).  The network's activation buffers are reused, so two calls that
+ * use one network must not overlap. */
+nssdoa_status nssdoa_estimate_learned(nssdoa_batch batch, nssdoa_mlp mlp, const void* X, size_t x_elems,
+                                      int32_t topk, double half_window_deg, double fallback_score,
+                                      void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks,
+                                      int32_t* npeaks, uint32_t* status, void* workspace,
+                                      size_t workspace_bytes, void* stream);
 
 /* Static description of a status code, and the last failure message on this thread. */
 const char* nssdoa_status_string(nssdoa_status status);

@@ -23,5 +23,6 @@ from .doa import (  # noqa: F401
     find_peaks,
     select_peaks,
     estimate,
+    estimate_windowed,
     percent_error,
 )

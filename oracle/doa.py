@@ -212,6 +212,36 @@ def estimate(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, *,
     return Estimate(R, lam, U, B, angles, Q, P, sel, angles[sel], allp)
 
 
+def estimate_windowed(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, windows, *,
+                      phi_deg=None) -> Estimate:
+    """Steps 1-6 with the Step-5 scan and the Step-6 search restricted to index windows.
+
+    Not part of the paper: the restriction used by proposal-driven (learned) estimation.
+    ``windows`` is a list of disjoint half-open index ranges [l0, l1) of the grid.  Spectrum
+    values outside every window are unknown, so each window is searched as a non-circular
+    spectrum of its own (Step-6 findPeaks on P[l0:l1]: its end points are never peaks) and the
+    peaks of all windows are ranked together (PeakSelection).  P holds NaN outside the windows.
+    """
+    R = covariance(X)
+    lam, U = eig_desc(R)
+    B = noise_subspace_matrix(alg, lam, U, D)
+    angles = grid_angles(*grid)
+    L = len(angles)
+    Q = np.full(L, np.nan)
+    P = np.full(L, np.nan)
+    allp = []
+    for l0, l1 in windows:
+        if l1 <= l0:
+            continue
+        Qw, Pw = spectrum_factored(B, pos, angles[l0:l1], phi_deg)
+        Q[l0:l1] = Qw
+        P[l0:l1] = Pw
+        allp.extend(int(i) + l0 for i in find_peaks(Pw, circular=False))
+    allp = np.asarray(sorted(allp), dtype=np.int64)
+    sel = select_peaks(P, allp, D)
+    return Estimate(R, lam, U, B, angles, Q, P, sel, angles[sel], allp)
+
+
 def percent_error(y_meas: np.ndarray, y_true: np.ndarray) -> float:
     """Eq. 4: mean relative deviation in percent, 100/N * sum |y_meas - y_true| / |y_true|."""
     y_meas = np.asarray(y_meas, dtype=np.float64)

@@ -43,13 +43,31 @@ def init_params(seed: int, sizes=SIZES):
     return params
 
 
-def forward(params, X: np.ndarray):
-    """Logits z (batch x 180) and the hidden activations, FP64.  ReLU after layers 1 and 2."""
+def bf16_round(x) -> np.ndarray:
+    """Values rounded as the matrix-core kernels round GEMM operands: first to FP32, then to
+    bfloat16 (the upper 16 bits of an FP32 word: 8 exponent bits, 7 stored fraction bits) with
+    round-to-nearest-even on the 16 discarded bits; returned as FP64.  Finite inputs only."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    bits = f.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1                      # keep-bit: ties go to the even result
+    bits = ((bits + 0x7FFF + lsb) >> 16) << 16
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _operand(x, precision):
+    return bf16_round(x) if precision == "bf16" else x
+
+
+def forward(params, X: np.ndarray, precision: str = "fp64"):
+    """Logits z (batch x 180) and the hidden pre-activations' ReLUs, FP64.  ReLU after layers 1
+    and 2.  precision="bf16" rounds both operands of every matrix product to bfloat16 first, as
+    the kernels do (products and sums stay FP64; biases are added unrounded); the ReLU decisions
+    then follow the kernels' arithmetic instead of exact arithmetic."""
     X = np.asarray(X, dtype=np.float64)
     acts = [X]
     h = X
     for li, (W, b) in enumerate(params):
-        z = h @ W.T + b
+        z = _operand(h, precision) @ _operand(W, precision).T + b
         if li < len(params) - 1:
             h = np.maximum(z, 0.0)
             acts.append(h)
@@ -65,9 +83,11 @@ def bce_with_logits(z: np.ndarray, y: np.ndarray) -> float:
     return float(np.mean(np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def backward(params, X: np.ndarray, y: np.ndarray):
-    """Loss and gradients (dW, db) of bce_with_logits(forward(X)) by the chain rule."""
-    z, acts = forward(params, X)
+def backward(params, X: np.ndarray, y: np.ndarray, precision: str = "fp64"):
+    """Loss and gradients (dW, db) of bce_with_logits(forward(X)) by the chain rule.
+    precision="bf16" rounds both operands of every matrix product (forward and backward) to
+    bfloat16 as the kernels do; bias gradients are unrounded column sums."""
+    z, acts = forward(params, X, precision)
     n = z.size
     sig = 1.0 / (1.0 + np.exp(-z))
     delta = (sig - np.asarray(y, dtype=np.float64)) / n        # dL/dz
@@ -75,9 +95,9 @@ def backward(params, X: np.ndarray, y: np.ndarray):
     for li in range(len(params) - 1, -1, -1):
         W, b = params[li]
         a = acts[li]
-        grads[li] = (delta.T @ a, delta.sum(axis=0))
+        grads[li] = (_operand(delta, precision).T @ _operand(a, precision), delta.sum(axis=0))
         if li > 0:
-            delta = (delta @ W) * (acts[li] > 0.0)
+            delta = (_operand(delta, precision) @ _operand(W, precision)) * (acts[li] > 0.0)
     return bce_with_logits(z, y), grads
 
 
@@ -107,16 +127,32 @@ def bin_labels(angles_deg, n_bins: int = N_BINS) -> np.ndarray:
 
 
 def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid_start: float,
-                     grid_step: float, L: int):
-    """Index ranges [l0, l1) of the global grid covered by +-half_window around the centres of the
-    topk best bins (ties to the lower bin), merged where they overlap, ascending."""
-    order = sorted(range(len(scores)), key=lambda b: (-float(scores[b]), b))[:topk]
+                     grid_step: float, L: int, threshold=None):
+    """Index ranges [l0, l1) of a grid covered by +-half_window around the centres of the topk
+    best bins, merged where they overlap or touch, ascending.
+
+    n_bins = len(scores) bins of width w = 180 / n_bins; bin b covers [-90 + b w, -90 + (b+1) w)
+    and its centre is -90 + (b + 1/2) w.  NaN scores are never chosen; ties go to the lower bin.
+    A window is snapped inward to the grid (a 1e-9 step guard absorbs the rounding of the
+    division) and clipped to [0, L); empty windows are dropped.  With a threshold, a frame whose
+    best score is below it (or has no non-NaN score) gets the whole grid [(0, L)] instead.
+    """
+    s = np.asarray(scores, dtype=np.float64)
+    n_bins = len(s)
+    eligible = [b for b in range(n_bins) if not np.isnan(s[b])]
+    order = sorted(eligible, key=lambda b: (-s[b], b))[:topk]
+    best = s[order[0]] if order else -np.inf
+    if threshold is not None and not (best >= threshold):
+        return [(0, int(L))]
+    width = 180.0 / n_bins
     rng = []
     for b in order:
-        c = -89.5 + b
+        c = -90.0 + (b + 0.5) * width
         l0 = int(np.ceil((c - half_window_deg - grid_start) / grid_step - 1e-9))
         l1 = int(np.floor((c + half_window_deg - grid_start) / grid_step + 1e-9)) + 1
-        rng.append((max(0, l0), min(L, l1)))
+        l0, l1 = max(0, l0), min(int(L), l1)
+        if l1 > l0:
+            rng.append((l0, l1))
     rng.sort()
     merged = []
     for a, b in rng:

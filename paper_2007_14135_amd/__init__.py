@@ -7,6 +7,7 @@ in include/nssdoa.h); this package only marshals arguments to it.
 from ._abi import (  # noqa: F401
     ALGS, PRECS, PEAK_DTYPE, NssdoaError, load,
     ST_NONFINITE_INPUT, ST_EVD_NOT_CONVERGED, ST_DEGENERATE, ST_FEWER_PEAKS, ST_PEAK_OVERFLOW,
+    ST_FALLBACK_USED,
     WS_COV, WS_EVALS, WS_EVECS, WS_B, WS_QREF, WS_SPECTRUM,
 )
-from .api import Batch, Options, Plan, decode_peaks  # noqa: F401
+from .api import MLP, Batch, Options, Plan, decode_peaks, flatten_params, unflatten_params  # noqa: F401

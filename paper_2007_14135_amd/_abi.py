@@ -18,12 +18,13 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ESTATE = range(6)
 ALGS = {"phd": 0, "music": 1, "ev": 2, "mn": 3}
 PRECS = {"c128": 0, "c64": 1, "bf16": 2, "f16": 3}
 WS_COV, WS_EVALS, WS_EVECS, WS_B, WS_QREF, WS_SPECTRUM = range(6)
-STAGES = {"covariance": 0, "eigen": 1, "scan": 2, "peaks": 3}
+STAGES = {"covariance": 0, "eigen": 1, "scan": 2, "peaks": 3, "proposal": 4}
 ST_NONFINITE_INPUT = 0x1
 ST_EVD_NOT_CONVERGED = 0x2
 ST_DEGENERATE = 0x4
 ST_FEWER_PEAKS = 0x8
 ST_PEAK_OVERFLOW = 0x10
+ST_FALLBACK_USED = 0x20
 
 
 class Array(ctypes.Structure):
@@ -71,6 +72,19 @@ _SIGNATURES = {
     "nssdoa_set_timing": [_P, ctypes.c_int32],
     "nssdoa_stage_time": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64)],
+    "nssdoa_mlp_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "nssdoa_mlp_destroy": [_P],
+    "nssdoa_mlp_param_count": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "nssdoa_mlp_save": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "nssdoa_mlp_load": [_P, _P, ctypes.c_size_t],
+    "nssdoa_mlp_forward": [_P, _P, ctypes.c_int32, _P, _P],
+    "nssdoa_mlp_train_step": [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P],
+    "nssdoa_mlp_gradients": [_P, _P, ctypes.c_size_t],
+    "nssdoa_windowed_workspace_size": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "nssdoa_estimate_windowed": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_float, _P, ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P],
+    "nssdoa_estimate_learned": [_P, _P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                _P, ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P],
 }
 
 _lib = None

@@ -130,6 +130,37 @@ class Batch:
                                        _stream_handle(stream)),
                    "nssdoa_estimate")
 
+    def windowed_workspace_size(self, mlp: Optional["MLP"] = None) -> int:
+        n = ctypes.c_size_t()
+        _abi.check(_abi.load().nssdoa_windowed_workspace_size(self.handle, mlp.handle if mlp is not None else None,
+                                                              ctypes.byref(n)), "nssdoa_windowed_workspace_size")
+        return int(n.value)
+
+    def estimate_windowed(self, X, scores, topk: int, half_window_deg: float, score_threshold: float,
+                          spectrum, peaks, npeaks, status, workspace, stream=None) -> None:
+        """Windowed estimation with caller scores (device float [n_frames][n_bins])."""
+        lib = _abi.load()
+        ws_bytes = workspace.numel() * workspace.element_size()
+        s_elems = spectrum.numel() if spectrum is not None else 0
+        _abi.check(lib.nssdoa_estimate_windowed(self.handle, _ptr(X), X.numel() // 2, _ptr(scores),
+                                                int(scores.shape[1]), int(topk), float(half_window_deg),
+                                                float(score_threshold), _ptr(spectrum), s_elems, _ptr(peaks),
+                                                _ptr(npeaks), _ptr(status), _ptr(workspace), ws_bytes,
+                                                _stream_handle(stream)),
+                   "nssdoa_estimate_windowed")
+
+    def estimate_learned(self, mlp: "MLP", X, topk: int, half_window_deg: float, fallback_score: float,
+                         spectrum, peaks, npeaks, status, workspace, stream=None) -> None:
+        """Windowed estimation with the learned proposal network."""
+        lib = _abi.load()
+        ws_bytes = workspace.numel() * workspace.element_size()
+        s_elems = spectrum.numel() if spectrum is not None else 0
+        _abi.check(lib.nssdoa_estimate_learned(self.handle, mlp.handle, _ptr(X), X.numel() // 2, int(topk),
+                                               float(half_window_deg), float(fallback_score), _ptr(spectrum),
+                                               s_elems, _ptr(peaks), _ptr(npeaks), _ptr(status), _ptr(workspace),
+                                               ws_bytes, _stream_handle(stream)),
+                   "nssdoa_estimate_learned")
+
     def set_timing(self, enable: bool) -> None:
         _abi.check(_abi.load().nssdoa_set_timing(self.handle, 1 if enable else 0), "nssdoa_set_timing")
 
@@ -144,3 +175,93 @@ class Batch:
 def decode_peaks(peaks_host_bytes: np.ndarray, n_frames: int, max_D: int) -> np.ndarray:
     """View a host copy of the peaks buffer as a structured (n_frames, max_D) array."""
     return np.frombuffer(np.ascontiguousarray(peaks_host_bytes).tobytes(), dtype=_abi.PEAK_DTYPE).reshape(n_frames, max_D)
+
+
+class MLP:
+    """The proposal network object (nssdoa_mlp): parameters, Adam state, activations on device."""
+
+    HEADER_WORDS = 8
+
+    def __init__(self, n_in: int, width: int, n_out: int, max_batch: int):
+        lib = _abi.load()
+        h = ctypes.c_void_p()
+        _abi.check(lib.nssdoa_mlp_create(ctypes.byref(h), int(n_in), int(width), int(n_out), int(max_batch)),
+                   "nssdoa_mlp_create")
+        self.handle = h
+        self.sizes = (int(n_in), int(width), int(n_out))
+        self.max_batch = int(max_batch)
+        n = ctypes.c_size_t()
+        _abi.check(lib.nssdoa_mlp_param_count(h, ctypes.byref(n)), "nssdoa_mlp_param_count")
+        self.n_params = int(n.value)
+
+    def close(self):
+        if self.handle:
+            _abi.check(_abi.load().nssdoa_mlp_destroy(self.handle), "nssdoa_mlp_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                _abi.load().nssdoa_mlp_destroy(self.handle)
+        except Exception:
+            pass
+
+    def save(self) -> bytes:
+        lib = _abi.load()
+        n = ctypes.c_size_t()
+        _abi.check(lib.nssdoa_mlp_save(self.handle, None, ctypes.byref(n)), "nssdoa_mlp_save")
+        buf = ctypes.create_string_buffer(n.value)
+        _abi.check(lib.nssdoa_mlp_save(self.handle, buf, ctypes.byref(n)), "nssdoa_mlp_save")
+        return buf.raw
+
+    def load(self, blob: bytes) -> None:
+        _abi.check(_abi.load().nssdoa_mlp_load(self.handle, blob, len(blob)), "nssdoa_mlp_load")
+
+    def load_params(self, flat_params: np.ndarray, step: int = 0, m=None, v=None) -> None:
+        """Load FP32 parameters (in the C ABI order) and optional Adam moments."""
+        p = np.ascontiguousarray(flat_params, dtype=np.float32)
+        assert p.size == self.n_params
+        z = np.zeros_like(p)
+        mm = z if m is None else np.ascontiguousarray(m, dtype=np.float32)
+        vv = z if v is None else np.ascontiguousarray(v, dtype=np.float32)
+        hdr = np.array([0x50434c4d, 1, self.sizes[0], self.sizes[1], self.sizes[2], int(step), 0, 0], dtype=np.int32)
+        self.load(hdr.tobytes() + p.tobytes() + mm.tobytes() + vv.tobytes())
+
+    def state(self):
+        """(params, m, v, step) as host arrays."""
+        raw = self.save()
+        hdr = np.frombuffer(raw[:32], dtype=np.int32)
+        f = np.frombuffer(raw[32:], dtype=np.float32)
+        n = self.n_params
+        return f[:n].copy(), f[n:2 * n].copy(), f[2 * n:].copy(), int(hdr[5])
+
+    def forward(self, feats, logits, stream=None) -> None:
+        _abi.check(_abi.load().nssdoa_mlp_forward(self.handle, _ptr(feats), int(feats.shape[0]), _ptr(logits),
+                                                  _stream_handle(stream)), "nssdoa_mlp_forward")
+
+    def train_step(self, feats, targets, lr: float, loss, stream=None) -> None:
+        _abi.check(_abi.load().nssdoa_mlp_train_step(self.handle, _ptr(feats), _ptr(targets), int(feats.shape[0]),
+                                                     float(lr), _ptr(loss), _stream_handle(stream)),
+                   "nssdoa_mlp_train_step")
+
+    def gradients(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _abi.check(_abi.load().nssdoa_mlp_gradients(self.handle, out.ctypes.data_as(ctypes.c_void_p), out.size),
+                   "nssdoa_mlp_gradients")
+        return out
+
+
+def flatten_params(params) -> np.ndarray:
+    """[(W1, b1), (W2, b2), (W3, b3)] -> one vector in the C ABI order."""
+    return np.concatenate([np.concatenate([W.reshape(-1), b.reshape(-1)]) for W, b in params])
+
+
+def unflatten_params(flat: np.ndarray, sizes):
+    out, o = [], 0
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        W = flat[o:o + fin * fout].reshape(fout, fin)
+        o += fin * fout
+        b = flat[o:o + fout]
+        o += fout
+        out.append((W, b))
+    return out

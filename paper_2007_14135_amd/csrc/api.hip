@@ -30,6 +30,15 @@ nssdoa_status fail(nssdoa_status st, const char* fmt, ...) {
     return st;
 }
 
+}  // namespace
+
+nssdoa_status nssdoa_internal_fail(nssdoa_status st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
+
+namespace {
+
 nssdoa_status hip_fail(hipError_t e, const char* what) {
     return fail(e == hipErrorOutOfMemory ? NSSDOA_ENOMEM : NSSDOA_EDEVICE, "%s: %s", what,
                 hipGetErrorString(e));
@@ -324,7 +333,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.ws_evecs = (int64_t)off;   off = align_up(off + MM * 16);
         fd.ws_B = (int64_t)off;       off = align_up(off + (size_t)fd.M * fd.K * 16);
         fd.ws_qref = (int64_t)off;    off = align_up(off + 8);
-        const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk;
+        // candidate chunks: one per 4096 grid points, plus one per window of windowed estimation
+        const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk + kMaxWindows;
         fd.ws_cand = (int64_t)off;    off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
         if (prec != NSSDOA_C128) {
             // low-Q list: room for an eighth of the grid (at least 256 points); a frame with more
@@ -542,10 +552,82 @@ nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* 
     return NSSDOA_OK;
 }
 
-nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
-                              size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
-                              uint32_t* status, void* workspace, size_t workspace_bytes,
-                              void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Arguments of windowed estimation; mlp != NULL selects the learned proposal (scores are the
+// network's logits of the frames' covariance features).
+struct WindowArgs {
+    nssdoa_mlp mlp;
+    const float* scores;
+    int32_t n_bins;
+    int32_t topk;
+    double half_window;
+    float threshold;
+};
+
+size_t windowed_layout(const nssdoa_batch_s* b, int n_feat, int n_bins, LearnedLayout* lay) {
+    const size_t F = (size_t)b->n_frames;
+    size_t off = align_up(b->ws_bytes);
+    lay->off_feat = (int64_t)off;      off = align_up(off + F * n_feat * sizeof(float));
+    lay->off_scores = (int64_t)off;    off = align_up(off + F * n_bins * sizeof(float));
+    lay->off_win = (int64_t)off;       off = align_up(off + F * kWinStride * sizeof(int32_t));
+    lay->off_items = (int64_t)off;     off = align_up(off + F * sizeof(int32_t));
+    lay->off_chunks = (int64_t)off;    off = align_up(off + F * sizeof(int32_t));
+    lay->off_lowq = (int64_t)off;      off = align_up(off + F * sizeof(int32_t));
+    lay->off_item_off = (int64_t)off;  off = align_up(off + (F + 1) * sizeof(int32_t));
+    lay->off_chunk_off = (int64_t)off; off = align_up(off + (F + 1) * sizeof(int32_t));
+    lay->off_lowq_off = (int64_t)off;  off = align_up(off + (F + 1) * sizeof(int32_t));
+    return off;
+}
+
+// workgroups of a grid-stride launch: `per_cu` resident workgroups on every compute unit
+int persistent_grid(int per_cu) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus * per_cu;
+}
+
+nssdoa_status check_windowed(nssdoa_batch batch, const WindowArgs& wa, int* n_feat, int* n_bins) {
+    if (batch->prec != NSSDOA_C64)
+        return fail(NSSDOA_EUNSUPPORTED, "windowed estimation runs the FP32 scan: create the batch with NSSDOA_C64");
+    const int M = batch->frames[0].M;
+    for (const FrameDev& fd : batch->frames)
+        if (fd.M != M) return fail(NSSDOA_EUNSUPPORTED, "windowed estimation needs one array size in the batch");
+    if (wa.topk < 1 || wa.topk > kMaxWindows) return fail(NSSDOA_EINVAL, "topk=%d outside [1, %d]", wa.topk, kMaxWindows);
+    if (!(wa.half_window > 0.0) || !(wa.half_window <= 180.0))
+        return fail(NSSDOA_EINVAL, "half_window_deg must be in (0, 180]");
+    if (wa.threshold != wa.threshold) return fail(NSSDOA_EINVAL, "threshold is NaN");
+    *n_feat = 0;
+    *n_bins = wa.n_bins;
+    if (wa.mlp) {
+        int32_t in, width, out, mb;
+        mlp_dims(wa.mlp, &in, &width, &out, &mb);
+        if (in != M * (M + 1))
+            return fail(NSSDOA_EINVAL, "the network takes %d inputs, covariance features of M=%d are %d", in, M, M * (M + 1));
+        *n_feat = in;
+        *n_bins = out;
+    } else if (!wa.scores) {
+        return fail(NSSDOA_EINVAL, "scores is NULL");
+    }
+    if (*n_bins < 1 || *n_bins > kMaxBins) return fail(NSSDOA_EINVAL, "n_bins=%d outside [1, %d]", *n_bins, kMaxBins);
+    for (int f = 0; f < batch->n_frames; ++f) {
+        const FrameDev& fd = batch->frames[f];
+        const int64_t slots = ((int64_t)(fd.L + kRefineChunk - 1) / kRefineChunk + wa.topk) *
+                              (fd.D + batch->plan->opt.extra_candidates);
+        if (slots > kSelCap)
+            return fail(NSSDOA_EINVAL, "frame %d: %d windows on a grid of %d points exceed the peak candidate capacity",
+                        f, wa.topk, fd.L);
+    }
+    return NSSDOA_OK;
+}
+
+nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                            size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                            void* workspace, size_t workspace_bytes, void* stream, const WindowArgs* wa) {
     if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
     if (!X || !peaks || !npeaks || !status || !workspace)
         return fail(NSSDOA_EINVAL, "NULL X, peaks, npeaks, status or workspace");
@@ -555,8 +637,17 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     if (spectrum && spectrum_elems < batch->spec_extent)
         return fail(NSSDOA_EINVAL, "spectrum holds %zu elements, the frames address %zu",
                     spectrum_elems, batch->spec_extent);
-    if (workspace_bytes < batch->ws_bytes)
-        return fail(NSSDOA_EINVAL, "workspace of %zu bytes < required %zu", workspace_bytes, batch->ws_bytes);
+    LearnedLayout lay;
+    memset(&lay, 0, sizeof(lay));
+    size_t need = batch->ws_bytes;
+    int n_feat = 0, n_bins = 0;
+    if (wa) {
+        nssdoa_status st = check_windowed(batch, *wa, &n_feat, &n_bins);
+        if (st != NSSDOA_OK) return st;
+        need = windowed_layout(batch, n_feat, wa->mlp ? n_bins : 0, &lay);
+    }
+    if (workspace_bytes < need)
+        return fail(NSSDOA_EINVAL, "workspace of %zu bytes < required %zu", workspace_bytes, need);
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
         return fail(NSSDOA_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -602,6 +693,54 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     }
     if ((st = stage_end(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
 
+    PeakParams pp;
+    memset(&pp, 0, sizeof(pp));
+    pp.lowq_tau = opt.lowq_tau;
+    pp.halfwidth = opt.refine_halfwidth;
+    pp.extra = opt.extra_candidates;
+    pp.max_D = batch->max_D;
+    pp.refine_lowq = c128 ? 0 : 1;
+    pp.use_user_spec = use_user;
+
+    if (wa) {
+        const int F = batch->n_frames, M = batch->frames[0].M;
+        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        const float* scores = wa->scores;
+        if (wa->mlp) {
+            float* feats = reinterpret_cast<float*>(ws + lay.off_feat);
+            float* logits = reinterpret_cast<float*>(ws + lay.off_scores);
+            e = launch_features(nullptr, F, batch->d_frames, ws, feats, n_feat, s);
+            if (e == hipSuccess) e = mlp_forward_rows(wa->mlp, feats, F, logits, s);
+            if (e != hipSuccess) return hip_fail(e, "proposal network launch");
+            scores = logits;
+        }
+        e = launch_proposals(batch->d_frames, F, scores, n_bins, wa->topk, wa->half_window, wa->threshold, ws, lay,
+                             status, s);
+        if (e != hipSuccess) return hip_fail(e, "proposal launch");
+        if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
+
+        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        e = launch_scan_windows(M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_pos, ws, lay,
+                                static_cast<float*>(spec), use_user, (float)opt.lowq_tau, persistent_grid(8), s);
+        if (e != hipSuccess) return hip_fail(e, "windowed scan launch");
+        if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
+
+        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
+        e = launch_window_peaks(bucket, batch->d_frames, F, batch->d_pos, batch->d_cis, ws, lay, opt.extra_candidates,
+                                opt.lowq_tau, static_cast<float*>(spec), use_user, persistent_grid(2), s);
+        if (e != hipSuccess) return hip_fail(e, "windowed peak launch");
+        pp.chunk_count = reinterpret_cast<const int32_t*>(ws + lay.off_chunks);
+        pp.windows = reinterpret_cast<const int32_t*>(ws + lay.off_win);
+        for (auto& r : batch->peak_ranges) {
+            e = launch_peaks(false, r.first, nullptr, 0, nullptr, 0, batch->d_plist + r.second.first,
+                             r.second.second - r.second.first, batch->d_frames, batch->d_pos, batch->d_cis, ws, spec,
+                             pp, peaks, npeaks, status, s);
+            if (e != hipSuccess) return hip_fail(e, "peak launch");
+        }
+        return stage_end(NSSDOA_STAGE_PEAKS);
+    }
+
     if ((st = stage_begin()) != NSSDOA_OK) return st;
     if (c128) {
         e = launch_scan_f64(batch->d_points, (int)batch->point_items.size(), batch->max_M, batch->d_frames,
@@ -624,14 +763,6 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
     if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
 
     if ((st = stage_begin()) != NSSDOA_OK) return st;
-    PeakParams pp;
-    pp.lowq_tau = opt.lowq_tau;
-    pp.halfwidth = opt.refine_halfwidth;
-    pp.extra = opt.extra_candidates;
-    pp.max_D = batch->max_D;
-    pp.refine_lowq = c128 ? 0 : 1;
-    pp.use_user_spec = use_user;
-    pp.pad = 0;
     for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
         const auto& r = batch->peak_ranges[i];
         const auto& ri = batch->refine_ranges[i];
@@ -642,8 +773,52 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
                          batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
         if (e != hipSuccess) return hip_fail(e, "peak launch");
     }
-    if ((st = stage_end(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;
+    return stage_end(NSSDOA_STAGE_PEAKS);
+}
+
+}  // namespace
+
+extern "C" {
+
+nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                              size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                              uint32_t* status, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+    return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
+                         workspace_bytes, stream, nullptr);
+}
+
+nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes) {
+    if (!batch || !bytes) return fail(NSSDOA_EINVAL, "NULL argument");
+    int32_t in = 0, width = 0, out = 0, mb = 0;
+    if (mlp) mlp_dims(mlp, &in, &width, &out, &mb);
+    LearnedLayout lay;
+    *bytes = windowed_layout(batch, in, out, &lay);
     return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_estimate_windowed(nssdoa_batch batch, const void* X, size_t x_elems, const float* scores,
+                                       int32_t n_bins, int32_t topk, double half_window_deg, float score_threshold,
+                                       void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                       uint32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    WindowArgs wa{nullptr, scores, n_bins, topk, half_window_deg, score_threshold};
+    return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
+                         workspace_bytes, stream, &wa);
+}
+
+nssdoa_status nssdoa_estimate_learned(nssdoa_batch batch, nssdoa_mlp mlp, const void* X, size_t x_elems,
+                                      int32_t topk, double half_window_deg, double fallback_score,
+                                      void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                      uint32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!mlp) return fail(NSSDOA_EINVAL, "mlp is NULL");
+    if (!(fallback_score >= 0.0 && fallback_score <= 1.0))
+        return fail(NSSDOA_EINVAL, "fallback_score must be in [0, 1]");
+    // sigmoid(z) < p  <=>  z < log(p / (1 - p))
+    const double thr = fallback_score == 0.0 ? -INFINITY : fallback_score == 1.0 ? INFINITY
+                                             : log(fallback_score) - log1p(-fallback_score);
+    WindowArgs wa{mlp, nullptr, 0, topk, half_window_deg, (float)thr};
+    return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
+                         workspace_bytes, stream, &wa);
 }
 
 }  // extern "C"

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "nssdoa.h"
+
 namespace nssdoa {
 
 constexpr double kDeg2Rad = 0.017453292519943295;   // pi / 180, the same constant numpy uses
@@ -14,6 +16,9 @@ constexpr int kScanAnglesPerWave = 64;              // two 32-angle MFMA column 
 constexpr int kScanAnglesPerWG = kScanWaves * kScanAnglesPerWave;
 constexpr int kRefineChunk = 4096;                  // grid points per refine/local-maximum workgroup
 constexpr int kSelCap = 4096;                       // chunk candidates gathered per frame
+constexpr int kMaxWindows = 16;                     // scan windows per frame (windowed estimation)
+constexpr int kWinStride = 1 + 2 * kMaxWindows;     // int32 per frame: count, then [l0, l1) pairs
+constexpr int kMaxBins = 256;                       // proposal bins
 
 enum Alg : int32_t { kPHD = 0, kMUSIC = 1, kEV = 2, kMN = 3 };
 
@@ -71,6 +76,24 @@ struct PeakParams {
     int32_t refine_lowq;        // 1 for FP32 spectra
     int32_t use_user_spec;      // spectrum lives in the caller's buffer
     int32_t pad;
+    // windowed estimation (both NULL otherwise): candidate chunks per frame, and the per-frame
+    // window tables (kWinStride int32 each); grid points outside every window count as unknown
+    const int32_t* chunk_count;
+    const int32_t* windows;
+};
+
+// Byte offsets, inside the workspace, of the windowed-estimation tables (after the batch's own
+// regions).  off_feat and off_scores are used by the learned path only.
+struct LearnedLayout {
+    int64_t off_feat;           // n_frames x n_feat float
+    int64_t off_scores;         // n_frames x n_bins float (network logits)
+    int64_t off_win;            // n_frames x kWinStride int32
+    int64_t off_items;          // n_frames int32: 64-angle scan items
+    int64_t off_chunks;         // n_frames int32: 4096-point peak chunks
+    int64_t off_lowq;           // n_frames int32: 64-entry low-Q slices
+    int64_t off_item_off;       // n_frames + 1 int32 exclusive prefix sums of the three counts
+    int64_t off_chunk_off;
+    int64_t off_lowq_off;
 };
 
 // Scan angle theta_l = start + l * step with the product and the sum rounded separately
@@ -219,5 +242,31 @@ hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* lowq_items, int
                         int n_frames, const FrameDev* frames, const double* pos,
                         const double2* cis, char* ws, void* spec, const PeakParams& p,
                         void* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s);
+
+hipError_t launch_gemm_bf16(int M, int N, int K, const float* A, int64_t sam, int64_t sak, int relu_in_a,
+                            const float* B, int64_t sbk, int64_t sbn, int relu_in_b, float alpha,
+                            const float* bias, const float* mask, int64_t ldm, int relu_out, float* C,
+                            int64_t ldc, hipStream_t s);
+hipError_t launch_colsum(int rows, int cols, const float* X, int64_t ld, float* out, hipStream_t s);
+hipError_t launch_bce(int rows, int cols, const float* Z, const float* Y, float* dZ, float* row_loss,
+                      float* loss, hipStream_t s);
+hipError_t launch_adam(int n, float* p, const float* g, float* m, float* v, float lr, int t, hipStream_t s);
+hipError_t launch_features(const int32_t* flist, int n, const FrameDev* frames, const char* ws, float* out,
+                           int nfeat, hipStream_t s);
+
+hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
+                            double half_window, float threshold, char* ws, const LearnedLayout& lay,
+                            uint32_t* status, hipStream_t s);
+hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+                               const int32_t* blkframe, const double* pos, char* ws, const LearnedLayout& lay,
+                               float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);
+hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,
+                               const double2* cis, char* ws, const LearnedLayout& lay, int extra, double lowq_tau,
+                               float* spec, int use_user, int n_wg, hipStream_t s);
+
+// Network dimensions and its forward pass for `rows` feature rows into logits[rows][out]
+// (processed in slices of the network's max_batch rows).
+void mlp_dims(nssdoa_mlp n, int32_t* in, int32_t* width, int32_t* out, int32_t* max_batch);
+hipError_t mlp_forward_rows(nssdoa_mlp n, const float* feats, int rows, float* logits, hipStream_t s);
 
 }  // namespace nssdoa

@@ -1,0 +1,483 @@
+// Windowed estimation: the Table 2 Step-5 scan and the Step-6 peak search restricted to angle
+// windows chosen from per-bin scores (the learned proposal network's logits, or any caller
+// scores).  Every kernel here reads the per-frame work that the proposal kernel wrote on the
+// device, so the host issues the whole sequence without waiting for it.
+//
+// proposal_kernel, one wave per frame: bin b covers [-90 + b w, -90 + (b+1) w) deg with
+//   w = 180 / n_bins.  The topk best bins (ties to the lower bin) give windows centre +- half
+//   width, snapped to the frame's grid, sorted and merged.  A frame whose best score is below
+//   the threshold falls back to one window over its whole grid.  It also counts the frame's
+//   64-angle scan items and 4096-point peak chunks.
+// prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan).
+// scan_win_kernel<M>, grid-stride over 64-angle items, one wave per item: one frame's angles in
+//   one window, contracted on the FP32 matrix cores with the frame's own 8-row blocks of the
+//   packed B tiles (the operands and epilogue of the group scan).
+// lowq_win_kernel<MB>, grid-stride over 64-entry slices of the frames' low-Q lists: FP64
+//   re-evaluation of the listed points.
+// winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
+//   chunk: the chunk's best D + extra local maxima to its candidate slots.  Values outside a
+//   window are unknown, so a window's end points are never peaks.
+#include <float.h>
+
+#include "nssdoa.h"
+#include "internal.h"
+
+namespace nssdoa {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int kHaloW = 16;
+
+__device__ inline double qnan_d() { return __longlong_as_double(0x7ff8000000000000LL); }
+
+__device__ inline const int* frame_windows(const char* ws, const LearnedLayout& lay, int f) {
+    return reinterpret_cast<const int*>(ws + lay.off_win) + (size_t)f * kWinStride;
+}
+
+// window of bin b: centre c, start index ceil((c - hw - start) / step - 1e-9), end (exclusive)
+// floor((c + hw - start) / step + 1e-9) + 1, every operation rounded separately
+__device__ inline void window_of_bin(int b, double width, double hw, double start, double step, int L,
+                                     int* l0, int* l1) {
+#pragma clang fp contract(off)
+    const double c = -90.0 + ((double)b + 0.5) * width;
+    const double lo = (c - hw - start) / step - 1e-9;
+    const double hi = (c + hw - start) / step + 1e-9;
+    *l0 = (int)fmax(ceil(lo), 0.0);
+    *l1 = (int)fmin(floor(hi) + 1.0, (double)L);
+}
+
+__global__ __launch_bounds__(64) void proposal_kernel(const FrameDev* __restrict__ frames, int n_frames,
+                                                      const float* __restrict__ scores, int n_bins, int topk,
+                                                      double half_window, float threshold,
+                                                      char* __restrict__ ws, LearnedLayout lay,
+                                                      uint32_t* __restrict__ status) {
+    const int f = blockIdx.x;
+    if (f >= n_frames) return;
+    const FrameDev& fr = frames[f];
+    const int lane = threadIdx.x;
+    __shared__ float sc[kMaxBins];
+    __shared__ int chosen[kMaxWindows];
+    const float* z = scores + (size_t)f * n_bins;
+    for (int b = lane; b < n_bins; b += 64) sc[b] = z[b];
+    __syncthreads();
+    // best score (the fallback test) and the topk best bins; NaN scores never win
+    float best = -INFINITY;
+    int nch = 0;
+    for (int r = 0; r < topk; ++r) {
+        float v = -INFINITY;
+        int bi = 1 << 30;
+        for (int b = lane; b < n_bins; b += 64)
+            if (sc[b] > v || (sc[b] == v && b < bi)) { v = sc[b]; bi = b; }
+        for (int o = 32; o > 0; o >>= 1) {
+            const float v2 = __shfl_xor(v, o);
+            const int b2 = __shfl_xor(bi, o);
+            if (v2 > v || (v2 == v && b2 < bi)) { v = v2; bi = b2; }
+        }
+        if (r == 0) best = v;
+        if (bi >= n_bins) break;          // uniform: every lane holds the reduced value
+        if (lane == 0) {
+            chosen[nch] = bi;
+            sc[bi] = -INFINITY;
+        }
+        ++nch;
+        __syncthreads();
+    }
+    if (lane != 0) return;
+    int* W = reinterpret_cast<int*>(ws + lay.off_win) + (size_t)f * kWinStride;
+    int nw = 0;
+    if (status[f] & NSSDOA_ST_NONFINITE_INPUT) {
+        nw = 0;                           // nothing to scan
+    } else if (!(best >= threshold)) {
+        W[1] = 0;
+        W[2] = fr.L;
+        nw = 1;
+        status[f] |= NSSDOA_ST_FALLBACK_USED;
+    } else {
+        const double width = 180.0 / (double)n_bins;
+        int l0s[kMaxWindows], l1s[kMaxWindows];
+        for (int i = 0; i < nch; ++i) {
+            int a, e;
+            window_of_bin(chosen[i], width, half_window, fr.grid_start, fr.grid_step, fr.L, &a, &e);
+            int j = i;                    // insertion by (start, end)
+            while (j > 0 && (l0s[j - 1] > a || (l0s[j - 1] == a && l1s[j - 1] > e))) {
+                l0s[j] = l0s[j - 1];
+                l1s[j] = l1s[j - 1];
+                --j;
+            }
+            l0s[j] = a;
+            l1s[j] = e;
+        }
+        for (int i = 0; i < nch; ++i) {
+            if (l1s[i] <= l0s[i]) continue;
+            if (nw > 0 && l0s[i] <= W[2 * nw]) {
+                W[2 * nw] = max(W[2 * nw], l1s[i]);
+            } else {
+                W[1 + 2 * nw] = l0s[i];
+                W[2 + 2 * nw] = l1s[i];
+                ++nw;
+            }
+        }
+    }
+    W[0] = nw;
+    int items = 0, chunks = 0;
+    for (int i = 0; i < nw; ++i) {
+        const int len = W[2 + 2 * i] - W[1 + 2 * i];
+        items += (len + kScanAnglesPerWave - 1) / kScanAnglesPerWave;
+        chunks += (len + kRefineChunk - 1) / kRefineChunk;
+    }
+    reinterpret_cast<int*>(ws + lay.off_items)[f] = items;
+    reinterpret_cast<int*>(ws + lay.off_chunks)[f] = chunks;
+}
+
+// low-Q slices per frame: ceil(min(count, capacity) / 64)
+__global__ void lowq_count_kernel(const FrameDev* __restrict__ frames, int n_frames, char* __restrict__ ws,
+                                  LearnedLayout lay) {
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < n_frames; f += gridDim.x * blockDim.x) {
+        const FrameDev& fr = frames[f];
+        const int n = min(*reinterpret_cast<const int*>(ws + fr.ws_lowq), fr.lowq_cap);
+        reinterpret_cast<int*>(ws + lay.off_lowq)[f] = (n + 63) / 64;
+    }
+}
+
+// off[i] = sum of cnt[0..i-1] for i = 0..n (off has n + 1 entries), for one or two arrays.
+__global__ __launch_bounds__(1024) void prefix_kernel(int n, const int* __restrict__ cnt_a, int* __restrict__ off_a,
+                                                      const int* __restrict__ cnt_b, int* __restrict__ off_b) {
+    __shared__ int sa[1024], sb[1024];
+    const int tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
+    int a = 0, b = 0;
+    for (int i = i0; i < i1; ++i) {
+        a += cnt_a[i];
+        if (cnt_b) b += cnt_b[i];
+    }
+    sa[tid] = a;
+    sb[tid] = b;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {          // inclusive Hillis-Steele scan
+        const int xa = tid >= d ? sa[tid - d] : 0;
+        const int xb = tid >= d ? sb[tid - d] : 0;
+        __syncthreads();
+        sa[tid] += xa;
+        sb[tid] += xb;
+        __syncthreads();
+    }
+    int ra = sa[tid] - a, rb = sb[tid] - b;       // exclusive
+    for (int i = i0; i < i1; ++i) {
+        off_a[i] = ra;
+        ra += cnt_a[i];
+        if (cnt_b) {
+            off_b[i] = rb;
+            rb += cnt_b[i];
+        }
+    }
+    if (tid == 1023) {
+        off_a[n] = sa[1023];
+        if (cnt_b) off_b[n] = sb[1023];
+    }
+}
+
+// largest f with off[f] <= item (off non-decreasing, off[0] = 0 <= item < off[n])
+__device__ inline int find_frame(const int* __restrict__ off, int n, int item) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the k-th `unit`-point piece of a frame's windows: its first index and its window's bounds
+__device__ inline void locate(const int* W, int k, int unit, int* first, int* wbegin, int* wend) {
+    int local = k;
+    *first = 0;
+    *wbegin = 0;
+    *wend = 0;
+    for (int w = 0; w < W[0]; ++w) {
+        const int l0 = W[1 + 2 * w], l1 = W[2 + 2 * w];
+        const int n = (l1 - l0 + unit - 1) / unit;
+        if (local < n) {
+            *first = l0 + local * unit;
+            *wbegin = l0;
+            *wend = l1;
+            return;
+        }
+        local -= n;
+    }
+}
+
+template <int M>
+__device__ inline void steering_regs_w(const double* __restrict__ p, double th, int h, float* st) {
+    double sth, cth;
+    sincos(th * kDeg2Rad, &sth, &cth);
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+        const int m = 2 * j + h;
+        const double c = p[3 * m] * sth + p[3 * m + 1] * cth;   // cycles, phi = 90 deg
+        float s, co;
+        sincospif((float)(2.0 * (c - rint(c))), &s, &co);
+        st[j] = co;
+        st[j + M / 2] = s;
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restrict__ frames, int n_frames,
+                                                       const GroupDev* __restrict__ groups,
+                                                       const int32_t* __restrict__ blkframe,
+                                                       const double* __restrict__ pos, char* __restrict__ ws,
+                                                       LearnedLayout lay, float* __restrict__ spec, int use_user,
+                                                       float lowq_tau) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
+    const int* ioff = reinterpret_cast<const int*>(ws + lay.off_item_off);
+    const int total = ioff[n_frames];
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); item < total; item += nwaves) {
+        const int f = find_frame(ioff, n_frames, item);
+        const FrameDev& fr = frames[f];
+        const GroupDev& g = groups[fr.group];
+        int a0, wb, a1;
+        locate(frame_windows(ws, lay, f), item - ioff[f], kScanAnglesPerWave, &a0, &wb, &a1);
+        float st0[M], st1[M];
+        const double* p = pos + fr.pos_off;
+        steering_regs_w<M>(p, grid_angle(fr.grid_start, fr.grid_step, a0 + j), h, st0);
+        steering_regs_w<M>(p, grid_angle(fr.grid_start, fr.grid_step, a0 + 32 + j), h, st1);
+        const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
+        const int t0 = fr.emb_row0 >> 5, t1 = ((fr.emb_row0 + 2 * fr.K - 1) >> 5) + 1;
+        float q0 = 0.0f, q1 = 0.0f;
+        for (int t = t0; t < t1; ++t) {
+            float b[M];
+            const float4* src = reinterpret_cast<const float4*>(emb + (size_t)t * 64 * M);
+#pragma unroll
+            for (int v = 0; v < M / 4; ++v) {
+                const float4 x = src[v];
+                b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
+            }
+            floatx16 acc0 = {0.0f}, acc1 = {0.0f};
+#pragma unroll
+            for (int s = 0; s < M; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st0[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st1[s], acc1, 0, 0, 0);
+            }
+            const int4 fb = reinterpret_cast<const int4*>(blkframe + g.blk_off)[t];
+            const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                if (fbk[gq] != f) continue;
+                q0 += acc0[4 * gq] * acc0[4 * gq] + acc0[4 * gq + 1] * acc0[4 * gq + 1] +
+                      acc0[4 * gq + 2] * acc0[4 * gq + 2] + acc0[4 * gq + 3] * acc0[4 * gq + 3];
+                q1 += acc1[4 * gq] * acc1[4 * gq] + acc1[4 * gq + 1] * acc1[4 * gq + 1] +
+                      acc1[4 * gq + 2] * acc1[4 * gq + 2] + acc1[4 * gq + 3] * acc1[4 * gq + 3];
+            }
+        }
+        const float u0 = q0 + __shfl_xor(q0, 32), u1 = q1 + __shfl_xor(q1, 32);
+        const float v = (lane < 32) ? u0 : u1;
+        const int l = a0 + lane;
+        if (l < a1) {
+            float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+            out[l] = 1.0f / fmaxf(v, FLT_MIN);
+            const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fr.ws_qref);
+            if (v < thr) {
+                int* cnt = reinterpret_cast<int*>(ws + fr.ws_lowq);
+                const int slot = atomicAdd(cnt, 1);
+                if (slot < fr.lowq_cap) cnt[1 + slot] = l;
+            }
+        }
+    }
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) void lowq_win_kernel(const FrameDev* __restrict__ frames, int n_frames,
+                                                       const double* __restrict__ pos,
+                                                       const double2* __restrict__ cis, char* __restrict__ ws,
+                                                       LearnedLayout lay, float* __restrict__ spec, int use_user) {
+    const int lane = threadIdx.x & 63;
+    const int* qoff = reinterpret_cast<const int*>(ws + lay.off_lowq_off);
+    const int total = qoff[n_frames];
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); item < total; item += nwaves) {
+        const int f = find_frame(qoff, n_frames, item);
+        const FrameDev& fr = frames[f];
+        const int* list = reinterpret_cast<const int*>(ws + fr.ws_lowq);
+        const int n = min(list[0], fr.lowq_cap);
+        const int i = (item - qoff[f]) * 64 + lane;
+        if (i >= n) continue;
+        const int l = list[1 + i];
+        const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
+        const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
+                                      grid_angle(fr.grid_start, fr.grid_step, l), cis);
+        float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+        P[l] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
+    }
+}
+
+struct CandW {
+    double v;
+    int32_t idx;
+    int32_t pad;
+};
+
+template <int MB>
+__global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restrict__ frames, int n_frames,
+                                                       const double* __restrict__ pos,
+                                                       const double2* __restrict__ cis, char* __restrict__ ws,
+                                                       LearnedLayout lay, int extra, double lowq_tau,
+                                                       float* __restrict__ spec, int use_user) {
+    __shared__ double v[kRefineChunk + 2 * kHaloW];
+    __shared__ int rlist[kRefineChunk + 2 * kHaloW];
+    __shared__ double lval[kRefineChunk / 2];
+    __shared__ int lidx[kRefineChunk / 2];
+    __shared__ int lcount, rcount;
+    const int tid = threadIdx.x;
+    const int* coff = reinterpret_cast<const int*>(ws + lay.off_chunk_off);
+    const int total = coff[n_frames];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int f = find_frame(coff, n_frames, item);
+        const FrameDev& fr = frames[f];
+        const int C = fr.D + extra;
+        CandW* slots = reinterpret_cast<CandW*>(ws + fr.ws_cand) + (size_t)(item - coff[f]) * C;
+        int c0, wl0, wl1;
+        locate(frame_windows(ws, lay, f), item - coff[f], kRefineChunk, &c0, &wl0, &wl1);
+        const int nown = min(kRefineChunk, wl1 - c0), span = nown + 2 * kHaloW;
+        float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+        __syncthreads();                  // the previous chunk's LDS is no longer read
+        if (tid == 0) {
+            lcount = 0;
+            rcount = 0;
+        }
+        for (int e = tid; e < span; e += blockDim.x) {
+            const int l = c0 - kHaloW + e;
+            v[e] = (l >= wl0 && l < wl1) ? (double)P[l] : qnan_d();
+        }
+        __syncthreads();
+        // a frame whose low-Q list overflowed re-evaluates its low-Q points here
+        if (*reinterpret_cast<const int*>(ws + fr.ws_lowq) > fr.lowq_cap) {
+            const double pthr = 1.0 / (lowq_tau * *reinterpret_cast<const double*>(ws + fr.ws_qref));
+            for (int e = tid; e < span; e += blockDim.x) {
+                const double x = v[e];
+                if (x == x && !(x < pthr)) rlist[atomicAdd(&rcount, 1)] = e;
+            }
+            __syncthreads();
+            const int nr = rcount;
+            const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
+            for (int i = tid; i < nr; i += blockDim.x) {
+                const int e = rlist[i];
+                const int l = c0 - kHaloW + e;
+                const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
+                                              grid_angle(fr.grid_start, fr.grid_step, l), cis);
+                const double x = 1.0 / fmax(Q, (double)FLT_MIN);
+                v[e] = x;
+                if (e >= kHaloW && e < kHaloW + nown) P[l] = (float)x;
+            }
+            __syncthreads();
+        }
+        for (int o = tid; o < nown; o += blockDim.x) {
+            const int e = o + kHaloW;
+            const double x = v[e];
+            if (!(x > v[e - 1])) continue;
+            int r = e + 1;
+            while (r < span && v[r] == x) ++r;
+            bool peak = false;
+            if (r < span) {
+                peak = v[r] < x;
+            } else {
+                // the run of equal values is longer than the halo: follow it inside the window
+                for (int rl = c0 - kHaloW + r; rl < wl1; ++rl) {
+                    const double y = (double)P[rl];
+                    if (y != x) {
+                        peak = y < x;
+                        break;
+                    }
+                }
+            }
+            if (peak) {
+                const int s = atomicAdd(&lcount, 1);
+                if (s < kRefineChunk / 2) {
+                    lval[s] = x;
+                    lidx[s] = c0 + o;
+                }
+            }
+        }
+        __syncthreads();
+        const int n = min(lcount, kRefineChunk / 2);
+        for (int i = tid; i < n; i += blockDim.x) {
+            const double vi = lval[i];
+            const int li = lidx[i];
+            int rank = 0;
+            for (int k = 0; k < n; ++k) rank += (lval[k] > vi) || (lval[k] == vi && lidx[k] < li);
+            if (rank < C) {
+                slots[rank].v = vi;
+                slots[rank].idx = li;
+            }
+        }
+        for (int s = n + tid; s < C; s += blockDim.x) {
+            slots[s].v = qnan_d();
+            slots[s].idx = -1;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
+                            double half_window, float threshold, char* ws, const LearnedLayout& lay,
+                            uint32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(proposal_kernel, dim3(n_frames), dim3(64), 0, s, frames, n_frames, scores, n_bins, topk,
+                       half_window, threshold, ws, lay, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(1024), 0, s, n_frames,
+                       reinterpret_cast<const int*>(ws + lay.off_items), reinterpret_cast<int*>(ws + lay.off_item_off),
+                       reinterpret_cast<const int*>(ws + lay.off_chunks),
+                       reinterpret_cast<int*>(ws + lay.off_chunk_off));
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+                               const int32_t* blkframe, const double* pos, char* ws, const LearnedLayout& lay,
+                               float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s) {
+#define NSSDOA_WIN_CASE(MM)                                                                             \
+    case MM:                                                                                         \
+        hipLaunchKernelGGL(scan_win_kernel<MM>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, groups, \
+                           blkframe, pos, ws, lay, spec, use_user, lowq_tau);                          \
+        return hipGetLastError();
+    switch (M) {
+        NSSDOA_WIN_CASE(8)
+        NSSDOA_WIN_CASE(16)
+        NSSDOA_WIN_CASE(32)
+        NSSDOA_WIN_CASE(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef NSSDOA_WIN_CASE
+}
+
+hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,
+                               const double2* cis, char* ws, const LearnedLayout& lay, int extra, double lowq_tau,
+                               float* spec, int use_user, int n_wg, hipStream_t s) {
+    hipLaunchKernelGGL(lowq_count_kernel, dim3((n_frames + 255) / 256), dim3(256), 0, s, frames, n_frames, ws, lay);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(1024), 0, s, n_frames,
+                       reinterpret_cast<const int*>(ws + lay.off_lowq), reinterpret_cast<int*>(ws + lay.off_lowq_off),
+                       nullptr, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+#define NSSDOA_WP_CASE(MB)                                                                                  \
+    case MB:                                                                                             \
+        hipLaunchKernelGGL(lowq_win_kernel<MB>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, pos, cis, ws, \
+                           lay, spec, use_user);                                                           \
+        if ((e = hipGetLastError()) != hipSuccess) return e;                                               \
+        hipLaunchKernelGGL(winpeaks_kernel<MB>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, pos, cis, ws, \
+                           lay, extra, lowq_tau, spec, use_user);                                          \
+        return hipGetLastError();
+    switch (bucket_M) {
+        NSSDOA_WP_CASE(8)
+        NSSDOA_WP_CASE(16)
+        NSSDOA_WP_CASE(32)
+        NSSDOA_WP_CASE(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef NSSDOA_WP_CASE
+}
+
+}  // namespace nssdoa

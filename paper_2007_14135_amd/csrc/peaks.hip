@@ -17,7 +17,9 @@
 //     result does not depend on scheduling.
 // select_kernel, one workgroup per frame:
 //  4. ranks the chunk candidates and keeps the best D + extra;
-//  5. evaluates a window of +-halfwidth points around each in FP64 (16 lanes per point);
+//  5. evaluates a window of +-halfwidth points around each in FP64 (16 lanes per point),
+//     sliding a window that holds no interior FP64 local maximum uphill; in windowed
+//     estimation points outside the scan windows are left unknown (NaN);
 //  6. ranks the distinct FP64 local maxima of the windows by (value desc, index asc) and writes
 //     the first D; slots beyond the number found get idx = -1 and NaN.
 #include <float.h>
@@ -33,6 +35,7 @@ constexpr int kLocalCap = kRefineChunk / 2;
 constexpr int kMaxSel = 96;      // D + extra <= 63 + 16 < 96
 constexpr int kMaxWin = 33;      // 2 * 16 + 1
 constexpr int kMaxFinal = 1024;
+constexpr int kMaxClimb = 32;    // slides of an FP64 window toward a flat peak's maximum
 
 struct Cand {
     double v;
@@ -41,6 +44,13 @@ struct Cand {
 };
 
 __device__ inline double qnan() { return __longlong_as_double(0x7ff8000000000000LL); }
+
+// l lies in one of the windows W = {count, [l0, l1) pairs}
+__device__ inline bool in_windows(const int32_t* W, int l) {
+    bool in = false;
+    for (int i = 0; i < W[0]; ++i) in |= (l >= W[1 + 2 * i]) && (l < W[2 + 2 * i]);
+    return in;
+}
 
 template <int MB>
 __global__ __launch_bounds__(256) void lowq_kernel(const PointItem* __restrict__ items,
@@ -221,7 +231,8 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     __shared__ double fval[kMaxFinal];
     __shared__ int fidx[kMaxFinal];
     __shared__ int rankpos[kMaxSel];
-    __shared__ int ccount, fcount, nuniq;
+    __shared__ int act[kMaxSel], climb[kMaxSel];
+    __shared__ int ccount, fcount, nuniq, nact;
     __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
 
     const int f = flist[blockIdx.x];
@@ -248,7 +259,8 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
 
     // 4. gather the chunk candidates and keep the best C
     const int Cc = D + prm.extra;
-    const int total = ((L + kRefineChunk - 1) / kRefineChunk) * Cc;
+    const int n_chunks = prm.chunk_count ? prm.chunk_count[f] : (L + kRefineChunk - 1) / kRefineChunk;
+    const int total = n_chunks * Cc;
     const Cand* slots = reinterpret_cast<const Cand*>(ws + fr.ws_cand);
     if (tid == 0) {
         ccount = 0;
@@ -276,27 +288,70 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     }
     __syncthreads();
 
-    // 5. FP64 windows around the kept candidates
+    // 5. FP64 windows around the kept candidates.  A window without an interior FP64 local
+    //    maximum (the FP32 maximum of a very flat peak can lie farther from the FP64 one than the
+    //    half width) slides toward its higher end by W - 2 points, keeping two points of overlap,
+    //    until it holds one or kMaxClimb slides are done.
     const double* ps = pos + fr.pos_off;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     const int w = prm.halfwidth, W = 2 * w + 1;
-    {
-        // 16 lanes per window point: 16 points per pass of the 256-thread workgroup
-        const int grp = tid >> 4, j = tid & 15;
-        double2* a = asteer + (tid >> 6) * 4 * MB;
-        for (int e0 = 0; e0 < C * W; e0 += 16) {
-            const int e = e0 + grp;
-            const bool valid = e < C * W;
-            const int c = valid ? e / W : 0, o = valid ? e - c * W : 0;
-            int l = valid ? sel[c] + o - w : 0;
-            if (circ) l = ((l % L) + L) % L;
-            const bool inside = valid && (circ || (l >= 0 && l < L));
-            const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
-                                           grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
-            if (valid && j == 0) win[c * kMaxWin + o] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
-        }
-    }
+    for (int i = tid; i < C; i += blockDim.x) act[i] = i;
+    if (tid == 0) nact = C;
     __syncthreads();
+    for (int iter = 0;; ++iter) {
+        const int na = nact;
+        {
+            // 16 lanes per window point: 16 points per pass of the 256-thread workgroup
+            const int grp = tid >> 4, j = tid & 15;
+            double2* a = asteer + (tid >> 6) * 4 * MB;
+            for (int e0 = 0; e0 < na * W; e0 += 16) {
+                const int e = e0 + grp;
+                const bool valid = e < na * W;
+                const int c = valid ? act[e / W] : 0, o = valid ? e - (e / W) * W : 0;
+                int l = valid ? sel[c] + o - w : 0;
+                if (circ) l = ((l % L) + L) % L;
+                bool inside = valid && (circ || (l >= 0 && l < L));
+                if (inside && prm.windows) inside = in_windows(prm.windows + (size_t)f * kWinStride, l);
+                const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
+                                               grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
+                if (valid && j == 0) win[c * kMaxWin + o] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
+            }
+        }
+        __syncthreads();
+        if (iter == kMaxClimb) break;
+        // one thread per active window: interior local maximum present? otherwise slide uphill
+        for (int i = tid; i < na; i += blockDim.x) {
+            const int c = act[i];
+            const double* wv = win + c * kMaxWin;
+            bool interior = false;
+            for (int o = 1; o < W - 1 && !interior; ++o) {
+                const double x = wv[o];
+                if (!(x > wv[o - 1])) continue;
+                int r = o + 1;
+                while (r < W && wv[r] == x) ++r;
+                interior = r < W && wv[r] < x;
+            }
+            int move = 0;
+            if (!interior) {
+                if (wv[W - 1] > wv[0] || (wv[W - 1] == wv[W - 1] && wv[0] != wv[0])) move = W - 2;
+                else if (wv[0] > wv[W - 1] || (wv[0] == wv[0] && wv[W - 1] != wv[W - 1])) move = -(W - 2);
+            }
+            climb[i] = move;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int n2 = 0;
+            for (int i = 0; i < na; ++i) {
+                if (climb[i] == 0) continue;
+                const int c = act[i];
+                sel[c] += climb[i];
+                act[n2++] = c;
+            }
+            nact = n2;
+        }
+        __syncthreads();
+        if (nact == 0) break;
+    }
 
     // 6. FP64 local maxima inside the windows (interior points: both neighbours known)
     for (int e = tid; e < C * W; e += blockDim.x) {

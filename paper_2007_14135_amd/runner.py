@@ -30,6 +30,24 @@ class DeviceBatch:
     def run(self, stream=None):
         self.batch.estimate(self.X, self.spectrum, self.peaks, self.npeaks, self.status, self.workspace, stream)
 
+    def _windowed_workspace(self, mlp=None):
+        import torch
+        need = self.batch.windowed_workspace_size(mlp)
+        if self.workspace.numel() < need:
+            self.workspace = torch.empty(need, dtype=torch.uint8, device=self.workspace.device)
+
+    def run_windowed(self, scores, topk: int, half_window_deg: float, score_threshold: float, stream=None):
+        """Windowed estimation with caller scores (device float tensor [n_frames][n_bins])."""
+        self._windowed_workspace()
+        self.batch.estimate_windowed(self.X, scores, topk, half_window_deg, score_threshold, self.spectrum,
+                                     self.peaks, self.npeaks, self.status, self.workspace, stream)
+
+    def run_learned(self, mlp, topk: int, half_window_deg: float, fallback_score: float, stream=None):
+        """Windowed estimation with the learned proposal network."""
+        self._windowed_workspace(mlp)
+        self.batch.estimate_learned(mlp, self.X, topk, half_window_deg, fallback_score, self.spectrum,
+                                    self.peaks, self.npeaks, self.status, self.workspace, stream)
+
     def host_results(self):
         import torch
         torch.cuda.synchronize()

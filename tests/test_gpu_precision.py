@@ -1,11 +1,20 @@
 """GPU parity of the 16-bit (BF16 / FP16) matrix-core scans against the FP64 oracle.
 
-Bound (derived from the arithmetic): operands rounded to 16 bits with FP32 accumulation give a
-relative error of Q of about 2u sqrt(||B||_F^2 / Q); points with Q < tau ||B||_F^2 (tau = 2e-3)
-are re-evaluated in FP64, so the worst remaining error is at Q = tau ||B||_F^2.  A numpy emulation
-of the rounding on 64-element frames gives at most 0.071 dB (BF16, u = 2^-9) and 0.012 dB (FP16,
-u = 2^-11); the gates below are twice that.  Peak indices must equal the oracle's (FP64 near-tie
-rule) because candidates are re-picked from FP64 windows.
+Bound, derived from the arithmetic and checked at every grid point.  The scan forms
+y_k = b_k^H a in the real embedding with both operands rounded to 16 bits (unit roundoff u:
+2^-9 BF16, 2^-11 FP16) and FP32 accumulation over 2M terms, so each real product carries a
+relative error <= 2u + u^2 (+ 4 2^-24 for the FP32 steering values before rounding) and the sum
+adds <= 2M 2^-24 of the sum of magnitudes; FP16 subnormals add at most 2^-25 per operand.  With
+|a_m| = 1 and ||b_k||_1 <= sqrt(M) ||b_k||_2 this gives |dy_k| <= c ||b_k||_2 + e0 with
+    c = sqrt(2) sqrt(M) (2u + u^2 + (2M + 4) 2^-24),   e0 = sqrt(2) M 2^-25 (FP16 only),
+and for Q = sum_k |y_k|^2, K columns and S = ||B||_F^2 (basis independent), Minkowski gives
+sqrt(sum_k |dy_k|^2) <= E = c sqrt(S) + e0 sqrt(K), so
+    |dQ| <= 2 E sqrt(Q) + E^2,   i.e.  |dQ| / Q <= r(theta) = 2 E / sqrt(Q) + E^2 / Q.
+Points with FP32 Q below tau S are re-evaluated in FP64, which only lowers the error.  The gate is
+|10 log10(P_gpu / P_oracle)| <= -10 log10(1 - r(theta)) (+1e-4 dB for the FP32 steering and
+output rounding) wherever r(theta) < 1; the few points near the peaks where the bound is vacuous
+are counted and reported.  Peak indices must equal the oracle's (FP64 near-tie rule) because
+candidates are re-picked from FP64 windows: the peak error is 0 deg.
 """
 
 import numpy as np
@@ -18,7 +27,20 @@ from gpu_common import frameset_inputs, oracle_frame, peaks_match
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-DB_GATE = {"bf16": 0.15, "f16": 0.03}
+UNIT_ROUNDOFF = {"bf16": 2.0 ** -9, "f16": 2.0 ** -11}
+
+
+def db_bound(Q, S, K, M, prec):
+    """Per-point bound (dB) on the 16-bit scan's spectrum error; inf where it is vacuous."""
+    u = UNIT_ROUNDOFF[prec]
+    c = np.sqrt(2.0) * np.sqrt(M) * (2 * u + u * u + (2 * M + 4) * 2.0 ** -24)
+    e0 = np.sqrt(2.0) * M * 2.0 ** -25 if prec == "f16" else 0.0
+    E = c * np.sqrt(S) + e0 * np.sqrt(K)
+    r = 2 * E / np.sqrt(Q) + E * E / Q
+    out = np.full(Q.shape, np.inf)
+    ok = r < 1.0
+    out[ok] = -10.0 * np.log10(1.0 - r[ok]) + 1e-4
+    return out
 
 
 def _run(fs, alg, prec, max_D):
@@ -34,14 +56,22 @@ def _run(fs, alg, prec, max_D):
 
 
 def _check(frames, res, idx, alg, prec):
-    worst_db, worst_deg = 0.0, 0.0
+    worst_db, worst_deg, worst_frac, vacuous = 0.0, 0.0, 0.0, 0
+    all_db = []
     for f, i in enumerate(idx):
         fr = frames[f]
         est = oracle_frame(fr, alg)
         P = res["spectra"][i].astype(np.float64)
         db = np.abs(10.0 * np.log10(P / est.P))
+        S = float(np.sum(np.abs(est.B) ** 2))
+        bound = db_bound(est.Q, S, est.B.shape[1], fr.M, prec)
+        fin = np.isfinite(bound)
+        vacuous += int((~fin).sum())
+        bad = np.nonzero(fin & (db > bound))[0]
+        assert bad.size == 0, (prec, alg, f, int(bad[0]), float(db[bad[0]]), float(bound[bad[0]]))
         worst_db = max(worst_db, float(db.max()))
-        assert db.max() <= DB_GATE[prec], (prec, alg, f, float(db.max()), int(np.argmax(db)))
+        worst_frac = max(worst_frac, float(np.max(db[fin] / bound[fin])))
+        all_db.append(db)
         n = int(res["npeaks"][i])
         pk = res["peaks"][i]
         assert n == len(est.peaks)
@@ -52,7 +82,10 @@ def _check(frames, res, idx, alg, prec):
             assert abs(pk["value"][r] - est.P[j]) <= 1e-8 * est.P[j]
         gdeg = np.sort(pk["angle_deg"][:n])
         worst_deg = max(worst_deg, float(np.max(np.abs(gdeg - np.sort(est.peak_angles)))) if n else 0.0)
-    print("%s %s: max |dB error| %.4f, max peak error %.4f deg" % (prec, alg, worst_db, worst_deg), flush=True)
+    all_db = np.concatenate(all_db)
+    print("%s %s: |dB error| max %.4f p99 %.4f median %.5f; max error/bound %.3f; %d points with a vacuous "
+          "bound; max peak error %.4f deg" % (prec, alg, worst_db, np.percentile(all_db, 99), np.median(all_db),
+                                               worst_frac, vacuous, worst_deg), flush=True)
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16"])

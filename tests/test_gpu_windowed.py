@@ -1,0 +1,230 @@
+"""GPU parity of windowed estimation (scan and peak search restricted to proposal windows).
+
+Scores are seeded test inputs.  The oracle derives the windows from the same FP32 scores
+(proposal_windows), so the windows must match exactly: every spectrum value the GPU writes lies
+in an oracle window and every oracle window point is written (the spectrum buffer starts as NaN).
+Inside the windows the FP32 spectrum is within 1e-4 relative of the FP64 oracle after the FP64
+re-evaluation of low-Q points, and the selected peaks equal the oracle's (FP64 near-tie rule).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import estimate_windowed
+from oracle import mlp as omlp
+from synth import make_frame, make_frames
+from synth.frames import pack_frames
+from gpu_common import frameset_inputs, peaks_match
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ST_FALLBACK = 0x20
+ST_FEWER = 0x8
+
+
+def _prepare(fs, alg="music", max_D=4):
+    from paper_2007_14135_amd.runner import prepare
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    arrays, grids, frames, X = frameset_inputs(fs)
+    return prepare(arrays, grids, frames, X, alg, "c64", max_D)
+
+
+def _bin_of(angle):
+    return int(np.clip(np.floor(angle + 90.0), 0, 179))
+
+
+def _check(fs, db, res, scores, topk, hw, thr, alg, tag):
+    worst, ties = 0.0, 0
+    for f, fr in enumerate(fs.frames):
+        wins = omlp.proposal_windows(scores[f].astype(np.float64), topk, hw, fr.grid_start, fr.grid_step,
+                                     fr.grid_L, threshold=float(thr))
+        fallback = not (np.nanmax(np.where(np.isnan(scores[f]), -np.inf, scores[f])) >= thr)
+        est = estimate_windowed(fr.X, fr.pos, fr.D, fr.grid, alg, wins)
+        P = res["spectra"][f].astype(np.float64)
+        written = ~np.isnan(P)
+        inwin = ~np.isnan(est.P)
+        assert np.array_equal(written, inwin), (tag, f, wins, np.nonzero(written != inwin)[0][:5])
+        if inwin.any():
+            rel = np.abs(P[inwin] - est.P[inwin]) / est.P[inwin]
+            worst = max(worst, float(rel.max()))
+            assert rel.max() <= 1e-4, (tag, f, float(rel.max()))
+        st = int(res["status"][f])
+        assert bool(st & ST_FALLBACK) == fallback, (tag, f, st, fallback)
+        n = int(res["npeaks"][f])
+        assert n == len(est.peaks), (tag, f, n, est.peaks.tolist())
+        assert bool(st & ST_FEWER) == (n < fr.D), (tag, f, st, n)
+        ok, t = peaks_match(res["peaks"][f]["idx"][:n], est, fr.D)
+        ties += t
+        assert ok, (tag, f, res["peaks"][f]["idx"][:n].tolist(), est.peaks.tolist(), wins)
+        for r in range(n):
+            j = int(res["peaks"][f]["idx"][r])
+            assert abs(res["peaks"][f]["value"][r] - est.P[j]) <= 1e-8 * est.P[j]
+    print("%s: %d frames, max rel spectrum error in windows %.3e, near-ties %d" % (tag, len(fs), worst, ties),
+          flush=True)
+
+
+def _designed_scores(fs, seed):
+    """Per frame: bins of the true angles high, the rest low, with cases for merging, edge bins,
+    NaN bins, ties and a fallback frame."""
+    rng = np.random.default_rng(seed)
+    F = len(fs)
+    s = rng.normal(-3.0, 1.0, size=(F, 180)).astype(np.float32)
+    for f, fr in enumerate(fs.frames):
+        case = f % 6
+        bins = [_bin_of(a) for a in fr.angles_deg]
+        if case == 0:                        # every source's bin
+            for b in bins:
+                s[f, b] = 2.0 + rng.uniform()
+        elif case == 1:                      # two sources plus both neighbours of one (merging)
+            for b in bins[:2]:
+                s[f, b] = 3.0
+            s[f, max(bins[0] - 1, 0)] = 2.5
+            s[f, min(bins[0] + 1, 179)] = 2.4
+        elif case == 2:                      # nothing reaches the threshold: full-grid fallback
+            s[f] = np.minimum(s[f], -0.5)
+        elif case == 3:                      # edge bins (windows clipped at the grid ends), NaN bins
+            s[f, 0], s[f, 179] = 4.0, 3.5
+            s[f, 5:9] = np.nan
+            for b in bins:
+                s[f, b] = 1.0
+        elif case == 4:                      # equal scores: the lower bins win
+            s[f, :] = -1.0
+            s[f, 10:30] = 1.5
+            for b in bins[:1]:
+                s[f, b] = 2.0
+        # case 5: random scores only (windows may miss every source)
+    return s
+
+
+def test_windowed_matches_oracle_designed_cases():
+    fs = make_frames("c2", n_frames=12, N=2048)
+    db = _prepare(fs)
+    scores = _designed_scores(fs, 7)
+    db.spectrum.fill_(float("nan"))
+    sd = torch.tensor(scores, device="cuda")
+    db.run_windowed(sd, 6, 1.0, 0.0)
+    res = db.host_results()
+    _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 designed")
+
+
+@pytest.mark.parametrize("alg", ["music", "ev", "mn", "phd"])
+def test_windowed_learned_workload_frames(alg):
+    # frames of the learned-proposal workload: 0.001 deg grid (L = 180000), D in 1..4, N in
+    # 256..4096; windows of +-1 deg around the 6 best bins, with the true bins scored highest
+    frames = [make_frame("c5", i) for i in range(10)]
+    fs = pack_frames(frames, dtype=np.complex64)
+    db = _prepare(fs, alg)
+    rng = np.random.default_rng(11)
+    scores = rng.normal(-2.0, 1.0, size=(len(fs), 180)).astype(np.float32)
+    for f, fr in enumerate(frames):
+        if f % 4 != 3:                      # every fourth frame keeps random scores
+            for a in fr.angles_deg:
+                scores[f, _bin_of(a)] = 3.0 + rng.uniform()
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(scores, device="cuda"), 6, 1.0, 0.0)
+    res = db.host_results()
+    _check(fs, db, res, scores, 6, 1.0, 0.0, alg, "windowed c5 " + alg)
+
+
+def test_windowed_half_width_and_bins_variants():
+    # 90 bins of 2 deg, 3 windows of +-0.37 deg: windows that fall between grid points
+    fs = make_frames("c2", n_frames=5, N=1024, grid_step=0.01, start=20)
+    db = _prepare(fs)
+    rng = np.random.default_rng(3)
+    scores = rng.normal(0.0, 1.0, size=(len(fs), 90)).astype(np.float32)
+    for f, fr in enumerate(fs.frames):
+        for a in fr.angles_deg:
+            scores[f, int(np.clip(np.floor((a + 90.0) / 2.0), 0, 89))] += 4.0
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(scores, device="cuda"), 3, 0.37, 1.0)
+    res = db.host_results()
+    _check(fs, db, res, scores, 3, 0.37, 1.0, "music", "windowed 90 bins")
+
+
+def test_windowed_twice_reuses_the_workspace():
+    # the second call must not see the first call's windows, lists or candidates
+    fs = make_frames("c2", n_frames=6, N=1024)
+    db = _prepare(fs)
+    s1 = _designed_scores(fs, 1)
+    s2 = _designed_scores(fs, 2)[::-1].copy()
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(s1, device="cuda"), 6, 1.0, 0.0)
+    torch.cuda.synchronize()
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(s2, device="cuda"), 4, 0.5, 0.0)
+    res = db.host_results()
+    _check(fs, db, res, s2, 4, 0.5, 0.0, "music", "windowed second call")
+
+
+def _host_features(R):
+    """Network inputs from a covariance, with the trace summed in index order as the kernel does."""
+    M = R.shape[0]
+    t = 0.0
+    for i in range(M):
+        t += float(R[i, i].real)
+    trs = M / t
+    iu, ju = np.triu_indices(M)
+    v = R[iu, ju]
+    out = np.empty(2 * len(v), dtype=np.float32)
+    out[0::2] = (v.real * trs).astype(np.float32)
+    out[1::2] = (v.imag * trs).astype(np.float32)
+    return out
+
+
+def test_learned_equals_windowed_with_network_scores():
+    # estimate_learned = features -> network -> windowed estimation with its logits; the same
+    # steps done through the separate entry points give identical results, bit for bit
+    import paper_2007_14135_amd as nd
+    fs = make_frames("c5", n_frames=40)
+    db = _prepare(fs)
+    net = nd.MLP(272, 512, 180, max_batch=16)          # several forward slices for 40 frames
+    net.load_params(nd.flatten_params(omlp.init_params(17)))
+    db.spectrum.fill_(float("nan"))
+    db.run_learned(net, 6, 1.0, 0.5)
+    res_l = db.host_results()
+    R = [db.workspace_array(nd.WS_COV, f, 256, np.complex128).reshape(16, 16) for f in range(len(fs))]
+    feats = torch.tensor(np.stack([_host_features(r) for r in R]), device="cuda")
+    logits = torch.empty(len(fs), 180, dtype=torch.float32, device="cuda")
+    for r0 in range(0, len(fs), 16):
+        net.forward(feats[r0:r0 + 16], logits[r0:r0 + 16])
+    torch.cuda.synchronize()
+    spec_l = [s.copy() for s in res_l["spectra"]]
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(logits, 6, 1.0, 0.0)                 # sigmoid(z) < 0.5  <=>  z < 0
+    res_w = db.host_results()
+    assert np.array_equal(res_l["npeaks"], res_w["npeaks"])
+    assert np.array_equal(res_l["status"], res_w["status"])
+    assert res_l["peaks"].tobytes() == res_w["peaks"].tobytes()
+    for a, b in zip(spec_l, res_w["spectra"]):
+        assert np.array_equal(a, b, equal_nan=True)
+    nfb = int(np.sum((res_l["status"] & ST_FALLBACK) != 0))
+    print("learned == windowed(network logits): %d frames, %d fallbacks" % (len(fs), nfb), flush=True)
+
+
+def test_windowed_argument_errors():
+    import paper_2007_14135_amd as nd
+    fs = make_frames("c2", n_frames=2, N=512)
+    db = _prepare(fs)
+    sc = torch.zeros(2, 180, device="cuda")
+    db._windowed_workspace()
+    for args in ((0, 1.0, 0.0), (17, 1.0, 0.0), (6, 0.0, 0.0), (6, 181.0, 0.0), (6, 1.0, float("nan"))):
+        with pytest.raises(nd.NssdoaError) as e:
+            db.batch.estimate_windowed(db.X, sc, *args, db.spectrum, db.peaks, db.npeaks, db.status, db.workspace)
+        assert e.value.status == 1
+    small = torch.empty(db.batch.workspace_size(), dtype=torch.uint8, device="cuda")
+    with pytest.raises(nd.NssdoaError) as e:
+        db.batch.estimate_windowed(db.X, sc, 6, 1.0, 0.0, db.spectrum, db.peaks, db.npeaks, db.status, small)
+    assert e.value.status == 1
+    net = nd.MLP(100, 8, 180, max_batch=4)              # wrong input size for M = 16
+    with pytest.raises(nd.NssdoaError) as e:
+        db.run_learned(net, 6, 1.0, 0.5)
+    assert e.value.status == 1
+    # a C128 batch is not supported
+    from paper_2007_14135_amd.runner import prepare
+    arrays, grids, frames, X = frameset_inputs(fs)
+    db64 = prepare(arrays, grids, frames, X, "music", "c128", 4)
+    with pytest.raises(nd.NssdoaError) as e:
+        db64.run_windowed(sc, 6, 1.0, 0.0)
+    assert e.value.status == 2

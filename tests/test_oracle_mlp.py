@@ -97,3 +97,33 @@ def test_proposal_windows_arithmetic():
     s[0] = 0.95                                       # centre -89.5: clipped at the grid start
     w = mlp.proposal_windows(s, 3, 1.0, -90.0, 0.001, 180000)
     assert w[0] == (0, 1501)
+
+
+def test_bf16_round_matches_the_format():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.normal(0, 1, 2000), rng.normal(0, 1e-3, 500), rng.normal(0, 1e4, 500)])
+    # exact ties between two bfloat16 neighbours: 1 + 2^-8 (tie, rounds to even 1.0) and
+    # 1 + 3 * 2^-8 (tie, rounds up to the even 1 + 2^-6), negative mirrors
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), -(1 + 3 * 2.0 ** -8)])
+    x = np.concatenate([x, ties])
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+    assert mlp.bf16_round(ties).tolist() == [1.0, 1 + 2.0 ** -6, -1.0, -(1 + 2.0 ** -6)]
+
+
+def test_bf16_mode_rounds_every_product_operand():
+    params, X, y = _small()
+    _, g = mlp.backward(params, X, y, precision="bf16")
+    # rounding X or the weights beforehand changes nothing: they are rounded at every use
+    _, gx = mlp.backward(params, mlp.bf16_round(X), y, precision="bf16")
+    pr = [(mlp.bf16_round(W), b) for W, b in params]
+    _, gw = mlp.backward(pr, X, y, precision="bf16")
+    for a, b, c in zip(g, gx, gw):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[0], c[0])
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[1], c[1])
+    # and the result is within bfloat16 rounding of the exact gradient, not equal to it
+    _, g64 = mlp.backward(params, X, y)
+    for (gw_, gb_), (ew, eb) in zip(g, g64):
+        rel = np.linalg.norm(gw_ - ew) / np.linalg.norm(ew)
+        assert 0 < rel < 0.05

@@ -1,0 +1,114 @@
+"""Pins for the oracle of windowed estimation (the Step-5 scan and Step-6 search restricted to
+proposal windows) and of the proposal windows themselves."""
+
+import numpy as np
+
+from oracle import estimate, estimate_windowed, grid_angles, steering
+from oracle import mlp
+
+
+def _ula(M):
+    pos = np.zeros((M, 3))
+    pos[:, 0] = 0.5 * np.arange(M)
+    return pos
+
+
+def _frame(seed=11, M=8, N=512, th=(-31.3, 12.7), s2=0.1):
+    rng = np.random.default_rng(seed)
+    pos = _ula(M)
+    A = steering(pos, np.asarray(th)).T
+    S = (rng.standard_normal((len(th), N)) + 1j * rng.standard_normal((len(th), N))) / np.sqrt(2)
+    W = np.sqrt(s2) * (rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))) / np.sqrt(2)
+    return pos, A @ S + W
+
+
+def test_whole_grid_window_is_the_plain_estimate():
+    pos, X = _frame()
+    grid = (-90.0, 0.1, 1800)
+    for alg in ("music", "ev", "mn", "phd"):
+        full = estimate(X, pos, 2, grid, alg)
+        win = estimate_windowed(X, pos, 2, grid, alg, [(0, 1800)])
+        assert np.array_equal(full.P, win.P)
+        assert np.array_equal(full.peaks, win.peaks)
+        assert np.array_equal(full.all_peaks, win.all_peaks)
+
+
+def test_windows_around_the_peaks_find_them():
+    # noise-free limit: exact R, true angles on grid points; windows around both
+    M, ang = 8, grid_angles(-90.0, 0.01, 18000)
+    idx = np.array([5870, 10270])
+    pos = _ula(M)
+    A = steering(pos, ang[idx]).T
+    R = A @ A.conj().T + 0.2 * np.eye(M)
+    # snapshots with exactly this covariance: X = R^(1/2) * sqrt(N) columns of an identity
+    w, V = np.linalg.eigh(R)
+    X = (V * np.sqrt(w)) @ V.conj().T * np.sqrt(M)
+    X = np.concatenate([X, np.zeros((M, 0))], axis=1)
+    full = estimate(X, pos, 2, (-90.0, 0.01, 18000), "music")
+    assert sorted(full.peaks) == sorted(idx)
+    win = estimate_windowed(X, pos, 2, (-90.0, 0.01, 18000), "music", [(5700, 6000), (10100, 10400)])
+    assert sorted(win.peaks) == sorted(idx)
+    assert np.isnan(win.P[:5700]).all() and np.isnan(win.P[6000:10100]).all() and np.isnan(win.P[10400:]).all()
+    assert np.array_equal(win.P[5700:6000], full.P[5700:6000])
+
+
+def test_window_end_is_never_a_peak():
+    M, ang = 8, grid_angles(-90.0, 0.01, 18000)
+    idx = np.array([5870, 10270])
+    pos = _ula(M)
+    A = steering(pos, ang[idx]).T
+    R = A @ A.conj().T + 0.2 * np.eye(M)
+    w, V = np.linalg.eigh(R)
+    X = (V * np.sqrt(w)) @ V.conj().T * np.sqrt(M)
+    # the first window ends exactly at the first peak, the second starts exactly at the second
+    win = estimate_windowed(X, pos, 2, (-90.0, 0.01, 18000), "music", [(5700, 5871), (10270, 10400)])
+    assert 5870 not in win.all_peaks and 10270 not in win.all_peaks
+    # one point more on each side makes both interior again
+    win = estimate_windowed(X, pos, 2, (-90.0, 0.01, 18000), "music", [(5700, 5872), (10269, 10400)])
+    assert sorted(win.peaks) == [5870, 10270]
+
+
+def test_peaks_of_windows_equal_brute_force():
+    # random spectra: the windowed peaks are those l with both neighbours in the same window,
+    # P[l] > P[l-1], and the run of values equal to P[l] ending inside the window in a smaller value
+    from oracle.doa import find_peaks
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        L = int(rng.integers(5, 60))
+        P = rng.integers(0, 4, size=L).astype(float)
+        cuts = sorted(set(int(c) for c in rng.integers(0, L + 1, size=4)))
+        wins = [(a, b) for a, b in zip(cuts[:-1], cuts[1:]) if b > a][::2]
+        got = []
+        for a, b in wins:
+            got.extend(int(i) + a for i in find_peaks(P[a:b]))
+        brute = []
+        for a, b in wins:
+            for l in range(a + 1, b - 1):
+                if not P[l] > P[l - 1]:
+                    continue
+                r = l
+                while r < b and P[r] == P[l]:
+                    r += 1
+                if r < b and P[r] < P[l]:
+                    brute.append(l)
+        assert sorted(got) == sorted(brute), (P, wins)
+
+
+def test_proposal_windows_threshold_nan_and_bin_width():
+    s = np.full(180, -3.0)
+    s[100] = 2.0                                   # centre 10.5 deg
+    assert mlp.proposal_windows(s, 1, 1.0, -90.0, 0.01, 18000, threshold=0.0) == [(9950, 10151)]
+    assert mlp.proposal_windows(s, 1, 1.0, -90.0, 0.01, 18000, threshold=2.5) == [(0, 18000)]
+    s2 = np.full(180, np.nan)
+    assert mlp.proposal_windows(s2, 3, 1.0, -90.0, 0.01, 18000, threshold=-1e30) == [(0, 18000)]
+    assert mlp.proposal_windows(s2, 3, 1.0, -90.0, 0.01, 18000) == []
+    s[7] = np.nan                                  # NaN never chosen, even among few bins
+    got = mlp.proposal_windows(s, 2, 0.5, -90.0, 0.01, 18000)
+    # bins 100 then 0 (lowest index among the -3.0 ties): centres 10.5 and -89.5
+    assert got == [(0, 101), (10000, 10101)]
+    # 90 bins of 2 degrees: bin 45 covers [0, 2), centre 1.0
+    s3 = np.zeros(90)
+    s3[45] = 1.0
+    assert mlp.proposal_windows(s3, 1, 1.0, -90.0, 0.5, 360) == [(180, 185)]
+    # a bin outside a partial grid gives an empty window, which is dropped
+    assert mlp.proposal_windows(s, 1, 1.0, 20.0, 0.01, 1000) == []
