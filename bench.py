@@ -6,14 +6,19 @@ selection, for 256 synthetic frames of the 16-element workload (N = 4096 snapsho
 18000-point grid at 0.01 deg), MUSIC.  Snapshots are resident in HBM before the timed region.
 
 Prints one JSON line with the throughput (spectrum points/s), the roofline position of the
-scan kernel (timed live with HIP events on the launch stream) and the FP64 oracle's throughput
-on the host cores over a bounded sample of the same frames.
+scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
+counter summary while the kernel source is unchanged), the FP64 oracle's throughput on the host
+cores over a bounded sample of the same frames, and, when trained proposal weights are present,
+the learned-proposal workload (8192 frames, 0.001 deg grid) run by the learned path and by the
+full scan on the same GPU.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -26,11 +31,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 METRIC = "MUSIC spectrum points/s & frames/s at ≤0.01° peak err, learned vs full scan"
+WEIGHTS = os.path.join(ROOT, "paper_2007_14135_amd", "weights", "proposal_ula16.npy")
+SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")
 
 
 def _oracle_worker(args):
-    """Generate the frames (untimed), then time the oracle on them."""
-    config, idx, alg = args
+    """Generate the frames (untimed), then time the oracle on them `repeats` times."""
+    config, idx, alg, repeats = args
     from threadpoolctl import threadpool_limits
     import oracle
     from synth import make_frame
@@ -38,32 +46,145 @@ def _oracle_worker(args):
         frames = [make_frame(config, i) for i in idx]
         t0 = time.perf_counter()
         out = []
-        for fr in frames:
-            est = oracle.estimate(fr.X, fr.pos, fr.D, fr.grid, alg)
-            out.append((est.peaks.tolist(), est.angles[est.peaks].tolist()))
+        for r in range(repeats):
+            for fr in frames:
+                est = oracle.estimate(fr.X, fr.pos, fr.D, fr.grid, alg)
+                if r == 0:
+                    out.append((est.peaks.tolist(), est.angles[est.peaks].tolist()))
         busy = time.perf_counter() - t0
     return busy, out
 
 
-def cpu_baseline(config, frame_ids, alg, L):
+def cpu_baseline(config, frame_ids, alg, L, repeats):
     import multiprocessing as mp
     cores = len(os.sched_getaffinity(0))
     workers = max(1, min(cores, 16, len(frame_ids)))
     chunks = [frame_ids[i::workers] for i in range(workers)]
-    ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
-        res = pool.map(_oracle_worker, [(config, c, alg) for c in chunks])
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [(config, c, alg, repeats) for c in chunks])
     wall = max(r[0] for r in res)           # the slowest worker bounds the parallel run
     cpu_s = sum(r[0] for r in res)
     peaks = {}
     for c, r in zip(chunks, res):
         for i, pk in zip(c, r[1]):
             peaks[i] = pk
-    value = len(frame_ids) * L / wall
+    value = repeats * len(frame_ids) * L / wall
     return dict(value=value, unit="points/s", cores=workers, kind="oracle",
-                sample="%d of the 256 frames (every %dth), FP64 numpy/LAPACK oracle, covariance to peaks, "
-                       "one process per core with BLAS threads = 1; %.1f s of CPU work" %
-                       (len(frame_ids), 256 // len(frame_ids), cpu_s)), peaks
+                sample="all %d frames of the workload, %d passes, FP64 numpy/LAPACK oracle, covariance to peaks, "
+                       "one process per core with BLAS threads = 1; %.1f s of CPU work in %.1f s"
+                       % (len(frame_ids), repeats, cpu_s, wall)), peaks
+
+
+def _frames_worker(args):
+    config, idx = args
+    from threadpoolctl import threadpool_limits
+    from synth import make_frame
+    with threadpool_limits(1):
+        return [make_frame(config, i) for i in idx]
+
+
+def make_frames_parallel(config, n):
+    """Frames 0..n-1 of a configuration, drawn by a fork pool (before the GPU is touched)."""
+    import multiprocessing as mp
+    from synth.frames import pack_frames
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    step = 256
+    jobs = [(config, list(range(s, min(n, s + step)))) for s in range(0, n, step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_frames_worker, jobs)
+    frames = [fr for p in parts for fr in p]
+    return pack_frames(frames, dtype=np.complex64)
+
+
+def scan_traffic():
+    """HBM bytes per scan launch from the committed counter summary, or None when the summary is
+    missing or was taken on another version of the scan kernel."""
+    try:
+        kv = {}
+        with open(PMC_SUMMARY) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(SCAN_SRC, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        if kv.get("source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _timed(run, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def learned_leg(fs, steps, warmup):
+    """The learned-proposal workload by the learned path and by the full scan."""
+    import torch
+    import paper_2007_14135_amd as nd
+    from paper_2007_14135_amd.runner import prepare
+    params = np.load(WEIGHTS, allow_pickle=False)
+    net = nd.MLP(272, 512, 180, max_batch=8192)
+    net.load_params(params)
+    fr0 = fs.frames[0]
+    F, L = len(fs), fr0.grid_L
+    frames = [(0, 0, fr.N, fr.D, int(fs.x_off[f]), int(fs.ld[f])) for f, fr in enumerate(fs.frames)]
+    db = prepare([fr0.pos], [(fr0.grid_start, fr0.grid_step, L, 0)], frames, fs.X_flat, "music", "c64", 4,
+                 with_spectrum=False, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    db._windowed_workspace(net)
+    ms_full = _timed(lambda: db.run(stream), steps, warmup, stream)
+    full = db.host_results()
+    db.batch.set_timing(True)
+    ms_learned = _timed(lambda: db.run_learned(net, 6, 1.0, 0.5, stream), steps * 4, warmup, stream)
+    stages = {s: db.batch.stage_time(s) for s in ("covariance", "eigen", "proposal", "scan", "peaks")}
+    db.batch.set_timing(False)
+    learned = db.host_results()
+    fallback = (learned["status"] & nd.ST_FALLBACK_USED) != 0
+    miss = 0
+    # RMSE over the sources of frames that report D peaks, matched in sorted order
+    sq = {"full": [0.0, 0], "learned": [0.0, 0]}
+    for f, fr in enumerate(fs.frames):
+        nf, nl = int(full["npeaks"][f]), int(learned["npeaks"][f])
+        a_full = np.sort(full["peaks"][f]["angle_deg"][:nf])
+        a_learned = np.sort(learned["peaks"][f]["angle_deg"][:nl])
+        if nf != nl or (nf and np.max(np.abs(a_full - a_learned)) > 0.01 + 1e-9):
+            miss += 1
+        truth = np.sort(fr.angles_deg)
+        for key, a in (("full", a_full), ("learned", a_learned)):
+            if len(a) == len(truth):
+                sq[key][0] += float(np.sum((a - truth) ** 2))
+                sq[key][1] += len(truth)
+    return {
+        "workload": "ULA M=16, D U{1..4}, SNR U[-5,20] dB, N log-U[256,4096] complex64, %d frames, "
+                    "grid [-90,90) at 0.001 deg (L=%d), MUSIC; learned: 6 windows of +-1 deg, "
+                    "full-scan fallback below score 0.5" % (F, L),
+        "frames": F,
+        "frames_per_s_full": F / (ms_full / 1e3),
+        "frames_per_s_learned": F / (ms_learned / 1e3),
+        "gain": ms_full / ms_learned,
+        "ms_per_batch_full": ms_full,
+        "ms_per_batch_learned": ms_learned,
+        "full_grid_equiv_points_per_s_learned": F * L / (ms_learned / 1e3),
+        "points_per_s_full": F * L / (ms_full / 1e3),
+        "miss_rate_vs_full": miss / F,
+        "fallback_rate": float(np.mean(fallback)),
+        "rmse_deg_vs_truth_full": math.sqrt(sq["full"][0] / max(sq["full"][1], 1)),
+        "rmse_deg_vs_truth_learned": math.sqrt(sq["learned"][0] / max(sq["learned"][1], 1)),
+        "learned_stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+    }
 
 
 def main():
@@ -73,7 +194,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alg", default="music", choices=["music", "ev", "mn", "phd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="frames timed on the host oracle")
+    ap.add_argument("--cpu-repeats", type=int, default=4, help="passes of the oracle over the 256 frames")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-frames", type=int, default=8192)
+    ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
+    ap.add_argument("--tune-cache", default="", help="JSON cache of autotuner choices")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is per-frame data parallel and this build "
@@ -81,19 +206,34 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    # host work first, in fork pools, before anything touches the GPU
     from synth import make_frames
-    from paper_2007_14135_amd.runner import prepare
-
-    torch.cuda.set_device(0)
     fs = make_frames("c2")
     F = len(fs)
     fr0 = fs.frames[0]
     L, M, D = fr0.grid_L, fr0.M, fr0.D
+    cb = opeaks = None
+    if not args.no_cpu_baseline:
+        cb, opeaks = cpu_baseline("c2", list(range(F)), args.alg, L, args.cpu_repeats)
+    fs5 = None
+    if not args.no_learned and os.path.exists(WEIGHTS):
+        fs5 = make_frames_parallel("c5", args.learned_frames)
+
+    import torch
+    from paper_2007_14135_amd import autotune
+    from paper_2007_14135_amd.api import Options
+    from paper_2007_14135_amd.runner import prepare
+
+    torch.cuda.set_device(0)
     arrays = [fr0.pos]
     grids = [(fr0.grid_start, fr0.grid_step, L, 0)]
     frames = [(0, 0, fr.N, fr.D, int(fs.x_off[f]), int(fs.ld[f])) for f, fr in enumerate(fs.frames)]
-    db = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0")
+    rows, tune_ms = 0, {}
+    if not args.no_tune:
+        rows, tune_ms = autotune.tune(arrays, grids, frames, fs.X_flat, args.alg, "c64", D,
+                                      cache_path=args.tune_cache or None)
+    db = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
+                 options=Options(scan_rows=rows))
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -144,7 +284,10 @@ def main():
                         "grid [-90,90) at 0.01 deg (L=18000), %s; FP64 covariance/eigensolve/refinement, "
                         "FP32 matrix-core scan" % args.alg.upper(),
             "frames": F, "M": M, "D": D, "N": fr0.N, "L": L, "alg": args.alg,
+            "scan_rows": rows or 384,
         },
+        "autotune": {"knob": "scan_rows", "chosen": rows or 384,
+                     "scan_ms_by_candidate": {str(k): v for k, v in tune_ms.items()}},
         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "roofline": {
             "kernel": "scan_f32_kernel<16>",
@@ -153,7 +296,7 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": None,
+            "traffic": scan_traffic() if args.alg == "music" else None,
             "algorithmic_flops_per_launch": scan_flops,
             "avg_launch_ms": scan_avg_s * 1e3,
         },
@@ -161,14 +304,11 @@ def main():
         "status_nonzero_frames": int(np.count_nonzero(res["status"])),
     }
 
-    if not args.no_cpu_baseline:
-        step = max(1, F // max(1, args.cpu_sample))
-        ids = list(range(0, F, step))
-        cb, opeaks = cpu_baseline("c2", ids, args.alg, L)
+    if cb is not None:
         out["cpu_baseline"] = cb
-        # peak error of the GPU path vs the oracle on the same sample (degrees)
+        # peak error of the GPU path vs the oracle on the same frames (degrees)
         worst, mism = 0.0, 0
-        for i in ids:
+        for i in range(F):
             oidx, oang = opeaks[i]
             n = int(res["npeaks"][i])
             gang = sorted(res["peaks"][i]["angle_deg"][:n].tolist())
@@ -179,6 +319,10 @@ def main():
             worst = max(worst, max(abs(a - b) for a, b in zip(gang, oang)))
         out["peak_err_deg_max_vs_oracle"] = worst
         out["peak_count_mismatch_frames"] = mism
+    if fs5 is not None:
+        del db
+        torch.cuda.empty_cache()
+        out["learned_vs_full"] = learned_leg(fs5, 3, 1)
     print(json.dumps(out))
 
 

@@ -124,7 +124,11 @@ typedef struct {
     int32_t refine_halfwidth; /* FP64 re-evaluation window around each candidate peak, 1..16; 4 */
     double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 2e-3 */
     int32_t extra_candidates; /* local maxima kept beyond D for the FP64 re-pick, 0..16; 4     */
-    int32_t reserved;         /* must be 0                                                     */
+    int32_t scan_rows;        /* rows of stacked B per matrix-core scan work item: 0 = default
+                                 (384 for C64, 4096 for BF16/F16), else a multiple of 32 in
+                                 [32, 16384].  A tuning knob: it moves frames' rows within the
+                                 32-row MFMA tiles, so FP32 spectra may change in their last
+                                 bits; peaks are re-picked in FP64                              */
 } nssdoa_options;
 
 typedef struct nssdoa_plan_s* nssdoa_plan;
@@ -175,7 +179,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* batch, nssdoa_plan plan, nssdoa_
                                   int32_t max_D);
 
 /* Free a batch (waits for nothing: the caller must not destroy a batch whose work is in flight).
- * NULL is accepted and ignored. */
+ * ESTATE while graphs captured from it exist.  NULL is accepted and ignored. */
 nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch);
 
 /* Bytes of device workspace nssdoa_estimate needs for this batch. */
@@ -203,6 +207,20 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
                               size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
                               uint32_t* status, void* workspace, size_t workspace_bytes,
                               void* stream);
+
+/* Graph capture: record the launch sequence of one nssdoa_estimate call with these arguments
+ * (validated as for nssdoa_estimate) into a HIP graph, captured on a stream of the library's own.
+ * nssdoa_graph_launch replays it on `stream` as one graph launch: the same computation on the
+ * same buffers, whose contents may change between launches.  No memory is allocated per launch.
+ * The batch must outlive the graph (nssdoa_batch_destroy returns ESTATE while graphs of it
+ * exist).  Stage timing does not apply to graph launches.
+ * EINVAL: as nssdoa_estimate; EDEVICE: capture or instantiation failed. */
+typedef struct nssdoa_graph_s* nssdoa_graph;
+nssdoa_status nssdoa_graph_create(nssdoa_graph* graph, nssdoa_batch batch, const void* X, size_t x_elems,
+                                  void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                  uint32_t* status, void* workspace, size_t workspace_bytes);
+nssdoa_status nssdoa_graph_launch(nssdoa_graph graph, void* stream);
+nssdoa_status nssdoa_graph_destroy(nssdoa_graph graph);
 
 /* Per-stage device timing.  While enabled, nssdoa_estimate records HIP events around each stage
  * on its stream; nssdoa_stage_time waits for them and returns the summed milliseconds and the

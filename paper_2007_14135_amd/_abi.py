@@ -51,7 +51,7 @@ class Peak(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("refine_halfwidth", ctypes.c_int32), ("lowq_tau", ctypes.c_double),
-                ("extra_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("extra_candidates", ctypes.c_int32), ("scan_rows", ctypes.c_int32)]
 
 
 PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8")])
@@ -81,6 +81,10 @@ _SIGNATURES = {
     "nssdoa_mlp_train_step": [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P],
     "nssdoa_mlp_gradients": [_P, _P, ctypes.c_size_t],
     "nssdoa_windowed_workspace_size": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "nssdoa_graph_create": [ctypes.POINTER(_P), _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, _P, _P,
+                            ctypes.c_size_t],
+    "nssdoa_graph_launch": [_P, _P],
+    "nssdoa_graph_destroy": [_P],
     "nssdoa_estimate_windowed": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_float, _P, ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P],
     "nssdoa_estimate_learned": [_P, _P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double, ctypes.c_double,

@@ -33,8 +33,8 @@ class Options:
     """Tunables of nssdoa_options (defaults as documented in the header)."""
 
     def __init__(self, jacobi_tol=1e-15, max_sweeps=30, refine_halfwidth=4, lowq_tau=2e-3,
-                 extra_candidates=4):
-        self.c = _abi.Options(jacobi_tol, max_sweeps, refine_halfwidth, lowq_tau, extra_candidates, 0)
+                 extra_candidates=4, scan_rows=0):
+        self.c = _abi.Options(jacobi_tol, max_sweeps, refine_halfwidth, lowq_tau, extra_candidates, scan_rows)
 
 
 class Plan:
@@ -161,6 +161,10 @@ class Batch:
                                                ws_bytes, _stream_handle(stream)),
                    "nssdoa_estimate_learned")
 
+    def graph(self, X, spectrum, peaks, npeaks, status, workspace) -> "Graph":
+        """Capture one nssdoa_estimate on these buffers into a replayable graph."""
+        return Graph(self, X, spectrum, peaks, npeaks, status, workspace)
+
     def set_timing(self, enable: bool) -> None:
         _abi.check(_abi.load().nssdoa_set_timing(self.handle, 1 if enable else 0), "nssdoa_set_timing")
 
@@ -170,6 +174,36 @@ class Batch:
         _abi.check(_abi.load().nssdoa_stage_time(self.handle, _abi.STAGES[stage], ctypes.byref(ms), ctypes.byref(n)),
                    "nssdoa_stage_time")
         return float(ms.value), int(n.value)
+
+
+class Graph:
+    """nssdoa_graph: a captured nssdoa_estimate launched as one graph."""
+
+    def __init__(self, batch: Batch, X, spectrum, peaks, npeaks, status, workspace):
+        lib = _abi.load()
+        h = ctypes.c_void_p()
+        ws_bytes = workspace.numel() * workspace.element_size()
+        s_elems = spectrum.numel() if spectrum is not None else 0
+        _abi.check(lib.nssdoa_graph_create(ctypes.byref(h), batch.handle, _ptr(X), X.numel() // 2, _ptr(spectrum),
+                                           s_elems, _ptr(peaks), _ptr(npeaks), _ptr(status), _ptr(workspace),
+                                           ws_bytes), "nssdoa_graph_create")
+        self.handle = h
+        self.batch = batch          # the batch must outlive the graph
+
+    def launch(self, stream=None) -> None:
+        _abi.check(_abi.load().nssdoa_graph_launch(self.handle, _stream_handle(stream)), "nssdoa_graph_launch")
+
+    def close(self):
+        if self.handle:
+            _abi.check(_abi.load().nssdoa_graph_destroy(self.handle), "nssdoa_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                _abi.load().nssdoa_graph_destroy(self.handle)
+        except Exception:
+            pass
 
 
 def decode_peaks(peaks_host_bytes: np.ndarray, n_frames: int, max_D: int) -> np.ndarray:

@@ -1,0 +1,116 @@
+"""Autotuner of the matrix-core scan's work-item size (nssdoa_options.scan_rows).
+
+A scan work item is one chunk of stacked noise-subspace rows times 256 grid angles: larger chunks
+reuse each steering tile over more frames, smaller ones give more work items to spread over the
+256 compute units and a shorter tail.  The best size depends on the batch (frames per group, rows
+per frame, grid lengths), so it is measured: for every candidate the batch is scheduled with that
+size and the scan stage of nssdoa_estimate is timed with HIP events on the launch stream
+(nssdoa_stage_time); the fastest candidate wins.  Choices are cached in a JSON file keyed by the
+device, the algorithm, the scan precision and a signature of the batch's shape, so a workload is
+tuned once per device.
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+CANDIDATES = {"c64": (64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048),
+              "bf16": (512, 1024, 2048, 4096, 8192, 16384),
+              "f16": (512, 1024, 2048, 4096, 8192, 16384)}
+
+
+def signature(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequence[tuple], alg: str,
+              prec: str) -> str:
+    """A digest of what the scan schedule depends on: per (array, grid) group its M, its L and
+    the multiset of noise-subspace ranks K of its frames, plus the algorithm and precision."""
+    groups: Dict[Tuple[int, int], list] = {}
+    for f in frames:
+        a, g, D = int(f[0]), int(f[1]), int(f[3])
+        M = int(np.asarray(arrays[a]).reshape(-1, 3).shape[0])
+        K = M - D if alg in ("music", "ev") else 1
+        groups.setdefault((a, g), []).append(K)
+    desc = []
+    for (a, g), ks in sorted(groups.items()):
+        M = int(np.asarray(arrays[a]).reshape(-1, 3).shape[0])
+        desc.append((M, int(grids[g][2]), tuple(np.bincount(ks).tolist())))
+    return hashlib.sha1(repr((alg, prec, desc)).encode()).hexdigest()[:20]
+
+
+def choose(timings: Dict[int, float]) -> int:
+    """The fastest candidate; ties go to the smaller work item."""
+    return min(timings, key=lambda c: (timings[c], c))
+
+
+class Cache:
+    """{device: {signature: {"scan_rows": n, "timings_ms": {...}}}} in a JSON file."""
+
+    def __init__(self, path: Optional[str]):
+        self.path = path
+        self.data = {}
+        if path and os.path.exists(path):
+            with open(path) as fh:
+                self.data = json.load(fh)
+
+    def get(self, device: str, sig: str) -> Optional[int]:
+        e = self.data.get(device, {}).get(sig)
+        return int(e["scan_rows"]) if e else None
+
+    def put(self, device: str, sig: str, rows: int, timings: Dict[int, float]) -> None:
+        self.data.setdefault(device, {})[sig] = {"scan_rows": int(rows),
+                                                 "timings_ms": {str(k): float(v) for k, v in timings.items()}}
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.data, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def device_name() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return "%s/%s/%d" % (p.name, getattr(p, "gcnArchName", "?"), p.multi_processor_count)
+
+
+def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, candidates: Optional[Iterable[int]] = None,
+         cache_path: Optional[str] = None, reps: int = 5, options=None, log=None) -> Tuple[int, Dict[int, float]]:
+    """Best scan_rows for this batch (from the cache when present) and the measured timings."""
+    import torch
+    from .api import Options
+    from .runner import prepare
+    if prec == "c128":
+        return 0, {}
+    dev = device_name()
+    sig = signature(arrays, grids, frames, alg, prec)
+    cache = Cache(cache_path)
+    hit = cache.get(dev, sig)
+    if hit is not None:
+        return hit, {}
+    timings = {}
+    X_dev = None
+    for rows in (candidates or CANDIDATES[prec]):
+        if options is None:
+            opt = Options(scan_rows=int(rows))
+        else:
+            c = options.c
+            opt = Options(c.jacobi_tol, c.max_sweeps, c.refine_halfwidth, c.lowq_tau, c.extra_candidates, int(rows))
+        db = prepare(arrays, grids, frames, X_flat, alg, prec, max_D, with_spectrum=False, options=opt, X_device=X_dev)
+        X_dev = db.X
+        db.run()
+        torch.cuda.synchronize()
+        db.batch.set_timing(True)
+        for _ in range(reps):
+            db.run()
+        ms, n = db.batch.stage_time("scan")
+        db.batch.set_timing(False)
+        timings[int(rows)] = ms / max(n, 1)
+        if log:
+            log("scan_rows %5d: scan %.4f ms" % (rows, timings[int(rows)]))
+        del db
+    best = choose(timings)
+    cache.put(dev, sig, best, timings)
+    return best, timings

@@ -51,6 +51,7 @@ inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
 constexpr int kChunkRows = 384;      // rows of stacked B per FP32 scan work item (12 tiles)
 constexpr int kChunkRowsLP = 4096;   // rows per 16-bit scan work item (128 tiles)
 constexpr int kCovTargetItems = 2048;
+constexpr double kPlateauRelScan = 1e-4;   // > the FP32 scan's relative error above the low-Q cut
 
 }  // namespace
 
@@ -103,6 +104,7 @@ struct nssdoa_batch_s {
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
     PointItem* d_lowq = nullptr;
+    int live_graphs = 0;
     // timing
     bool timing = false;
     std::vector<StageEvents> pending;
@@ -139,7 +141,7 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     opt.refine_halfwidth = 4;
     opt.lowq_tau = 2e-3;
     opt.extra_candidates = 4;
-    opt.reserved = 0;
+    opt.scan_rows = 0;
     if (options) {
         opt = *options;
         if (!(opt.jacobi_tol > 0.0 && opt.jacobi_tol < 1.0))
@@ -152,7 +154,8 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
             return fail(NSSDOA_EINVAL, "lowq_tau must be finite and >= 0");
         if (opt.extra_candidates < 0 || opt.extra_candidates > 16)
             return fail(NSSDOA_EINVAL, "extra_candidates must be in [0, 16]");
-        if (opt.reserved != 0) return fail(NSSDOA_EINVAL, "options.reserved must be 0");
+        if (opt.scan_rows != 0 && (opt.scan_rows < 32 || opt.scan_rows > 16384 || opt.scan_rows % 32 != 0))
+            return fail(NSSDOA_EINVAL, "scan_rows must be 0 or a multiple of 32 in [32, 16384]");
     }
     auto* p = new (std::nothrow) nssdoa_plan_s();
     if (!p) return fail(NSSDOA_ENOMEM, "host allocation failed");
@@ -202,6 +205,7 @@ nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan) {
 
 nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch) {
     if (!batch) return NSSDOA_OK;
+    if (batch->live_graphs > 0) return fail(NSSDOA_ESTATE, "batch still has %d live graphs", batch->live_graphs);
     for (auto& e : batch->pending) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -348,7 +352,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         // rows of stacked B per scan work item: the 16-bit scans form their steering operands
         // per work item at a cost comparable to 64 tiles of their MFMA work, so they take
         // longer chunks
-        const int chunk_rows = lp ? kChunkRowsLP : kChunkRows;
+        const int chunk_rows = plan->opt.scan_rows > 0 ? plan->opt.scan_rows : lp ? kChunkRowsLP : kChunkRows;
         const size_t emb_elem = lp ? 2 : sizeof(float);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             GroupDev& gd = b->groups[g];
@@ -627,7 +631,8 @@ nssdoa_status check_windowed(nssdoa_batch batch, const WindowArgs& wa, int* n_fe
 
 nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
                             size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
-                            void* workspace, size_t workspace_bytes, void* stream, const WindowArgs* wa) {
+                            void* workspace, size_t workspace_bytes, void* stream, const WindowArgs* wa,
+                            bool capturing = false) {
     if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
     if (!X || !peaks || !npeaks || !status || !workspace)
         return fail(NSSDOA_EINVAL, "NULL X, peaks, npeaks, status or workspace");
@@ -658,14 +663,15 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     const nssdoa_options& opt = batch->plan->opt;
 
     hipEvent_t ev0 = nullptr;
+    const bool timing = batch->timing && !capturing;
     auto stage_begin = [&]() -> nssdoa_status {
-        if (!batch->timing) return NSSDOA_OK;
+        if (!timing) return NSSDOA_OK;
         hipError_t e = hipEventCreate(&ev0);
         if (e == hipSuccess) e = hipEventRecord(ev0, s);
         return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "hipEventRecord");
     };
     auto stage_end = [&](int stage) -> nssdoa_status {
-        if (!batch->timing) return NSSDOA_OK;
+        if (!timing) return NSSDOA_OK;
         hipEvent_t ev1;
         hipError_t e = hipEventCreate(&ev1);
         if (e == hipSuccess) e = hipEventRecord(ev1, s);
@@ -701,6 +707,9 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     pp.max_D = batch->max_D;
     pp.refine_lowq = c128 ? 0 : 1;
     pp.use_user_spec = use_user;
+    // plateau depth of the peak candidates: above the relative error of the scanned spectrum
+    // (FP32 and 16-bit scans after the FP64 re-evaluation of low-Q points; FP64 scan)
+    pp.plateau_rel = c128 ? 1e-10 : kPlateauRelScan;
 
     if (wa) {
         const int F = batch->n_frames, M = batch->frames[0].M;
@@ -728,7 +737,8 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if ((st = stage_begin()) != NSSDOA_OK) return st;
         const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
         e = launch_window_peaks(bucket, batch->d_frames, F, batch->d_pos, batch->d_cis, ws, lay, opt.extra_candidates,
-                                opt.lowq_tau, static_cast<float*>(spec), use_user, persistent_grid(2), s);
+                                opt.lowq_tau, pp.plateau_rel, static_cast<float*>(spec), use_user,
+                                persistent_grid(2), s);
         if (e != hipSuccess) return hip_fail(e, "windowed peak launch");
         pp.chunk_count = reinterpret_cast<const int32_t*>(ws + lay.off_chunks);
         pp.windows = reinterpret_cast<const int32_t*>(ws + lay.off_win);
@@ -819,6 +829,67 @@ nssdoa_status nssdoa_estimate_learned(nssdoa_batch batch, nssdoa_mlp mlp, const 
     WindowArgs wa{mlp, nullptr, 0, topk, half_window_deg, (float)thr};
     return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
                          workspace_bytes, stream, &wa);
+}
+
+struct nssdoa_graph_s {
+    nssdoa_batch batch = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+nssdoa_status nssdoa_graph_create(nssdoa_graph* out, nssdoa_batch batch, const void* X, size_t x_elems,
+                                  void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                  uint32_t* status, void* workspace, size_t workspace_bytes) {
+    if (!out) return fail(NSSDOA_EINVAL, "graph is NULL");
+    *out = nullptr;
+    if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate(capture)");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    nssdoa_status st = estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
+                                     workspace_bytes, cs, nullptr, true);
+    const std::string msg = g_last_error;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (st != NSSDOA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        g_last_error = msg;
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    auto* gr = new (std::nothrow) nssdoa_graph_s();
+    if (!gr) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(NSSDOA_ENOMEM, "host allocation failed");
+    }
+    gr->batch = batch;
+    gr->exec = exec;
+    batch->live_graphs++;
+    *out = gr;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_graph_launch(nssdoa_graph graph, void* stream) {
+    if (!graph) return fail(NSSDOA_EINVAL, "graph is NULL");
+    hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+nssdoa_status nssdoa_graph_destroy(nssdoa_graph graph) {
+    if (!graph) return NSSDOA_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->batch) graph->batch->live_graphs--;
+    delete graph;
+    return NSSDOA_OK;
 }
 
 }  // extern "C"

@@ -80,6 +80,7 @@ struct PeakParams {
     // window tables (kWinStride int32 each); grid points outside every window count as unknown
     const int32_t* chunk_count;
     const int32_t* windows;
+    double plateau_rel;         // relative depth of a candidate's plateau (see plateau_walk)
 };
 
 // Byte offsets, inside the workspace, of the windowed-estimation tables (after the batch's own
@@ -221,6 +222,85 @@ __device__ __forceinline__ double q64_group(const double* __restrict__ pos, int 
     return q;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Peak candidates.  On a fine grid a broad maximum of P is flatter than the scan's rounding, so
+// the rounded spectrum shows many small local maxima around it.  A local maximum x at l is kept
+// only if it wins its plateau, the contiguous points around l with values >= x (1 - rel): no
+// point of the plateau holds a larger value, nor an equal one at a lower index.  Each broad
+// maximum then gives one candidate, which carries its plateau's extent; the exact maximum lies
+// in the plateau when rel exceeds the spectrum's relative error.
+constexpr int kMaxPlateau = 4096;   // points walked on each side of a candidate
+
+struct CandSlot {
+    double v;                   // value at idx (NaN for an unused slot)
+    int32_t idx;                // grid index, -1 for an unused slot
+    uint32_t span;              // plateau points left of idx << 16 | points right of idx
+};
+
+// Walk the plateau of the local maximum x at grid index l through val(g) (NaN: unknown, ends the
+// walk).  Returns false when the plateau holds a better point, else its extent in *span.
+template <typename F>
+__device__ inline bool plateau_walk(double x, int l, double rel, F val, uint32_t* span) {
+    const double thr = x - x * rel;
+    int left = 0, right = 0;
+    for (int k = 1; k <= kMaxPlateau; ++k) {
+        const double y = val(l - k);
+        if (!(y >= thr)) break;
+        if (y >= x) return false;              // larger, or equal at a lower index
+        left = k;
+    }
+    for (int k = 1; k <= kMaxPlateau; ++k) {
+        const double y = val(l + k);
+        if (!(y >= thr)) break;
+        if (y > x) return false;
+        right = k;
+    }
+    *span = ((uint32_t)left << 16) | (uint32_t)right;
+    return true;
+}
+
+// The best C plateau winners among the n local maxima (lval, lidx) of a chunk, by (value desc,
+// index asc), to slots[0..C); unused slots get idx -1.  flag: n ints of LDS; sv: 2 * n doubles of
+// LDS that val() no longer reads; cnt: one LDS int.  Every thread of the workgroup calls it.
+template <typename F>
+__device__ inline void chunk_candidates(int n, const double* lval, const int* lidx, uint32_t* flag, double* sv,
+                                        int* cnt, double rel, F val, CandSlot* slots, int C) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += blockDim.x) {
+        uint32_t span = 0xFFFFFFFFu;           // not a winner
+        uint32_t sp;
+        if (plateau_walk(lval[i], lidx[i], rel, val, &sp)) span = sp;
+        flag[i] = span;
+    }
+    if (tid == 0) *cnt = 0;
+    __syncthreads();
+    long long* pk = reinterpret_cast<long long*>(sv + n);
+    for (int i = tid; i < n; i += blockDim.x) {
+        if (flag[i] == 0xFFFFFFFFu) continue;
+        const int s = atomicAdd(cnt, 1);
+        sv[s] = lval[i];
+        pk[s] = ((long long)lidx[i] << 32) | (long long)flag[i];
+    }
+    __syncthreads();
+    const int m = *cnt;
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double vi = sv[i];
+        const int li = (int)(pk[i] >> 32);
+        int rank = 0;
+        for (int k = 0; k < m; ++k) rank += (sv[k] > vi) || (sv[k] == vi && (int)(pk[k] >> 32) < li);
+        if (rank < C) {
+            slots[rank].v = vi;
+            slots[rank].idx = li;
+            slots[rank].span = (uint32_t)(pk[i] & 0xFFFFFFFFll);
+        }
+    }
+    for (int s = m + tid; s < C; s += blockDim.x) {
+        slots[s].v = __longlong_as_double(0x7ff8000000000000LL);
+        slots[s].idx = -1;
+        slots[s].span = 0;
+    }
+}
+
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
                       const void* X, char* ws, hipStream_t s);
@@ -262,7 +342,7 @@ hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, cons
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);
 hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,
                                const double2* cis, char* ws, const LearnedLayout& lay, int extra, double lowq_tau,
-                               float* spec, int use_user, int n_wg, hipStream_t s);
+                               double plateau_rel, float* spec, int use_user, int n_wg, hipStream_t s);
 
 // Network dimensions and its forward pass for `rows` feature rows into logits[rows][out]
 // (processed in slices of the network's max_batch rows).

@@ -15,7 +15,7 @@
 // lowq_win_kernel<MB>, grid-stride over 64-entry slices of the frames' low-Q lists: FP64
 //   re-evaluation of the listed points.
 // winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
-//   chunk: the chunk's best D + extra local maxima to its candidate slots.  Values outside a
+//   chunk: the chunk's best D + extra plateau winners to its candidate slots.  Values outside a
 //   window are unknown, so a window's end points are never peaks.
 #include <float.h>
 
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64) void proposal_kernel(const FrameDev* __restrict
         if (bi >= n_bins) break;          // uniform: every lane holds the reduced value
         if (lane == 0) {
             chosen[nch] = bi;
-            sc[bi] = -INFINITY;
+            sc[bi] = __int_as_float(0x7fc00000);   // NaN: never chosen again
         }
         ++nch;
         __syncthreads();
@@ -312,18 +312,13 @@ __global__ __launch_bounds__(256) void lowq_win_kernel(const FrameDev* __restric
     }
 }
 
-struct CandW {
-    double v;
-    int32_t idx;
-    int32_t pad;
-};
-
 template <int MB>
 __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restrict__ frames, int n_frames,
                                                        const double* __restrict__ pos,
                                                        const double2* __restrict__ cis, char* __restrict__ ws,
                                                        LearnedLayout lay, int extra, double lowq_tau,
-                                                       float* __restrict__ spec, int use_user) {
+                                                       double plateau_rel, float* __restrict__ spec,
+                                                       int use_user) {
     __shared__ double v[kRefineChunk + 2 * kHaloW];
     __shared__ int rlist[kRefineChunk + 2 * kHaloW];
     __shared__ double lval[kRefineChunk / 2];
@@ -336,7 +331,7 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
         const int f = find_frame(coff, n_frames, item);
         const FrameDev& fr = frames[f];
         const int C = fr.D + extra;
-        CandW* slots = reinterpret_cast<CandW*>(ws + fr.ws_cand) + (size_t)(item - coff[f]) * C;
+        CandSlot* slots = reinterpret_cast<CandSlot*>(ws + fr.ws_cand) + (size_t)(item - coff[f]) * C;
         int c0, wl0, wl1;
         locate(frame_windows(ws, lay, f), item - coff[f], kRefineChunk, &c0, &wl0, &wl1);
         const int nown = min(kRefineChunk, wl1 - c0), span = nown + 2 * kHaloW;
@@ -401,20 +396,12 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
         }
         __syncthreads();
         const int n = min(lcount, kRefineChunk / 2);
-        for (int i = tid; i < n; i += blockDim.x) {
-            const double vi = lval[i];
-            const int li = lidx[i];
-            int rank = 0;
-            for (int k = 0; k < n; ++k) rank += (lval[k] > vi) || (lval[k] == vi && lidx[k] < li);
-            if (rank < C) {
-                slots[rank].v = vi;
-                slots[rank].idx = li;
-            }
-        }
-        for (int s = n + tid; s < C; s += blockDim.x) {
-            slots[s].v = qnan_d();
-            slots[s].idx = -1;
-        }
+        auto val = [&](int g) -> double {
+            if (g < wl0 || g >= wl1) return qnan_d();
+            const int e = g - (c0 - kHaloW);
+            return (e >= 0 && e < span) ? v[e] : (double)P[g];
+        };
+        chunk_candidates(n, lval, lidx, reinterpret_cast<uint32_t*>(rlist), v, &rcount, plateau_rel, val, slots, C);
     }
 }
 
@@ -454,7 +441,7 @@ hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, cons
 
 hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,
                                const double2* cis, char* ws, const LearnedLayout& lay, int extra, double lowq_tau,
-                               float* spec, int use_user, int n_wg, hipStream_t s) {
+                               double plateau_rel, float* spec, int use_user, int n_wg, hipStream_t s) {
     hipLaunchKernelGGL(lowq_count_kernel, dim3((n_frames + 255) / 256), dim3(256), 0, s, frames, n_frames, ws, lay);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -468,7 +455,7 @@ hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frame
                            lay, spec, use_user);                                                           \
         if ((e = hipGetLastError()) != hipSuccess) return e;                                               \
         hipLaunchKernelGGL(winpeaks_kernel<MB>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, pos, cis, ws, \
-                           lay, extra, lowq_tau, spec, use_user);                                          \
+                           lay, extra, lowq_tau, plateau_rel, spec, use_user);                             \
         return hipGetLastError();
     switch (bucket_M) {
         NSSDOA_WP_CASE(8)

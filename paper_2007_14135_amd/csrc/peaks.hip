@@ -12,16 +12,19 @@
 //  2. finds the local maxima of its own points: P[l] > P[l-1] and the run of values equal to
 //     P[l] ends in a strictly smaller value (the run is reported at its first index); grid ends
 //     are not peaks unless the grid is circular;
-//  3. writes its best D + extra maxima by (value desc, index asc) to the chunk's reserved slots,
+//  3. keeps the maxima that win their plateau (chunk_candidates) and writes the best D + extra
+//     by (value desc, index asc), with their plateau extents, to the chunk's reserved slots;
 //     unused slots get index -1.  Slots are per chunk, so no atomics cross workgroups and the
 //     result does not depend on scheduling.
 // select_kernel, one workgroup per frame:
-//  4. ranks the chunk candidates and keeps the best D + extra;
-//  5. evaluates a window of +-halfwidth points around each in FP64 (16 lanes per point),
-//     sliding a window that holds no interior FP64 local maximum uphill; in windowed
-//     estimation points outside the scan windows are left unknown (NaN);
-//  6. ranks the distinct FP64 local maxima of the windows by (value desc, index asc) and writes
-//     the first D; slots beyond the number found get idx = -1 and NaN.
+//  4. orders the chunk candidates by (value desc, index asc);
+//  5. takes them in that order, in batches, and evaluates each one's plateau +- halfwidth points
+//     in FP64 (16 lanes per point), listing the FP64 local maxima interior to these spans (in
+//     windowed estimation points outside the scan windows are unknown, NaN); it stops once D
+//     distinct FP64 maxima are known and the next candidate, raised by the plateau depth, is
+//     below the D-th of them;
+//  6. ranks the distinct FP64 local maxima by (value desc, index asc) and writes the first D;
+//     slots beyond the number found get idx = -1 and NaN.
 #include <float.h>
 
 #include "nssdoa.h"
@@ -33,15 +36,10 @@ namespace {
 constexpr int kHalo = 16;
 constexpr int kLocalCap = kRefineChunk / 2;
 constexpr int kMaxSel = 96;      // D + extra <= 63 + 16 < 96
-constexpr int kMaxWin = 33;      // 2 * 16 + 1
 constexpr int kMaxFinal = 1024;
-constexpr int kMaxClimb = 32;    // slides of an FP64 window toward a flat peak's maximum
+constexpr int kSpanCap = 2048;   // FP64 points evaluated per batch of candidates
+constexpr int kMaxBatch = 96;    // candidates per batch (D + extra of them, at most)
 
-struct Cand {
-    double v;
-    int32_t idx;
-    int32_t pad;
-};
 
 __device__ inline double qnan() { return __longlong_as_double(0x7ff8000000000000LL); }
 
@@ -96,7 +94,7 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     const bool circ = fr.circular != 0;
     const int C = fr.D + prm.extra;
     TS* P = spec + (prm.use_user_spec ? fr.spec_off_user : fr.spec_off_ws);
-    Cand* slots = reinterpret_cast<Cand*>(ws + fr.ws_cand) + (size_t)(l0 / kRefineChunk) * C;
+    CandSlot* slots = reinterpret_cast<CandSlot*>(ws + fr.ws_cand) + (size_t)(l0 / kRefineChunk) * C;
 
     if (status[f] & NSSDOA_ST_NONFINITE_INPUT) {
         for (int o = tid; o < nown; o += blockDim.x) P[l0 + o] = (TS)qnan();
@@ -198,21 +196,15 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
         }
     }
     __syncthreads();
+    // 3. plateau winners, best C to the chunk's slots
     const int n = min(lcount, kLocalCap);
-    for (int i = tid; i < n; i += blockDim.x) {
-        const double vi = lval[i];
-        const int li = lidx[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) rank += (lval[j] > vi) || (lval[j] == vi && lidx[j] < li);
-        if (rank < C) {
-            slots[rank].v = vi;
-            slots[rank].idx = li;
-        }
-    }
-    for (int s = n + tid; s < C; s += blockDim.x) {
-        slots[s].v = qnan();
-        slots[s].idx = -1;
-    }
+    auto val = [&](int g) -> double {
+        const int e = g - (l0 - kHalo);
+        if (e >= 0 && e < span) return v[e];
+        if (circ) return (double)P[((g % L) + L) % L];
+        return (g >= 0 && g < L) ? (double)P[g] : qnan();
+    };
+    chunk_candidates(n, lval, lidx, reinterpret_cast<uint32_t*>(rlist), v, &rcount, prm.plateau_rel, val, slots, C);
 }
 
 template <int MB>
@@ -226,13 +218,15 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
                                                      uint32_t* __restrict__ status) {
     __shared__ double cval[kSelCap];
     __shared__ int cidx[kSelCap];
-    __shared__ int sel[kMaxSel];
-    __shared__ double win[kMaxSel * kMaxWin];
+    __shared__ uint32_t cspan[kSelCap];
+    __shared__ int ord[kSelCap];
+    __shared__ double buf[kSpanCap];
+    __shared__ int sp_lo[kMaxBatch], sp_off[kMaxBatch + 1];
     __shared__ double fval[kMaxFinal];
     __shared__ int fidx[kMaxFinal];
     __shared__ int rankpos[kMaxSel];
-    __shared__ int act[kMaxSel], climb[kMaxSel];
-    __shared__ int ccount, fcount, nuniq, nact;
+    __shared__ int ccount, fcount, nuniq, nproc, nbatch, done;
+    __shared__ double dth;
     __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
 
     const int f = flist[blockIdx.x];
@@ -257,138 +251,156 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
         return;
     }
 
-    // 4. gather the chunk candidates and keep the best C
+    // 4. gather the chunk candidates and order them by (value desc, index asc)
     const int Cc = D + prm.extra;
     const int n_chunks = prm.chunk_count ? prm.chunk_count[f] : (L + kRefineChunk - 1) / kRefineChunk;
     const int total = n_chunks * Cc;
-    const Cand* slots = reinterpret_cast<const Cand*>(ws + fr.ws_cand);
+    const CandSlot* slots = reinterpret_cast<const CandSlot*>(ws + fr.ws_cand);
     if (tid == 0) {
         ccount = 0;
         fcount = 0;
         nuniq = 0;
+        nproc = 0;
+        dth = 0.0;
     }
     __syncthreads();
     for (int i = tid; i < total; i += blockDim.x) {
-        const Cand c = slots[i];
+        const CandSlot c = slots[i];
         if (c.idx >= 0) {
             const int s = atomicAdd(&ccount, 1);
             cval[s] = c.v;
             cidx[s] = c.idx;
+            cspan[s] = c.span;
         }
     }
     __syncthreads();
     const int nc = ccount;
-    const int C = min(nc, Cc);
     for (int i = tid; i < nc; i += blockDim.x) {
         const double vi = cval[i];
         const int li = cidx[i];
         int rank = 0;
-        for (int j = 0; j < nc; ++j) rank += (cval[j] > vi) || (cval[j] == vi && cidx[j] < li);
-        if (rank < C) sel[rank] = li;
+        for (int k = 0; k < nc; ++k) rank += (cval[k] > vi) || (cval[k] == vi && cidx[k] < li);
+        ord[rank] = i;
     }
     __syncthreads();
 
-    // 5. FP64 windows around the kept candidates.  A window without an interior FP64 local
-    //    maximum (the FP32 maximum of a very flat peak can lie farther from the FP64 one than the
-    //    half width) slides toward its higher end by W - 2 points, keeping two points of overlap,
-    //    until it holds one or kMaxClimb slides are done.
+    // 5. FP64 evaluation of each candidate's plateau +- halfwidth, in batches taken in candidate
+    //    order, until D distinct FP64 maxima are known and the next candidate cannot beat the D-th
+    //    (a plateau's FP64 values exceed its candidate's value by less than plateau_rel)
     const double* ps = pos + fr.pos_off;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
-    const int w = prm.halfwidth, W = 2 * w + 1;
-    for (int i = tid; i < C; i += blockDim.x) act[i] = i;
-    if (tid == 0) nact = C;
-    __syncthreads();
-    for (int iter = 0;; ++iter) {
-        const int na = nact;
-        {
-            // 16 lanes per window point: 16 points per pass of the 256-thread workgroup
-            const int grp = tid >> 4, j = tid & 15;
-            double2* a = asteer + (tid >> 6) * 4 * MB;
-            for (int e0 = 0; e0 < na * W; e0 += 16) {
-                const int e = e0 + grp;
-                const bool valid = e < na * W;
-                const int c = valid ? act[e / W] : 0, o = valid ? e - (e / W) * W : 0;
-                int l = valid ? sel[c] + o - w : 0;
-                if (circ) l = ((l % L) + L) % L;
-                bool inside = valid && (circ || (l >= 0 && l < L));
-                if (inside && prm.windows) inside = in_windows(prm.windows + (size_t)f * kWinStride, l);
-                const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
-                                               grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
-                if (valid && j == 0) win[c * kMaxWin + o] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
-            }
-        }
-        __syncthreads();
-        if (iter == kMaxClimb) break;
-        // one thread per active window: interior local maximum present? otherwise slide uphill
-        for (int i = tid; i < na; i += blockDim.x) {
-            const int c = act[i];
-            const double* wv = win + c * kMaxWin;
-            bool interior = false;
-            for (int o = 1; o < W - 1 && !interior; ++o) {
-                const double x = wv[o];
-                if (!(x > wv[o - 1])) continue;
-                int r = o + 1;
-                while (r < W && wv[r] == x) ++r;
-                interior = r < W && wv[r] < x;
-            }
-            int move = 0;
-            if (!interior) {
-                if (wv[W - 1] > wv[0] || (wv[W - 1] == wv[W - 1] && wv[0] != wv[0])) move = W - 2;
-                else if (wv[0] > wv[W - 1] || (wv[0] == wv[0] && wv[W - 1] != wv[W - 1])) move = -(W - 2);
-            }
-            climb[i] = move;
-        }
-        __syncthreads();
+    const int w = prm.halfwidth;
+    const int grp = tid >> 4, j = tid & 15;
+    double2* a = asteer + (tid >> 6) * 4 * MB;
+    const int32_t* W = prm.windows ? prm.windows + (size_t)f * kWinStride : nullptr;
+    for (;;) {
         if (tid == 0) {
-            int n2 = 0;
-            for (int i = 0; i < na; ++i) {
-                if (climb[i] == 0) continue;
-                const int c = act[i];
-                sel[c] += climb[i];
-                act[n2++] = c;
+            int stop = nproc >= nc;
+            if (!stop && nuniq >= D && cval[ord[nproc]] * (1.0 + prm.plateau_rel) < dth) stop = 1;
+            int nb = 0, tot = 0;
+            while (!stop && nproc + nb < nc && nb < min(Cc, kMaxBatch)) {
+                const int i = ord[nproc + nb];
+                const int l = cidx[i];
+                int lo = l - (int)(cspan[i] >> 16) - w, hi = l + (int)(cspan[i] & 0xFFFFu) + w;
+                if (!circ) {
+                    lo = max(lo, 0);
+                    hi = min(hi, L - 1);
+                }
+                if (hi - lo + 1 > kSpanCap) {          // a very long plateau: its central part
+                    lo = max(lo, l - kSpanCap / 2);
+                    hi = lo + kSpanCap - 1;
+                }
+                const int len = hi - lo + 1;
+                if (tot + len > kSpanCap) break;
+                sp_lo[nb] = lo;
+                sp_off[nb] = tot;
+                tot += len;
+                ++nb;
             }
-            nact = n2;
+            sp_off[nb] = tot;
+            nbatch = nb;
+            nproc += nb;
+            done = stop || nb == 0;
         }
         __syncthreads();
-        if (nact == 0) break;
+        if (done) break;
+        const int nb = nbatch, tot = sp_off[nb];
+        // 16 lanes per point: 16 points per pass of the 256-thread workgroup
+        for (int e0 = 0; e0 < tot; e0 += 16) {
+            const int e = e0 + grp;
+            const bool valid = e < tot;
+            int b = 0;
+            if (valid)
+                while (sp_off[b + 1] <= e) ++b;
+            int l = valid ? sp_lo[b] + (e - sp_off[b]) : 0;
+            if (circ) l = ((l % L) + L) % L;
+            bool inside = valid && (circ || (l >= 0 && l < L));
+            if (inside && W) inside = in_windows(W, l);
+            const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
+                                           grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
+            if (valid && j == 0) buf[e] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
+        }
+        __syncthreads();
+        // FP64 local maxima interior to the spans (both neighbours and the plateau run known)
+        for (int e = tid; e < tot; e += blockDim.x) {
+            int b = 0;
+            while (sp_off[b + 1] <= e) ++b;
+            const int beg = sp_off[b], end = sp_off[b + 1];
+            if (e == beg || e == end - 1) continue;
+            int l = sp_lo[b] + (e - beg);
+            if (circ) l = ((l % L) + L) % L;
+            else if (l <= 0 || l >= L - 1) continue;
+            const double x = buf[e];
+            if (!(x > buf[e - 1])) continue;
+            int r = e + 1;
+            while (r < end && buf[r] == x) ++r;
+            if (r < end && buf[r] < x) {
+                const int s = atomicAdd(&fcount, 1);
+                if (s < kMaxFinal) {
+                    fval[s] = x;
+                    fidx[s] = l;
+                }
+            }
+        }
+        if (tid == 0) nuniq = 0;
+        __syncthreads();
+        // distinct maxima so far and the D-th best value
+        const int nf = min(fcount, kMaxFinal);
+        for (int i = tid; i < nf; i += blockDim.x) {
+            const int li = fidx[i];
+            bool dup = false;
+            for (int k = 0; k < i; ++k) dup |= (fidx[k] == li);
+            if (dup) continue;
+            atomicAdd(&nuniq, 1);
+            const double vi = fval[i];
+            int rank = 0;
+            for (int k = 0; k < nf; ++k) {
+                const int lk = fidx[k];
+                bool kdup = false;
+                for (int q = 0; q < k; ++q) kdup |= (fidx[q] == lk);
+                if (kdup) continue;
+                rank += (fval[k] > vi) || (fval[k] == vi && lk < li);
+            }
+            if (rank == D - 1) dth = vi;
+        }
+        __syncthreads();
     }
 
-    // 6. FP64 local maxima inside the windows (interior points: both neighbours known)
-    for (int e = tid; e < C * W; e += blockDim.x) {
-        const int c = e / W, o = e - c * W;
-        if (o == 0 || o == W - 1) continue;
-        int l = sel[c] + o - w;
-        if (circ) l = ((l % L) + L) % L;
-        else if (l <= 0 || l >= L - 1) continue;
-        const double* wv = win + c * kMaxWin;
-        const double x = wv[o];
-        if (!(x > wv[o - 1])) continue;
-        int r = o + 1;
-        while (r < W && wv[r] == x) ++r;
-        if (r < W && wv[r] < x) {
-            const int s = atomicAdd(&fcount, 1);
-            if (s < kMaxFinal) {
-                fval[s] = x;
-                fidx[s] = l;
-            }
-        }
-    }
-    __syncthreads();
+    // 6. rank the distinct FP64 maxima by (value desc, index asc) and write the first D
     const int nf = min(fcount, kMaxFinal);
     for (int i = tid; i < nf; i += blockDim.x) {
         const int li = fidx[i];
         bool dup = false;
-        for (int j = 0; j < i; ++j) dup |= (fidx[j] == li);
+        for (int k = 0; k < i; ++k) dup |= (fidx[k] == li);
         if (dup) continue;
-        atomicAdd(&nuniq, 1);
         const double vi = fval[i];
         int rank = 0;
-        for (int j = 0; j < nf; ++j) {
-            const int lj = fidx[j];
-            bool djdup = false;
-            for (int k = 0; k < j; ++k) djdup |= (fidx[k] == lj);
-            if (djdup) continue;
-            rank += (fval[j] > vi) || (fval[j] == vi && lj < li);
+        for (int k = 0; k < nf; ++k) {
+            const int lk = fidx[k];
+            bool kdup = false;
+            for (int q = 0; q < k; ++q) kdup |= (fidx[q] == lk);
+            if (kdup) continue;
+            rank += (fval[k] > vi) || (fval[k] == vi && lk < li);
         }
         if (rank < D) rankpos[rank] = i;
     }
@@ -411,6 +423,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     if (tid == 0) {
         npeaks[f] = nout;
         if (nout < D) st |= NSSDOA_ST_FEWER_PEAKS;
+        if (fcount > kMaxFinal) st |= NSSDOA_ST_PEAK_OVERFLOW;
         status[f] = st;
     }
 }

@@ -30,6 +30,10 @@ class DeviceBatch:
     def run(self, stream=None):
         self.batch.estimate(self.X, self.spectrum, self.peaks, self.npeaks, self.status, self.workspace, stream)
 
+    def capture(self):
+        """A graph of nssdoa_estimate on this batch's buffers (replay with .launch(stream))."""
+        return self.batch.graph(self.X, self.spectrum, self.peaks, self.npeaks, self.status, self.workspace)
+
     def _windowed_workspace(self, mlp=None):
         import torch
         need = self.batch.windowed_workspace_size(mlp)
@@ -70,7 +74,7 @@ class DeviceBatch:
 
 def prepare(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequence[tuple],
             X_flat: np.ndarray, alg: str, prec: str, max_D: int, *, with_spectrum: bool = True,
-            options: Optional[Options] = None, device: str = "cuda") -> DeviceBatch:
+            options: Optional[Options] = None, device: str = "cuda", X_device=None) -> DeviceBatch:
     """Create plan and batch, upload X, allocate outputs.  frames: (array_id, grid_id, N, D,
     x_off, ldx) tuples; spectrum offsets are assigned here, frame after frame."""
     import torch
@@ -85,14 +89,13 @@ def prepare(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequen
         full.append(tuple(f[:6]) + (off,))
         off += L
     batch = Batch(plan, alg, prec, full, max_D)
-    if prec == "c128":
-        Xh = np.ascontiguousarray(X_flat, dtype=np.complex128).view(np.float64)
-        X = torch.from_numpy(Xh).to(device)
-        sdt = torch.float64
+    sdt = torch.float64 if prec == "c128" else torch.float32
+    if X_device is not None:
+        X = X_device                               # snapshots already on the device
+    elif prec == "c128":
+        X = torch.from_numpy(np.ascontiguousarray(X_flat, dtype=np.complex128).view(np.float64)).to(device)
     else:
-        Xh = np.ascontiguousarray(X_flat, dtype=np.complex64).view(np.float32)
-        X = torch.from_numpy(Xh).to(device)
-        sdt = torch.float32
+        X = torch.from_numpy(np.ascontiguousarray(X_flat, dtype=np.complex64).view(np.float32)).to(device)
     spectrum = torch.empty(off, dtype=sdt, device=device) if with_spectrum else None
     n = len(frames)
     peaks = torch.empty(n * max_D * _abi.PEAK_DTYPE.itemsize, dtype=torch.uint8, device=device)

@@ -187,10 +187,21 @@ def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
     Mv, Dv, Nv = p["M"], p["D"], p["N"]
     angles = draw_angles(rng, Dv, p["angle_lo"], p["angle_hi"], p["gap"])
     A = _source_manifold(p["pos"], angles)
-    S = (rng.standard_normal((Dv, Nv)) + 1j * rng.standard_normal((Dv, Nv))) / np.sqrt(2.0)
+    # complex draws built part by part (the same values as re + 1j * im, without temporaries):
+    # S = (g1 + j g2) / sqrt(2), W = sqrt(sigma2) (g3 + j g4) / sqrt(2), in this draw order
+    S = np.empty((Dv, Nv), dtype=np.complex128)
+    S.real = rng.standard_normal((Dv, Nv))
+    S.imag = rng.standard_normal((Dv, Nv))
+    S /= np.sqrt(2.0)
     sigma2 = 10.0 ** (-p["snr_db"] / 10.0)
-    W = np.sqrt(sigma2) * (rng.standard_normal((Mv, Nv)) + 1j * rng.standard_normal((Mv, Nv))) / np.sqrt(2.0)
-    X = (A @ S + W).astype(cfg.dtype)
+    W = np.empty((Mv, Nv), dtype=np.complex128)
+    W.real = rng.standard_normal((Mv, Nv))
+    W.imag = rng.standard_normal((Mv, Nv))
+    W.real *= np.sqrt(sigma2)
+    W.imag *= np.sqrt(sigma2)
+    W /= np.sqrt(2.0)
+    W += A @ S
+    X = W.astype(cfg.dtype)
     g = p["grid"]
     return Frame(M=Mv, N=Nv, D=Dv, pos=p["pos"], geometry=p["geometry"], snr_db=p["snr_db"],
                  sigma2=sigma2, angles_deg=angles, grid_start=g[0], grid_step=g[1], grid_L=g[2],

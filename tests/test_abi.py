@@ -58,7 +58,8 @@ def test_plan_rejects_invalid(arrays, grids, msg):
 
 
 @pytest.mark.parametrize("kw", [dict(jacobi_tol=0.0), dict(max_sweeps=0), dict(refine_halfwidth=0),
-                                dict(refine_halfwidth=17), dict(lowq_tau=-1.0), dict(extra_candidates=17)])
+                                dict(refine_halfwidth=17), dict(lowq_tau=-1.0), dict(extra_candidates=17),
+                                dict(scan_rows=16), dict(scan_rows=100), dict(scan_rows=32768)])
 def test_plan_rejects_bad_options(kw):
     with pytest.raises(nd.NssdoaError) as e:
         nd.Plan([_ula(8)], [(-90, 0.1, 1800)], nd.Options(**kw))
@@ -101,3 +102,7 @@ def test_null_handles_rejected():
     assert lib.nssdoa_plan_destroy(None) == _abi.OK
     assert lib.nssdoa_batch_destroy(None) == _abi.OK
     assert lib.nssdoa_plan_create(None, None, 0, None, 0, None) == _abi.EINVAL
+
+
+def test_plan_accepts_scan_rows():
+    nd.Plan([_ula(8)], [(-90, 0.1, 1800)], nd.Options(scan_rows=1024)).close()

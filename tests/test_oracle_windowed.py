@@ -112,3 +112,12 @@ def test_proposal_windows_threshold_nan_and_bin_width():
     assert mlp.proposal_windows(s3, 1, 1.0, -90.0, 0.5, 360) == [(180, 185)]
     # a bin outside a partial grid gives an empty window, which is dropped
     assert mlp.proposal_windows(s, 1, 1.0, 20.0, 0.01, 1000) == []
+
+
+def test_proposal_windows_with_fewer_finite_bins_than_topk():
+    # -inf scores stay eligible (lowest first by bin), NaN never; no bin is chosen twice
+    s = np.full(180, np.nan)
+    s[40], s[100] = 1.0, -np.inf
+    s[120] = -np.inf
+    got = mlp.proposal_windows(s, 5, 0.5, -90.0, 0.01, 18000)
+    assert got == [(4000, 4101), (10000, 10101), (12000, 12101)]   # centres -49.5, 10.5, 30.5
