@@ -199,6 +199,9 @@ def main():
     ap.add_argument("--learned-frames", type=int, default=8192)
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of autotuner choices")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="finish with one device-to-device copy of this many MiB (the reference of the HBM "
+                         "byte counters: a plain copy reads and writes exactly that much)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is per-frame data parallel and this build "
@@ -323,6 +326,14 @@ def main():
         del db
         torch.cuda.empty_cache()
         out["learned_vs_full"] = learned_leg(fs5, 3, 1)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n
     print(json.dumps(out))
 
 

@@ -238,39 +238,50 @@ struct CandSlot {
 };
 
 // Walk the plateau of the local maximum x at grid index l through val(g) (NaN: unknown, ends the
-// walk).  Returns false when the plateau holds a better point, else its extent in *span.
+// walk).  Returns false when the plateau holds a better point, else its extent in *span.  The 64
+// lanes of a wave walk together, 64 points per step (every lane must call it with the same
+// arguments); the first point that ends the plateau or beats x decides.
 template <typename F>
 __device__ inline bool plateau_walk(double x, int l, double rel, F val, uint32_t* span) {
+    const int lane = threadIdx.x & 63;
     const double thr = x - x * rel;
-    int left = 0, right = 0;
-    for (int k = 1; k <= kMaxPlateau; ++k) {
-        const double y = val(l - k);
-        if (!(y >= thr)) break;
-        if (y >= x) return false;              // larger, or equal at a lower index
-        left = k;
+    int ext[2] = {kMaxPlateau, kMaxPlateau};
+    for (int side = 0; side < 2; ++side) {
+        for (int base = 1; base <= kMaxPlateau; base += 64) {
+            const int k = base + lane;
+            bool stop = true, beat = false;
+            if (k <= kMaxPlateau) {
+                const double y = val(side == 0 ? l - k : l + k);
+                stop = !(y >= thr);
+                // on the left an equal value wins (lower index); on the right it does not
+                beat = !stop && (side == 0 ? y >= x : y > x);
+            }
+            const unsigned long long sb = __ballot(stop), bb = __ballot(beat);
+            if (sb | bb) {
+                const int first = __ffsll((long long)(sb | bb)) - 1;
+                if ((bb >> first) & 1ull) return false;
+                ext[side] = base + first - 1;
+                break;
+            }
+        }
     }
-    for (int k = 1; k <= kMaxPlateau; ++k) {
-        const double y = val(l + k);
-        if (!(y >= thr)) break;
-        if (y > x) return false;
-        right = k;
-    }
-    *span = ((uint32_t)left << 16) | (uint32_t)right;
+    *span = ((uint32_t)ext[0] << 16) | (uint32_t)ext[1];
     return true;
 }
 
 // The best C plateau winners among the n local maxima (lval, lidx) of a chunk, by (value desc,
 // index asc), to slots[0..C); unused slots get idx -1.  flag: n ints of LDS; sv: 2 * n doubles of
-// LDS that val() no longer reads; cnt: one LDS int.  Every thread of the workgroup calls it.
+// LDS that val() no longer reads; cnt: one LDS int.  Every thread of the workgroup calls it; each
+// wave walks one local maximum at a time.
 template <typename F>
 __device__ inline void chunk_candidates(int n, const double* lval, const int* lidx, uint32_t* flag, double* sv,
                                         int* cnt, double rel, F val, CandSlot* slots, int C) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += blockDim.x) {
-        uint32_t span = 0xFFFFFFFFu;           // not a winner
-        uint32_t sp;
-        if (plateau_walk(lval[i], lidx[i], rel, val, &sp)) span = sp;
-        flag[i] = span;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = tid >> 6, nwaves = blockDim.x >> 6;
+    for (int i = wave; i < n; i += nwaves) {
+        uint32_t sp = 0;
+        const bool win = plateau_walk(lval[i], lidx[i], rel, val, &sp);
+        if (lane == 0) flag[i] = win ? sp : 0xFFFFFFFFu;   // a span never has all bits set
     }
     if (tid == 0) *cnt = 0;
     __syncthreads();

@@ -298,7 +298,10 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
             int stop = nproc >= nc;
             if (!stop && nuniq >= D && cval[ord[nproc]] * (1.0 + prm.plateau_rel) < dth) stop = 1;
             int nb = 0, tot = 0;
-            while (!stop && nproc + nb < nc && nb < min(Cc, kMaxBatch)) {
+            // the first batch holds the best D candidates: for well separated peaks it is all
+            // the FP64 work there is
+            const int cap = min(nproc == 0 ? D : Cc, kMaxBatch);
+            while (!stop && nproc + nb < nc && nb < cap) {
                 const int i = ord[nproc + nb];
                 const int l = cidx[i];
                 int lo = l - (int)(cspan[i] >> 16) - w, hi = l + (int)(cspan[i] & 0xFFFFu) + w;
