@@ -34,6 +34,7 @@ METRIC = "MUSIC spectrum points/s & frames/s at ≤0.01° peak err, learned vs f
 WEIGHTS = os.path.join(ROOT, "paper_2007_14135_amd", "weights", "proposal_ula16.npy")
 SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")
+TUNE_CACHE = os.path.join(ROOT, "paper_2007_14135_amd", "tuning", "autotune_cache.json")
 
 
 def _oracle_worker(args):
@@ -96,9 +97,9 @@ def make_frames_parallel(config, n):
     return pack_frames(frames, dtype=np.complex64)
 
 
-def scan_traffic():
+def scan_traffic(scan_rows):
     """HBM bytes per scan launch from the committed counter summary, or None when the summary is
-    missing or was taken on another version of the scan kernel."""
+    missing or was taken on another version of the scan kernel or another work-item size."""
     try:
         kv = {}
         with open(PMC_SUMMARY) as fh:
@@ -108,7 +109,7 @@ def scan_traffic():
                     kv[k.strip()] = v.strip()
         with open(SCAN_SRC, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
-        if kv.get("source_sha256") != sha:
+        if kv.get("source_sha256") != sha or int(kv.get("scan_rows", -1)) != scan_rows:
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -198,7 +199,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-frames", type=int, default=8192)
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
-    ap.add_argument("--tune-cache", default="", help="JSON cache of autotuner choices")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="JSON cache of autotuner choices")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (the reference of the HBM "
                          "byte counters: a plain copy reads and writes exactly that much)")
@@ -299,7 +300,7 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": scan_traffic() if args.alg == "music" else None,
+            "traffic": scan_traffic(rows or 384) if args.alg == "music" else None,
             "algorithmic_flops_per_launch": scan_flops,
             "avg_launch_ms": scan_avg_s * 1e3,
         },

@@ -71,9 +71,10 @@ class Cache:
 
 
 def device_name() -> str:
+    """Architecture and compute-unit count of the current device (the tuning depends on these)."""
     import torch
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return "%s/%s/%d" % (p.name, getattr(p, "gcnArchName", "?"), p.multi_processor_count)
+    return "%s/%dCU" % (getattr(p, "gcnArchName", "?").split(":")[0], p.multi_processor_count)
 
 
 def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, candidates: Optional[Iterable[int]] = None,
