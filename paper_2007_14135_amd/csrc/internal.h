@@ -269,25 +269,83 @@ __device__ inline bool plateau_walk(double x, int l, double rel, F val, uint32_t
     return true;
 }
 
+// Extrema of the 32-point blocks of v[0..span): bmax[b], bmin[b] for b < ceil(span / 32); a block
+// holding a NaN gets bmin = NaN.  Every thread of the workgroup calls it (one wave per block pair).
+constexpr int kPlateauBlock = 32;
+__device__ inline void block_extrema(const double* v, int span, double* bmax, double* bmin) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int nb = (span + kPlateauBlock - 1) / kPlateauBlock;
+    for (int b0 = 2 * wave; b0 < nb; b0 += 2 * nwaves) {
+        const int e = b0 * kPlateauBlock + lane;            // lanes 0-31: block b0, 32-63: b0 + 1
+        const double x = e < span ? v[e] : -INFINITY;
+        double hi = x, lo = e < span ? x : INFINITY;
+        for (int o = 16; o > 0; o >>= 1) {
+            const double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
+            hi = fmax(hi, h2);
+            lo = (l2 < lo || l2 != l2) ? l2 : lo;               // NaN sticks
+        }
+        if ((lane & 31) == 0 && b0 + (lane >> 5) < nb) {
+            bmax[b0 + (lane >> 5)] = hi;
+            bmin[b0 + (lane >> 5)] = lo;
+        }
+    }
+}
+
+// True when the local maximum x at v-index e certainly loses its plateau: the 32-point block
+// holding e and its two neighbours contain a larger value and no value below x (1 - rel) or NaN,
+// so the plateau walk would reach that larger value.
+__device__ inline bool plateau_prefilter(int e, double x, double rel, int span, const double* bmax,
+                                         const double* bmin) {
+    const int b = e / kPlateauBlock, nb = (span + kPlateauBlock - 1) / kPlateauBlock;
+    if (b < 1 || b + 1 >= nb) return false;
+    const double hi = fmax(bmax[b - 1], fmax(bmax[b], bmax[b + 1]));
+    const double lo0 = bmin[b - 1], lo1 = bmin[b], lo2 = bmin[b + 1];
+    const double thr = x - x * rel;
+    return hi > x && lo0 >= thr && lo1 >= thr && lo2 >= thr;
+}
+
+constexpr uint32_t kLoser = 0xFFFFFFFFu;       // flag of a local maximum that lost its plateau
+constexpr int kPrefilterMin = 64;              // local maxima in a chunk worth the block extrema
+
+// Marks in flag[0..n) (kLoser or 0) the local maxima of a chunk that plateau_prefilter drops,
+// when the chunk has more than kPrefilterMin of them (a fine grid, where rounding makes many);
+// v_index(i) gives the v-index of local maximum i.  Every thread of the workgroup calls it.
+template <typename FI>
+__device__ inline void prefilter_losers(int n, const double* lval, FI v_index, const double* v, int span,
+                                        double rel, double* bmax, double* bmin, uint32_t* flag) {
+    const int tid = threadIdx.x;
+    const bool use = n > kPrefilterMin;
+    if (use) {
+        block_extrema(v, span, bmax, bmin);
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += blockDim.x)
+        flag[i] = (use && plateau_prefilter(v_index(i), lval[i], rel, span, bmax, bmin)) ? kLoser : 0u;
+    __syncthreads();
+}
+
 // The best C plateau winners among the n local maxima (lval, lidx) of a chunk, by (value desc,
-// index asc), to slots[0..C); unused slots get idx -1.  flag: n ints of LDS; sv: 2 * n doubles of
-// LDS that val() no longer reads; cnt: one LDS int.  Every thread of the workgroup calls it; each
-// wave walks one local maximum at a time.
+// index asc), to slots[0..C); unused slots get idx -1.  flag: n ints of LDS holding kLoser for
+// maxima already known to lose (prefilter_losers), else 0; sv: 2 * n doubles of LDS that val() no
+// longer reads; cnt: one LDS int.  Every thread of the workgroup calls it; each wave walks one
+// local maximum at a time.
 template <typename F>
 __device__ inline void chunk_candidates(int n, const double* lval, const int* lidx, uint32_t* flag, double* sv,
                                         int* cnt, double rel, F val, CandSlot* slots, int C) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = tid >> 6, nwaves = blockDim.x >> 6;
     for (int i = wave; i < n; i += nwaves) {
+        if (flag[i] == kLoser) continue;             // uniform: one i per wave
         uint32_t sp = 0;
         const bool win = plateau_walk(lval[i], lidx[i], rel, val, &sp);
-        if (lane == 0) flag[i] = win ? sp : 0xFFFFFFFFu;   // a span never has all bits set
+        if (lane == 0) flag[i] = win ? sp : kLoser;  // a span never has all bits set
     }
+    __syncthreads();
     if (tid == 0) *cnt = 0;
     __syncthreads();
     long long* pk = reinterpret_cast<long long*>(sv + n);
     for (int i = tid; i < n; i += blockDim.x) {
-        if (flag[i] == 0xFFFFFFFFu) continue;
+        if (flag[i] == kLoser) continue;
         const int s = atomicAdd(cnt, 1);
         sv[s] = lval[i];
         pk[s] = ((long long)lidx[i] << 32) | (long long)flag[i];

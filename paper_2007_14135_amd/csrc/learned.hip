@@ -323,6 +323,8 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
     __shared__ int rlist[kRefineChunk + 2 * kHaloW];
     __shared__ double lval[kRefineChunk / 2];
     __shared__ int lidx[kRefineChunk / 2];
+    __shared__ double bmax[(kRefineChunk + 2 * kHaloW) / kPlateauBlock + 1];
+    __shared__ double bmin[(kRefineChunk + 2 * kHaloW) / kPlateauBlock + 1];
     __shared__ int lcount, rcount;
     const int tid = threadIdx.x;
     const int* coff = reinterpret_cast<const int*>(ws + lay.off_chunk_off);
@@ -401,7 +403,10 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
             const int e = g - (c0 - kHaloW);
             return (e >= 0 && e < span) ? v[e] : (double)P[g];
         };
-        chunk_candidates(n, lval, lidx, reinterpret_cast<uint32_t*>(rlist), v, &rcount, plateau_rel, val, slots, C);
+        uint32_t* flag = reinterpret_cast<uint32_t*>(rlist);
+        prefilter_losers(n, lval, [&](int i) { return lidx[i] - (c0 - kHaloW); }, v, span, plateau_rel, bmax, bmin,
+                         flag);
+        chunk_candidates(n, lval, lidx, flag, v, &rcount, plateau_rel, val, slots, C);
     }
 }
 

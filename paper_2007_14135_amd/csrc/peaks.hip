@@ -82,6 +82,8 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     __shared__ int rlist[kRefineChunk + 2 * kHalo];
     __shared__ double lval[kLocalCap];
     __shared__ int lidx[kLocalCap];
+    __shared__ double bmax[(kRefineChunk + 2 * kHalo) / kPlateauBlock + 1];
+    __shared__ double bmin[(kRefineChunk + 2 * kHalo) / kPlateauBlock + 1];
     __shared__ int lcount, rcount;
 
     const PointItem it = items[blockIdx.x];
@@ -204,7 +206,10 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
         if (circ) return (double)P[((g % L) + L) % L];
         return (g >= 0 && g < L) ? (double)P[g] : qnan();
     };
-    chunk_candidates(n, lval, lidx, reinterpret_cast<uint32_t*>(rlist), v, &rcount, prm.plateau_rel, val, slots, C);
+    uint32_t* flag = reinterpret_cast<uint32_t*>(rlist);
+    prefilter_losers(n, lval, [&](int i) { return lidx[i] - (l0 - kHalo); }, v, span, prm.plateau_rel, bmax, bmin,
+                     flag);
+    chunk_candidates(n, lval, lidx, flag, v, &rcount, prm.plateau_rel, val, slots, C);
 }
 
 template <int MB>
