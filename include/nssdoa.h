@@ -167,7 +167,9 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
 nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan);
 
 /* Validate a set of frames for one algorithm and scan precision, group the frames that share an
- * array and a grid, and upload the schedule to the current device (the batch owns it).
+ * array and a grid, and upload the schedule to the current device (the batch owns it).  For
+ * C64 it also computes, once, the steering vectors of every group's grid (Eq. 2) into a table the
+ * batch owns: (L rounded up to 256, plus 64) * 2M floats per group; the call waits for them. 
  * frames[n_frames] is a host array, copied.  max_D is the peak slots per frame in the outputs.
  * EINVAL: NULL pointers, n_frames < 1, unknown array/grid ids, N < 1, D < 1, D >= M, D > max_D,
  * ldx < N, negative offsets, max_D > 64, a grid longer than 4096 * floor(4096 / (D +

@@ -104,6 +104,7 @@ struct nssdoa_batch_s {
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
     PointItem* d_lowq = nullptr;
+    float* d_steer = nullptr;                   // steering tables of the FP32 scans (batch-owned)
     int live_graphs = 0;
     // timing
     bool timing = false;
@@ -347,6 +348,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             fd.ws_lowq = (int64_t)off;  off = align_up(off + (size_t)(fd.lowq_cap + 1) * 4);
         }
     }
+    int64_t steer_floats = 0;
+    for (auto& gd : b->groups) gd.steer_off = -1;
     if (prec != NSSDOA_C128) {
         const bool lp = prec != NSSDOA_C64;
         // rows of stacked B per scan work item: the 16-bit scans form their steering operands
@@ -388,6 +391,10 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             }
             gd.ws_emb = (int64_t)off;
             off = align_up(off + (size_t)gd.n_tiles * 64 * gd.M * emb_elem);
+            if (!lp) {
+                gd.steer_off = steer_floats;
+                steer_floats += (steer_table_floats(gd.M, gd.L) + 63) / 64 * 64;
+            }
             const int n_at = (gd.L + kScanAnglesPerWG - 1) / kScanAnglesPerWG;
             for (auto& ch : chunks)
                 for (int at = 0; at < n_at; ++at)
@@ -447,8 +454,10 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     size_t o_ri = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
     size_t o_lq = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
     size_t o_cis = align_up(o_lq + b->lowq_items.size() * sizeof(PointItem));
-    size_t total = align_up(o_cis + kCisTable * sizeof(double2));
-    std::vector<char> host(total, 0);
+    const size_t o_steer = align_up(o_cis + kCisTable * sizeof(double2));
+    const size_t n_host = o_steer;                       // tables uploaded from the host
+    size_t total = align_up(o_steer + (size_t)steer_floats * sizeof(float));
+    std::vector<char> host(n_host, 0);
     auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(host.data() + o, src, n); };
     put(o_frames, b->frames.data(), b->frames.size() * sizeof(FrameDev));
     put(o_groups, b->groups.data(), b->groups.size() * sizeof(GroupDev));
@@ -475,7 +484,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         delete b;
         return hip_fail(e, "hipMalloc(batch tables)");
     }
-    e = hipMemcpy(b->dev, host.data(), total, hipMemcpyHostToDevice);
+    e = hipMemcpy(b->dev, host.data(), n_host, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(b->dev);
         delete b;
@@ -492,6 +501,20 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->d_refine = reinterpret_cast<PointItem*>(b->dev + o_ri);
     b->d_cis = reinterpret_cast<double2*>(b->dev + o_cis);
     b->d_lowq = reinterpret_cast<PointItem*>(b->dev + o_lq);
+    b->d_steer = reinterpret_cast<float*>(b->dev + o_steer);
+    // steering tables of the FP32 scans, computed once per batch on the device
+    for (const GroupDev& gd : b->groups) {
+        if (gd.steer_off < 0) continue;
+        e = launch_steer_table(b->d_pos + gd.pos_off, gd.M, gd.grid_start, gd.grid_step, gd.L,
+                               b->d_steer + gd.steer_off, nullptr);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipFree(b->dev);
+        delete b;
+        return hip_fail(e, "steering tables");
+    }
     plan->live_batches++;
     *out = b;
     return NSSDOA_OK;
@@ -583,6 +606,13 @@ size_t windowed_layout(const nssdoa_batch_s* b, int n_feat, int n_bins, LearnedL
     lay->off_item_off = (int64_t)off;  off = align_up(off + (F + 1) * sizeof(int32_t));
     lay->off_chunk_off = (int64_t)off; off = align_up(off + (F + 1) * sizeof(int32_t));
     lay->off_lowq_off = (int64_t)off;  off = align_up(off + (F + 1) * sizeof(int32_t));
+    int64_t n_scan = 0, n_chunk = 0;
+    for (const FrameDev& fd : b->frames) {
+        n_scan += max_scan_items(fd.L);
+        n_chunk += max_chunk_items(fd.L);
+    }
+    lay->off_scan_items = (int64_t)off;  off = align_up(off + (size_t)n_scan * 8);
+    lay->off_chunk_items = (int64_t)off; off = align_up(off + (size_t)n_chunk * 16);
     return off;
 }
 
@@ -729,7 +759,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
 
         if ((st = stage_begin()) != NSSDOA_OK) return st;
-        e = launch_scan_windows(M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_pos, ws, lay,
+        e = launch_scan_windows(M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
                                 static_cast<float*>(spec), use_user, (float)opt.lowq_tau, persistent_grid(8), s);
         if (e != hipSuccess) return hip_fail(e, "windowed scan launch");
         if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
@@ -760,7 +790,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         for (auto& r : batch->scan_ranges) {
             if (batch->prec == NSSDOA_C64)
                 e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
-                                    batch->d_groups, batch->d_frames, batch->d_blk, batch->d_pos, ws,
+                                    batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,
                                     static_cast<float*>(spec), use_user, (float)opt.lowq_tau, s);
             else
                 e = launch_scan_lp(batch->prec == NSSDOA_F16, r.first, batch->d_scan + r.second.first,

@@ -56,7 +56,20 @@ struct GroupDev {
     int64_t ws_emb;             // byte offset of n_tiles * 64 lanes * M floats
     int32_t blk_off;            // offset of this group's 8-row-block -> frame table
     int32_t pad;
+    int64_t steer_off;          // FP32 scans: float offset of the group's steering table, else -1
 };
+
+// Steering table of a group for the FP32 scans: for grid index l (rounded up to whole 256-angle
+// tiles) and h = 0, 1, the M floats T[(2 l + h) M + k] are Re a_{2k+h}(theta_l) for k < M/2 and
+// Im a_{2(k-M/2)+h}(theta_l) for k >= M/2: the steering operand of MFMA lane h*32 + j for angle
+// l, as contiguous 16-byte loads.  Values: phase in cycles formed and reduced to [-1/2, 1/2] in
+// FP64, then FP32 sincospi.
+// Rows: whole 256-angle tiles of the group scan plus 64 more for a windowed item that starts at
+// the last grid point (points beyond the grid hold zeros and are never written out).
+inline int steer_table_rows(int L) {
+    return (L + kScanAnglesPerWG - 1) / kScanAnglesPerWG * kScanAnglesPerWG + kScanAnglesPerWave;
+}
+inline int64_t steer_table_floats(int M, int L) { return (int64_t)steer_table_rows(L) * 2 * M; }
 
 struct CovItem { int32_t frame, chunk, n0, n1; };
 struct ScanItem { int32_t group, angle_tile, t0, t1; };       // t1 exclusive, whole frames
@@ -95,7 +108,13 @@ struct LearnedLayout {
     int64_t off_item_off;       // n_frames + 1 int32 exclusive prefix sums of the three counts
     int64_t off_chunk_off;
     int64_t off_lowq_off;
+    int64_t off_scan_items;     // int2 {frame, first angle | angles << 24} per 64-angle scan item
+    int64_t off_chunk_items;    // int4 {frame, first point, window start, window end} per chunk
 };
+
+// Upper bounds of the windowed work lists of one frame (a fallback frame scans its whole grid).
+inline int64_t max_scan_items(int L) { return (L + kScanAnglesPerWave - 1) / kScanAnglesPerWave + kMaxWindows; }
+inline int64_t max_chunk_items(int L) { return (L + kRefineChunk - 1) / kRefineChunk + kMaxWindows; }
 
 // Scan angle theta_l = start + l * step with the product and the sum rounded separately
 // (contraction into one fused multiply-add is switched off here).
@@ -370,14 +389,33 @@ __device__ inline void chunk_candidates(int n, const double* lval, const int* li
     }
 }
 
+// Appends grid index l to a frame's low-Q list (int count, then entries) when `low`, with one
+// atomic per wave: every lane of the wave calls it for the same list; entries beyond `cap` are
+// only counted.
+__device__ inline void lowq_append(bool low, int l, int* cnt, int cap) {
+    const unsigned long long mask = __ballot(low);
+    if (mask == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(mask));
+    base = __shfl(base, leader);
+    if (low) {
+        const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < cap) cnt[1 + slot] = l;
+    }
+}
+
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
                       const void* X, char* ws, hipStream_t s);
 hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s);
+hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
+                              hipStream_t s);
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
-                           const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                           const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user_spec, float lowq_tau,
                            hipStream_t s);
 hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
@@ -407,7 +445,7 @@ hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* s
                             double half_window, float threshold, char* ws, const LearnedLayout& lay,
                             uint32_t* status, hipStream_t s);
 hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
-                               const int32_t* blkframe, const double* pos, char* ws, const LearnedLayout& lay,
+                               const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);
 hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,
                                const double2* cis, char* ws, const LearnedLayout& lay, int extra, double lowq_tau,

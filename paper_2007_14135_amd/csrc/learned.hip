@@ -8,10 +8,12 @@
 //   width, snapped to the frame's grid, sorted and merged.  A frame whose best score is below
 //   the threshold falls back to one window over its whole grid.  It also counts the frame's
 //   64-angle scan items and 4096-point peak chunks.
-// prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan).
+// prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan);
+// expand_kernel, one wave per frame: the frame's scan items and peak chunks written out at those
+//   offsets, so that the kernels below read their work item with one load.
 // scan_win_kernel<M>, grid-stride over 64-angle items, one wave per item: one frame's angles in
 //   one window, contracted on the FP32 matrix cores with the frame's own 8-row blocks of the
-//   packed B tiles (the operands and epilogue of the group scan).
+//   packed B tiles (the operands, steering table and epilogue of the group scan).
 // lowq_win_kernel<MB>, grid-stride over 64-entry slices of the frames' low-Q lists: FP64
 //   re-evaluation of the listed points.
 // winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
@@ -29,10 +31,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kHaloW = 16;
 
 __device__ inline double qnan_d() { return __longlong_as_double(0x7ff8000000000000LL); }
-
-__device__ inline const int* frame_windows(const char* ws, const LearnedLayout& lay, int f) {
-    return reinterpret_cast<const int*>(ws + lay.off_win) + (size_t)f * kWinStride;
-}
 
 // window of bin b: centre c, start index ceil((c - hw - start) / step - 1e-9), end (exclusive)
 // floor((c + hw - start) / step + 1e-9) + 1, every operation rounded separately
@@ -177,6 +175,33 @@ __global__ __launch_bounds__(1024) void prefix_kernel(int n, const int* __restri
     }
 }
 
+// One wave per frame: the frame's scan items and peak chunks, at its prefix-sum offsets.
+__global__ void expand_kernel(const FrameDev* __restrict__ frames, int n_frames, char* __restrict__ ws,
+                              LearnedLayout lay) {
+    const int f = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (f >= n_frames) return;                     // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int* W = reinterpret_cast<const int*>(ws + lay.off_win) + (size_t)f * kWinStride;
+    int ki = reinterpret_cast<const int*>(ws + lay.off_item_off)[f];
+    int kc = reinterpret_cast<const int*>(ws + lay.off_chunk_off)[f];
+    int2* sitems = reinterpret_cast<int2*>(ws + lay.off_scan_items);
+    int4* citems = reinterpret_cast<int4*>(ws + lay.off_chunk_items);
+    const int nw = W[0];
+    for (int w = 0; w < nw; ++w) {
+        const int l0 = W[1 + 2 * w], l1 = W[2 + 2 * w];
+        const int n = (l1 - l0 + kScanAnglesPerWave - 1) / kScanAnglesPerWave;
+        for (int k = lane; k < n; k += 64) {
+            const int a0 = l0 + k * kScanAnglesPerWave;
+            const int cnt = min(kScanAnglesPerWave, l1 - a0);
+            sitems[ki + k] = make_int2(f, a0 | (cnt << 24));
+        }
+        const int nc = (l1 - l0 + kRefineChunk - 1) / kRefineChunk;
+        for (int k = lane; k < nc; k += 64) citems[kc + k] = make_int4(f, l0 + k * kRefineChunk, l0, l1);
+        ki += n;
+        kc += nc;
+    }
+}
+
 // largest f with off[f] <= item (off non-decreasing, off[0] = 0 <= item < off[n])
 __device__ inline int find_frame(const int* __restrict__ off, int n, int item) {
     int lo = 0, hi = n - 1;
@@ -188,37 +213,13 @@ __device__ inline int find_frame(const int* __restrict__ off, int n, int item) {
     return lo;
 }
 
-// the k-th `unit`-point piece of a frame's windows: its first index and its window's bounds
-__device__ inline void locate(const int* W, int k, int unit, int* first, int* wbegin, int* wend) {
-    int local = k;
-    *first = 0;
-    *wbegin = 0;
-    *wend = 0;
-    for (int w = 0; w < W[0]; ++w) {
-        const int l0 = W[1 + 2 * w], l1 = W[2 + 2 * w];
-        const int n = (l1 - l0 + unit - 1) / unit;
-        if (local < n) {
-            *first = l0 + local * unit;
-            *wbegin = l0;
-            *wend = l1;
-            return;
-        }
-        local -= n;
-    }
-}
-
 template <int M>
-__device__ inline void steering_regs_w(const double* __restrict__ p, double th, int h, float* st) {
-    double sth, cth;
-    sincos(th * kDeg2Rad, &sth, &cth);
+__device__ inline void steering_load_w(const float* __restrict__ T, int l, int h, float* st) {
+    const float4* src = reinterpret_cast<const float4*>(T + (size_t)(2 * l + h) * M);
 #pragma unroll
-    for (int j = 0; j < M / 2; ++j) {
-        const int m = 2 * j + h;
-        const double c = p[3 * m] * sth + p[3 * m + 1] * cth;   // cycles, phi = 90 deg
-        float s, co;
-        sincospif((float)(2.0 * (c - rint(c))), &s, &co);
-        st[j] = co;
-        st[j + M / 2] = s;
+    for (int v = 0; v < M / 4; ++v) {
+        const float4 x = src[v];
+        st[4 * v] = x.x; st[4 * v + 1] = x.y; st[4 * v + 2] = x.z; st[4 * v + 3] = x.w;
     }
 }
 
@@ -226,23 +227,24 @@ template <int M>
 __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restrict__ frames, int n_frames,
                                                        const GroupDev* __restrict__ groups,
                                                        const int32_t* __restrict__ blkframe,
-                                                       const double* __restrict__ pos, char* __restrict__ ws,
+                                                       const float* __restrict__ steer, char* __restrict__ ws,
                                                        LearnedLayout lay, float* __restrict__ spec, int use_user,
                                                        float lowq_tau) {
     const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
     const int* ioff = reinterpret_cast<const int*>(ws + lay.off_item_off);
     const int total = ioff[n_frames];
     const int nwaves = gridDim.x * (blockDim.x >> 6);
+    const int2* sitems = reinterpret_cast<const int2*>(ws + lay.off_scan_items);
     for (int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); item < total; item += nwaves) {
-        const int f = find_frame(ioff, n_frames, item);
+        const int2 it = sitems[item];
+        const int f = it.x;
+        const int a0 = it.y & 0xFFFFFF, a1 = a0 + (it.y >> 24);
         const FrameDev& fr = frames[f];
         const GroupDev& g = groups[fr.group];
-        int a0, wb, a1;
-        locate(frame_windows(ws, lay, f), item - ioff[f], kScanAnglesPerWave, &a0, &wb, &a1);
         float st0[M], st1[M];
-        const double* p = pos + fr.pos_off;
-        steering_regs_w<M>(p, grid_angle(fr.grid_start, fr.grid_step, a0 + j), h, st0);
-        steering_regs_w<M>(p, grid_angle(fr.grid_start, fr.grid_step, a0 + 32 + j), h, st1);
+        const float* T = steer + g.steer_off;
+        steering_load_w<M>(T, a0 + j, h, st0);
+        steering_load_w<M>(T, a0 + 32 + j, h, st1);
         const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
         const int t0 = fr.emb_row0 >> 5, t1 = ((fr.emb_row0 + 2 * fr.K - 1) >> 5) + 1;
         float q0 = 0.0f, q1 = 0.0f;
@@ -274,16 +276,13 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
         const float u0 = q0 + __shfl_xor(q0, 32), u1 = q1 + __shfl_xor(q1, 32);
         const float v = (lane < 32) ? u0 : u1;
         const int l = a0 + lane;
-        if (l < a1) {
+        const bool in = l < a1;
+        if (in) {
             float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
-            const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fr.ws_qref);
-            if (v < thr) {
-                int* cnt = reinterpret_cast<int*>(ws + fr.ws_lowq);
-                const int slot = atomicAdd(cnt, 1);
-                if (slot < fr.lowq_cap) cnt[1 + slot] = l;
-            }
         }
+        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fr.ws_qref);
+        lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fr.ws_lowq), fr.lowq_cap);
     }
 }
 
@@ -329,13 +328,13 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
     const int tid = threadIdx.x;
     const int* coff = reinterpret_cast<const int*>(ws + lay.off_chunk_off);
     const int total = coff[n_frames];
+    const int4* citems = reinterpret_cast<const int4*>(ws + lay.off_chunk_items);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int f = find_frame(coff, n_frames, item);
+        const int4 ci = citems[item];
+        const int f = ci.x, c0 = ci.y, wl0 = ci.z, wl1 = ci.w;
         const FrameDev& fr = frames[f];
         const int C = fr.D + extra;
         CandSlot* slots = reinterpret_cast<CandSlot*>(ws + fr.ws_cand) + (size_t)(item - coff[f]) * C;
-        int c0, wl0, wl1;
-        locate(frame_windows(ws, lay, f), item - coff[f], kRefineChunk, &c0, &wl0, &wl1);
         const int nown = min(kRefineChunk, wl1 - c0), span = nown + 2 * kHaloW;
         float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
         __syncthreads();                  // the previous chunk's LDS is no longer read
@@ -423,16 +422,18 @@ hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* s
                        reinterpret_cast<const int*>(ws + lay.off_items), reinterpret_cast<int*>(ws + lay.off_item_off),
                        reinterpret_cast<const int*>(ws + lay.off_chunks),
                        reinterpret_cast<int*>(ws + lay.off_chunk_off));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(expand_kernel, dim3((n_frames + 3) / 4), dim3(256), 0, s, frames, n_frames, ws, lay);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
-                               const int32_t* blkframe, const double* pos, char* ws, const LearnedLayout& lay,
+                               const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s) {
 #define NSSDOA_WIN_CASE(MM)                                                                             \
     case MM:                                                                                         \
         hipLaunchKernelGGL(scan_win_kernel<MM>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, groups, \
-                           blkframe, pos, ws, lay, spec, use_user, lowq_tau);                          \
+                           blkframe, steer, ws, lay, spec, use_user, lowq_tau);                        \
         return hipGetLastError();
     switch (M) {
         NSSDOA_WIN_CASE(8)

@@ -16,9 +16,9 @@
 //   sum of squares of registers 4g..4g+3 is the half of 8-row block g held by this lane; the
 //   other half is in lane j + 32(1-h) and is added once per frame at the write.
 // Each wave owns 64 angles (two 32-angle column tiles sharing every A operand); a workgroup of
-// four waves owns 256 angles and one chunk of whole frames.  Steering values are generated once
-// per work item: the phase in cycles is formed and reduced to [-1/2, 1/2] in FP64, then
-// sincospi runs in FP32.
+// four waves owns 256 angles and one chunk of whole frames.  Steering values come from the
+// group's table (built once per batch by steer_table_kernel: the phase in cycles formed and
+// reduced to [-1/2, 1/2] in FP64, then FP32 sincospi), loaded once per work item.
 #include <float.h>
 
 #include "internal.h"
@@ -28,19 +28,32 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// One thread per (angle, element): a_m(theta_l) into the group's steering table (see internal.h).
+__global__ void steer_table_kernel(const double* __restrict__ pos, int M, double start, double step, int L,
+                                   int Lpad, float* __restrict__ T) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Lpad * M) return;
+    const int l = t / M, m = t - l * M;
+    float s = 0.0f, co = 0.0f;
+    if (l < L) {
+        double sth, cth;
+        sincos(grid_angle(start, step, l) * kDeg2Rad, &sth, &cth);
+        const double c = fma(pos[3 * m], sth, pos[3 * m + 1] * cth);   // cycles, phi = 90 deg
+        sincospif((float)(2.0 * (c - rint(c))), &s, &co);
+    }
+    const int h = m & 1, j = m >> 1;
+    T[(size_t)(2 * l + h) * M + j] = co;
+    T[(size_t)(2 * l + h) * M + M / 2 + j] = s;
+}
+
+// The steering operand of lane h*32 + j for grid index l: M contiguous floats of the table.
 template <int M>
-__device__ inline void steering_regs(const double* __restrict__ p, double th, int h, float* st) {
-    double sth, cth;
-    sincos(th * kDeg2Rad, &sth, &cth);
+__device__ inline void steering_load(const float* __restrict__ T, int l, int h, float* st) {
+    const float4* src = reinterpret_cast<const float4*>(T + (size_t)(2 * l + h) * M);
 #pragma unroll
-    for (int j = 0; j < M / 2; ++j) {
-        const int m = 2 * j + h;
-        const double c = p[3 * m] * sth + p[3 * m + 1] * cth;   // cycles, phi = 90 deg
-        const double r = c - rint(c);
-        float s, co;
-        sincospif((float)(2.0 * r), &s, &co);
-        st[j] = co;            // inner index 2j+h < M      : Re a_m
-        st[j + M / 2] = s;     // inner index M+2j+h >= M   : Im a_m
+    for (int v = 0; v < M / 4; ++v) {
+        const float4 x = src[v];
+        st[4 * v] = x.x; st[4 * v + 1] = x.y; st[4 * v + 2] = x.z; st[4 * v + 3] = x.w;
     }
 }
 
@@ -49,7 +62,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
                                                        const GroupDev* __restrict__ groups,
                                                        const FrameDev* __restrict__ frames,
                                                        const int32_t* __restrict__ blkframe,
-                                                       const double* __restrict__ pos,
+                                                       const float* __restrict__ steer,
                                                        char* __restrict__ ws,
                                                        float* __restrict__ spec, int use_user,
                                                        float lowq_tau) {
@@ -62,10 +75,10 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 
     float st0[M], st1[M];
     {
-        const double* p = pos + g.pos_off;
+        const float* T = steer + g.steer_off;
         const int j = lane & 31;
-        steering_regs<M>(p, grid_angle(g.grid_start, g.grid_step, base + j), h, st0);
-        steering_regs<M>(p, grid_angle(g.grid_start, g.grid_step, base + 32 + j), h, st1);
+        steering_load<M>(T, base + j, h, st0);
+        steering_load<M>(T, base + 32 + j, h, st1);
     }
 
     const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
@@ -79,18 +92,15 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         const float v = (lane < 32) ? t0 : t1;
         const int l = base + lane;          // col tile lane/32, angle lane%32
         const FrameDev& fd = frames[f];
-        if (l < g.L) {
+        const bool in = l < g.L;
+        if (in) {
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
-            // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
-            // re-evaluation (entries beyond the capacity are only counted)
-            const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
-            if (v < thr) {
-                int* cnt = reinterpret_cast<int*>(ws + fd.ws_lowq);
-                const int slot = atomicAdd(cnt, 1);
-                if (slot < fd.lowq_cap) cnt[1 + slot] = l;
-            }
         }
+        // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
+        // re-evaluation
+        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
+        lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fd.ws_lowq), fd.lowq_cap);
     };
 
     float b[M];
@@ -142,24 +152,33 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 
 template <int M>
 hipError_t launch_m(const ScanItem* items, int n_items, const GroupDev* groups,
-                    const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                    const FrameDev* frames, const int32_t* blkframe, const float* steer,
                     char* ws, float* spec, int use_user, float tau, hipStream_t s) {
     hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
-                       blkframe, pos, ws, spec, use_user, tau);
+                       blkframe, steer, ws, spec, use_user, tau);
     return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
+                              hipStream_t s) {
+    const int Lpad = steer_table_rows(L);
+    const int64_t n = (int64_t)Lpad * M;
+    hipLaunchKernelGGL(steer_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, M, start, step,
+                       L, Lpad, table);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
-                           const FrameDev* frames, const int32_t* blkframe, const double* pos,
+                           const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user, float tau, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (M) {
-        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
+        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -89,16 +89,15 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
         const float v = (lane < 32) ? t0 : t1;
         const int l = base + lane;
         const FrameDev& fd = frames[f];
-        if (l < g.L) {
+        const bool in = l < g.L;
+        if (in) {
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
-            const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
-            if (v < thr) {
-                int* cnt = reinterpret_cast<int*>(ws + fd.ws_lowq);
-                const int slot = atomicAdd(cnt, 1);
-                if (slot < fd.lowq_cap) cnt[1 + slot] = l;
-            }
         }
+        // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
+        // re-evaluation
+        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
+        lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fd.ws_lowq), fd.lowq_cap);
     };
 
     V b[S];
