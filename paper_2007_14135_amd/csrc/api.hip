@@ -78,6 +78,7 @@ struct nssdoa_batch_s {
     std::vector<CovItem> cov_items;
     std::vector<ScanItem> scan_items;           // sorted by group M
     std::vector<std::pair<int, std::pair<int, int>>> scan_ranges;   // M -> [begin, end)
+    std::vector<int> scan_max_tiles;                                // per range: largest t1 - t0
     std::vector<PointItem> point_items;
     std::vector<int32_t> blk;
     std::vector<double> pos;
@@ -355,10 +356,13 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         // rows of stacked B per scan work item: the 16-bit scans form their steering operands
         // per work item at a cost comparable to 64 tiles of their MFMA work, so they take
         // longer chunks
-        const int chunk_rows = plan->opt.scan_rows > 0 ? plan->opt.scan_rows : lp ? kChunkRowsLP : kChunkRows;
+        const int chunk_rows_req = plan->opt.scan_rows > 0 ? plan->opt.scan_rows : lp ? kChunkRowsLP : kChunkRows;
         const size_t emb_elem = lp ? 2 : sizeof(float);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             GroupDev& gd = b->groups[g];
+            // the FP32 scan stages a work item's rows in LDS (8M bytes per row)
+            const int chunk_rows = lp ? chunk_rows_req
+                                      : std::min(chunk_rows_req, (int)(kScanLdsBytes / (8 * gd.M)) / 32 * 32);
             int row = 0, chunk_start = 0, chunk_frames = 0;
             std::vector<std::pair<int, int>> chunks;
             int last_f = -1;
@@ -407,6 +411,9 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             size_t j = i;
             while (j < b->scan_items.size() && b->groups[b->scan_items[j].group].M == M) ++j;
             b->scan_ranges.push_back({M, {(int)i, (int)j}});
+            int mt = 0;
+            for (size_t k = i; k < j; ++k) mt = std::max(mt, b->scan_items[k].t1 - b->scan_items[k].t0);
+            b->scan_max_tiles.push_back(mt);
             i = j;
         }
     } else {
@@ -790,6 +797,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         for (auto& r : batch->scan_ranges) {
             if (batch->prec == NSSDOA_C64)
                 e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
+                                    batch->scan_max_tiles[&r - &batch->scan_ranges[0]],
                                     batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,
                                     static_cast<float*>(spec), use_user, (float)opt.lowq_tau, s);
             else

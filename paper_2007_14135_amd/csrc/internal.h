@@ -414,7 +414,8 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
                       hipStream_t s);
 hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
                               hipStream_t s);
-hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
+constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
+hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user_spec, float lowq_tau,
                            hipStream_t s);

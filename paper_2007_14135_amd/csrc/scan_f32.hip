@@ -16,7 +16,8 @@
 //   sum of squares of registers 4g..4g+3 is the half of 8-row block g held by this lane; the
 //   other half is in lane j + 32(1-h) and is added once per frame at the write.
 // Each wave owns 64 angles (two 32-angle column tiles sharing every A operand); a workgroup of
-// four waves owns 256 angles and one chunk of whole frames.  Steering values come from the
+// four waves owns 256 angles and one chunk of whole frames, whose B tiles it stages in LDS once
+// (all four waves read every tile).  Steering values come from the
 // group's table (built once per batch by steer_table_kernel: the phase in cycles formed and
 // reduced to [-1/2, 1/2] in FP64, then FP32 sincospi), loaded once per work item.
 #include <float.h>
@@ -81,7 +82,15 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         steering_load<M>(T, base + 32 + j, h, st1);
     }
 
-    const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
+    // the work item's B tiles, staged once in LDS for the four waves (they share every row)
+    extern __shared__ float4 embs[];
+    constexpr int kTile4 = 64 * M / 4;                       // float4 per 32-row tile
+    {
+        const float4* src = reinterpret_cast<const float4*>(ws + g.ws_emb) + (size_t)it.t0 * kTile4;
+        const int n4 = (it.t1 - it.t0) * kTile4;
+        for (int i = threadIdx.x; i < n4; i += blockDim.x) embs[i] = src[i];
+    }
+    __syncthreads();
     const int4* blk4 = reinterpret_cast<const int4*>(blkframe + g.blk_off);
     float q0 = 0.0f, q1 = 0.0f;
     int cur = -1;
@@ -103,24 +112,13 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fd.ws_lowq), fd.lowq_cap);
     };
 
-    float b[M];
-    if (it.t0 < it.t1) {
-        const float4* src = reinterpret_cast<const float4*>(emb + (size_t)it.t0 * 64 * M);
+    for (int t = it.t0; t < it.t1; ++t) {
+        float b[M];
+        const float4* src = embs + (t - it.t0) * kTile4 + lane * (M / 4);
 #pragma unroll
         for (int v = 0; v < M / 4; ++v) {
             const float4 x = src[v];
             b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
-        }
-    }
-    for (int t = it.t0; t < it.t1; ++t) {
-        float bn[M];
-        if (t + 1 < it.t1) {
-            const float4* src = reinterpret_cast<const float4*>(emb + (size_t)(t + 1) * 64 * M);
-#pragma unroll
-            for (int v = 0; v < M / 4; ++v) {
-                const float4 x = src[v];
-                bn[4 * v] = x.x; bn[4 * v + 1] = x.y; bn[4 * v + 2] = x.z; bn[4 * v + 3] = x.w;
-            }
         }
         floatx16 a0 = {0.0f}, a1 = {0.0f};
 #pragma unroll
@@ -144,17 +142,16 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
             q1 += a1[4 * gq] * a1[4 * gq] + a1[4 * gq + 1] * a1[4 * gq + 1] +
                   a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
         }
-#pragma unroll
-        for (int s = 0; s < M; ++s) b[s] = bn[s];
     }
     if (cur >= 0) flush(cur);
 }
 
 template <int M>
-hipError_t launch_m(const ScanItem* items, int n_items, const GroupDev* groups,
+hipError_t launch_m(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                     const FrameDev* frames, const int32_t* blkframe, const float* steer,
                     char* ws, float* spec, int use_user, float tau, hipStream_t s) {
-    hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
+    const size_t lds = (size_t)max_tiles * 64 * M * sizeof(float);
+    hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), lds, s, items, groups, frames,
                        blkframe, steer, ws, spec, use_user, tau);
     return hipGetLastError();
 }
@@ -170,15 +167,16 @@ hipError_t launch_steer_table(const double* pos, int M, double start, double ste
     return hipGetLastError();
 }
 
-hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, const GroupDev* groups,
+hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user, float tau, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if ((size_t)max_tiles * 64 * M * sizeof(float) > kScanLdsBytes) return hipErrorInvalidValue;
     switch (M) {
-        case 8: return launch_m<8>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 16: return launch_m<16>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 32: return launch_m<32>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 64: return launch_m<64>(items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 8: return launch_m<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 16: return launch_m<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 32: return launch_m<32>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 64: return launch_m<64>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
         default: return hipErrorInvalidValue;
     }
 }
