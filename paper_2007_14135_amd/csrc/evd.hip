@@ -4,7 +4,8 @@
 // One workgroup per frame.  The workgroup first adds the frame's partial covariances in chunk
 // order and divides by N (Eq. 3), then diagonalises R in LDS with complex Jacobi rotations in
 // round-robin order: M/2 disjoint pivot pairs per step, M-1 steps per sweep, so every step is
-// one fully parallel two-sided update of the 2x2 blocks of A and one update of V.  A rotation
+// one fully parallel two-sided update of the 2x2 blocks of A and one update of V; each wave
+// computes the step's M/2 rotations once into LDS and its tasks read them there.  A rotation
 // for pivot (p, q) first removes the phase of r_pq with diag(1, exp(-j arg r_pq)) and then
 // applies the real rotation [[c, s], [-s, c]] with t = sgn(theta) / (|theta| + sqrt(theta^2+1)),
 // theta = (r_qq - r_pp) / (2 |r_pq|).  Sweeps stop when every |r_pq| <= tol * sqrt(r_pp r_qq),
@@ -113,6 +114,23 @@ __device__ __forceinline__ Rot rotation(const double2* __restrict__ A, int ld, i
     return r;
 }
 
+// A step's rotation as stored in LDS: one copy per wave, written by lanes 0..np-1.
+struct RotL {
+    double c, s, t, ex, ey;
+    int32_t p, q;
+};
+
+__device__ __forceinline__ Rot load_rot(const RotL& x) {
+    Rot r;
+    r.p = x.p;
+    r.q = x.q;
+    r.c = x.c;
+    r.s = x.s;
+    r.t = x.t;
+    r.e = make_double2(x.ex, x.ey);
+    return r;
+}
+
 constexpr int kMaxTasksPerThread = 3;
 constexpr int kMaxPairChecks = 2;   // off-diagonal pairs checked per thread and sweep
 
@@ -135,6 +153,7 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
     double2* A = lds;
     double2* V = lds + Mp * ld;
     double2* A2 = DB ? lds + 2 * Mp * ld : lds;   // second copy of A when double buffered
+    RotL* rotw = reinterpret_cast<RotL*>(lds + (DB ? 3 : 2) * Mp * ld) + (threadIdx.x >> 6) * np;
 
     if (tid == 0) {
         bad = 0;
@@ -247,9 +266,25 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
             }
             if (sweep == prm.max_sweeps) break;
             for (int step = 0; step < Mp - 1; ++step) {
-                // Each task derives the rotations it needs from the current A, reads its block and
-                // computes the new values.  Double buffered: written at once to the other copy.
-                // In place: kept in registers until every thread has read, then written.
+                // The step's np rotations from the current A, one copy per wave (no block-wide
+                // barrier: each wave reads only its own copy).
+                if ((tid & 63) < np) {
+                    const Rot r = rotation(A, ld, M, Mp, step, tid & 63, tol2, floor2);
+                    RotL& o = rotw[tid & 63];
+                    o.c = r.c;
+                    o.s = r.s;
+                    o.t = r.t;
+                    o.ex = r.e.x;
+                    o.ey = r.e.y;
+                    o.p = r.p;
+                    o.q = r.q;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // Each task reads the rotations it needs, reads its block and computes the new
+                // values.  Double buffered: written at once to the other copy.  In place: kept in
+                // registers until every thread has read, then written.
                 double2 keep[kMaxTasksPerThread][4];
                 int kp[kMaxTasksPerThread][4];
 #pragma unroll
@@ -257,8 +292,8 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
                     const int task = tid + u * bd;
                     if (task < nA) {
                         const int k = tk[u], l = tl[u];
-                        const Rot r1 = rotation(A, ld, M, Mp, step, k, tol2, floor2);
-                        const Rot r2 = (l == k) ? r1 : rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        const Rot r1 = load_rot(rotw[k]);
+                        const Rot r2 = (l == k) ? r1 : load_rot(rotw[l]);
                         const double2 b11 = A[r1.p * ld + r2.p], b12 = A[r1.p * ld + r2.q];
                         const double2 b21 = A[r1.q * ld + r2.p], b22 = A[r1.q * ld + r2.q];
                         double2 o11, o12, o21, o22;
@@ -299,7 +334,7 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
                     } else if (task < nT) {
                         // V <- V J_l on row i: no other task touches these two entries this step
                         const int i = tk[u], l = tl[u];
-                        const Rot r = rotation(A, ld, M, Mp, step, l, tol2, floor2);
+                        const Rot r = load_rot(rotw[l]);
                         const double2 v1 = V[i * ld + r.p], v2 = V[i * ld + r.q];
                         V[i * ld + r.p] = csub(cscale(r.c, v1), cmul(v2, cscale(r.s, r.e)));
                         V[i * ld + r.q] = cadd(cscale(r.s, v1), cmul(v2, cscale(r.c, r.e)));
@@ -436,7 +471,8 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
     const int threads = std::min(db ? 256 : 1024, std::max(64, (tasks + 63) / 64 * 64));
     if (tasks > threads * kMaxTasksPerThread) return hipErrorInvalidValue;
     if (max_M * (max_M - 1) / 2 > threads * kMaxPairChecks) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(db ? 3 : 2) * Mp * (Mp + 1) * sizeof(double2);
+    const size_t lds = (size_t)(db ? 3 : 2) * Mp * (Mp + 1) * sizeof(double2) +
+                       (size_t)(threads / 64) * (Mp / 2) * sizeof(RotL);
     const void* fn = db ? (const void*)evd_kernel<true> : (const void*)evd_kernel<false>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
