@@ -224,10 +224,11 @@ nssdoa_status nssdoa_graph_create(nssdoa_graph* graph, nssdoa_batch batch, const
 nssdoa_status nssdoa_graph_launch(nssdoa_graph graph, void* stream);
 nssdoa_status nssdoa_graph_destroy(nssdoa_graph graph);
 
-/* Per-stage device timing.  While enabled, nssdoa_estimate records HIP events around each stage
- * on its stream; nssdoa_stage_time waits for them and returns the summed milliseconds and the
- * number of launches of `stage` since timing was (re)enabled. */
-nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable);
+/* Per-stage device timing.  stage_mask selects stages (bit 1 << NSSDOA_STAGE_*; 0 = off, -1 =
+ * all); while set, nssdoa_estimate records HIP events around those stages on its stream (each
+ * pair costs a few microseconds of stream time).  nssdoa_stage_time waits for them and returns
+ * the summed milliseconds and the number of launches of `stage` since timing was (re)set. */
+nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t stage_mask);
 nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* total_ms,
                                 int64_t* launches);
 

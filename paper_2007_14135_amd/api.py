@@ -165,8 +165,15 @@ class Batch:
         """Capture one nssdoa_estimate on these buffers into a replayable graph."""
         return Graph(self, X, spectrum, peaks, npeaks, status, workspace)
 
-    def set_timing(self, enable: bool) -> None:
-        _abi.check(_abi.load().nssdoa_set_timing(self.handle, 1 if enable else 0), "nssdoa_set_timing")
+    def set_timing(self, enable) -> None:
+        """True: time every stage; False: off; a list of stage names: only those."""
+        if isinstance(enable, (list, tuple, set)):
+            mask = 0
+            for name in enable:
+                mask |= 1 << _abi.STAGES[name]
+        else:
+            mask = -1 if enable else 0
+        _abi.check(_abi.load().nssdoa_set_timing(self.handle, mask), "nssdoa_set_timing")
 
     def stage_time(self, stage: str):
         ms = ctypes.c_double()

@@ -107,7 +107,7 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
         X_dev = db.X
         db.run()
         torch.cuda.synchronize()
-        db.batch.set_timing(True)
+        db.batch.set_timing(["scan"])
         for _ in range(reps):
             db.run()
         ms, n = db.batch.stage_time("scan")

@@ -108,7 +108,7 @@ struct nssdoa_batch_s {
     float* d_steer = nullptr;                   // steering tables of the FP32 scans (batch-owned)
     int live_graphs = 0;
     // timing
-    bool timing = false;
+    uint32_t timing = 0;                        // stages with HIP events (bit 1 << stage)
     std::vector<StageEvents> pending;
     double stage_ms[NSSDOA_STAGE_COUNT] = {0, 0, 0, 0};
     int64_t stage_n[NSSDOA_STAGE_COUNT] = {0, 0, 0, 0};
@@ -550,7 +550,7 @@ nssdoa_status nssdoa_workspace_offset(nssdoa_batch batch, nssdoa_ws_item item, i
     return NSSDOA_OK;
 }
 
-nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable) {
+nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t stage_mask) {
     if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
     for (auto& e : batch->pending) {
         (void)hipEventDestroy(e.a);
@@ -561,7 +561,7 @@ nssdoa_status nssdoa_set_timing(nssdoa_batch batch, int32_t enable) {
         batch->stage_ms[s] = 0.0;
         batch->stage_n[s] = 0;
     }
-    batch->timing = enable != 0;
+    batch->timing = (uint32_t)stage_mask & ((1u << NSSDOA_STAGE_COUNT) - 1u);
     return NSSDOA_OK;
 }
 
@@ -700,15 +700,15 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     const nssdoa_options& opt = batch->plan->opt;
 
     hipEvent_t ev0 = nullptr;
-    const bool timing = batch->timing && !capturing;
-    auto stage_begin = [&]() -> nssdoa_status {
-        if (!timing) return NSSDOA_OK;
+    const uint32_t timing = capturing ? 0u : batch->timing;
+    auto stage_begin = [&](int stage) -> nssdoa_status {
+        if (!(timing & (1u << stage))) return NSSDOA_OK;
         hipError_t e = hipEventCreate(&ev0);
         if (e == hipSuccess) e = hipEventRecord(ev0, s);
         return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "hipEventRecord");
     };
     auto stage_end = [&](int stage) -> nssdoa_status {
-        if (!timing) return NSSDOA_OK;
+        if (!(timing & (1u << stage))) return NSSDOA_OK;
         hipEvent_t ev1;
         hipError_t e = hipEventCreate(&ev1);
         if (e == hipSuccess) e = hipEventRecord(ev1, s);
@@ -719,12 +719,12 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     nssdoa_status st;
     hipError_t e;
 
-    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    if ((st = stage_begin(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
     e = launch_cov(c128, batch->max_M, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, s);
     if (e != hipSuccess) return hip_fail(e, "covariance launch");
     if ((st = stage_end(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
 
-    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    if ((st = stage_begin(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
     EvdParams ep;
     ep.tol = opt.jacobi_tol;
     ep.max_sweeps = opt.max_sweeps;
@@ -750,7 +750,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
 
     if (wa) {
         const int F = batch->n_frames, M = batch->frames[0].M;
-        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        if ((st = stage_begin(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
         const float* scores = wa->scores;
         if (wa->mlp) {
             float* feats = reinterpret_cast<float*>(ws + lay.off_feat);
@@ -765,13 +765,13 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if (e != hipSuccess) return hip_fail(e, "proposal launch");
         if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
 
-        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        if ((st = stage_begin(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
         e = launch_scan_windows(M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
                                 static_cast<float*>(spec), use_user, (float)opt.lowq_tau, persistent_grid(8), s);
         if (e != hipSuccess) return hip_fail(e, "windowed scan launch");
         if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
 
-        if ((st = stage_begin()) != NSSDOA_OK) return st;
+        if ((st = stage_begin(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;
         const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
         e = launch_window_peaks(bucket, batch->d_frames, F, batch->d_pos, batch->d_cis, ws, lay, opt.extra_candidates,
                                 opt.lowq_tau, pp.plateau_rel, static_cast<float*>(spec), use_user,
@@ -788,7 +788,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         return stage_end(NSSDOA_STAGE_PEAKS);
     }
 
-    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    if ((st = stage_begin(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
     if (c128) {
         e = launch_scan_f64(batch->d_points, (int)batch->point_items.size(), batch->max_M, batch->d_frames,
                             batch->d_pos, batch->d_cis, ws, static_cast<double*>(spec), use_user, s);
@@ -810,7 +810,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     }
     if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
 
-    if ((st = stage_begin()) != NSSDOA_OK) return st;
+    if ((st = stage_begin(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;
     for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
         const auto& r = batch->peak_ranges[i];
         const auto& ri = batch->refine_ranges[i];
