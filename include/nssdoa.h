@@ -69,8 +69,9 @@ typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 
 
 /* Per-frame status bits written to status[] by nssdoa_estimate. */
 #define NSSDOA_ST_NONFINITE_INPUT   0x1u  /* R has a NaN/Inf entry; no peaks, spectrum is NaN      */
-#define NSSDOA_ST_EVD_NOT_CONVERGED 0x2u  /* Jacobi stopped at max_sweeps above tolerance          */
-#define NSSDOA_ST_DEGENERATE        0x4u  /* EV: a noise eigenvalue <= 0; MN: (P_n)_11 <= 1e-300   */
+#define NSSDOA_ST_EVD_NOT_CONVERGED 0x2u  /* eigensolver stopped at eig_max_iter above eig_tol     */
+#define NSSDOA_ST_DEGENERATE        0x4u  /* EV: a noise eigenvalue <= M 2^-52 lambda_1 (zero to
+                                             working precision); MN: (P_n)_11 <= 1e-300            */
 #define NSSDOA_ST_FEWER_PEAKS       0x8u  /* fewer than D local maxima; unused slots idx = -1      */
 #define NSSDOA_ST_PEAK_OVERFLOW     0x10u /* more local maxima than the candidate buffer holds     */
 #define NSSDOA_ST_FALLBACK_USED     0x20u /* windowed estimation scanned the whole grid (best score
@@ -117,10 +118,21 @@ typedef struct {
     double value;         /* P at idx evaluated in FP64, NaN for an unused slot                */
 } nssdoa_peak;
 
+/* Hermitian eigensolver of Step-2 (Table 2).  Both run in FP64 with one workgroup per frame.
+ *   NSSDOA_EIG_QL:     Householder reduction to a real tridiagonal matrix, implicit QL with
+ *                      Wilkinson's shift, back-transformation.  Block splits where
+ *                      |e_i| <= eig_tol * (|d_i| + |d_{i+1}|); at most eig_max_iter QL
+ *                      iterations per eigenvalue.  Eigenvalue errors are of the order of
+ *                      eig_tol * ||R||.  The default.
+ *   NSSDOA_EIG_JACOBI: cyclic complex Jacobi; stops when |r_pq| <= eig_tol * sqrt(r_pp r_qq) for
+ *                      all p < q, at most eig_max_iter sweeps.  Slower, but small eigenvalues
+ *                      are accurate relative to themselves. */
+typedef enum { NSSDOA_EIG_QL = 0, NSSDOA_EIG_JACOBI = 1 } nssdoa_eig_method;
+
 /* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */
 typedef struct {
-    double jacobi_tol;        /* stop when |r_pq| <= tol * sqrt(r_pp r_qq) for all p<q; 1e-15  */
-    int32_t max_sweeps;       /* Jacobi sweep limit, >= 1; 30                                  */
+    double eig_tol;           /* eigensolver tolerance (see nssdoa_eig_method), (0, 1); 1e-15  */
+    int32_t eig_max_iter;     /* QL iterations per eigenvalue / Jacobi sweeps, 1..1000; 30     */
     int32_t refine_halfwidth; /* FP64 re-evaluation window around each candidate peak, 1..16; 4 */
     double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 2e-3 */
     int32_t extra_candidates; /* local maxima kept beyond D for the FP64 re-pick, 0..16; 4     */
@@ -129,6 +141,7 @@ typedef struct {
                                  [32, 16384].  A tuning knob: it moves frames' rows within the
                                  32-row MFMA tiles, so FP32 spectra may change in their last
                                  bits; peaks are re-picked in FP64                              */
+    int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_QL                              */
 } nssdoa_options;
 
 typedef struct nssdoa_plan_s* nssdoa_plan;

@@ -49,9 +49,13 @@ class Peak(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+    _fields_ = [("eig_tol", ctypes.c_double), ("eig_max_iter", ctypes.c_int32),
                 ("refine_halfwidth", ctypes.c_int32), ("lowq_tau", ctypes.c_double),
-                ("extra_candidates", ctypes.c_int32), ("scan_rows", ctypes.c_int32)]
+                ("extra_candidates", ctypes.c_int32), ("scan_rows", ctypes.c_int32),
+                ("eig_method", ctypes.c_int32)]
+
+
+EIG_METHODS = {"ql": 0, "jacobi": 1}
 
 
 PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8")])

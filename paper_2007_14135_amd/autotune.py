@@ -102,7 +102,8 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
             opt = Options(scan_rows=int(rows))
         else:
             c = options.c
-            opt = Options(c.jacobi_tol, c.max_sweeps, c.refine_halfwidth, c.lowq_tau, c.extra_candidates, int(rows))
+            opt = Options(c.eig_tol, c.eig_max_iter, c.refine_halfwidth, c.lowq_tau, c.extra_candidates, int(rows),
+                          c.eig_method)
         db = prepare(arrays, grids, frames, X_flat, alg, prec, max_D, with_spectrum=False, options=opt, X_device=X_dev)
         X_dev = db.X
         db.run()

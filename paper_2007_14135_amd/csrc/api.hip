@@ -138,18 +138,21 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     if (!arrays || n_arrays < 1) return fail(NSSDOA_EINVAL, "need at least one array");
     if (!grids || n_grids < 1) return fail(NSSDOA_EINVAL, "need at least one grid");
     nssdoa_options opt;
-    opt.jacobi_tol = 1e-15;
-    opt.max_sweeps = 30;
+    opt.eig_tol = 1e-15;
+    opt.eig_max_iter = 30;
     opt.refine_halfwidth = 4;
     opt.lowq_tau = 2e-3;
     opt.extra_candidates = 4;
     opt.scan_rows = 0;
+    opt.eig_method = NSSDOA_EIG_QL;
     if (options) {
         opt = *options;
-        if (!(opt.jacobi_tol > 0.0 && opt.jacobi_tol < 1.0))
-            return fail(NSSDOA_EINVAL, "jacobi_tol must be in (0, 1)");
-        if (opt.max_sweeps < 1 || opt.max_sweeps > 1000)
-            return fail(NSSDOA_EINVAL, "max_sweeps must be in [1, 1000]");
+        if (!(opt.eig_tol > 0.0 && opt.eig_tol < 1.0))
+            return fail(NSSDOA_EINVAL, "eig_tol must be in (0, 1)");
+        if (opt.eig_max_iter < 1 || opt.eig_max_iter > 1000)
+            return fail(NSSDOA_EINVAL, "eig_max_iter must be in [1, 1000]");
+        if (opt.eig_method != NSSDOA_EIG_QL && opt.eig_method != NSSDOA_EIG_JACOBI)
+            return fail(NSSDOA_EINVAL, "eig_method must be NSSDOA_EIG_QL or NSSDOA_EIG_JACOBI");
         if (opt.refine_halfwidth < 1 || opt.refine_halfwidth > 16)
             return fail(NSSDOA_EINVAL, "refine_halfwidth must be in [1, 16]");
         if (!(opt.lowq_tau >= 0.0) || !isfinite(opt.lowq_tau))
@@ -726,8 +729,9 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
 
     if ((st = stage_begin(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
     EvdParams ep;
-    ep.tol = opt.jacobi_tol;
-    ep.max_sweeps = opt.max_sweeps;
+    ep.tol = opt.eig_tol;
+    ep.max_iter = opt.eig_max_iter;
+    ep.method = opt.eig_method;
     ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? 1 : batch->prec == NSSDOA_BF16 ? 2 : 3;
     for (auto& r : batch->peak_ranges) {
         e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,

@@ -1,17 +1,31 @@
-// Steps 2-4 (Table 2 Step-2, Table 3): FP64 Hermitian eigendecomposition by cyclic Jacobi and
-// the noise-subspace matrix B with C = B B^H.
+// Steps 2-4 (Table 2 Step-2, Table 3): FP64 Hermitian eigendecomposition of R and the
+// noise-subspace matrix B with C = B B^H.
 //
 // One workgroup per frame.  The workgroup first adds the frame's partial covariances in chunk
-// order and divides by N (Eq. 3), then diagonalises R in LDS with complex Jacobi rotations in
-// round-robin order: M/2 disjoint pivot pairs per step, M-1 steps per sweep, so every step is
-// one fully parallel two-sided update of the 2x2 blocks of A and one update of V; each wave
-// computes the step's M/2 rotations once into LDS and its tasks read them there.  A rotation
-// for pivot (p, q) first removes the phase of r_pq with diag(1, exp(-j arg r_pq)) and then
-// applies the real rotation [[c, s], [-s, c]] with t = sgn(theta) / (|theta| + sqrt(theta^2+1)),
-// theta = (r_qq - r_pp) / (2 |r_pq|).  Sweeps stop when every |r_pq| <= tol * sqrt(r_pp r_qq),
-// the relative criterion that keeps small (noise) eigenvalues accurate.  Eigenvalues are then
-// ranked in descending order and B is built for the requested method, in FP64 and (for the FP32
-// scan) as the packed real-embedded FP32 operand tiles of the scan kernel.
+// order and divides by N (Eq. 3).  Two eigensolvers:
+//
+// * Householder + implicit QL (default).  R is reduced to a real symmetric tridiagonal matrix
+//   T = Q^H R Q with Q = H_0 H_1 ... H_{M-2}, H_k = I - tau_k v_k v_k^H chosen so that H_k^H maps
+//   the part of column k below the diagonal onto a real multiple of its first unit vector (the
+//   two-sided update of the trailing block is the rank-2 form A -= v w^H + w v^H,
+//   w = tau A v - |tau|^2 (v^H A v) / 2 v).  T is diagonalised by implicit QL sweeps with
+//   Wilkinson's shift (a bulge chased from the bottom of the unreduced block to its top with
+//   Givens rotations, the rotations accumulated into Z; the block splits where
+//   |e_i| <= tol (|d_i| + |d_{i+1}|)), one wave running the sequential rotation chain while each
+//   lane updates one row of Z.  The eigenvectors are V = Q Z, applied reflector by reflector to
+//   the columns of Z.  About 3 M^2 / 2 dependent rotations per frame, against 8-10 Jacobi sweeps
+//   of M - 1 dependent steps that each need a workgroup barrier.
+// * Cyclic Jacobi.  Complex Jacobi rotations in round-robin order: M/2 disjoint pivot pairs per
+//   step, M-1 steps per sweep, so every step is one fully parallel two-sided update of the 2x2
+//   blocks of A and one update of V; each wave computes the step's M/2 rotations once into LDS
+//   and its tasks read them there.  A rotation for pivot (p, q) first removes the phase of r_pq
+//   with diag(1, exp(-j arg r_pq)) and then applies the real rotation [[c, s], [-s, c]] with
+//   t = sgn(theta) / (|theta| + sqrt(theta^2+1)), theta = (r_qq - r_pp) / (2 |r_pq|).  Sweeps
+//   stop when every |r_pq| <= tol * sqrt(r_pp r_qq), a relative criterion that also keeps
+//   eigenvalues far below ||R|| accurate to working precision relative to themselves.
+//
+// Eigenvalues are then ranked in descending order and B is built for the requested method, in
+// FP64 and (for the matrix-core scans) as the packed real-embedded operand tiles of the scan.
 #include <float.h>
 
 #include <algorithm>
@@ -22,7 +36,6 @@
 namespace nssdoa {
 namespace {
 
-constexpr int kMaxPairs = 32;
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -66,6 +79,60 @@ __device__ __forceinline__ double rcp64(double x) {
     double r = __builtin_amdgcn_rcp(x);
     r = fma(r, fma(-x, r, 1.0), r);
     r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// rsqrt to working precision in one step: from the hardware estimate r0 (relative error near
+// 2^-24), h = 1 - x r0^2 and r = r0 (1 + h/2 + 3h^2/8), which leaves an O(h^3) error.
+__device__ __forceinline__ double rsq_full(double x) {
+    const double r0 = __builtin_amdgcn_rsq(x);
+    const double h = fma(-(x * r0), r0, 1.0);
+    return fma(r0 * h, fma(h, 0.375, 0.5), r0);
+}
+// reciprocal to about 2^-48 (one Newton step), enough for a QL shift
+__device__ __forceinline__ double rcp_approx(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Cross-lane moves of doubles (two 32-bit DPP moves or lane reads).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowMirror = 0x140;     // lane i <- lane 15 - i within each row of 16
+constexpr int kDppRowHalfMirror = 0x141; // lane i <- lane 7 - i within each half row
+
+// Sum over each aligned group of four lanes, in all four (the group must be active).
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_f64<kDppQuadXor1>(v);
+    return v + dpp_f64<kDppQuadXor2>(v);
+}
+// Sum over the 64 lanes of a fully active wave; every lane gets the same value.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_f64<kDppRowHalfMirror>(v);
+    v += dpp_f64<kDppRowMirror>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+// Block-wide sum of fully active waves: wave sums, then (with several waves) one LDS pass.
+__device__ inline double block_sum_fast(double v, double* red) {
+    v = wave_sum(v);
+    const int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return v;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < nw; ++w) r += red[w];
+    __syncthreads();
     return r;
 }
 
@@ -134,6 +201,161 @@ __device__ __forceinline__ Rot load_rot(const RotL& x) {
 constexpr int kMaxTasksPerThread = 3;
 constexpr int kMaxPairChecks = 2;   // off-diagonal pairs checked per thread and sweep
 
+// Step-1 completion: R = (sum of chunk partials, in chunk order) / N, Hermitian by construction,
+// into A (row stride ld, padded to Mp x Mp with zeros) and the workspace; `bad` is set when R is
+// not finite.
+__device__ void load_covariance(const FrameDev& fr, char* __restrict__ ws, double2* __restrict__ A, int ld,
+                                int Mp, int* bad) {
+    const int M = fr.M, tid = threadIdx.x, bd = blockDim.x;
+    const double2* part = reinterpret_cast<const double2*>(ws + fr.ws_partial);
+    double2* Rout = reinterpret_cast<double2*>(ws + fr.ws_R);
+    const double dN = (double)fr.N;
+    const int nch = fr.n_chunks;
+    for (int e = tid; e < Mp * Mp; e += bd) {
+        const int i = e / Mp, j = e - i * Mp;
+        if (i < M && j < M) {
+            if (i <= j) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int c0 = 0; c0 < nch; c0 += 8) {
+                    double2 v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        v[u] = (c0 + u < nch) ? part[(size_t)(c0 + u) * M * M + i * M + j] : make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        s.x += v[u].x;
+                        s.y += v[u].y;
+                    }
+                }
+                s.x = s.x / dN;
+                s.y = (i == j) ? 0.0 : s.y / dN;
+                if (!isfinite(s.x) || !isfinite(s.y)) *bad = 1;
+                A[i * ld + j] = s;
+                A[j * ld + i] = cconj(s);
+                Rout[i * M + j] = s;
+                Rout[j * M + i] = cconj(s);
+            }
+        } else {
+            A[i * ld + j] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
+// Everything after the eigenpairs: eigenvalue i is lamv[i * lstride] and its eigenvector column
+// i of V (row stride ld).  Ranks the eigenvalues (Table 2 Step-2: descending, ties keep the lower
+// index first), writes them and the eigenvectors, builds B (Table 3 Step-3/4) in Bs (LDS, M x K
+// column-major, which must not overlap V; lamv is read before B is written), ||B||_F^2, the embedded operand tiles of the
+// scan, and the frame status.  With bad set the outputs are NaN and B is zero.
+__device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm, const GroupDev* __restrict__ groups,
+                             char* __restrict__ ws, uint32_t* __restrict__ status, const double* lamv, int lstride,
+                             const double2* V, int ld, double2* Bs, int bad, uint32_t st, int* perm, double* lam,
+                             double* red) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int M = fr.M, K = fr.K;
+    double* evals = reinterpret_cast<double*>(ws + fr.ws_evals);
+    double2* evecs = reinterpret_cast<double2*>(ws + fr.ws_evecs);
+    double2* Bout = reinterpret_cast<double2*>(ws + fr.ws_B);
+    double* qref = reinterpret_cast<double*>(ws + fr.ws_qref);
+    if (bad) {
+        st |= NSSDOA_ST_NONFINITE_INPUT;
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        for (int e = tid; e < M; e += bd) evals[e] = nan;
+        for (int e = tid; e < M * M; e += bd) evecs[e] = make_double2(nan, nan);
+        for (int e = tid; e < M * K; e += bd) Bs[e] = make_double2(0.0, 0.0);
+        if (tid == 0) *qref = nan;
+    } else {
+        if (tid < M) {
+            const double li = lamv[tid * lstride];
+            int r = 0;
+            for (int j = 0; j < M; ++j) {
+                const double lj = lamv[j * lstride];
+                r += (lj > li) || (lj == li && j < tid);
+            }
+            perm[r] = tid;
+            lam[tid] = li;
+        }
+        __syncthreads();
+        for (int e = tid; e < M; e += bd) evals[e] = lam[perm[e]];
+        for (int e = tid; e < M * M; e += bd) {
+            const int i = e / M, r = e - i * M;
+            evecs[e] = V[i * ld + perm[r]];
+        }
+        if (fr.alg == kMUSIC || fr.alg == kEV) {
+            for (int e = tid; e < M * K; e += bd) {
+                const int k = e / M, m = e - k * M;
+                double2 v = V[m * ld + perm[fr.D + k]];
+                if (fr.alg == kEV) {
+                    const double l = lam[perm[fr.D + k]];
+                    v = cscale(l > 0.0 ? 1.0 / sqrt(l) : 0.0, v);
+                }
+                Bs[e] = v;
+            }
+            // EV weights 1/sqrt(lambda): a noise eigenvalue at the rounding level of ||R|| (below
+            // M 2^-52 lambda_1) is zero to working precision
+            if (fr.alg == kEV && lam[perm[M - 1]] <= (double)M * 0x1p-52 * fmax(lam[perm[0]], 0.0))
+                st |= NSSDOA_ST_DEGENERATE;
+        } else if (fr.alg == kPHD) {
+            for (int m = tid; m < M; m += bd) Bs[m] = V[m * ld + perm[M - 1]];
+        } else {   // MN: d = P_n e_1 / (P_n)_11 with P_n = E_n E_n^H
+            double pn11 = 0.0;
+            for (int k = fr.D; k < M; ++k) {
+                const double2 u0 = V[0 * ld + perm[k]];
+                pn11 += u0.x * u0.x + u0.y * u0.y;
+            }
+            const bool degen = !(pn11 > 1e-300);
+            if (degen) st |= NSSDOA_ST_DEGENERATE;
+            for (int m = tid; m < M; m += bd) {
+                double2 d = make_double2(0.0, 0.0);
+                for (int k = fr.D; k < M; ++k) {
+                    const double2 u0 = V[0 * ld + perm[k]];
+                    d = cadd(d, cmul(V[m * ld + perm[k]], cconj(u0)));
+                }
+                Bs[m] = degen ? make_double2(0.0, 0.0) : cscale(1.0 / pn11, d);
+            }
+        }
+        __syncthreads();
+        double q = 0.0;
+        for (int e = tid; e < M * K; e += bd) q += Bs[e].x * Bs[e].x + Bs[e].y * Bs[e].y;
+        q = block_sum(q, red);
+        if (tid == 0) *qref = q;
+    }
+    __syncthreads();
+    for (int e = tid; e < M * K; e += bd) Bout[e] = Bs[e];
+
+    if (prm.write_emb) {
+        // Real embedding of B for the scan: column k gives two rows over the inner index
+        // kk in [0, 2M):  re-row (Re b, Im b) and im-row (-Im b, Re b), so that the row dot the
+        // embedded steering (Re a, Im a) is Re(b^H a) and Im(b^H a).  Rows are packed per 32-row
+        // tile as [64 lanes][M values], in the operand order of the scan's MFMA:
+        //   FP32 (32x32x2):        lane h*32+i holds inner kk = 2s + h of row i at position s;
+        //   BF16/FP16 (32x32x16):  lane h*32+i holds inner kk = 16s + 8h + t at position 8s + t.
+        const GroupDev& g = groups[fr.group];
+        const int rows = fr.emb_rows, inner = 2 * M;
+        for (int e = tid; e < rows * inner; e += bd) {
+            const int rl = e / inner, kk = e - rl * inner;
+            const int col = rl >> 1;
+            float v = 0.0f;
+            if (col < K) {
+                const double2 b = Bs[col * M + (kk < M ? kk : kk - M)];
+                if ((rl & 1) == 0) v = (float)(kk < M ? b.x : b.y);
+                else v = (float)(kk < M ? -b.y : b.x);
+            }
+            const int r = fr.emb_row0 + rl;
+            const int tile = r >> 5, i = r & 31;
+            if (prm.write_emb == 1) {
+                const int h = kk & 1, s2 = kk >> 1;
+                reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * 64 + h * 32 + i) * M + s2] = v;
+            } else {
+                const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
+                const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;
+                if (prm.write_emb == 2) reinterpret_cast<__bf16*>(ws + g.ws_emb)[o] = (__bf16)v;
+                else reinterpret_cast<_Float16*>(ws + g.ws_emb)[o] = (_Float16)v;
+            }
+        }
+    }
+    if (tid == 0) status[fidx] = st;
+}
+
 template <bool DB>
 __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __restrict__ flist,
                                                    const FrameDev* __restrict__ frames, EvdParams prm,
@@ -160,60 +382,15 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
         if (prm.write_emb) *reinterpret_cast<int*>(ws + fr.ws_lowq) = 0;   // low-Q list of the scan
     }
     __syncthreads();
-
-    // Step-1 completion: R = (sum of chunk partials, in chunk order) / N, Hermitian by construction.
-    const double2* part = reinterpret_cast<const double2*>(ws + fr.ws_partial);
-    double2* Rout = reinterpret_cast<double2*>(ws + fr.ws_R);
-    const double dN = (double)fr.N;
-    const int nch = fr.n_chunks;
+    load_covariance(fr, ws, A, ld, Mp, &bad);
     for (int e = tid; e < Mp * Mp; e += bd) {
         const int i = e / Mp, j = e - i * Mp;
         V[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-        if (i < M && j < M) {
-            if (i <= j) {
-                double2 s = make_double2(0.0, 0.0);
-                for (int c0 = 0; c0 < nch; c0 += 8) {
-                    double2 v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        v[u] = (c0 + u < nch) ? part[(size_t)(c0 + u) * M * M + i * M + j] : make_double2(0.0, 0.0);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        s.x += v[u].x;
-                        s.y += v[u].y;
-                    }
-                }
-                s.x = s.x / dN;
-                s.y = (i == j) ? 0.0 : s.y / dN;
-                if (!isfinite(s.x) || !isfinite(s.y)) bad = 1;
-                A[i * ld + j] = s;
-                A[j * ld + i] = cconj(s);
-                Rout[i * M + j] = s;
-                Rout[j * M + i] = cconj(s);
-            }
-        } else {
-            A[i * ld + j] = make_double2(0.0, 0.0);
-        }
     }
     __syncthreads();
 
     uint32_t st = 0;
-    const int K = fr.K;
-    double* evals = reinterpret_cast<double*>(ws + fr.ws_evals);
-    double2* evecs = reinterpret_cast<double2*>(ws + fr.ws_evecs);
-    double2* Bout = reinterpret_cast<double2*>(ws + fr.ws_B);
-    double* qref = reinterpret_cast<double*>(ws + fr.ws_qref);
-    double2* Bs = lds;   // B is staged over the first copy of A once the eigenpairs are read
-
-    if (bad) {
-        st |= NSSDOA_ST_NONFINITE_INPUT;
-        const double nan = __longlong_as_double(0x7ff8000000000000LL);
-        for (int e = tid; e < M; e += bd) evals[e] = nan;
-        for (int e = tid; e < M * M; e += bd) evecs[e] = make_double2(nan, nan);
-        __syncthreads();
-        for (int e = tid; e < M * K; e += bd) Bs[e] = make_double2(0.0, 0.0);
-        if (tid == 0) *qref = nan;
-    } else {
+    if (!bad) {
         const double tol2 = prm.tol * prm.tol;
         // Entries below 1e-2 * tol * trace(R) are rounding noise of a positive semi-definite R:
         // the relative test r_pq^2 <= tol^2 r_pp r_qq is floored there so that exactly singular
@@ -249,7 +426,7 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
             cj[u] = i + 1 + t;
         }
         bool converged = false;
-        for (int sweep = 0; sweep <= prm.max_sweeps; ++sweep) {
+        for (int sweep = 0; sweep <= prm.max_iter; ++sweep) {
             int above = 0;
 #pragma unroll
             for (int v = 0; v < kMaxPairChecks; ++v) {
@@ -264,7 +441,7 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
                 converged = true;
                 break;
             }
-            if (sweep == prm.max_sweeps) break;
+            if (sweep == prm.max_iter) break;
             for (int step = 0; step < Mp - 1; ++step) {
                 // The step's np rotations from the current A, one copy per wave (no block-wide
                 // barrier: each wave reads only its own copy).
@@ -359,102 +536,233 @@ __global__ __launch_bounds__(DB ? 256 : 1024) void evd_kernel(const int32_t* __r
             }
         }
         if (!converged) st |= NSSDOA_ST_EVD_NOT_CONVERGED;
-
-        // Table 2 Step-2 ordering: eigenvalues descending (ties keep the lower index first).
-        if (tid < M) {
-            const double li = A[tid * ld + tid].x;
-            int r = 0;
-            for (int j = 0; j < M; ++j) {
-                const double lj = A[j * ld + j].x;
-                r += (lj > li) || (lj == li && j < tid);
-            }
-            perm[r] = tid;
-        }
-        __syncthreads();
-        for (int e = tid; e < M; e += bd) evals[e] = A[perm[e] * ld + perm[e]].x;
-        for (int e = tid; e < M * M; e += bd) {
-            const int i = e / M, r = e - i * M;
-            evecs[e] = V[i * ld + perm[r]];
-        }
-        // the noise eigenvalues are needed after A is overwritten by B
-        double lam_k = 0.0;
-        if (tid < M) lam_k = A[perm[tid] * ld + perm[tid]].x;
-        __syncthreads();
-        if (tid < M) lam[tid] = lam_k;
-        __syncthreads();
-
-        // Table 3, Step-3/4: B with C = B B^H
-        if (fr.alg == kMUSIC || fr.alg == kEV) {
-            for (int e = tid; e < M * K; e += bd) {
-                const int k = e / M, m = e - k * M;
-                double2 v = V[m * ld + perm[fr.D + k]];
-                if (fr.alg == kEV) {
-                    const double l = lam[fr.D + k];
-                    v = cscale(l > 0.0 ? 1.0 / sqrt(l) : 0.0, v);
-                }
-                Bs[e] = v;
-            }
-            if (fr.alg == kEV && lam[M - 1] <= 0.0) st |= NSSDOA_ST_DEGENERATE;
-        } else if (fr.alg == kPHD) {
-            for (int m = tid; m < M; m += bd) Bs[m] = V[m * ld + perm[M - 1]];
-        } else {   // MN: d = P_n e_1 / (P_n)_11 with P_n = E_n E_n^H
-            double pn11 = 0.0;
-            for (int k = fr.D; k < M; ++k) {
-                const double2 u0 = V[0 * ld + perm[k]];
-                pn11 += u0.x * u0.x + u0.y * u0.y;
-            }
-            const bool degen = !(pn11 > 1e-300);
-            if (degen) st |= NSSDOA_ST_DEGENERATE;
-            for (int m = tid; m < M; m += bd) {
-                double2 d = make_double2(0.0, 0.0);
-                for (int k = fr.D; k < M; ++k) {
-                    const double2 u0 = V[0 * ld + perm[k]];
-                    d = cadd(d, cmul(V[m * ld + perm[k]], cconj(u0)));
-                }
-                Bs[m] = degen ? make_double2(0.0, 0.0) : cscale(1.0 / pn11, d);
-            }
-        }
-        __syncthreads();
-        double q = 0.0;
-        for (int e = tid; e < M * K; e += bd) q += Bs[e].x * Bs[e].x + Bs[e].y * Bs[e].y;
-        q = block_sum(q, red);
-        if (tid == 0) *qref = q;
     }
     __syncthreads();
-    for (int e = tid; e < M * K; e += bd) Bout[e] = Bs[e];
+    // eigenvalue i = A[i][i].x; B is staged over the first copy of A (finish_frame reads the
+    // eigenvalues before it writes B)
+    finish_frame(fr, fidx, prm, groups, ws, status, &A[0].x, 2 * (ld + 1), V, ld, lds, bad, st, perm, lam, red);
+}
 
-    if (prm.write_emb) {
-        // Real embedding of B for the scan: column k gives two rows over the inner index
-        // kk in [0, 2M):  re-row (Re b, Im b) and im-row (-Im b, Re b), so that the row dot the
-        // embedded steering (Re a, Im a) is Re(b^H a) and Im(b^H a).  Rows are packed per 32-row
-        // tile as [64 lanes][M values], in the operand order of the scan's MFMA:
-        //   FP32 (32x32x2):        lane h*32+i holds inner kk = 2s + h of row i at position s;
-        //   BF16/FP16 (32x32x16):  lane h*32+i holds inner kk = 16s + 8h + t at position 8s + t.
-        const GroupDev& g = groups[fr.group];
-        const int rows = fr.emb_rows, inner = 2 * M;
-        for (int e = tid; e < rows * inner; e += bd) {
-            const int rl = e / inner, kk = e - rl * inner;
-            const int col = rl >> 1;
-            float v = 0.0f;
-            if (col < K) {
-                const double2 b = Bs[col * M + (kk < M ? kk : kk - M)];
-                if ((rl & 1) == 0) v = (float)(kk < M ? b.x : b.y);
-                else v = (float)(kk < M ? -b.y : b.x);
+// Householder tridiagonalisation, implicit QL and back-transformation.  LDS: region 0
+// (Mp x ld complex) holds R, then Z (real values in .x), then V = Q Z; region 1 holds v_k in
+// column k, rows k+1..M-1, and later B.
+__global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__ flist,
+                                                     const FrameDev* __restrict__ frames, EvdParams prm,
+                                                     const GroupDev* __restrict__ groups,
+                                                     char* __restrict__ ws,
+                                                     uint32_t* __restrict__ status) {
+    extern __shared__ double2 lds[];
+    __shared__ int perm[64];
+    __shared__ double red[32];
+    __shared__ double lam[64];
+    __shared__ double dq[64], eq[64];      // diagonal and off-diagonal of T (eq[i] couples i, i+1)
+    __shared__ double2 tq[64];             // tau_k
+    __shared__ double2 vb[64], wb[64];     // the current reflector v and the vector w of its update
+    __shared__ int bad;
+
+    const int fidx = flist[blockIdx.x];
+    const FrameDev& fr = frames[fidx];
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int M = fr.M, Mp = M + (M & 1), ld = Mp + 1;
+    double2* A = lds;
+    double2* Hv = lds + Mp * ld;
+
+    if (tid == 0) {
+        bad = 0;
+        if (prm.write_emb) *reinterpret_cast<int*>(ws + fr.ws_lowq) = 0;   // low-Q list of the scan
+    }
+    __syncthreads();
+    load_covariance(fr, ws, A, ld, Mp, &bad);
+    __syncthreads();
+
+    uint32_t st = 0;
+    // four lanes per matrix row (or column) in the parallel phases
+    const int grp = tid >> 2, q = tid & 3, gstep = bd >> 2;
+    if (!bad) {
+        // T = Q^H R Q.  Step k reflects rows/columns k+1..M-1 so that column k below the
+        // subdiagonal vanishes and the subdiagonal entry becomes the real beta.
+        for (int k = 0; k < M - 1; ++k) {
+            const int m = M - 1 - k;
+            const double2* col = A + (k + 1) * ld + k;          // col[i * ld] = A[k+1+i][k]
+            double part = 0.0;
+            for (int i = 1 + tid; i < m; i += bd) {
+                const double2 x = col[i * ld];
+                part = fma(x.x, x.x, fma(x.y, x.y, part));
             }
-            const int r = fr.emb_row0 + rl;
-            const int tile = r >> 5, i = r & 31;
-            if (prm.write_emb == 1) {
-                const int h = kk & 1, s2 = kk >> 1;
-                reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * 64 + h * 32 + i) * M + s2] = v;
-            } else {
-                const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
-                const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;
-                if (prm.write_emb == 2) reinterpret_cast<__bf16*>(ws + g.ws_emb)[o] = (__bf16)v;
-                else reinterpret_cast<_Float16*>(ws + g.ws_emb)[o] = (_Float16)v;
+            const double xn2 = block_sum_fast(part, red);
+            const double2 alpha = col[0];
+            double beta = alpha.x;
+            double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
+            if (xn2 > 0.0 || alpha.y != 0.0) {
+                // beta = -sgn(Re alpha) ||(alpha, x)||, tau = (beta - alpha) / beta,
+                // v = (1, x / (alpha - beta)): then H^H (alpha, x) = (beta, 0)
+                beta = -copysign(sqrt(fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2))), alpha.x);
+                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double2 den = make_double2(alpha.x - beta, alpha.y);
+                const double dn2 = fma(den.x, den.x, den.y * den.y);
+                scl = make_double2(den.x / dn2, -den.y / dn2);
+            }
+            for (int i = tid; i < m; i += bd) {
+                const double2 v = (i == 0) ? make_double2(1.0, 0.0) : cmul(col[i * ld], scl);
+                Hv[(k + 1 + i) * ld + k] = v;
+                vb[i] = v;
+            }
+            if (tid == 0) {
+                dq[k] = A[k * ld + k].x;
+                eq[k] = beta;
+                tq[k] = tau;
+            }
+            __syncthreads();
+            if (tau.x == 0.0 && tau.y == 0.0) continue;        // uniform: H_k = I
+            // y = B v for the trailing block B, gamma = v^H y (real), w = tau y - |tau|^2 gamma / 2 v
+            double gp = 0.0;
+            for (int r = grp; r < m; r += gstep) {
+                const double2* arow = A + (k + 1 + r) * ld + k + 1;
+                double2 acc = make_double2(0.0, 0.0);
+                for (int j = q; j < m; j += 4) {
+                    const double2 a = arow[j], v = vb[j];
+                    acc.x = fma(a.x, v.x, fma(-a.y, v.y, acc.x));
+                    acc.y = fma(a.x, v.y, fma(a.y, v.x, acc.y));
+                }
+                acc.x = quad_sum(acc.x);
+                acc.y = quad_sum(acc.y);
+                if (q == 0) {
+                    const double2 v = vb[r];
+                    gp = fma(v.x, acc.x, fma(v.y, acc.y, gp));
+                    wb[r] = acc;
+                }
+            }
+            const double gam = block_sum_fast(gp, red);
+            const double h = 0.5 * fma(tau.x, tau.x, tau.y * tau.y) * gam;
+            for (int r = grp; r < m; r += gstep) {
+                if (q == 0) wb[r] = csub(cmul(tau, wb[r]), cscale(h, vb[r]));
+            }
+            __syncthreads();
+            // B -= v w^H + w v^H
+            for (int r = grp; r < m; r += gstep) {
+                const double2 vi = vb[r], wi = wb[r];
+                double2* arow = A + (k + 1 + r) * ld + k + 1;
+                for (int j = q; j < m; j += 4) {
+                    const double2 vj = vb[j], wj = wb[j];
+                    double2 a = arow[j];
+                    a.x -= fma(vi.x, wj.x, vi.y * wj.y) + fma(wi.x, vj.x, wi.y * vj.y);
+                    a.y -= fma(vi.y, wj.x, -vi.x * wj.y) + fma(wi.y, vj.x, -wi.x * vj.y);
+                    arow[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            dq[M - 1] = A[(M - 1) * ld + M - 1].x;
+            eq[M - 1] = 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < Mp * Mp; e += bd) {
+            const int i = e / Mp, j = e - i * Mp;
+            A[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);      // Z = I
+        }
+        __syncthreads();
+
+        // Implicit QL on (dq, eq) in the first M lanes of wave 0.  Lane j keeps d_j and e_j in
+        // registers (the others read them with readlane) and row j of Z in LDS; every lane runs
+        // the rotation chain, whose values are uniform.
+        if (tid < M) {
+            const int lane = tid;
+            double dl = dq[lane], el = eq[lane];
+            double2* zrow = A + lane * ld;
+            const double tol = prm.tol;
+            for (int l = 0; l < M; ++l) {
+                for (int it = 0;; ++it) {
+                    // the block [l, m]: m is the first index >= l whose e_m is negligible
+                    const double dnx = __shfl_down(dl, 1);
+                    const bool split = (lane == M - 1) || fabs(el) <= tol * (fabs(dl) + fabs(dnx));
+                    const unsigned long long bal = __ballot(split && lane >= l);
+                    const int m = __builtin_ctzll(bal);
+                    if (m == l) break;
+                    if (it == prm.max_iter) {
+                        st |= NSSDOA_ST_EVD_NOT_CONVERGED;
+                        break;
+                    }
+                    // shift: the eigenvalue of the leading 2x2 of the block nearer to d_l (its
+                    // precision only affects the convergence rate)
+                    const double d_l = readlane_f64(dl, l), e_l = readlane_f64(el, l);
+                    const double d_m = readlane_f64(dl, m);
+                    double g = (readlane_f64(dl, l + 1) - d_l) * rcp_approx(2.0 * e_l);
+                    const double g21 = fma(g, g, 1.0);
+                    double r = g21 * rsq_full(g21);
+                    g = d_m - d_l + e_l * rcp_approx(g + copysign(r, g));
+                    double s = 1.0, c = 1.0, p = 0.0;
+                    int i = m - 1;
+                    double di1 = d_m, di = readlane_f64(dl, i), ei = readlane_f64(el, i);
+                    double zc = zrow[m].x, zi = zrow[i].x;   // column i+1 (carried) and column i
+                    bool early = false;
+                    for (; i >= l; --i) {
+                        const int in = i > 0 ? i - 1 : 0;      // the next rotation's index
+                        const double dn = readlane_f64(dl, in), en = readlane_f64(el, in);
+                        const double zn = zrow[in].x;
+                        const double f = s * ei, b = c * ei;
+                        const double t = fma(f, f, g * g);
+                        if (t == 0.0) {
+                            early = true;
+                            break;
+                        }
+                        const double rr = rsq_full(t);
+                        const double enew = t * rr;
+                        s = f * rr;
+                        c = g * rr;
+                        g = di1 - p;
+                        r = fma(di - g, s, 2.0 * c * b);
+                        p = s * r;
+                        const double dnew = g + p;
+                        g = fma(c, r, -b);
+                        el = (lane == i + 1) ? enew : el;
+                        dl = (lane == i + 1) ? dnew : dl;
+                        zrow[i + 1].x = fma(s, zi, c * zc);
+                        zc = fma(c, zi, -s * zc);
+                        di1 = di;
+                        di = dn;
+                        ei = en;
+                        zi = zn;
+                    }
+                    zrow[i + 1].x = zc;
+                    if (early) {                                // the chase vanished: restart
+                        dl = (lane == i + 1) ? di1 - p : dl;
+                        el = (lane == m) ? 0.0 : el;
+                        continue;
+                    }
+                    dl = (lane == l) ? di1 - p : dl;
+                    el = (lane == l) ? g : (lane == m) ? 0.0 : el;
+                }
+            }
+            dq[lane] = dl;
+        }
+        __syncthreads();
+
+        // V = H_0 (H_1 (... H_{M-2} Z)); H_k Z = Z - tau_k v_k (v_k^H Z).  Four lanes own one
+        // column of Z for all reflectors, so no barrier is needed between them.
+        for (int j = grp; j < M; j += gstep) {
+            for (int k = M - 2; k >= 0; --k) {
+                const double2 tau = tq[k];
+                if (tau.x == 0.0 && tau.y == 0.0) continue;
+                const int m = M - 1 - k;
+                double2 sa = make_double2(0.0, 0.0);
+                for (int i = q; i < m; i += 4) {
+                    const double2 v = Hv[(k + 1 + i) * ld + k], z = A[(k + 1 + i) * ld + j];
+                    sa.x = fma(v.x, z.x, fma(v.y, z.y, sa.x));
+                    sa.y = fma(v.x, z.y, fma(-v.y, z.x, sa.y));
+                }
+                sa.x = quad_sum(sa.x);
+                sa.y = quad_sum(sa.y);
+                const double2 ts = cmul(tau, sa);
+                for (int i = q; i < m; i += 4) {
+                    const double2 v = Hv[(k + 1 + i) * ld + k];
+                    A[(k + 1 + i) * ld + j] = csub(A[(k + 1 + i) * ld + j], cmul(v, ts));
+                }
             }
         }
+        __syncthreads();
     }
-    if (tid == 0) status[fidx] = st;
+    finish_frame(fr, fidx, prm, groups, ws, status, dq, 1, A, ld, Hv, bad, st, perm, lam, red);
 }
 
 }  // namespace
@@ -463,9 +771,22 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
+    if (max_M < 2 || max_M > 64) return hipErrorInvalidValue;
     const int Mp = max_M + (max_M & 1);
-    // one thread per 2x2 block update and per V row-pair update of a step: 3 Mp^2 / 4 tasks,
-    // at most kMaxTasksPerThread per thread
+    if (p.method == NSSDOA_EIG_QL) {
+        const int threads = max_M <= 16 ? 64 : max_M <= 32 ? 128 : 256;
+        const size_t lds = (size_t)2 * Mp * (Mp + 1) * sizeof(double2);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)evd_ql_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(evd_ql_kernel, dim3(n_frames), dim3(threads), lds, s, frame_list, frames, p, groups, ws,
+                           status);
+        return hipGetLastError();
+    }
+    // Jacobi: one thread per 2x2 block update and per V row-pair update of a step:
+    // 3 Mp^2 / 4 tasks, at most kMaxTasksPerThread per thread
     const int tasks = 3 * Mp * Mp / 4;
     const bool db = Mp <= 32;     // a second copy of A fits in LDS: one barrier per step
     const int threads = std::min(db ? 256 : 1024, std::max(64, (tasks + 63) / 64 * 64));

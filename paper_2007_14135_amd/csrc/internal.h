@@ -77,7 +77,8 @@ struct PointItem { int32_t frame, l0; };                      // FP64 scan: 256 
 
 struct EvdParams {
     double tol;
-    int32_t max_sweeps;
+    int32_t max_iter;           // Jacobi: sweeps; QL: iterations per eigenvalue
+    int32_t method;             // nssdoa_eig_method
     int32_t write_emb;          // packed B tiles for the scan: 0 none, 1 FP32, 2 BF16, 3 FP16
 };
 

@@ -105,6 +105,57 @@ def test_eigendecomposition_matches_oracle():
     assert np.all(res["status"] & 0x3 == 0)
 
 
+def _custom_frame(X):
+    M, N = X.shape
+    return Frame(M=M, N=N, D=1, pos=ula_positions(M), geometry="ula", snr_db=0.0, sigma2=1.0,
+                 angles_deg=np.zeros(1), grid_start=-90.0, grid_step=1.0, grid_L=180, X=X)
+
+
+@pytest.mark.parametrize("method", ["ql", "jacobi"])
+def test_eigensolvers_across_sizes_and_structures(method):
+    # Both solvers against the oracle's LAPACK eigensolve for M = 2 .. 64 (odd, even, the
+    # maximum), and on structures that stress the deflation logic: a scaled identity (T is
+    # diagonal from the start), rank one (N = 1, a cluster of zero eigenvalues) and R = 0.
+    from paper_2007_14135_amd import WS_EVALS, WS_EVECS, WS_COV
+    from paper_2007_14135_amd.api import Options
+    frames = [make_frame("c1", i, M=M, D=D, N=N) for i, (M, D, N) in enumerate(
+        [(2, 1, 300), (3, 1, 500), (8, 3, 4096), (16, 4, 1000), (17, 5, 999), (32, 6, 2000), (64, 8, 3000)])]
+    frames.append(_custom_frame(np.sqrt(12.0) * np.eye(12, dtype=np.complex128)))
+    rng = np.random.default_rng(5)
+    frames.append(_custom_frame((rng.standard_normal((16, 1)) + 1j * rng.standard_normal((16, 1)))))
+    frames.append(_custom_frame(np.zeros((8, 40), dtype=np.complex128)))
+    fs = pack_frames(frames, dtype=np.complex128)
+    db, res = _run(fs, "music", "c128", max_D=8, options=Options(eig_method=method))
+    assert np.all(res["status"] & 0x2 == 0), res["status"]
+    for f, fr in enumerate(frames):
+        M = fr.M
+        R = db.workspace_array(WS_COV, f, M * M, np.complex128).reshape(M, M)
+        lam = db.workspace_array(WS_EVALS, f, M, np.float64)
+        U = db.workspace_array(WS_EVECS, f, M * M, np.complex128).reshape(M, M)
+        lo, Uo = oracle.eig_desc(oracle.covariance(fr.X))
+        scale = max(abs(lo[0]), 1e-300)
+        assert np.all(np.diff(lam) <= 0), (method, f)
+        assert np.allclose(lam, lo, rtol=1e-11, atol=1e-13 * scale), (method, f, np.abs(lam - lo).max() / scale)
+        assert np.linalg.norm(R - U @ np.diag(lam) @ U.conj().T) <= 1e-13 * np.linalg.norm(R), (method, f)
+        assert np.linalg.norm(U.conj().T @ U - np.eye(M)) <= 1e-13 * M, (method, f)
+        if f < 7:   # the generated frames: a clear signal/noise gap at D
+            D = fr.D
+            Pn = U[:, D:] @ U[:, D:].conj().T
+            Pno = Uo[:, D:] @ Uo[:, D:].conj().T
+            assert np.abs(Pn - Pno).max() <= 1e-10, (method, f)
+
+
+def test_eigensolver_iteration_limit_sets_status():
+    # One QL iteration per eigenvalue (or one Jacobi sweep) is not enough for a 16-element
+    # covariance: the frame is flagged and the call still completes.
+    from paper_2007_14135_amd.api import Options
+    from paper_2007_14135_amd import ST_EVD_NOT_CONVERGED
+    fs = make_frames("c2", n_frames=2, N=1024, grid_step=0.1)
+    for method in ("ql", "jacobi"):
+        db, res = _run(fs, "music", "c64", options=Options(eig_method=method, eig_max_iter=1))
+        assert np.all(res["status"] & ST_EVD_NOT_CONVERGED), (method, res["status"])
+
+
 @pytest.mark.parametrize("alg", ["music", "ev", "mn", "phd"])
 def test_c2_frames_fp32_scan_parity(alg):
     # 12 frames of the 16-element workload at its full 18000-point grid (71 angle tiles, ragged
@@ -180,7 +231,7 @@ def test_single_snapshot_rank_one():
     frames = [make_frame("c1", 0, N=1, D=1)]
     fs = pack_frames(frames, dtype=np.complex128)
     db, res = _run(fs, "music", "c128")
-    assert not (res["status"][0] & 0x2), "Jacobi must converge on a singular R"
+    assert not (res["status"][0] & 0x2), "the eigensolver must converge on a singular R"
     est = oracle_frame(frames[0], "music")
     rel = spectrum_rel_err(res["spectra"][0], est)
     assert rel.max() <= 1e-9
