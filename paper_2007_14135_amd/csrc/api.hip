@@ -51,6 +51,8 @@ inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
 constexpr int kChunkRows = 384;      // rows of stacked B per FP32 scan work item (12 tiles)
 constexpr int kChunkRowsLP = 4096;   // rows per 16-bit scan work item (128 tiles)
 constexpr int kCovTargetItems = 2048;
+constexpr int64_t kLowqListMax = 1 << 22;     // entries of a batch's low-Q list
+constexpr int kLowqRefineGrid = 1024;         // workgroups of the low-Q re-evaluation
 constexpr double kPlateauRelScan = 1e-4;   // > the FP32 scan's relative error above the low-Q cut
 
 }  // namespace
@@ -86,9 +88,9 @@ struct nssdoa_batch_s {
     std::vector<std::pair<int, std::pair<int, int>>> peak_ranges;   // bucket M -> [begin, end)
     std::vector<PointItem> refine_items;        // (frame, chunk start), grouped like peak_list
     std::vector<std::pair<int, int>> refine_ranges;                 // per bucket [begin, end)
-    std::vector<PointItem> lowq_items;          // (frame, first list entry) slices of 256
-    std::vector<std::pair<int, int>> lowq_ranges;                   // per bucket [begin, end)
     size_t ws_bytes = 0;
+    int64_t ws_lowq_all = -1;                   // the scans' low-Q list (count, then cap entries)
+    int32_t lowq_all_cap = 0;
     size_t spec_elem = 4;
     size_t x_extent = 0;       // complex elements of X the frames address
     size_t spec_extent = 0;    // elements of the caller's spectrum the frames address
@@ -104,7 +106,6 @@ struct nssdoa_batch_s {
     int32_t* d_plist = nullptr;
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
-    PointItem* d_lowq = nullptr;
     float* d_steer = nullptr;                   // steering tables of the FP32 scans (batch-owned)
     int live_graphs = 0;
     // timing
@@ -352,6 +353,16 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             fd.ws_lowq = (int64_t)off;  off = align_up(off + (size_t)(fd.lowq_cap + 1) * 4);
         }
     }
+    if (prec != NSSDOA_C128) {
+        // the matrix-core scans' list of low-Q points: an int count (padded to 256 bytes), then
+        // (frame, grid index) pairs; its capacity is the sum of the frames' list capacities, at
+        // most kLowqListMax (points beyond it are re-evaluated by their frame's peak search)
+        int64_t cap = 0;
+        for (const FrameDev& fd : b->frames) cap += fd.lowq_cap;
+        b->lowq_all_cap = (int32_t)std::min<int64_t>(cap, kLowqListMax);
+        b->ws_lowq_all = (int64_t)off;
+        off = align_up(off + 256 + (size_t)b->lowq_all_cap * sizeof(int2));
+    }
     int64_t steer_floats = 0;
     for (auto& gd : b->groups) gd.steer_off = -1;
     if (prec != NSSDOA_C128) {
@@ -436,19 +447,16 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     for (int mb : {8, 16, 32, 64}) {
         const int begin = (int)b->peak_list.size();
         const int ibegin = (int)b->refine_items.size();
-        const int lbegin = (int)b->lowq_items.size();
         for (int f = 0; f < n_frames; ++f) {
             const int M = b->frames[f].M;
             const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
             if (bucket != mb) continue;
             b->peak_list.push_back(f);
             for (int l0 = 0; l0 < b->frames[f].L; l0 += kRefineChunk) b->refine_items.push_back({f, l0});
-            for (int i0 = 0; i0 < b->frames[f].lowq_cap; i0 += 256) b->lowq_items.push_back({f, i0});
         }
         if ((int)b->peak_list.size() > begin) {
             b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
             b->refine_ranges.push_back({ibegin, (int)b->refine_items.size()});
-            b->lowq_ranges.push_back({lbegin, (int)b->lowq_items.size()});
         }
     }
 
@@ -462,8 +470,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     size_t o_pos = align_up(o_blk + b->blk.size() * sizeof(int32_t));
     size_t o_pl = align_up(o_pos + b->pos.size() * sizeof(double));
     size_t o_ri = align_up(o_pl + b->peak_list.size() * sizeof(int32_t));
-    size_t o_lq = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
-    size_t o_cis = align_up(o_lq + b->lowq_items.size() * sizeof(PointItem));
+    size_t o_cis = align_up(o_ri + b->refine_items.size() * sizeof(PointItem));
     const size_t o_steer = align_up(o_cis + kCisTable * sizeof(double2));
     const size_t n_host = o_steer;                       // tables uploaded from the host
     size_t total = align_up(o_steer + (size_t)steer_floats * sizeof(float));
@@ -478,7 +485,6 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     put(o_pos, b->pos.data(), b->pos.size() * sizeof(double));
     put(o_pl, b->peak_list.data(), b->peak_list.size() * sizeof(int32_t));
     put(o_ri, b->refine_items.data(), b->refine_items.size() * sizeof(PointItem));
-    put(o_lq, b->lowq_items.data(), b->lowq_items.size() * sizeof(PointItem));
     {
         // exp(j 2 pi k / 256), k = -128..128, from extended-precision host sin/cos
         std::vector<double2> cis(kCisTable);
@@ -510,7 +516,6 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->d_plist = reinterpret_cast<int32_t*>(b->dev + o_pl);
     b->d_refine = reinterpret_cast<PointItem*>(b->dev + o_ri);
     b->d_cis = reinterpret_cast<double2*>(b->dev + o_cis);
-    b->d_lowq = reinterpret_cast<PointItem*>(b->dev + o_lq);
     b->d_steer = reinterpret_cast<float*>(b->dev + o_steer);
     // steering tables of the FP32 scans, computed once per batch on the device
     for (const GroupDev& gd : b->groups) {
@@ -723,7 +728,12 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     hipError_t e;
 
     if ((st = stage_begin(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
-    e = launch_cov(c128, batch->max_M, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, s);
+    LowqList lql = {nullptr, nullptr, 0};
+    if (batch->ws_lowq_all >= 0)
+        lql = {reinterpret_cast<int*>(ws + batch->ws_lowq_all), reinterpret_cast<int2*>(ws + batch->ws_lowq_all + 256),
+               batch->lowq_all_cap};
+    e = launch_cov(c128, batch->max_M, batch->d_cov, (int)batch->cov_items.size(), batch->d_frames, X, ws, lql.count,
+                   s);
     if (e != hipSuccess) return hip_fail(e, "covariance launch");
     if ((st = stage_end(NSSDOA_STAGE_COVARIANCE)) != NSSDOA_OK) return st;
 
@@ -784,7 +794,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         pp.chunk_count = reinterpret_cast<const int32_t*>(ws + lay.off_chunks);
         pp.windows = reinterpret_cast<const int32_t*>(ws + lay.off_win);
         for (auto& r : batch->peak_ranges) {
-            e = launch_peaks(false, r.first, nullptr, 0, nullptr, 0, batch->d_plist + r.second.first,
+            e = launch_peaks(false, r.first, nullptr, 0, batch->d_plist + r.second.first,
                              r.second.second - r.second.first, batch->d_frames, batch->d_pos, batch->d_cis, ws, spec,
                              pp, peaks, npeaks, status, s);
             if (e != hipSuccess) return hip_fail(e, "peak launch");
@@ -803,24 +813,28 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
                 e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
                                     batch->scan_max_tiles[&r - &batch->scan_ranges[0]],
                                     batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,
-                                    static_cast<float*>(spec), use_user, (float)opt.lowq_tau, s);
+                                    static_cast<float*>(spec), use_user, (float)opt.lowq_tau, lql, s);
             else
                 e = launch_scan_lp(batch->prec == NSSDOA_F16, r.first, batch->d_scan + r.second.first,
                                    r.second.second - r.second.first, batch->d_groups, batch->d_frames,
                                    batch->d_blk, batch->d_pos, ws, static_cast<float*>(spec), use_user,
-                                   (float)opt.lowq_tau, s);
+                                   (float)opt.lowq_tau, lql, s);
             if (e != hipSuccess) return hip_fail(e, "scan launch");
         }
     }
     if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
 
     if ((st = stage_begin(NSSDOA_STAGE_PEAKS)) != NSSDOA_OK) return st;
+    if (!c128) {
+        const int bucket = batch->max_M <= 8 ? 8 : batch->max_M <= 16 ? 16 : batch->max_M <= 32 ? 32 : 64;
+        e = launch_lowq_refine(bucket, lql, batch->d_frames, batch->d_pos, batch->d_cis, ws, static_cast<float*>(spec),
+                               use_user, kLowqRefineGrid, s);
+        if (e != hipSuccess) return hip_fail(e, "low-Q refine launch");
+    }
     for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
         const auto& r = batch->peak_ranges[i];
         const auto& ri = batch->refine_ranges[i];
-        const auto& rq = batch->lowq_ranges[i];
-        e = launch_peaks(c128, r.first, batch->d_lowq + rq.first, rq.second - rq.first,
-                         batch->d_refine + ri.first, ri.second - ri.first,
+        e = launch_peaks(c128, r.first, batch->d_refine + ri.first, ri.second - ri.first,
                          batch->d_plist + r.second.first, r.second.second - r.second.first,
                          batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
         if (e != hipSuccess) return hip_fail(e, "peak launch");

@@ -42,11 +42,12 @@ template <typename TIn>
 __global__ __launch_bounds__(kThreads) void cov_kernel(const CovItem* __restrict__ items,
                                                        const FrameDev* __restrict__ frames,
                                                        const TIn* __restrict__ X,
-                                                       char* __restrict__ ws) {
+                                                       char* __restrict__ ws, int* reset) {
     __shared__ double2 xs[kTileElems + 64];     // rows padded by one element (bank conflicts)
     __shared__ double2 red[kThreads];
 
     const CovItem it = items[blockIdx.x];
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;   // the batch's low-Q count
     const FrameDev& fr = frames[it.frame];
     const int M = fr.M;
     const int T = (M + 3) >> 2;              // 4-row blocks
@@ -149,13 +150,14 @@ template <typename TIn, int RB>   // RB = 16-row blocks (M <= 16 RB)
 __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict__ items,
                                                        const FrameDev* __restrict__ frames,
                                                        const TIn* __restrict__ X,
-                                                       char* __restrict__ ws) {
+                                                       char* __restrict__ ws, int* reset) {
     constexpr int NP = RB * (RB + 1) / 2;          // symmetric block pairs (I <= J)
     constexpr int NX = RB * RB;                    // all block pairs of Xi Xr^T
     __shared__ double sre[4][RB * 16][RB * 16 + 1];
     __shared__ double sim[4][RB * 16][RB * 16 + 1];
 
     const CovItem it = items[blockIdx.x];
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *reset = 0;   // the batch's low-Q count
     const FrameDev& fr = frames[it.frame];
     const int M = fr.M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -248,32 +250,32 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
 }  // namespace
 
 hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
-                      const void* X, char* ws, hipStream_t s) {
+                      const void* X, char* ws, int* reset, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (max_M <= 32) {
         if (c128) {
             if (max_M <= 16)
                 hipLaunchKernelGGL((cov_mfma_kernel<double2, 1>), dim3(n_items), dim3(256), 0, s, items, frames,
-                                   static_cast<const double2*>(X), ws);
+                                   static_cast<const double2*>(X), ws, reset);
             else
                 hipLaunchKernelGGL((cov_mfma_kernel<double2, 2>), dim3(n_items), dim3(256), 0, s, items, frames,
-                                   static_cast<const double2*>(X), ws);
+                                   static_cast<const double2*>(X), ws, reset);
         } else {
             if (max_M <= 16)
                 hipLaunchKernelGGL((cov_mfma_kernel<float2, 1>), dim3(n_items), dim3(256), 0, s, items, frames,
-                                   static_cast<const float2*>(X), ws);
+                                   static_cast<const float2*>(X), ws, reset);
             else
                 hipLaunchKernelGGL((cov_mfma_kernel<float2, 2>), dim3(n_items), dim3(256), 0, s, items, frames,
-                                   static_cast<const float2*>(X), ws);
+                                   static_cast<const float2*>(X), ws, reset);
         }
         return hipGetLastError();
     }
     if (c128)
         hipLaunchKernelGGL(cov_kernel<double2>, dim3(n_items), dim3(kThreads), 0, s, items, frames,
-                           static_cast<const double2*>(X), ws);
+                           static_cast<const double2*>(X), ws, reset);
     else
         hipLaunchKernelGGL(cov_kernel<float2>, dim3(n_items), dim3(kThreads), 0, s, items, frames,
-                           static_cast<const float2*>(X), ws);
+                           static_cast<const float2*>(X), ws, reset);
     return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <float.h>
+
 #include "nssdoa.h"
 
 namespace nssdoa {
@@ -39,7 +41,9 @@ struct FrameDev {
     int64_t ws_B;               // M*K complex128, column-major
     int64_t ws_qref;            // 1 double
     int64_t ws_cand;            // ceil(L / kRefineChunk) * (D + extra) candidate slots of 16 bytes
-    int64_t ws_lowq;            // int32 count, then lowq_cap int32 grid indices with low FP32 Q
+    int64_t ws_lowq;            // int32, then lowq_cap int32 grid indices with low FP32 Q: the windowed
+                                // scan keeps a count and the list there; the full scans keep only a
+                                // flag, set when a work item's LDS list of low-Q points overflowed
     double grid_start, grid_step;
     int32_t L, circular;
     int32_t pos_off;            // offset (doubles) of this frame's 3*M positions
@@ -292,12 +296,13 @@ __device__ inline bool plateau_walk(double x, int l, double rel, F val, uint32_t
 // Extrema of the 32-point blocks of v[0..span): bmax[b], bmin[b] for b < ceil(span / 32); a block
 // holding a NaN gets bmin = NaN.  Every thread of the workgroup calls it (one wave per block pair).
 constexpr int kPlateauBlock = 32;
-__device__ inline void block_extrema(const double* v, int span, double* bmax, double* bmin) {
+template <typename TV>
+__device__ inline void block_extrema(const TV* v, int span, double* bmax, double* bmin) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int nb = (span + kPlateauBlock - 1) / kPlateauBlock;
     for (int b0 = 2 * wave; b0 < nb; b0 += 2 * nwaves) {
         const int e = b0 * kPlateauBlock + lane;            // lanes 0-31: block b0, 32-63: b0 + 1
-        const double x = e < span ? v[e] : -INFINITY;
+        const double x = e < span ? (double)v[e] : -INFINITY;
         double hi = x, lo = e < span ? x : INFINITY;
         for (int o = 16; o > 0; o >>= 1) {
             const double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
@@ -330,8 +335,8 @@ constexpr int kPrefilterMin = 64;              // local maxima in a chunk worth 
 // Marks in flag[0..n) (kLoser or 0) the local maxima of a chunk that plateau_prefilter drops,
 // when the chunk has more than kPrefilterMin of them (a fine grid, where rounding makes many);
 // v_index(i) gives the v-index of local maximum i.  Every thread of the workgroup calls it.
-template <typename FI>
-__device__ inline void prefilter_losers(int n, const double* lval, FI v_index, const double* v, int span,
+template <typename FI, typename TV>
+__device__ inline void prefilter_losers(int n, const double* lval, FI v_index, const TV* v, int span,
                                         double rel, double* bmax, double* bmin, uint32_t* flag) {
     const int tid = threadIdx.x;
     const bool use = n > kPrefilterMin;
@@ -346,12 +351,12 @@ __device__ inline void prefilter_losers(int n, const double* lval, FI v_index, c
 
 // The best C plateau winners among the n local maxima (lval, lidx) of a chunk, by (value desc,
 // index asc), to slots[0..C); unused slots get idx -1.  flag: n ints of LDS holding kLoser for
-// maxima already known to lose (prefilter_losers), else 0; sv: 2 * n doubles of LDS that val() no
-// longer reads; cnt: one LDS int.  Every thread of the workgroup calls it; each wave walks one
-// local maximum at a time.
+// maxima already known to lose (prefilter_losers), else 0; cnt: one LDS int.  Every thread of the
+// workgroup calls it; each wave walks one local maximum at a time, then every winner finds its
+// rank among the winners.
 template <typename F>
-__device__ inline void chunk_candidates(int n, const double* lval, const int* lidx, uint32_t* flag, double* sv,
-                                        int* cnt, double rel, F val, CandSlot* slots, int C) {
+__device__ inline void chunk_candidates(int n, const double* lval, const int* lidx, uint32_t* flag, int* cnt,
+                                        double rel, F val, CandSlot* slots, int C) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = tid >> 6, nwaves = blockDim.x >> 6;
     for (int i = wave; i < n; i += nwaves) {
@@ -363,26 +368,23 @@ __device__ inline void chunk_candidates(int n, const double* lval, const int* li
     __syncthreads();
     if (tid == 0) *cnt = 0;
     __syncthreads();
-    long long* pk = reinterpret_cast<long long*>(sv + n);
     for (int i = tid; i < n; i += blockDim.x) {
-        if (flag[i] == kLoser) continue;
-        const int s = atomicAdd(cnt, 1);
-        sv[s] = lval[i];
-        pk[s] = ((long long)lidx[i] << 32) | (long long)flag[i];
-    }
-    __syncthreads();
-    const int m = *cnt;
-    for (int i = tid; i < m; i += blockDim.x) {
-        const double vi = sv[i];
-        const int li = (int)(pk[i] >> 32);
+        const uint32_t fi = flag[i];
+        if (fi == kLoser) continue;
+        atomicAdd(cnt, 1);
+        const double vi = lval[i];
+        const int li = lidx[i];
         int rank = 0;
-        for (int k = 0; k < m; ++k) rank += (sv[k] > vi) || (sv[k] == vi && (int)(pk[k] >> 32) < li);
+        for (int k = 0; k < n; ++k)
+            rank += flag[k] != kLoser && ((lval[k] > vi) || (lval[k] == vi && lidx[k] < li));
         if (rank < C) {
             slots[rank].v = vi;
             slots[rank].idx = li;
-            slots[rank].span = (uint32_t)(pk[i] & 0xFFFFFFFFll);
+            slots[rank].span = fi;
         }
     }
+    __syncthreads();
+    const int m = *cnt;
     for (int s = m + tid; s < C; s += blockDim.x) {
         slots[s].v = __longlong_as_double(0x7ff8000000000000LL);
         slots[s].idx = -1;
@@ -407,30 +409,84 @@ __device__ inline void lowq_append(bool low, int l, int* cnt, int cap) {
     }
 }
 
+// Low-Q points of a matrix-core scan work item (Q = ||B^H a||^2 below lowq_tau ||B||_F^2, where
+// its FP32 value has a large relative error), collected in LDS while the scan runs and published
+// after its matrix-core loop to the batch's list, which lowq_refine_kernel re-evaluates in FP64
+// (balanced over the whole GPU: low-Q points cluster around the peaks of a few frames).  Entry:
+// frame << 8 | angle within the work item's 256 angles.
+constexpr int kScanLowqCap = 1024;
+struct ScanLowq {
+    int n;
+    int base;
+    int list[kScanLowqCap];
+};
+
+// Every lane of a wave calls it for one frame's 64 angles; lanes with `low` append their entry
+// (one LDS atomic per wave).  When the list is full the frame's flag is set instead, and the
+// peak search re-evaluates that frame's low-Q points itself.
+__device__ inline void scan_lowq_collect(bool low, int f, int a, ScanLowq& q, int* frame_flag) {
+    const unsigned long long mask = __ballot(low);
+    if (mask == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&q.n, __popcll(mask));
+    base = __shfl(base, leader);
+    if (low) {
+        const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < kScanLowqCap) q.list[slot] = (f << 8) | a;
+        else *frame_flag = 1;
+    }
+}
+
+// Reserves room for the work item's entries in the batch list (count, then (frame, grid index)
+// pairs) with one atomic and writes them; entries beyond the list's capacity set their frame's
+// flag.  Called by every thread after a workgroup barrier.
+__device__ inline void scan_lowq_publish(ScanLowq& q, int angle0, int* count, int2* list, int cap,
+                                         const FrameDev* __restrict__ frames, char* __restrict__ ws) {
+    const int n = min(q.n, kScanLowqCap);
+    if (threadIdx.x == 0) q.base = n > 0 ? atomicAdd(count, n) : 0;
+    __syncthreads();
+    const int base = q.base;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ent = q.list[i];
+        const int f = ent >> 8, l = angle0 + (ent & 255);
+        if (base + i < cap) list[base + i] = make_int2(f, l);
+        else *reinterpret_cast<int*>(ws + frames[f].ws_lowq) = 1;
+    }
+}
+
 // Host-side launchers (defined next to their kernels).
 hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, const FrameDev* frames,
-                      const void* X, char* ws, hipStream_t s);
+                      const void* X, char* ws, int* reset, hipStream_t s);
 hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s);
 hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
                               hipStream_t s);
 constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
+// Low-Q list of a batch: an int count (reset by the covariance launch), then cap (frame, index).
+struct LowqList {
+    int* count;
+    int2* list;
+    int cap;
+};
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
-                           char* ws, float* spec, int use_user_spec, float lowq_tau,
-                           hipStream_t s);
+                           char* ws, float* spec, int use_user_spec, float lowq_tau, LowqList lq, hipStream_t s);
 hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
                           const FrameDev* frames, const int32_t* blkframe, const double* pos, char* ws,
-                          float* spec, int use_user, float lowq_tau, hipStream_t s);
+                          float* spec, int use_user, float lowq_tau, LowqList lq, hipStream_t s);
+hipError_t launch_lowq_refine(int bucket_M, LowqList lq, const FrameDev* frames, const double* pos,
+                              const double2* cis, const char* ws, float* spec, int use_user, int n_wg,
+                              hipStream_t s);
 hipError_t launch_scan_f64(const PointItem* items, int n_items, int max_M,
                            const FrameDev* frames, const double* pos, const double2* cis,
                            const char* ws, double* spec, int use_user_spec, hipStream_t s);
-hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* lowq_items, int n_lowq_items,
-                        const PointItem* items, int n_items, const int32_t* frame_list,
-                        int n_frames, const FrameDev* frames, const double* pos,
-                        const double2* cis, char* ws, void* spec, const PeakParams& p,
-                        void* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s);
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items, const int32_t* frame_list,
+                        int n_frames, const FrameDev* frames, const double* pos, const double2* cis, char* ws,
+                        void* spec, const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
+                        hipStream_t s);
 
 hipError_t launch_gemm_bf16(int M, int N, int K, const float* A, int64_t sam, int64_t sak, int relu_in_a,
                             const float* B, int64_t sbk, int64_t sbn, int relu_in_b, float alpha,

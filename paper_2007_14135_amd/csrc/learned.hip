@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
         uint32_t* flag = reinterpret_cast<uint32_t*>(rlist);
         prefilter_losers(n, lval, [&](int i) { return lidx[i] - (c0 - kHaloW); }, v, span, plateau_rel, bmax, bmin,
                          flag);
-        chunk_candidates(n, lval, lidx, flag, v, &rcount, plateau_rel, val, slots, C);
+        chunk_candidates(n, lval, lidx, flag, &rcount, plateau_rel, val, slots, C);
     }
 }
 

@@ -7,8 +7,10 @@
 //  256-entry slices of the lists, so the FP64 work is spread over the whole GPU whatever the
 //  per-frame counts are.
 // localmax_kernel, one workgroup per (frame, chunk of 4096 grid points):
-//  1. loads the chunk plus a halo of 16 points on each side into LDS (a frame whose list
-//     overflowed re-evaluates its low-Q points here instead);
+//  1. loads the chunk plus a halo of 16 points on each side into LDS (the FP32 scan has already
+//     re-evaluated its low-Q points in FP64; for a frame whose scan list overflowed this kernel
+//     re-evaluates every point at or above 1 / (lowq_tau ||B||_F^2) itself, writes the chunk's
+//     own points back to the spectrum and uses the same rounded values for the halo);
 //  2. finds the local maxima of its own points: P[l] > P[l-1] and the run of values equal to
 //     P[l] ends in a strictly smaller value (the run is reported at its first index); grid ends
 //     are not peaks unless the grid is circular;
@@ -50,24 +52,44 @@ __device__ inline bool in_windows(const int32_t* W, int l) {
     return in;
 }
 
+// FP64 re-evaluation of the batch's low-Q list (published by the matrix-core scans), one point
+// per thread over a fixed grid: the list's length is known only on the device.
 template <int MB>
-__global__ __launch_bounds__(256) void lowq_kernel(const PointItem* __restrict__ items,
-                                                   const FrameDev* __restrict__ frames,
-                                                   const double* __restrict__ pos,
-                                                   const double2* __restrict__ cis,
-                                                   const char* __restrict__ ws, float* __restrict__ spec,
-                                                   int use_user, const uint32_t* __restrict__ status) {
-    const PointItem it = items[blockIdx.x];
-    const FrameDev& fr = frames[it.frame];
-    const int* list = reinterpret_cast<const int*>(ws + fr.ws_lowq);
-    const int n = min(list[0], fr.lowq_cap);
-    const int i = it.l0 + (int)threadIdx.x;
-    if (i >= n || (status[it.frame] & NSSDOA_ST_NONFINITE_INPUT)) return;
-    const int l = list[1 + i];
-    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
-    const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis);
-    float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
-    P[l] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
+__global__ __launch_bounds__(256) void lowq_refine_kernel(LowqList lq, const FrameDev* __restrict__ frames,
+                                                          const double* __restrict__ pos,
+                                                          const double2* __restrict__ cis,
+                                                          const char* __restrict__ ws, float* __restrict__ spec,
+                                                          int use_user) {
+    const int n = min(*lq.count, lq.cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int2 e = lq.list[i];
+        const FrameDev& fr = frames[e.x];
+        const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, reinterpret_cast<const double2*>(ws + fr.ws_B),
+                                      grid_angle(fr.grid_start, fr.grid_step, e.y), cis);
+        float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+        out[e.y] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
+    }
+}
+
+// True when the local-maximum candidate x at v-index e (P[l] > P[l-1], P[l+1] == x) is a peak:
+// the run of values equal to x ends in a strictly smaller value.  Runs longer than the halo
+// are followed in the stored spectrum.
+template <typename TS>
+__device__ bool equal_run_ends_lower(const TS* v, int e, int span, double x, const TS* P, int l0, int L, bool circ) {
+    int r = e + 1;
+    while (r < span && (double)v[r] == x) ++r;
+    if (r < span) return (double)v[r] < x;
+    int rl = l0 - kHalo + r, steps = 0;
+    for (;;) {
+        if (rl >= L) {
+            if (!circ) return false;
+            rl -= L;
+        }
+        const double y = (double)P[rl];
+        if (y != x) return y < x;
+        if (++steps >= L) return false;
+        ++rl;
+    }
 }
 
 template <int MB, typename TS>
@@ -78,12 +100,14 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
                                                      char* __restrict__ ws, TS* __restrict__ spec,
                                                      PeakParams prm,
                                                      const uint32_t* __restrict__ status) {
-    __shared__ double v[kRefineChunk + 2 * kHalo];
-    __shared__ int rlist[kRefineChunk + 2 * kHalo];
+    constexpr int kSpanMax = kRefineChunk + 2 * kHalo;
+    constexpr int kPerT = kRefineChunk / 256;          // own points per thread in the maximum test
+    __shared__ TS v[kSpanMax];
+    __shared__ int rlist[kSpanMax];
     __shared__ double lval[kLocalCap];
     __shared__ int lidx[kLocalCap];
-    __shared__ double bmax[(kRefineChunk + 2 * kHalo) / kPlateauBlock + 1];
-    __shared__ double bmin[(kRefineChunk + 2 * kHalo) / kPlateauBlock + 1];
+    __shared__ double bmax[kSpanMax / kPlateauBlock + 1];
+    __shared__ double bmin[kSpanMax / kPlateauBlock + 1];
     __shared__ int lcount, rcount;
 
     const PointItem it = items[blockIdx.x];
@@ -98,7 +122,26 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     TS* P = spec + (prm.use_user_spec ? fr.spec_off_user : fr.spec_off_ws);
     CandSlot* slots = reinterpret_cast<CandSlot*>(ws + fr.ws_cand) + (size_t)(l0 / kRefineChunk) * C;
 
-    if (status[f] & NSSDOA_ST_NONFINITE_INPUT) {
+    // Every global load is issued before the first one is used: the frame status, ||B||_F^2 and
+    // the chunk with its halo (points beyond a non-circular grid end hold NaN, which compares
+    // false both ways).
+    const uint32_t fst = status[f];
+    const int overflow = prm.refine_lowq ? *reinterpret_cast<const int*>(ws + fr.ws_lowq) : 0;
+    const double qref = prm.refine_lowq ? *reinterpret_cast<const double*>(ws + fr.ws_qref) : 0.0;
+    constexpr int kPer = (kSpanMax + 255) / 256;
+    TS xs[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * 256;
+        const int l = l0 - kHalo + e;
+        TS x = (TS)qnan();
+        if (e < span) {
+            if (l >= 0 && l < L) x = P[l];
+            else if (circ) x = P[((l % L) + L) % L];
+        }
+        xs[u] = x;
+    }
+    if (fst & NSSDOA_ST_NONFINITE_INPUT) {
         for (int o = tid; o < nown; o += blockDim.x) P[l0 + o] = (TS)qnan();
         for (int s = tid; s < C; s += blockDim.x) {
             slots[s].v = qnan();
@@ -106,94 +149,72 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
         }
         return;
     }
-
-    // FP32 spectra were re-evaluated by lowq_kernel unless the frame's list overflowed
-    const bool overflow = prm.refine_lowq && *reinterpret_cast<const int*>(ws + fr.ws_lowq) > fr.lowq_cap;
-    double pthr = INFINITY;
-    if (overflow) pthr = 1.0 / (prm.lowq_tau * *reinterpret_cast<const double*>(ws + fr.ws_qref));
-    const double* ps = pos + fr.pos_off;
-    const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     if (tid == 0) {
         lcount = 0;
         rcount = 0;
     }
-    // load the chunk and its halo; points beyond a non-circular grid end hold NaN, which
-    // compares false both ways
-    {
-        // every load of this thread is issued before the first LDS store
-        constexpr int kPer = (kRefineChunk + 2 * kHalo + 255) / 256;
-        double xs[kPer];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = tid + u * 256;
-            const int l = l0 - kHalo + e;
-            double x = qnan();
-            if (e < span) {
-                if (l >= 0 && l < L) x = (double)P[l];
-                else if (circ) x = (double)P[((l % L) + L) % L];
-            }
-            xs[u] = x;
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = tid + u * 256;
-            if (e < span) v[e] = xs[u];
-        }
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + u * 256;
+        if (e < span) v[e] = xs[u];
     }
     __syncthreads();
     if (overflow) {
-        // list the low-Q points, then re-evaluate them in FP64 one per thread
-        for (int e = tid; e < span; e += blockDim.x) {
-            const double x = v[e];
-            if (x == x && !(x < pthr)) rlist[atomicAdd(&rcount, 1)] = e;
+        // list the low-Q points (one LDS atomic per wave), then re-evaluate them in FP64, one per
+        // thread; the halo gets the same rounded values the neighbouring chunk writes
+        const double pthr = 1.0 / (prm.lowq_tau * qref);
+        const int lane = tid & 63;
+        for (int e0 = 0; e0 < span; e0 += blockDim.x) {
+            const int e = e0 + tid;
+            const double x = e < span ? (double)v[e] : qnan();
+            const bool low = x == x && !(x < pthr);
+            const unsigned long long mask = __ballot(low);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&rcount, __popcll(mask));
+                base = __shfl(base, leader);
+                if (low) rlist[base + __popcll(mask & ((1ull << lane) - 1ull))] = e;
+            }
         }
         __syncthreads();
         const int nr = rcount;
+        const double* ps = pos + fr.pos_off;
+        const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
         for (int i = tid; i < nr; i += blockDim.x) {
             const int e = rlist[i];
             int l = l0 - kHalo + e;
             if (l < 0 || l >= L) l = ((l % L) + L) % L;
             const double Q = q64_eval<MB>(ps, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis);
-            const double x = 1.0 / fmax(Q, (double)FLT_MIN);
+            const TS x = (TS)(1.0 / fmax(Q, (double)FLT_MIN));
             v[e] = x;
-            if (e >= kHalo && e < kHalo + nown) P[l] = (TS)x;
+            if (e >= kHalo && e < kHalo + nown) P[l] = x;
         }
         __syncthreads();
     }
 
-    for (int o = tid; o < nown; o += blockDim.x) {
-        const int l = l0 + o;
-        if (!circ && (l == 0 || l == L - 1)) continue;
-        const int e = o + kHalo;
-        const double x = v[e];
-        if (!(x > v[e - 1])) continue;
-        int r = e + 1;
-        while (r < span && v[r] == x) ++r;
-        bool peak = false;
-        if (r < span) {
-            peak = v[r] < x;
-        } else {
-            // the run of equal values is longer than the halo: follow it in the stored spectrum
-            int rl = l0 - kHalo + r, steps = 0;
-            for (;;) {
-                if (rl >= L) {
-                    if (!circ) break;
-                    rl -= L;
+    // 2. local maxima: thread t tests its own points o = 16 t .. 16 t + 15 from registers
+    {
+        const int o0 = tid * kPerT;
+        if (o0 < nown) {
+            double w[kPerT + 2];                         // v-indices kHalo + o0 - 1 .. kHalo + o0 + 16
+#pragma unroll
+            for (int k = 0; k < kPerT + 2; ++k) w[k] = (double)v[kHalo + o0 - 1 + k];
+#pragma unroll
+            for (int k = 0; k < kPerT; ++k) {
+                const int o = o0 + k;
+                const int l = l0 + o;
+                const double x = w[k + 1];
+                if (o >= nown || (!circ && (l == 0 || l == L - 1)) || !(x > w[k])) continue;
+                const double y = w[k + 2];
+                const bool peak = (y != x) ? (y < x) : equal_run_ends_lower(v, kHalo + o, span, x, P, l0, L, circ);
+                if (peak) {
+                    const int slot = atomicAdd(&lcount, 1);
+                    if (slot < kLocalCap) {
+                        lval[slot] = x;
+                        lidx[slot] = l;
+                    }
                 }
-                const double y = (double)P[rl];
-                if (y != x) {
-                    peak = y < x;
-                    break;
-                }
-                if (++steps >= L) break;
-                ++rl;
-            }
-        }
-        if (peak) {
-            const int slot = atomicAdd(&lcount, 1);
-            if (slot < kLocalCap) {
-                lval[slot] = x;
-                lidx[slot] = l;
             }
         }
     }
@@ -202,14 +223,14 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     const int n = min(lcount, kLocalCap);
     auto val = [&](int g) -> double {
         const int e = g - (l0 - kHalo);
-        if (e >= 0 && e < span) return v[e];
+        if (e >= 0 && e < span) return (double)v[e];
         if (circ) return (double)P[((g % L) + L) % L];
         return (g >= 0 && g < L) ? (double)P[g] : qnan();
     };
     uint32_t* flag = reinterpret_cast<uint32_t*>(rlist);
     prefilter_losers(n, lval, [&](int i) { return lidx[i] - (l0 - kHalo); }, v, span, prm.plateau_rel, bmax, bmin,
                      flag);
-    chunk_candidates(n, lval, lidx, flag, v, &rcount, prm.plateau_rel, val, slots, C);
+    chunk_candidates(n, lval, lidx, flag, &rcount, prm.plateau_rel, val, slots, C);
 }
 
 template <int MB>
@@ -437,16 +458,9 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
 }
 
 template <int MB>
-hipError_t launch_mb(bool f64, const PointItem* lowq_items, int n_lowq, const PointItem* items, int n_items,
-                     const int32_t* flist, int n_frames, const FrameDev* frames, const double* pos,
-                     const double2* cis, char* ws, void* spec, const PeakParams& p, nssdoa_peak* peaks,
-                     int32_t* npeaks, uint32_t* status, hipStream_t s) {
-    if (!f64 && p.refine_lowq && n_lowq > 0) {
-        hipLaunchKernelGGL((lowq_kernel<MB>), dim3(n_lowq), dim3(256), 0, s, lowq_items, frames, pos, cis, ws,
-                           static_cast<float*>(spec), p.use_user_spec, status);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_t* flist, int n_frames,
+                     const FrameDev* frames, const double* pos, const double2* cis, char* ws, void* spec,
+                     const PeakParams& p, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s) {
     if (n_items > 0) {
         if (f64)
             hipLaunchKernelGGL((localmax_kernel<MB, double>), dim3(n_items), dim3(256), 0, s, items, frames, pos,
@@ -465,16 +479,29 @@ hipError_t launch_mb(bool f64, const PointItem* lowq_items, int n_lowq, const Po
 
 }  // namespace
 
-hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* lowq_items, int n_lowq_items,
-                        const PointItem* items, int n_items, const int32_t* frame_list,
-                        int n_frames, const FrameDev* frames, const double* pos,
-                        const double2* cis, char* ws, void* spec, const PeakParams& p,
-                        void* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s) {
+hipError_t launch_lowq_refine(int bucket_M, LowqList lq, const FrameDev* frames, const double* pos,
+                              const double2* cis, const char* ws, float* spec, int use_user, int n_wg,
+                              hipStream_t s) {
+    if (!lq.count || lq.cap <= 0 || n_wg <= 0) return hipSuccess;
+    switch (bucket_M) {
+        case 8: hipLaunchKernelGGL(lowq_refine_kernel<8>, dim3(n_wg), dim3(256), 0, s, lq, frames, pos, cis, ws, spec, use_user); break;
+        case 16: hipLaunchKernelGGL(lowq_refine_kernel<16>, dim3(n_wg), dim3(256), 0, s, lq, frames, pos, cis, ws, spec, use_user); break;
+        case 32: hipLaunchKernelGGL(lowq_refine_kernel<32>, dim3(n_wg), dim3(256), 0, s, lq, frames, pos, cis, ws, spec, use_user); break;
+        case 64: hipLaunchKernelGGL(lowq_refine_kernel<64>, dim3(n_wg), dim3(256), 0, s, lq, frames, pos, cis, ws, spec, use_user); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_items, const int32_t* frame_list,
+                        int n_frames, const FrameDev* frames, const double* pos, const double2* cis, char* ws,
+                        void* spec, const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
+                        hipStream_t s) {
     nssdoa_peak* pk = static_cast<nssdoa_peak*>(peaks);
 #define NSSDOA_PEAKS_CASE(MB)                                                                       \
     case MB:                                                                                     \
-        return launch_mb<MB>(f64, lowq_items, n_lowq_items, items, n_items, frame_list, n_frames,   \
-                             frames, pos, cis, ws, spec, p, pk, npeaks, status, s);
+        return launch_mb<MB>(f64, items, n_items, frame_list, n_frames, frames, pos, cis, ws, spec, p, pk, \
+                             npeaks, status, s);
     switch (bucket_M) {
         NSSDOA_PEAKS_CASE(8)
         NSSDOA_PEAKS_CASE(16)

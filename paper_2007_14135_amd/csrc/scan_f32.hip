@@ -19,7 +19,9 @@
 // four waves owns 256 angles and one chunk of whole frames, whose B tiles it stages in LDS once
 // (all four waves read every tile).  Steering values come from the
 // group's table (built once per batch by steer_table_kernel: the phase in cycles formed and
-// reduced to [-1/2, 1/2] in FP64, then FP32 sincospi), loaded once per work item.
+// reduced to [-1/2, 1/2] in FP64, then FP32 sincospi), loaded once per work item.  Points whose
+// FP32 Q is below lowq_tau ||B||_F^2 are listed in LDS and published to the batch's low-Q list
+// after the matrix-core loop.
 #include <float.h>
 
 #include "internal.h"
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
                                                        const float* __restrict__ steer,
                                                        char* __restrict__ ws,
                                                        float* __restrict__ spec, int use_user,
-                                                       float lowq_tau) {
+                                                       float lowq_tau, LowqList lql) {
     const ScanItem it = items[blockIdx.x];
     const GroupDev& g = groups[it.group];
     const int lane = threadIdx.x & 63;
@@ -84,7 +86,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 
     // the work item's B tiles, staged once in LDS for the four waves (they share every row)
     extern __shared__ float4 embs[];
+    __shared__ ScanLowq lq;
     constexpr int kTile4 = 64 * M / 4;                       // float4 per 32-row tile
+    if (threadIdx.x == 0) lq.n = 0;
     {
         const float4* src = reinterpret_cast<const float4*>(ws + g.ws_emb) + (size_t)it.t0 * kTile4;
         const int n4 = (it.t1 - it.t0) * kTile4;
@@ -106,10 +110,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
         }
-        // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
-        // re-evaluation
         const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
-        lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fd.ws_lowq), fd.lowq_cap);
+        scan_lowq_collect(in && v < thr, f, wave * kScanAnglesPerWave + lane, lq,
+                          reinterpret_cast<int*>(ws + fd.ws_lowq));
     };
 
     for (int t = it.t0; t < it.t1; ++t) {
@@ -144,15 +147,17 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         }
     }
     if (cur >= 0) flush(cur);
+    __syncthreads();
+    scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
 template <int M>
 hipError_t launch_m(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
-                    const FrameDev* frames, const int32_t* blkframe, const float* steer,
-                    char* ws, float* spec, int use_user, float tau, hipStream_t s) {
+                    const FrameDev* frames, const int32_t* blkframe, const float* steer, char* ws, float* spec,
+                    int use_user, float tau, LowqList lq, hipStream_t s) {
     const size_t lds = (size_t)max_tiles * 64 * M * sizeof(float);
     hipLaunchKernelGGL(scan_f32_kernel<M>, dim3(n_items), dim3(256), lds, s, items, groups, frames,
-                       blkframe, steer, ws, spec, use_user, tau);
+                       blkframe, steer, ws, spec, use_user, tau, lq);
     return hipGetLastError();
 }
 
@@ -169,14 +174,14 @@ hipError_t launch_steer_table(const double* pos, int M, double start, double ste
 
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
-                           char* ws, float* spec, int use_user, float tau, hipStream_t s) {
+                           char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if ((size_t)max_tiles * 64 * M * sizeof(float) > kScanLdsBytes) return hipErrorInvalidValue;
     switch (M) {
-        case 8: return launch_m<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 16: return launch_m<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 32: return launch_m<32>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
-        case 64: return launch_m<64>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, s);
+        case 8: return launch_m<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 16: return launch_m<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 32: return launch_m<32>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 64: return launch_m<64>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
         default: return hipErrorInvalidValue;
     }
 }

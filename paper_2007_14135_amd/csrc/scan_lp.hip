@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
                                                       const double* __restrict__ pos,
                                                       char* __restrict__ ws,
                                                       float* __restrict__ spec, int use_user,
-                                                      float lowq_tau) {
+                                                      float lowq_tau, LowqList lql) {
     typedef typename Vec8<T>::type V;
     constexpr int S = M / 8;
     const ScanItem it = items[blockIdx.x];
@@ -82,6 +82,9 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
     const int4* blk4 = reinterpret_cast<const int4*>(blkframe + g.blk_off);
     float q0 = 0.0f, q1 = 0.0f;
     int cur = -1;
+    __shared__ ScanLowq lq;                 // low-Q points, published after the loop
+    if (threadIdx.x == 0) lq.n = 0;
+    __syncthreads();
 
     auto flush = [&](int f) {
         const float t0 = q0 + __shfl_xor(q0, 32);
@@ -94,10 +97,9 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
         }
-        // points whose FP32 Q is small relative to ||B||_F^2 go to the frame's list for FP64
-        // re-evaluation
         const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
-        lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fd.ws_lowq), fd.lowq_cap);
+        scan_lowq_collect(in && v < thr, f, wave * kScanAnglesPerWave + lane, lq,
+                          reinterpret_cast<int*>(ws + fd.ws_lowq));
     };
 
     V b[S];
@@ -137,26 +139,28 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
         for (int s = 0; s < S; ++s) b[s] = bn[s];
     }
     if (cur >= 0) flush(cur);
+    __syncthreads();
+    scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
 template <int M, typename T>
 hipError_t launch_mt(const ScanItem* items, int n_items, const GroupDev* groups, const FrameDev* frames,
                      const int32_t* blkframe, const double* pos, char* ws, float* spec, int use_user,
-                     float tau, hipStream_t s) {
+                     float tau, LowqList lq, hipStream_t s) {
     hipLaunchKernelGGL((scan_lp_kernel<M, T>), dim3(n_items), dim3(256), 0, s, items, groups, frames,
-                       blkframe, pos, ws, spec, use_user, tau);
+                       blkframe, pos, ws, spec, use_user, tau, lq);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_t(int M, const ScanItem* items, int n_items, const GroupDev* groups, const FrameDev* frames,
                     const int32_t* blkframe, const double* pos, char* ws, float* spec, int use_user,
-                    float tau, hipStream_t s) {
+                    float tau, LowqList lq, hipStream_t s) {
     switch (M) {
-        case 8: return launch_mt<8, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 16: return launch_mt<16, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 32: return launch_mt<32, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
-        case 64: return launch_mt<64, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, s);
+        case 8: return launch_mt<8, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
+        case 16: return launch_mt<16, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
+        case 32: return launch_mt<32, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
+        case 64: return launch_mt<64, T>(items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -165,10 +169,10 @@ hipError_t launch_t(int M, const ScanItem* items, int n_items, const GroupDev* g
 
 hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
                           const FrameDev* frames, const int32_t* blkframe, const double* pos, char* ws,
-                          float* spec, int use_user, float lowq_tau, hipStream_t s) {
+                          float* spec, int use_user, float tau, LowqList lq, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (f16) return launch_t<_Float16>(M, items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, lowq_tau, s);
-    return launch_t<__bf16>(M, items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, lowq_tau, s);
+    if (f16) return launch_t<_Float16>(M, items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
+    return launch_t<__bf16>(M, items, n_items, groups, frames, blkframe, pos, ws, spec, use_user, tau, lq, s);
 }
 
 }  // namespace nssdoa
