@@ -294,25 +294,24 @@ __device__ inline bool plateau_walk(double x, int l, double rel, F val, uint32_t
 }
 
 // Extrema of the 32-point blocks of v[0..span): bmax[b], bmin[b] for b < ceil(span / 32); a block
-// holding a NaN gets bmin = NaN.  Every thread of the workgroup calls it (one wave per block pair).
+// holding a NaN gets bmin = NaN.  Every thread of the workgroup calls it; thread b scans block b.
 constexpr int kPlateauBlock = 32;
 template <typename TV>
 __device__ inline void block_extrema(const TV* v, int span, double* bmax, double* bmin) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int nb = (span + kPlateauBlock - 1) / kPlateauBlock;
-    for (int b0 = 2 * wave; b0 < nb; b0 += 2 * nwaves) {
-        const int e = b0 * kPlateauBlock + lane;            // lanes 0-31: block b0, 32-63: b0 + 1
-        const double x = e < span ? (double)v[e] : -INFINITY;
-        double hi = x, lo = e < span ? x : INFINITY;
-        for (int o = 16; o > 0; o >>= 1) {
-            const double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
-            hi = fmax(hi, h2);
-            lo = (l2 < lo || l2 != l2) ? l2 : lo;               // NaN sticks
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int e0 = b * kPlateauBlock, e1 = min(span, e0 + kPlateauBlock);
+        double hi = -INFINITY, lo = INFINITY;
+#pragma unroll
+        for (int j = 0; j < kPlateauBlock; ++j) {
+            const int e = e0 + ((j + b) & (kPlateauBlock - 1));   // rotated start: no bank conflicts
+            if (e >= e1) continue;
+            const double x = (double)v[e];
+            hi = fmax(hi, x);
+            lo = (x < lo || x != x) ? x : lo;               // NaN sticks
         }
-        if ((lane & 31) == 0 && b0 + (lane >> 5) < nb) {
-            bmax[b0 + (lane >> 5)] = hi;
-            bmin[b0 + (lane >> 5)] = lo;
-        }
+        bmax[b] = hi;
+        bmin[b] = lo;
     }
 }
 
@@ -330,7 +329,7 @@ __device__ inline bool plateau_prefilter(int e, double x, double rel, int span, 
 }
 
 constexpr uint32_t kLoser = 0xFFFFFFFFu;       // flag of a local maximum that lost its plateau
-constexpr int kPrefilterMin = 64;              // local maxima in a chunk worth the block extrema
+constexpr int kPrefilterMin = 8;               // local maxima in a chunk worth the block extrema
 
 // Marks in flag[0..n) (kLoser or 0) the local maxima of a chunk that plateau_prefilter drops,
 // when the chunk has more than kPrefilterMin of them (a fine grid, where rounding makes many);

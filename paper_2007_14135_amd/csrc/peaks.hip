@@ -1,14 +1,13 @@
 // Step-6 (Table 2): peak search and selection, preceded for FP32 spectra by the FP64
 // re-evaluation of low-Q points.
 //
-// lowq_kernel: the scan appends, per frame, every grid point whose FP32 ||B^H a||^2 is below
-//  tau ||B||_F^2 (the spectrum peaks, where FP32 rounding is largest relative to Q); one thread
-//  per listed point recomputes it in FP64 and writes the rounded value back.  Work items are
-//  256-entry slices of the lists, so the FP64 work is spread over the whole GPU whatever the
-//  per-frame counts are.
+// lowq_refine_kernel: the matrix-core scans publish every grid point whose FP32 ||B^H a||^2 is
+//  below tau ||B||_F^2 (the spectrum peaks, where FP32 rounding is largest relative to Q) to one
+//  list per batch; one thread per listed point recomputes it in FP64 and writes the rounded value
+//  back, so the FP64 work is spread over the whole GPU whatever the per-frame counts are.
 // localmax_kernel, one workgroup per (frame, chunk of 4096 grid points):
-//  1. loads the chunk plus a halo of 16 points on each side into LDS (the FP32 scan has already
-//     re-evaluated its low-Q points in FP64; for a frame whose scan list overflowed this kernel
+//  1. loads the chunk plus a halo of 16 points on each side into LDS (lowq_refine_kernel has
+//     re-evaluated the low-Q points in FP64; for a frame whose scan list overflowed this kernel
 //     re-evaluates every point at or above 1 / (lowq_tau ||B||_F^2) itself, writes the chunk's
 //     own points back to the spectrum and uses the same rounded values for the halo);
 //  2. finds the local maxima of its own points: P[l] > P[l-1] and the run of values equal to
@@ -92,8 +91,10 @@ __device__ bool equal_run_ends_lower(const TS* v, int e, int span, double x, con
     }
 }
 
+constexpr int kLmThreads = 512;       // threads of a local-maximum workgroup
+
 template <int MB, typename TS>
-__global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restrict__ items,
+__global__ __launch_bounds__(kLmThreads, 4) void localmax_kernel(const PointItem* __restrict__ items,
                                                      const FrameDev* __restrict__ frames,
                                                      const double* __restrict__ pos,
                                                      const double2* __restrict__ cis,
@@ -101,14 +102,18 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
                                                      PeakParams prm,
                                                      const uint32_t* __restrict__ status) {
     constexpr int kSpanMax = kRefineChunk + 2 * kHalo;
-    constexpr int kPerT = kRefineChunk / 256;          // own points per thread in the maximum test
+    constexpr int kPerT = kRefineChunk / kLmThreads;   // own points per thread in the maximum test
+    static_assert(kSpanMax * sizeof(int) >= kLocalCap * sizeof(double), "union layout");
     __shared__ TS v[kSpanMax];
-    __shared__ int rlist[kSpanMax];
-    __shared__ double lval[kLocalCap];
+    // the low-Q point list of an overflowed frame, then (once it is used) the local maxima's values
+    __shared__ double rl_union[kSpanMax * sizeof(int) / sizeof(double) + 1];
     __shared__ int lidx[kLocalCap];
+    __shared__ uint32_t flag[kLocalCap];
     __shared__ double bmax[kSpanMax / kPlateauBlock + 1];
     __shared__ double bmin[kSpanMax / kPlateauBlock + 1];
     __shared__ int lcount, rcount;
+    int* rlist = reinterpret_cast<int*>(rl_union);
+    double* lval = rl_union;
 
     const PointItem it = items[blockIdx.x];
     const int f = it.frame;
@@ -128,11 +133,11 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     const uint32_t fst = status[f];
     const int overflow = prm.refine_lowq ? *reinterpret_cast<const int*>(ws + fr.ws_lowq) : 0;
     const double qref = prm.refine_lowq ? *reinterpret_cast<const double*>(ws + fr.ws_qref) : 0.0;
-    constexpr int kPer = (kSpanMax + 255) / 256;
+    constexpr int kPer = (kSpanMax + kLmThreads - 1) / kLmThreads;
     TS xs[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * 256;
+        const int e = tid + u * kLmThreads;
         const int l = l0 - kHalo + e;
         TS x = (TS)qnan();
         if (e < span) {
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        const int e = tid + u * 256;
+        const int e = tid + u * kLmThreads;
         if (e < span) v[e] = xs[u];
     }
     __syncthreads();
@@ -193,27 +198,40 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
         __syncthreads();
     }
 
-    // 2. local maxima: thread t tests its own points o = 16 t .. 16 t + 15 from registers
+    // 2. local maxima: thread t tests its own points o = 8 t .. 8 t + 7 from registers (one
+    // aligned vector read of them plus their two neighbours), first as two bit masks: points
+    // above their left neighbour and above / equal to their right one
     {
         const int o0 = tid * kPerT;
         if (o0 < nown) {
-            double w[kPerT + 2];                         // v-indices kHalo + o0 - 1 .. kHalo + o0 + 16
+            TS w[kPerT + 2];                             // v-indices kHalo + o0 - 1 .. kHalo + o0 + kPerT
+            w[0] = v[kHalo + o0 - 1];
 #pragma unroll
-            for (int k = 0; k < kPerT + 2; ++k) w[k] = (double)v[kHalo + o0 - 1 + k];
+            for (int k = 0; k < kPerT; ++k) w[k + 1] = v[kHalo + o0 + k];
+            w[kPerT + 1] = v[kHalo + o0 + kPerT];
+            const int lo_ok = circ ? 0 : 1 - l0;        // first own o that may be a peak
+            const int hi_ok = circ ? nown : min(nown, L - 1 - l0);   // one past the last
+            uint32_t above = 0, level = 0;
 #pragma unroll
             for (int k = 0; k < kPerT; ++k) {
                 const int o = o0 + k;
-                const int l = l0 + o;
-                const double x = w[k + 1];
-                if (o >= nown || (!circ && (l == 0 || l == L - 1)) || !(x > w[k])) continue;
-                const double y = w[k + 2];
-                const bool peak = (y != x) ? (y < x) : equal_run_ends_lower(v, kHalo + o, span, x, P, l0, L, circ);
-                if (peak) {
-                    const int slot = atomicAdd(&lcount, 1);
-                    if (slot < kLocalCap) {
-                        lval[slot] = x;
-                        lidx[slot] = l;
-                    }
+                const bool ok = o >= lo_ok && o < hi_ok && w[k + 1] > w[k];
+                above |= (uint32_t)(ok && w[k + 2] < w[k + 1]) << k;
+                level |= (uint32_t)(ok && w[k + 2] == w[k + 1]) << k;
+            }
+            while (level) {                              // a run of equal values: follow it
+                const int k = __builtin_ctz(level);
+                level &= level - 1;
+                if (equal_run_ends_lower(v, kHalo + o0 + k, span, (double)v[kHalo + o0 + k], P, l0, L, circ))
+                    above |= 1u << k;
+            }
+            while (above) {
+                const int k = __builtin_ctz(above);
+                above &= above - 1;
+                const int slot = atomicAdd(&lcount, 1);
+                if (slot < kLocalCap) {
+                    lval[slot] = (double)v[kHalo + o0 + k];
+                    lidx[slot] = l0 + o0 + k;
                 }
             }
         }
@@ -227,7 +245,6 @@ __global__ __launch_bounds__(256) void localmax_kernel(const PointItem* __restri
         if (circ) return (double)P[((g % L) + L) % L];
         return (g >= 0 && g < L) ? (double)P[g] : qnan();
     };
-    uint32_t* flag = reinterpret_cast<uint32_t*>(rlist);
     prefilter_losers(n, lval, [&](int i) { return lidx[i] - (l0 - kHalo); }, v, span, prm.plateau_rel, bmax, bmin,
                      flag);
     chunk_candidates(n, lval, lidx, flag, &rcount, prm.plateau_rel, val, slots, C);
@@ -463,10 +480,10 @@ hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_
                      const PeakParams& p, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status, hipStream_t s) {
     if (n_items > 0) {
         if (f64)
-            hipLaunchKernelGGL((localmax_kernel<MB, double>), dim3(n_items), dim3(256), 0, s, items, frames, pos,
+            hipLaunchKernelGGL((localmax_kernel<MB, double>), dim3(n_items), dim3(kLmThreads), 0, s, items, frames, pos,
                                cis, ws, static_cast<double*>(spec), p, status);
         else
-            hipLaunchKernelGGL((localmax_kernel<MB, float>), dim3(n_items), dim3(256), 0, s, items, frames, pos,
+            hipLaunchKernelGGL((localmax_kernel<MB, float>), dim3(n_items), dim3(kLmThreads), 0, s, items, frames, pos,
                                cis, ws, static_cast<float*>(spec), p, status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
