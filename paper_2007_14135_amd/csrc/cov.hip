@@ -8,8 +8,9 @@
 // block pair three 16x16x4 products are accumulated.  Lane l holds element l%16 of snapshot
 // group l/16: that one register is both the A operand (A[i][k], i = l%16, k = l/16) and the
 // B operand (B[k][j], j = l%16) of v_mfma_f64_16x16x4f64, whose result register r of lane l is
-// D[l/16 + 4r][l%16].  Each wave owns every fourth 16-snapshot block of the chunk and prefetches
-// the next block while the matrix cores run; the four waves are reduced in LDS in fixed order.
+// D[l/16 + 4r][l%16].  Each wave owns every fourth 16-snapshot block of the chunk and keeps
+// three blocks of loads in flight (raw complex64 read as aligned float4 when the layout allows)
+// while the matrix cores run; the four waves are reduced in LDS in fixed order.
 //
 // cov_kernel (any M): the chunk is staged through LDS in tiles of
 // 1024 complex values converted to FP64; each thread owns a 4x4 block of the upper block
@@ -179,40 +180,101 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
         rowok[b] = m < M;
         rowp[b] = xf + (size_t)(rowok[b] ? m : 0) * fr.ldx;
     }
-    double2 cur[RB][4], nxt[RB][4];
-    auto fetch = [&](int n, double2 (&dst)[RB][4]) {
+    // one 16-snapshot step of the three products from lane (mi, q)'s four snapshots n + 4q + u
+    auto mfma_step = [&](const double (&xr)[RB], const double (&xi)[RB]) {
+        int t = 0;
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = I; J < RB; ++J, ++t) {
+                drr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[I], xr[J], drr[t], 0, 0, 0);
+                dii[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[I], xi[J], dii[t], 0, 0, 0);
+            }
+#pragma unroll
+        for (int I = 0; I < RB; ++I)
+#pragma unroll
+            for (int J = 0; J < RB; ++J)
+                dir[I * RB + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[I], xr[J], dir[I * RB + J], 0, 0, 0);
+    };
+    const int first = it.n0 + 16 * wave;           // this wave's blocks: first + 64 k
+    const int nblk = first < it.n1 ? (it.n1 - first + 63) / 64 : 0;
+    bool vec = false;
+    if constexpr (sizeof(TIn) == 8) {
+        // complex64 frames whose rows and chunks start on 16-byte boundaries and whose chunk is
+        // whole 16-snapshot blocks: the four snapshots of a lane are two aligned float4, kept
+        // raw in a ring of three blocks in flight per wave
+        vec = ((fr.x_off | fr.ldx | it.n0) & 1) == 0 && ((it.n1 - it.n0) & 15) == 0 &&
+              (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+    }
+    if (vec) {
+        struct Raw { float4 a[RB][2]; };
+        auto load_raw = [&](int n, Raw& r) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    r.a[b][h] = rowok[b] ? *reinterpret_cast<const float4*>(rowp[b] + n + 4 * q + 2 * h)
+                                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        };
+        auto process = [&](const Raw& r) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int nn = n + 4 * q + u;
-                dst[b][u] = (rowok[b] && nn < it.n1) ? load_c<TIn>(rowp[b] + nn) : make_double2(0.0, 0.0);
-            }
-    };
-    int n = it.n0 + 16 * wave;
-    if (n < it.n1) fetch(n, cur);
-    for (; n < it.n1; n += 64) {
-        if (n + 64 < it.n1) fetch(n + 64, nxt);
+                double xr[RB], xi[RB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int t = 0;
-#pragma unroll
-            for (int I = 0; I < RB; ++I)
-#pragma unroll
-                for (int J = I; J < RB; ++J, ++t) {
-                    drr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].x, cur[J][u].x, drr[t], 0, 0, 0);
-                    dii[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].y, cur[J][u].y, dii[t], 0, 0, 0);
+                for (int b = 0; b < RB; ++b) {
+                    const float4 v = r.a[b][u >> 1];
+                    xr[b] = (double)((u & 1) ? v.z : v.x);
+                    xi[b] = (double)((u & 1) ? v.w : v.y);
                 }
-#pragma unroll
-            for (int I = 0; I < RB; ++I)
-#pragma unroll
-                for (int J = 0; J < RB; ++J)
-                    dir[I * RB + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[I][u].y, cur[J][u].x, dir[I * RB + J], 0, 0, 0);
+                mfma_step(xr, xi);
+            }
+        };
+        Raw r0, r1, r2;
+        if (nblk > 0) load_raw(first, r0);
+        if (nblk > 1) load_raw(first + 64, r1);
+        if (nblk > 2) load_raw(first + 128, r2);
+        for (int k = 0; k < nblk; k += 3) {
+            process(r0);
+            if (k + 3 < nblk) load_raw(first + 64 * (k + 3), r0);
+            if (k + 1 < nblk) {
+                process(r1);
+                if (k + 4 < nblk) load_raw(first + 64 * (k + 4), r1);
+            }
+            if (k + 2 < nblk) {
+                process(r2);
+                if (k + 5 < nblk) load_raw(first + 64 * (k + 5), r2);
+            }
         }
+    } else {
+        double2 cur[RB][4], nxt[RB][4];
+        auto fetch = [&](int n, double2 (&dst)[RB][4]) {
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
+            for (int b = 0; b < RB; ++b)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cur[b][u] = nxt[b][u];
+                for (int u = 0; u < 4; ++u) {
+                    const int nn = n + 4 * q + u;
+                    dst[b][u] = (rowok[b] && nn < it.n1) ? load_c<TIn>(rowp[b] + nn) : make_double2(0.0, 0.0);
+                }
+        };
+        int n = first;
+        if (n < it.n1) fetch(n, cur);
+        for (; n < it.n1; n += 64) {
+            if (n + 64 < it.n1) fetch(n + 64, nxt);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double xr[RB], xi[RB];
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    xr[b] = cur[b][u].x;
+                    xi[b] = cur[b][u].y;
+                }
+                mfma_step(xr, xi);
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cur[b][u] = nxt[b][u];
+        }
     }
 
     // scatter this wave's sums to LDS: Re R over I <= J, Xi Xr^T over all block pairs
