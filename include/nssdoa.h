@@ -118,20 +118,23 @@ typedef struct {
     double value;         /* P at idx evaluated in FP64, NaN for an unused slot                */
 } nssdoa_peak;
 
-/* Hermitian eigensolver of Step-2 (Table 2).  Both run in FP64 with one workgroup per frame.
- *   NSSDOA_EIG_QL:     Householder reduction to a real tridiagonal matrix, implicit QL with
- *                      Wilkinson's shift, back-transformation.  Block splits where
- *                      |e_i| <= eig_tol * (|d_i| + |d_{i+1}|); at most eig_max_iter QL
- *                      iterations per eigenvalue.  Eigenvalue errors are of the order of
- *                      eig_tol * ||R||.  The default.
- *   NSSDOA_EIG_JACOBI: cyclic complex Jacobi; stops when |r_pq| <= eig_tol * sqrt(r_pp r_qq) for
- *                      all p < q, at most eig_max_iter sweeps.  Slower, but small eigenvalues
- *                      are accurate relative to themselves. */
-typedef enum { NSSDOA_EIG_QL = 0, NSSDOA_EIG_JACOBI = 1 } nssdoa_eig_method;
+/* Hermitian eigensolver of Step-2 (Table 2).  All run in FP64 with one workgroup per frame and
+ * start from the Householder reduction of R to a real symmetric tridiagonal T (except Jacobi).
+ *   NSSDOA_EIG_AUTO:   M <= 16: eigenvalues of T by bisection (Sturm counts, to 2 eps ||T||),
+ *                      eigenvectors by inverse iteration with modified Gram-Schmidt
+ *                      orthonormalisation; larger M: as NSSDOA_EIG_QL.  The default.
+ *   NSSDOA_EIG_QL:     implicit QL with Wilkinson's shift on T; the block splits where
+ *                      |e_i| <= eig_tol * (|d_i| + |d_{i+1}|); at most eig_max_iter QL iterations
+ *                      per eigenvalue.
+ *   NSSDOA_EIG_JACOBI: cyclic complex Jacobi on R; stops when |r_pq| <= eig_tol * sqrt(r_pp r_qq)
+ *                      for all p < q, at most eig_max_iter sweeps.  Slower, but small eigenvalues
+ *                      are accurate relative to themselves.
+ * Eigenvalue errors of AUTO and QL are of the order of eps ||R||. */
+typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } nssdoa_eig_method;
 
 /* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */
 typedef struct {
-    double eig_tol;           /* eigensolver tolerance (see nssdoa_eig_method), (0, 1); 1e-15  */
+    double eig_tol;           /* QL / Jacobi tolerance (see nssdoa_eig_method), (0, 1); 1e-15  */
     int32_t eig_max_iter;     /* QL iterations per eigenvalue / Jacobi sweeps, 1..1000; 30     */
     int32_t refine_halfwidth; /* FP64 re-evaluation window around each candidate peak, 1..16; 4 */
     double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 2e-3 */
@@ -141,7 +144,7 @@ typedef struct {
                                  [32, 16384].  A tuning knob: it moves frames' rows within the
                                  32-row MFMA tiles, so FP32 spectra may change in their last
                                  bits; peaks are re-picked in FP64                              */
-    int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_QL                              */
+    int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_AUTO                            */
 } nssdoa_options;
 
 typedef struct nssdoa_plan_s* nssdoa_plan;

@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
                 ("eig_method", ctypes.c_int32)]
 
 
-EIG_METHODS = {"ql": 0, "jacobi": 1}
+EIG_METHODS = {"auto": 0, "ql": 1, "jacobi": 2}
 
 
 PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8")])

@@ -145,15 +145,15 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     opt.lowq_tau = 2e-3;
     opt.extra_candidates = 4;
     opt.scan_rows = 0;
-    opt.eig_method = NSSDOA_EIG_QL;
+    opt.eig_method = NSSDOA_EIG_AUTO;
     if (options) {
         opt = *options;
         if (!(opt.eig_tol > 0.0 && opt.eig_tol < 1.0))
             return fail(NSSDOA_EINVAL, "eig_tol must be in (0, 1)");
         if (opt.eig_max_iter < 1 || opt.eig_max_iter > 1000)
             return fail(NSSDOA_EINVAL, "eig_max_iter must be in [1, 1000]");
-        if (opt.eig_method != NSSDOA_EIG_QL && opt.eig_method != NSSDOA_EIG_JACOBI)
-            return fail(NSSDOA_EINVAL, "eig_method must be NSSDOA_EIG_QL or NSSDOA_EIG_JACOBI");
+        if (opt.eig_method != NSSDOA_EIG_AUTO && opt.eig_method != NSSDOA_EIG_QL && opt.eig_method != NSSDOA_EIG_JACOBI)
+            return fail(NSSDOA_EINVAL, "eig_method must be NSSDOA_EIG_AUTO, NSSDOA_EIG_QL or NSSDOA_EIG_JACOBI");
         if (opt.refine_halfwidth < 1 || opt.refine_halfwidth > 16)
             return fail(NSSDOA_EINVAL, "refine_halfwidth must be in [1, 16]");
         if (!(opt.lowq_tau >= 0.0) || !isfinite(opt.lowq_tau))

@@ -136,6 +136,208 @@ __device__ inline double block_sum_fast(double v, double* red) {
     return r;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Tridiagonal eigenpairs by bisection and inverse iteration (M <= kBisectMaxM, one wave).  The
+// eigenvalues are found together by multisection: lane j + 16 p evaluates the Sturm count (the
+// number of negative pivots of T - x I, each pivot floored at pivmin in magnitude) at the point
+// p + 1 of 5 equally spaced points inside eigenvalue j's current interval, so every iteration
+// shrinks each interval fivefold; the number of iterations is fixed by the Gershgorin interval and
+// the tolerance 2 eps ||T|| + 4 pivmin.  Lane j then solves (T - lambda_j I) x = b three times by
+// LU with partial pivoting (a zero pivot is replaced by eps ||T||) from a pseudo-random start,
+// the vectors are orthonormalised by modified Gram-Schmidt, solved once more and orthonormalised
+// again (the second solve removes what the first orthonormalisation mixed in from far
+// eigenvectors when a cluster's vectors were nearly dependent).
+constexpr int kBisectMaxM = 16;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Deterministic pseudo-random start of inverse iteration, in [-1, 1).
+__device__ __forceinline__ double ii_start(int i, int j) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u + (uint32_t)j * 0x85EBCA77u + 0x165667B1u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (double)h * 0x1p-31 - 1.0;
+}
+
+// T from dq (diagonal) and eq (off-diagonal, eq[M-1] = 0).  Writes the eigenvalues in ascending
+// order to dq and eigenvector j as column j of Z (.x, row stride ld).  Every lane of the wave
+// calls it; cs: 64 ints of LDS.
+__device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2* Z, int ld, int* cs) {
+    constexpr int MB = kBisectMaxM;
+    constexpr double eps = 0x1p-52;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, p = lane >> 4;
+    double d[MB], e[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        d[i] = i < M ? dq[i] : 0.0;
+        e[i] = i < M - 1 ? eq[i] : 0.0;
+    }
+    double gl = INFINITY, gu = -INFINITY, e2max = 0.0;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        if (i < M) {
+            const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+            gl = fmin(gl, d[i] - r);
+            gu = fmax(gu, d[i] + r);
+            e2max = fmax(e2max, e[i] * e[i]);
+        }
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    double lam = 0.0;
+    if (tnorm > 0.0) {
+        const double pivmin = DBL_MIN * fmax(1.0, e2max);
+        const double pad = 2.1 * (tnorm * eps * M + 2.0 * pivmin);
+        double lo = gl - pad, hi = gu + pad;
+        const double tol = 2.0 * eps * tnorm + 4.0 * pivmin;
+        const int its = min(64, max(1, (int)ceil(log2((hi - lo) / tol) / log2(5.0))));
+        for (int it = 0; it < its; ++it) {
+            const double w = hi - lo;
+            const double x = lo + w * (0.2 * (p + 1));
+            double q = d[0] - x;
+            q = fabs(q) < pivmin ? -pivmin : q;
+            int cnt = q < 0.0;
+#pragma unroll
+            for (int i = 1; i < MB; ++i) {
+                if (i < M) {
+                    q = (d[i] - x) - (e[i - 1] * e[i - 1]) * rcp64(q);
+                    q = fabs(q) < pivmin ? -pivmin : q;
+                    cnt += q < 0.0;
+                }
+            }
+            cs[lane] = cnt;
+            wave_sync();
+            const int c0 = cs[j], c1 = cs[j + 16], c2 = cs[j + 32], c3 = cs[j + 48];
+            wave_sync();
+            // the first point below which more than j eigenvalues lie bounds eigenvalue j above
+            const int k = c0 > j ? 0 : c1 > j ? 1 : c2 > j ? 2 : c3 > j ? 3 : 4;
+            const double nlo = k == 0 ? lo : lo + w * (0.2 * k);
+            const double nhi = k == 4 ? hi : lo + w * (0.2 * (k + 1));
+            lo = nlo;
+            hi = nhi;
+        }
+        lam = 0.5 * (lo + hi);
+    }
+
+    double z[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) z[i] = (tnorm == 0.0 && i == lane) ? 1.0 : 0.0;
+    if (tnorm > 0.0) {
+        // LU with partial pivoting of T - lam I (lanes j < M; rows i, i+1 per step)
+        const double epsp = eps * tnorm;
+        double mul[MB], ru1[MB], u2[MB], u3[MB];
+        uint32_t piv = 0;
+        double u = d[0] - lam, v = e[0];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            mul[i] = 0.0;
+            ru1[i] = 0.0;
+            u2[i] = 0.0;
+            u3[i] = 0.0;
+            if (i < M - 1) {
+                const double ei = e[i], ai1 = d[i + 1] - lam, ei1 = (i + 1 < MB) ? e[i + 1] : 0.0;
+                const bool sw = fabs(u) < fabs(ei);
+                const double den = sw ? ei : (u == 0.0 ? epsp : u);
+                const double rden = rcp64(den);
+                const double m = (sw ? u : ei) * rden;
+                ru1[i] = rden;
+                u2[i] = sw ? ai1 : v;
+                u3[i] = sw ? ei1 : 0.0;
+                const double nu = sw ? fma(-m, ai1, v) : fma(-m, v, ai1);
+                v = sw ? -m * ei1 : ei1;
+                u = nu;
+                mul[i] = m;
+                piv |= (uint32_t)sw << i;
+            } else if (i == M - 1) {
+                ru1[i] = rcp64(fabs(u) < epsp ? (u < 0.0 ? -epsp : epsp) : u);
+            }
+        }
+        // x = (T - lam I)^-1 b for b scaled to unit max norm
+        auto solve = [&](double (&x)[MB]) {
+            double b[MB];
+            double mx = 0.0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) mx = fmax(mx, fabs(x[i]));
+            const double s = mx > 0.0 ? 1.0 / mx : 1.0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) b[i] = x[i] * s;
+#pragma unroll
+            for (int i = 0; i < MB - 1; ++i) {
+                if (i < M - 1) {
+                    const bool sw = (piv >> i) & 1u;
+                    const double bi = b[i], bi1 = b[i + 1];
+                    b[i] = sw ? bi1 : bi;
+                    b[i + 1] = sw ? fma(-mul[i], bi1, bi) : fma(-mul[i], bi, bi1);
+                }
+            }
+            double x1 = 0.0, x2 = 0.0;
+#pragma unroll
+            for (int i = MB - 1; i >= 0; --i) {
+                if (i < M) {
+                    const double xi = (b[i] - u2[i] * x1 - u3[i] * x2) * ru1[i];
+                    x[i] = xi;
+                    x2 = x1;
+                    x1 = xi;
+                } else {
+                    x[i] = 0.0;
+                }
+            }
+        };
+        auto normalise = [&](double (&x)[MB]) {
+            double n2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) n2 = fma(x[i], x[i], n2);
+            const double r = n2 > 0.0 ? rsq_full(n2) : 0.0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) x[i] *= r;
+        };
+        // modified Gram-Schmidt over the lanes' vectors in lane order
+        auto mgs = [&]() {
+            for (int k = 0; k < M; ++k) {
+                double zk[MB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) zk[i] = readlane_f64(z[i], k);
+                normalise(zk);
+                if (lane == k) {
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) z[i] = zk[i];
+                } else if (lane > k && lane < M) {
+                    double dt = 0.0;
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) dt = fma(zk[i], z[i], dt);
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) z[i] = fma(-dt, zk[i], z[i]);
+                }
+            }
+        };
+        if (lane < M) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i) z[i] = i < M ? ii_start(i, lane) : 0.0;
+            solve(z);
+            solve(z);
+            solve(z);
+            normalise(z);
+        }
+        mgs();
+        if (lane < M) {
+            solve(z);
+            normalise(z);
+        }
+        mgs();
+    }
+    if (lane < M) {
+        dq[lane] = lam;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < M) Z[i * ld + lane] = make_double2(z[i], 0.0);
+    }
+}
+
 struct Rot {
     int p, q;
     double c, s, t;   // t = tan * |r_pq|, the shift of the two diagonal entries
@@ -558,6 +760,7 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
     __shared__ double dq[64], eq[64];      // diagonal and off-diagonal of T (eq[i] couples i, i+1)
     __shared__ double2 tq[64];             // tau_k
     __shared__ double2 vb[64], wb[64];     // the current reflector v and the vector w of its update
+    __shared__ int bcs[64];                // Sturm counts of the bisection
     __shared__ int bad;
 
     const int fidx = flist[blockIdx.x];
@@ -657,6 +860,10 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
             eq[M - 1] = 0.0;
         }
         __syncthreads();
+        const bool bisect = prm.method == NSSDOA_EIG_AUTO && M <= kBisectMaxM && bd == 64;
+        if (bisect) {
+            tridiag_eig_bisect(M, dq, eq, A, ld, bcs);
+        } else {
         for (int e = tid; e < Mp * Mp; e += bd) {
             const int i = e / Mp, j = e - i * Mp;
             A[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);      // Z = I
@@ -736,6 +943,7 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
             }
             dq[lane] = dl;
         }
+        }
         __syncthreads();
 
         // V = H_0 (H_1 (... H_{M-2} Z)); H_k Z = Z - tau_k v_k (v_k^H Z).  Four lanes own one
@@ -773,7 +981,7 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
     if (n_frames <= 0) return hipSuccess;
     if (max_M < 2 || max_M > 64) return hipErrorInvalidValue;
     const int Mp = max_M + (max_M & 1);
-    if (p.method == NSSDOA_EIG_QL) {
+    if (p.method != NSSDOA_EIG_JACOBI) {
         const int threads = max_M <= 16 ? 64 : max_M <= 32 ? 128 : 256;
         const size_t lds = (size_t)2 * Mp * (Mp + 1) * sizeof(double2);
         if (lds > 65536) {

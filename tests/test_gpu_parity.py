@@ -111,7 +111,7 @@ def _custom_frame(X):
                  angles_deg=np.zeros(1), grid_start=-90.0, grid_step=1.0, grid_L=180, X=X)
 
 
-@pytest.mark.parametrize("method", ["ql", "jacobi"])
+@pytest.mark.parametrize("method", ["auto", "ql", "jacobi"])
 def test_eigensolvers_across_sizes_and_structures(method):
     # Both solvers against the oracle's LAPACK eigensolve for M = 2 .. 64 (odd, even, the
     # maximum), and on structures that stress the deflation logic: a scaled identity (T is
@@ -151,7 +151,7 @@ def test_eigensolver_iteration_limit_sets_status():
     from paper_2007_14135_amd.api import Options
     from paper_2007_14135_amd import ST_EVD_NOT_CONVERGED
     fs = make_frames("c2", n_frames=2, N=1024, grid_step=0.1)
-    for method in ("ql", "jacobi"):
+    for method in ("ql", "jacobi"):      # the bisection of "auto" (M <= 16) always completes
         db, res = _run(fs, "music", "c64", options=Options(eig_method=method, eig_max_iter=1))
         assert np.all(res["status"] & ST_EVD_NOT_CONVERGED), (method, res["status"])
 
