@@ -138,11 +138,12 @@ __device__ inline double block_sum_fast(double v, double* red) {
 
 // ---------------------------------------------------------------------------------------------
 // Tridiagonal eigenpairs by bisection and inverse iteration (M <= kBisectMaxM, one wave).  The
-// eigenvalues are found together by multisection: lane j + 16 p evaluates the Sturm count (the
-// number of negative pivots of T - x I, each pivot floored at pivmin in magnitude) at the point
-// p + 1 of 5 equally spaced points inside eigenvalue j's current interval, so every iteration
-// shrinks each interval fivefold; the number of iterations is fixed by the Gershgorin interval and
-// the tolerance 2 eps ||T|| + 4 pivmin.  Lane j then solves (T - lambda_j I) x = b three times by
+// eigenvalues are found together: a coarse pass counts eigenvalues below 64 points across the
+// Gershgorin interval (Sturm counts: the number of negative pivots of T - x I, each pivot floored
+// at pivmin in magnitude), then multisection: lane j + 16 p counts at point p + 1 of 5 equally
+// spaced points inside eigenvalue j's current interval, so every iteration shrinks each interval
+// fivefold; the number of iterations is fixed by the interval and the tolerance
+// 2 eps ||T|| + 4 pivmin.  Lane j then solves (T - lambda_j I) x = b three times by
 // LU with partial pivoting (a zero pivot is replaced by eps ||T||) from a pseudo-random start,
 // the vectors are orthonormalised by modified Gram-Schmidt, solved once more and orthonormalised
 // again (the second solve removes what the first orthonormalisation mixed in from far
@@ -193,31 +194,47 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
     if (tnorm > 0.0) {
         const double pivmin = DBL_MIN * fmax(1.0, e2max);
         const double pad = 2.1 * (tnorm * eps * M + 2.0 * pivmin);
-        double lo = gl - pad, hi = gu + pad;
-        const double tol = 2.0 * eps * tnorm + 4.0 * pivmin;
-        const int its = min(64, max(1, (int)ceil(log2((hi - lo) / tol) / log2(5.0))));
-        for (int it = 0; it < its; ++it) {
-            const double w = hi - lo;
-            const double x = lo + w * (0.2 * (p + 1));
+        // Sturm count at x: eigenvalues of T below x (the reciprocal to about 2^-48 suffices:
+        // the count is then exact for a matrix within a few 1e-15 ||T|| of T)
+        auto sturm = [&](double x) {
             double q = d[0] - x;
             q = fabs(q) < pivmin ? -pivmin : q;
             int cnt = q < 0.0;
 #pragma unroll
             for (int i = 1; i < MB; ++i) {
                 if (i < M) {
-                    q = (d[i] - x) - (e[i - 1] * e[i - 1]) * rcp64(q);
+                    q = (d[i] - x) - (e[i - 1] * e[i - 1]) * rcp_approx(q);
                     q = fabs(q) < pivmin ? -pivmin : q;
                     cnt += q < 0.0;
                 }
             }
-            cs[lane] = cnt;
+            return cnt;
+        };
+        // coarse pass: lane k counts at the point k + 1 of 65 across the Gershgorin interval, and
+        // each eigenvalue takes the first point above which it lies
+        const double g0 = gl - pad, gw = (gu + pad) - g0;
+        const int c = sturm(g0 + gw * ((double)(lane + 1) * (1.0 / 65.0)));
+        int kf = 64;
+        for (int jj = 0; jj < M; ++jj) {
+            const unsigned long long bal = __ballot(c > jj);
+            const int k = bal ? __builtin_ctzll(bal) : 64;
+            kf = (j == jj) ? k : kf;
+        }
+        double lo = kf == 0 ? g0 : g0 + gw * ((double)kf * (1.0 / 65.0));
+        double hi = kf == 64 ? g0 + gw : g0 + gw * ((double)(kf + 1) * (1.0 / 65.0));
+        const double tol = 2.0 * eps * tnorm + 4.0 * pivmin;
+        const int its = min(64, max(1, (int)ceil(log2(gw * (1.0 / 65.0) / tol) / log2(5.0)) + 1));
+        // multisection: lane j + 16 p counts at point p + 1 of 5 inside eigenvalue j's interval
+        for (int it = 0; it < its; ++it) {
+            const double w = hi - lo;
+            cs[lane] = sturm(lo + w * ((double)(p + 1) * 0.2));
             wave_sync();
             const int c0 = cs[j], c1 = cs[j + 16], c2 = cs[j + 32], c3 = cs[j + 48];
             wave_sync();
             // the first point below which more than j eigenvalues lie bounds eigenvalue j above
             const int k = c0 > j ? 0 : c1 > j ? 1 : c2 > j ? 2 : c3 > j ? 3 : 4;
-            const double nlo = k == 0 ? lo : lo + w * (0.2 * k);
-            const double nhi = k == 4 ? hi : lo + w * (0.2 * (k + 1));
+            const double nlo = k == 0 ? lo : lo + w * ((double)k * 0.2);
+            const double nhi = k == 4 ? hi : lo + w * ((double)(k + 1) * 0.2);
             lo = nlo;
             hi = nhi;
         }
