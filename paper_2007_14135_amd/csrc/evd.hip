@@ -545,9 +545,12 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         // Real embedding of B for the scan: column k gives two rows over the inner index
         // kk in [0, 2M):  re-row (Re b, Im b) and im-row (-Im b, Re b), so that the row dot the
         // embedded steering (Re a, Im a) is Re(b^H a) and Im(b^H a).  Rows are packed per 32-row
-        // tile as [64 lanes][M values], in the operand order of the scan's MFMA:
-        //   FP32 (32x32x2):        lane h*32+i holds inner kk = 2s + h of row i at position s;
-        //   BF16/FP16 (32x32x16):  lane h*32+i holds inner kk = 16s + 8h + t at position 8s + t.
+        // tile in the operand order of the scan's MFMA:
+        //   FP32 (32x32x2):        lane h*32+i holds inner kk = 2s + h of row i as value s, stored
+        //                          [M/4][64 lanes][4 values] so that lane-contiguous float4 reads
+        //                          are conflict-free in LDS and coalesced in global memory;
+        //   BF16/FP16 (32x32x16):  [64 lanes][M values], lane h*32+i holds inner kk = 16s + 8h + t
+        //                          at position 8s + t.
         const GroupDev& g = groups[fr.group];
         const int rows = fr.emb_rows, inner = 2 * M;
         for (int e = tid; e < rows * inner; e += bd) {
@@ -563,7 +566,8 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
             const int tile = r >> 5, i = r & 31;
             if (prm.write_emb == 1) {
                 const int h = kk & 1, s2 = kk >> 1;
-                reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * 64 + h * 32 + i) * M + s2] = v;
+                reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * (M / 4) + (s2 >> 2)) * 256 +
+                                                        (h * 32 + i) * 4 + (s2 & 3)] = v;
             } else {
                 const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
                 const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;

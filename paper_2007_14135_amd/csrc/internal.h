@@ -57,7 +57,7 @@ struct GroupDev {
     int32_t M, L;
     int32_t pos_off, n_tiles;   // packed FP32 B tiles of 32 rows
     double grid_start, grid_step;
-    int64_t ws_emb;             // byte offset of n_tiles * 64 lanes * M floats
+    int64_t ws_emb;             // byte offset of n_tiles 32-row MFMA operand tiles of 64 M values
     int32_t blk_off;            // offset of this group's 8-row-block -> frame table
     int32_t pad;
     int64_t steer_off;          // FP32 scans: float offset of the group's steering table, else -1
@@ -464,6 +464,7 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
 hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
                               hipStream_t s);
 constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
+constexpr int kScanMaxBlocks = kScanLdsBytes / (64 * 8 * 4) * 4;   // 8-row blocks of one, M >= 8
 // Low-Q list of a batch: an int count (reset by the covariance launch), then cap (frame, index).
 struct LowqList {
     int* count;

@@ -245,15 +245,15 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
         const float* T = steer + g.steer_off;
         steering_load_w<M>(T, a0 + j, h, st0);
         steering_load_w<M>(T, a0 + 32 + j, h, st1);
-        const float* emb = reinterpret_cast<const float*>(ws + g.ws_emb) + (size_t)lane * M;
+        const float4* emb = reinterpret_cast<const float4*>(ws + g.ws_emb) + lane;   // [tile][M/4][64]
         const int t0 = fr.emb_row0 >> 5, t1 = ((fr.emb_row0 + 2 * fr.K - 1) >> 5) + 1;
         float q0 = 0.0f, q1 = 0.0f;
         for (int t = t0; t < t1; ++t) {
             float b[M];
-            const float4* src = reinterpret_cast<const float4*>(emb + (size_t)t * 64 * M);
+            const float4* src = emb + (size_t)t * (16 * M);
 #pragma unroll
             for (int v = 0; v < M / 4; ++v) {
-                const float4 x = src[v];
+                const float4 x = src[v * 64];
                 b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
             }
             floatx16 acc0 = {0.0f}, acc1 = {0.0f};

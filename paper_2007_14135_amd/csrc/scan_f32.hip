@@ -84,43 +84,52 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
         steering_load<M>(T, base + 32 + j, h, st1);
     }
 
-    // the work item's B tiles, staged once in LDS for the four waves (they share every row)
+    // the work item's B tiles, staged once in LDS for the four waves (they share every row), and
+    // per 8-row block its frame with that frame's output row, low-Q threshold and flag
     extern __shared__ float4 embs[];
     __shared__ ScanLowq lq;
+    __shared__ __align__(16) int bfr[kScanMaxBlocks];
+    __shared__ float bthr[kScanMaxBlocks];
+    __shared__ float* bout[kScanMaxBlocks];
+    __shared__ int* bflag[kScanMaxBlocks];
     constexpr int kTile4 = 64 * M / 4;                       // float4 per 32-row tile
+    const int nblk = (it.t1 - it.t0) * 4;
     if (threadIdx.x == 0) lq.n = 0;
     {
         const float4* src = reinterpret_cast<const float4*>(ws + g.ws_emb) + (size_t)it.t0 * kTile4;
         const int n4 = (it.t1 - it.t0) * kTile4;
         for (int i = threadIdx.x; i < n4; i += blockDim.x) embs[i] = src[i];
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+            const int f = blkframe[g.blk_off + it.t0 * 4 + i];
+            bfr[i] = f;
+            if (f >= 0) {
+                const FrameDev& fd = frames[f];
+                bout[i] = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
+                bthr[i] = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
+                bflag[i] = reinterpret_cast<int*>(ws + fd.ws_lowq);
+            }
+        }
     }
     __syncthreads();
-    const int4* blk4 = reinterpret_cast<const int4*>(blkframe + g.blk_off);
     float q0 = 0.0f, q1 = 0.0f;
-    int cur = -1;
+    int cur = -1, curf = -1;                     // a block and the frame being summed (-1: padding)
 
-    auto flush = [&](int f) {
+    auto flush = [&](int bi) {
         const float t0 = q0 + __shfl_xor(q0, 32);
         const float t1 = q1 + __shfl_xor(q1, 32);
         const float v = (lane < 32) ? t0 : t1;
         const int l = base + lane;          // col tile lane/32, angle lane%32
-        const FrameDev& fd = frames[f];
         const bool in = l < g.L;
-        if (in) {
-            float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
-            out[l] = 1.0f / fmaxf(v, FLT_MIN);
-        }
-        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
-        scan_lowq_collect(in && v < thr, f, wave * kScanAnglesPerWave + lane, lq,
-                          reinterpret_cast<int*>(ws + fd.ws_lowq));
+        if (in) bout[bi][l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
+        scan_lowq_collect(in && v < bthr[bi], bfr[bi], wave * kScanAnglesPerWave + lane, lq, bflag[bi]);
     };
 
     for (int t = it.t0; t < it.t1; ++t) {
         float b[M];
-        const float4* src = embs + (t - it.t0) * kTile4 + lane * (M / 4);
+        const float4* src = embs + (t - it.t0) * kTile4 + lane;
 #pragma unroll
         for (int v = 0; v < M / 4; ++v) {
-            const float4 x = src[v];
+            const float4 x = src[v * 64];
             b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
         }
         floatx16 a0 = {0.0f}, a1 = {0.0f};
@@ -129,14 +138,16 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
             a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st0[s], a0, 0, 0, 0);
             a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st1[s], a1, 0, 0, 0);
         }
-        const int4 fb = blk4[t];
+        const int b0 = (t - it.t0) * 4;
+        const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
         const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
         for (int gq = 0; gq < 4; ++gq) {
             const int f = fbk[gq];
-            if (f != cur) {
-                if (cur >= 0) flush(cur);
-                cur = f;
+            if (f != curf) {
+                if (curf >= 0) flush(cur);
+                cur = b0 + gq;
+                curf = f;
                 q0 = 0.0f;
                 q1 = 0.0f;
             }
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
                   a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
         }
     }
-    if (cur >= 0) flush(cur);
+    if (curf >= 0) flush(cur);
     __syncthreads();
     scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
