@@ -145,9 +145,10 @@ __device__ inline double block_sum_fast(double v, double* red) {
 // fivefold; the number of iterations is fixed by the interval and the tolerance
 // 2 eps ||T|| + 4 pivmin.  Lane j then solves (T - lambda_j I) x = b three times by
 // LU with partial pivoting (a zero pivot is replaced by eps ||T||) from a pseudo-random start,
-// the vectors are orthonormalised by modified Gram-Schmidt, solved once more and orthonormalised
-// again (the second solve removes what the first orthonormalisation mixed in from far
-// eigenvectors when a cluster's vectors were nearly dependent).
+// the vectors are orthonormalised by modified Gram-Schmidt within clusters of close eigenvalues,
+// solved once more and orthonormalised again (the second solve removes what the first
+// orthonormalisation mixed in from far eigenvectors when a cluster's vectors were nearly
+// dependent).
 constexpr int kBisectMaxM = 16;
 
 __device__ __forceinline__ void wave_sync() {
@@ -305,17 +306,33 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
                 }
             }
         };
-        auto normalise = [&](double (&x)[MB]) {
-            double n2 = 0.0;
+        // dot products with four partial sums (MB is a multiple of 4)
+        auto dot = [&](const double (&x)[MB], const double (&y)[MB]) {
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < MB; ++i) n2 = fma(x[i], x[i], n2);
+            for (int i = 0; i < MB; ++i) a[i & 3] = fma(x[i], y[i], a[i & 3]);
+            return (a[0] + a[1]) + (a[2] + a[3]);
+        };
+        auto normalise = [&](double (&x)[MB]) {
+            const double n2 = dot(x, x);
             const double r = n2 > 0.0 ? rsq_full(n2) : 0.0;
 #pragma unroll
             for (int i = 0; i < MB; ++i) x[i] *= r;
         };
-        // modified Gram-Schmidt over the lanes' vectors in lane order
+        // clusters: maximal runs of eigenvalues (ascending) less than 1e-3 ||T|| apart; bit k of
+        // cend is set when eigenvalue k ends its cluster.  Vectors of different clusters are
+        // orthogonal to about eps ||T|| / gap already, so Gram-Schmidt runs within clusters.
+        const double lam_next = __shfl_down(lam, 1);
+        const unsigned long long cend =
+            __ballot(lane < M && (lane == M - 1 || lam_next - lam > 1e-3 * tnorm)) | (1ull << (M - 1));
+        // modified Gram-Schmidt within each cluster, in lane order
         auto mgs = [&]() {
             for (int k = 0; k < M; ++k) {
+                if ((cend >> k) & 1ull) {            // last of its cluster: only normalised
+                    if (lane == k) normalise(z);
+                    continue;
+                }
+                const int ce = k + 2 + __builtin_ctzll(cend >> (k + 1));   // cluster end, exclusive
                 double zk[MB];
 #pragma unroll
                 for (int i = 0; i < MB; ++i) zk[i] = readlane_f64(z[i], k);
@@ -323,10 +340,8 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
                 if (lane == k) {
 #pragma unroll
                     for (int i = 0; i < MB; ++i) z[i] = zk[i];
-                } else if (lane > k && lane < M) {
-                    double dt = 0.0;
-#pragma unroll
-                    for (int i = 0; i < MB; ++i) dt = fma(zk[i], z[i], dt);
+                } else if (lane > k && lane < ce) {
+                    const double dt = dot(zk, z);
 #pragma unroll
                     for (int i = 0; i < MB; ++i) z[i] = fma(-dt, zk[i], z[i]);
                 }
