@@ -132,6 +132,18 @@ typedef struct {
  * Eigenvalue errors of AUTO and QL are of the order of eps ||R||. */
 typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } nssdoa_eig_method;
 
+/* Matrix-core kernel of the C64 (FP32-accuracy) scans of Step-5 (Table 2).  Both form the
+ * real-embedded product of the B tiles and the FP32 steering values and accumulate in FP32.
+ *   NSSDOA_C64_SCAN_SPLIT16: every FP32 operand x is split into FP16 parts x = hi + lo + r with
+ *                            |r| <= 2^-22 |x| (after an exact power-of-two scaling per frame and
+ *                            per steering table that keeps the parts in the FP16 range), and a b
+ *                            is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b on the FP16 matrix
+ *                            cores (v_mfma_f32_32x32x16_f16); the neglected terms are below
+ *                            2^-21 |a b|, the order of the FP32 accumulation error.  The default.
+ *   NSSDOA_C64_SCAN_FP32:    FP32 operands on v_mfma_f32_32x32x2f32.
+ * The windowed and learned estimators always use FP32 operands. */
+typedef enum { NSSDOA_C64_SCAN_SPLIT16 = 0, NSSDOA_C64_SCAN_FP32 = 1 } nssdoa_c64_scan;
+
 /* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */
 typedef struct {
     double eig_tol;           /* QL / Jacobi tolerance (see nssdoa_eig_method), (0, 1); 1e-15  */
@@ -145,6 +157,7 @@ typedef struct {
                                  32-row MFMA tiles, so FP32 spectra may change in their last
                                  bits; peaks are re-picked in FP64                              */
     int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_AUTO                            */
+    int32_t c64_scan;         /* nssdoa_c64_scan: matrix-core kernel of the C64 scans; 0       */
 } nssdoa_options;
 
 typedef struct nssdoa_plan_s* nssdoa_plan;

@@ -52,10 +52,11 @@ class Options(ctypes.Structure):
     _fields_ = [("eig_tol", ctypes.c_double), ("eig_max_iter", ctypes.c_int32),
                 ("refine_halfwidth", ctypes.c_int32), ("lowq_tau", ctypes.c_double),
                 ("extra_candidates", ctypes.c_int32), ("scan_rows", ctypes.c_int32),
-                ("eig_method", ctypes.c_int32)]
+                ("eig_method", ctypes.c_int32), ("c64_scan", ctypes.c_int32)]
 
 
 EIG_METHODS = {"auto": 0, "ql": 1, "jacobi": 2}
+C64_SCANS = {"split16": 0, "fp32": 1}
 
 
 PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8")])

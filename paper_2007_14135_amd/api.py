@@ -33,11 +33,14 @@ class Options:
     """Tunables of nssdoa_options (defaults as documented in the header)."""
 
     def __init__(self, eig_tol=1e-15, eig_max_iter=30, refine_halfwidth=4, lowq_tau=2e-3,
-                 extra_candidates=4, scan_rows=0, eig_method="auto"):
+                 extra_candidates=4, scan_rows=0, eig_method="auto", c64_scan="split16"):
         m = _abi.EIG_METHODS.get(eig_method, eig_method) if isinstance(eig_method, str) else int(eig_method)
         if isinstance(m, str):
             raise ValueError("eig_method must be one of %s" % sorted(_abi.EIG_METHODS))
-        self.c = _abi.Options(eig_tol, eig_max_iter, refine_halfwidth, lowq_tau, extra_candidates, scan_rows, m)
+        k = _abi.C64_SCANS.get(c64_scan, c64_scan) if isinstance(c64_scan, str) else int(c64_scan)
+        if isinstance(k, str):
+            raise ValueError("c64_scan must be one of %s" % sorted(_abi.C64_SCANS))
+        self.c = _abi.Options(eig_tol, eig_max_iter, refine_halfwidth, lowq_tau, extra_candidates, scan_rows, m, k)
 
 
 class Plan:

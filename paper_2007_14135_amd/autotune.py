@@ -21,7 +21,7 @@ import numpy as np
 
 # Revision of the scan kernels the cached choices were measured on; changing the kernels makes
 # old entries miss.
-KERNEL_REV = "scan-lds-3"
+KERNEL_REV = "scan-lds-4"
 
 CANDIDATES = {"c64": (64, 96, 128, 160, 192, 256, 320, 384, 512),
               "bf16": (512, 1024, 2048, 4096, 8192, 16384),
@@ -29,9 +29,10 @@ CANDIDATES = {"c64": (64, 96, 128, 160, 192, 256, 320, 384, 512),
 
 
 def signature(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequence[tuple], alg: str,
-              prec: str) -> str:
+              prec: str, kernel: str = "split16") -> str:
     """A digest of what the scan schedule depends on: per (array, grid) group its M, its L and
-    the multiset of noise-subspace ranks K of its frames, plus the algorithm and precision."""
+    the multiset of noise-subspace ranks K of its frames, plus the algorithm, the precision and
+    the C64 scan kernel."""
     groups: Dict[Tuple[int, int], list] = {}
     for f in frames:
         a, g, D = int(f[0]), int(f[1]), int(f[3])
@@ -42,7 +43,8 @@ def signature(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequ
     for (a, g), ks in sorted(groups.items()):
         M = int(np.asarray(arrays[a]).reshape(-1, 3).shape[0])
         desc.append((M, int(grids[g][2]), tuple(np.bincount(ks).tolist())))
-    return hashlib.sha1(repr((KERNEL_REV, alg, prec, desc)).encode()).hexdigest()[:20]
+    key = (KERNEL_REV, alg, prec, desc) if prec != "c64" else (KERNEL_REV, alg, prec, kernel, desc)
+    return hashlib.sha1(repr(key).encode()).hexdigest()[:20]
 
 
 def choose(timings: Dict[int, float]) -> int:
@@ -90,7 +92,8 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
     if prec == "c128":
         return 0, {}
     dev = device_name()
-    sig = signature(arrays, grids, frames, alg, prec)
+    kernel = "split16" if options is None or options.c.c64_scan == 0 else "fp32"
+    sig = signature(arrays, grids, frames, alg, prec, kernel)
     cache = Cache(cache_path)
     hit = cache.get(dev, sig)
     if hit is not None:
@@ -103,7 +106,7 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
         else:
             c = options.c
             opt = Options(c.eig_tol, c.eig_max_iter, c.refine_halfwidth, c.lowq_tau, c.extra_candidates, int(rows),
-                          c.eig_method)
+                          c.eig_method, c.c64_scan)
         db = prepare(arrays, grids, frames, X_flat, alg, prec, max_D, with_spectrum=False, options=opt, X_device=X_dev)
         X_dev = db.X
         db.run()

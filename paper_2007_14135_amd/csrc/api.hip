@@ -106,7 +106,8 @@ struct nssdoa_batch_s {
     int32_t* d_plist = nullptr;
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
-    float* d_steer = nullptr;                   // steering tables of the FP32 scans (batch-owned)
+    float* d_steer = nullptr;                   // steering tables of the C64 scans (batch-owned)
+    bool split16 = false;                       // C64 scans on FP16 split operands
     int live_graphs = 0;
     // timing
     uint32_t timing = 0;                        // stages with HIP events (bit 1 << stage)
@@ -146,6 +147,7 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     opt.extra_candidates = 4;
     opt.scan_rows = 0;
     opt.eig_method = NSSDOA_EIG_AUTO;
+    opt.c64_scan = NSSDOA_C64_SCAN_SPLIT16;
     if (options) {
         opt = *options;
         if (!(opt.eig_tol > 0.0 && opt.eig_tol < 1.0))
@@ -162,6 +164,8 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
             return fail(NSSDOA_EINVAL, "extra_candidates must be in [0, 16]");
         if (opt.scan_rows != 0 && (opt.scan_rows < 32 || opt.scan_rows > 16384 || opt.scan_rows % 32 != 0))
             return fail(NSSDOA_EINVAL, "scan_rows must be 0 or a multiple of 32 in [32, 16384]");
+        if (opt.c64_scan != NSSDOA_C64_SCAN_SPLIT16 && opt.c64_scan != NSSDOA_C64_SCAN_FP32)
+            return fail(NSSDOA_EINVAL, "c64_scan must be NSSDOA_C64_SCAN_SPLIT16 or NSSDOA_C64_SCAN_FP32");
     }
     auto* p = new (std::nothrow) nssdoa_plan_s();
     if (!p) return fail(NSSDOA_ENOMEM, "host allocation failed");
@@ -265,6 +269,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->n_frames = n_frames;
     b->max_D = max_D;
     b->spec_elem = prec == NSSDOA_C128 ? sizeof(double) : sizeof(float);
+    b->split16 = prec == NSSDOA_C64 && plan->opt.c64_scan == NSSDOA_C64_SCAN_SPLIT16;
 
     // positions table (one copy per array)
     std::vector<int> pos_off(n_arr);
@@ -342,7 +347,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.ws_evals = (int64_t)off;   off = align_up(off + (size_t)fd.M * 8);
         fd.ws_evecs = (int64_t)off;   off = align_up(off + MM * 16);
         fd.ws_B = (int64_t)off;       off = align_up(off + (size_t)fd.M * fd.K * 16);
-        fd.ws_qref = (int64_t)off;    off = align_up(off + 8);
+        fd.ws_qref = (int64_t)off;    off = align_up(off + 16);   // ||B||_F^2, then the FP16 split Q scale
         // candidate chunks: one per 4096 grid points, plus one per window of windowed estimation
         const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk + kMaxWindows;
         fd.ws_cand = (int64_t)off;    off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
@@ -364,7 +369,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         off = align_up(off + 256 + (size_t)b->lowq_all_cap * sizeof(int2));
     }
     int64_t steer_floats = 0;
-    for (auto& gd : b->groups) gd.steer_off = -1;
+    for (auto& gd : b->groups) gd.steer_off = gd.steer_x16_off = -1;
     if (prec != NSSDOA_C128) {
         const bool lp = prec != NSSDOA_C64;
         // rows of stacked B per scan work item: the 16-bit scans form their steering operands
@@ -412,6 +417,10 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             if (!lp) {
                 gd.steer_off = steer_floats;
                 steer_floats += (steer_table_floats(gd.M, gd.L) + 63) / 64 * 64;
+                if (b->split16) {   // the split table holds as many bytes as the FP32 one
+                    gd.steer_x16_off = steer_floats;
+                    steer_floats += (steer_table_floats(gd.M, gd.L) + 63) / 64 * 64;
+                }
             }
             const int n_at = (gd.L + kScanAnglesPerWG - 1) / kScanAnglesPerWG;
             for (auto& ch : chunks)
@@ -522,6 +531,9 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         if (gd.steer_off < 0) continue;
         e = launch_steer_table(b->d_pos + gd.pos_off, gd.M, gd.grid_start, gd.grid_step, gd.L,
                                b->d_steer + gd.steer_off, nullptr);
+        if (e == hipSuccess && gd.steer_x16_off >= 0)
+            e = launch_steer_table_split16(b->d_pos + gd.pos_off, gd.M, gd.grid_start, gd.grid_step, gd.L,
+                                           b->d_steer + gd.steer_x16_off, nullptr);
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -742,7 +754,9 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     ep.tol = opt.eig_tol;
     ep.max_iter = opt.eig_max_iter;
     ep.method = opt.eig_method;
-    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? 1 : batch->prec == NSSDOA_BF16 ? 2 : 3;
+    // operand tiles of the scan: FP32 (the windowed scans always take these), FP16 split, BF16, FP16
+    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split16 && !wa ? 4 : 1)
+                                                         : batch->prec == NSSDOA_BF16 ? 2 : 3;
     for (auto& r : batch->peak_ranges) {
         e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
                        batch->d_frames, batch->d_groups, ws, status, s);
@@ -809,7 +823,12 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if (e != hipSuccess) return hip_fail(e, "FP64 scan launch");
     } else {
         for (auto& r : batch->scan_ranges) {
-            if (batch->prec == NSSDOA_C64)
+            if (batch->prec == NSSDOA_C64 && batch->split16)
+                e = launch_scan_split16(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
+                                        batch->scan_max_tiles[&r - &batch->scan_ranges[0]],
+                                        batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,
+                                        static_cast<float*>(spec), use_user, (float)opt.lowq_tau, lql, s);
+            else if (batch->prec == NSSDOA_C64)
                 e = launch_scan_f32(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
                                     batch->scan_max_tiles[&r - &batch->scan_ranges[0]],
                                     batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,

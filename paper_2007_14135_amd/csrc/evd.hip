@@ -565,9 +565,24 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         //                          [M/4][64 lanes][4 values] so that lane-contiguous float4 reads
         //                          are conflict-free in LDS and coalesced in global memory;
         //   BF16/FP16 (32x32x16):  [64 lanes][M values], lane h*32+i holds inner kk = 16s + 8h + t
-        //                          at position 8s + t.
+        //                          at position 8s + t;
+        //   FP16 split (32x32x16): [part][M/8][64 lanes][8 values] with the lane mapping of the
+        //                          16-bit tiles, part 0 = hi = fp16(2^e v), part 1 = lo =
+        //                          fp16(2^e v - hi); 2^e puts the largest |component| of B in
+        //                          [2^12, 2^13) and the scan's Q scale 2^-2e / 2^26 goes to qref[1].
         const GroupDev& g = groups[fr.group];
         const int rows = fr.emb_rows, inner = 2 * M;
+        double bscale = 1.0;
+        if (prm.write_emb == 4) {
+            double mx = 0.0;
+            for (int e = tid; e < M * K; e += bd) mx = fmax(mx, fmax(fabs(Bs[e].x), fabs(Bs[e].y)));
+            mx = block_max(mx, red);
+            if (mx > 0.0 && isfinite(mx)) bscale = ldexp(1.0, 12 - ilogb(mx));
+            if (tid == 0) {
+                const double sab = (double)kSplitSteerScale * bscale;
+                qref[1] = 1.0 / (sab * sab);
+            }
+        }
         for (int e = tid; e < rows * inner; e += bd) {
             const int rl = e / inner, kk = e - rl * inner;
             const int col = rl >> 1;
@@ -583,6 +598,20 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                 const int h = kk & 1, s2 = kk >> 1;
                 reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * (M / 4) + (s2 >> 2)) * 256 +
                                                         (h * 32 + i) * 4 + (s2 & 3)] = v;
+            } else if (prm.write_emb == 4) {
+                double vd = 0.0;
+                if (col < K) {
+                    const double2 b = Bs[col * M + (kk < M ? kk : kk - M)];
+                    vd = (rl & 1) == 0 ? (kk < M ? b.x : b.y) : (kk < M ? -b.y : b.x);
+                }
+                vd *= bscale;
+                const _Float16 hi = (_Float16)vd;
+                const _Float16 lo = (_Float16)(vd - (double)hi);
+                const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
+                _Float16* o = reinterpret_cast<_Float16*>(ws + g.ws_emb);
+                const size_t o0 = (((size_t)tile * 2 * (M / 8) + s16) * 64 + h * 32 + i) * 8 + t;
+                o[o0] = hi;
+                o[o0 + (size_t)(M / 8) * 512] = lo;
             } else {
                 const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
                 const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;

@@ -61,7 +61,15 @@ struct GroupDev {
     int32_t blk_off;            // offset of this group's 8-row-block -> frame table
     int32_t pad;
     int64_t steer_off;          // FP32 scans: float offset of the group's steering table, else -1
+    int64_t steer_x16_off;      // FP16 split scan: float offset of the group's split table, else -1
 };
+
+// Split steering table of a group for the FP16 split scan (same rows as the FP32 table, same
+// bytes): for grid index l, part p (0: hi, 1: lo) and h = 0, 1, the M halves at
+// ((4 l + 2 p + h) M + 8 s + t) hold part p of 2^13 v for the inner index k = 16 s + 8 h + t of
+// the real-embedded steering vector (v = Re a_k for k < M, Im a_(k-M) otherwise, the FP32 value
+// of the FP32 table): hi = fp16(2^13 v), lo = fp16(2^13 v - hi).
+constexpr float kSplitSteerScale = 8192.0f;
 
 // Steering table of a group for the FP32 scans: for grid index l (rounded up to whole 256-angle
 // tiles) and h = 0, 1, the M floats T[(2 l + h) M + k] are Re a_{2k+h}(theta_l) for k < M/2 and
@@ -463,6 +471,8 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
                       hipStream_t s);
 hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
                               hipStream_t s);
+hipError_t launch_steer_table_split16(const double* pos, int M, double start, double step, int L, float* table,
+                                      hipStream_t s);
 constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
 constexpr int kScanMaxBlocks = kScanLdsBytes / (64 * 8 * 4) * 4;   // 8-row blocks of one, M >= 8
 // Low-Q list of a batch: an int count (reset by the covariance launch), then cap (frame, index).
@@ -474,6 +484,9 @@ struct LowqList {
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user_spec, float lowq_tau, LowqList lq, hipStream_t s);
+hipError_t launch_scan_split16(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
+                               const FrameDev* frames, const int32_t* blkframe, const float* steer,
+                               char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s);
 hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
                           const FrameDev* frames, const int32_t* blkframe, const double* pos, char* ws,
                           float* spec, int use_user, float lowq_tau, LowqList lq, hipStream_t s);

@@ -30,6 +30,7 @@ namespace nssdoa {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 // One thread per (angle, element): a_m(theta_l) into the group's steering table (see internal.h).
 __global__ void steer_table_kernel(const double* __restrict__ pos, int M, double start, double step, int L,
@@ -47,6 +48,32 @@ __global__ void steer_table_kernel(const double* __restrict__ pos, int M, double
     const int h = m & 1, j = m >> 1;
     T[(size_t)(2 * l + h) * M + j] = co;
     T[(size_t)(2 * l + h) * M + M / 2 + j] = s;
+}
+
+// One thread per (angle, element): the FP16 split steering table (layout in internal.h) from the
+// same FP32 values as steer_table_kernel.
+__global__ void steer_split_kernel(const double* __restrict__ pos, int M, double start, double step, int L,
+                                   int Lpad, _Float16* __restrict__ T) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Lpad * M) return;
+    const int l = t / M, m = t - l * M;
+    float s = 0.0f, co = 0.0f;
+    if (l < L) {
+        double sth, cth;
+        sincos(grid_angle(start, step, l) * kDeg2Rad, &sth, &cth);
+        const double c = fma(pos[3 * m], sth, pos[3 * m + 1] * cth);   // cycles, phi = 90 deg
+        sincospif((float)(2.0 * (c - rint(c))), &s, &co);
+    }
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {   // inner k = m (Re a_m) and k = M + m (Im a_m)
+        const int k = part == 0 ? m : M + m;
+        const float v = (part == 0 ? co : s) * kSplitSteerScale;   // exact: a power of two
+        const _Float16 hi = (_Float16)v;
+        const _Float16 lo = (_Float16)(v - (float)hi);               // v - hi is exact in FP32
+        const int s16 = k >> 4, h = (k >> 3) & 1, tt = k & 7;
+        T[((size_t)4 * l + h) * M + 8 * s16 + tt] = hi;
+        T[((size_t)4 * l + 2 + h) * M + 8 * s16 + tt] = lo;
+    }
 }
 
 // The steering operand of lane h*32 + j for grid index l: M contiguous floats of the table.
@@ -162,6 +189,139 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
     scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
+// The FP16 split scan (C64 default): the same work items, LDS staging, per-frame reduction and
+// low-Q collection as scan_f32_kernel, on v_mfma_f32_32x32x16_f16.  Each FP32 product a b of the
+// real-embedded contraction is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b of the operands'
+// FP16 parts (B tiles scaled per frame by 2^e, steering by 2^13, both exact), accumulated in FP32;
+// the frame's Q is the sum of squares times its scale 2^-2e 2^-26 (qref[1]).
+// Operand layout (D[i][j] += sum_k A[i][k] B[k][j], k < 16 per step s): lane h*32+i holds
+// A[i][16s + 8h .. 16s + 8h + 7] (B rows) and lane h*32+j holds B[16s + 8h .. +7][j] (steering);
+// the result layout is that of the FP32 32x32 instruction.
+template <int M>
+__global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __restrict__ items,
+                                                           const GroupDev* __restrict__ groups,
+                                                           const FrameDev* __restrict__ frames,
+                                                           const int32_t* __restrict__ blkframe,
+                                                           const float* __restrict__ steer,
+                                                           char* __restrict__ ws,
+                                                           float* __restrict__ spec, int use_user,
+                                                           float lowq_tau, LowqList lql) {
+    constexpr int S = M / 8;                                 // 16-deep MFMA steps over 2M
+    const ScanItem it = items[blockIdx.x];
+    const GroupDev& g = groups[it.group];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const int base = it.angle_tile * kScanAnglesPerWG + wave * kScanAnglesPerWave;
+
+    halfx8 sh0[S], sl0[S], sh1[S], sl1[S];
+    {
+        const _Float16* T = reinterpret_cast<const _Float16*>(steer + g.steer_x16_off);
+        const int j = lane & 31;
+        const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (base + j) + h) * M);
+        const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (base + 32 + j) + h) * M);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            sh0[s] = p0[s];
+            sl0[s] = p0[2 * S + s];          // part 1 is 2M halves further
+            sh1[s] = p1[s];
+            sl1[s] = p1[2 * S + s];
+        }
+    }
+
+    extern __shared__ halfx8 embx[];
+    __shared__ ScanLowq lq;
+    __shared__ __align__(16) int bfr[kScanMaxBlocks];
+    __shared__ float bthr[kScanMaxBlocks];
+    __shared__ float bqs[kScanMaxBlocks];
+    __shared__ float* bout[kScanMaxBlocks];
+    __shared__ int* bflag[kScanMaxBlocks];
+    constexpr int kTile8 = 2 * S * 64;                       // halfx8 per 32-row tile (both parts)
+    const int nblk = (it.t1 - it.t0) * 4;
+    if (threadIdx.x == 0) lq.n = 0;
+    {
+        const halfx8* src = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + (size_t)it.t0 * kTile8;
+        const int n8 = (it.t1 - it.t0) * kTile8;
+        for (int i = threadIdx.x; i < n8; i += blockDim.x) embx[i] = src[i];
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+            const int f = blkframe[g.blk_off + it.t0 * 4 + i];
+            bfr[i] = f;
+            if (f >= 0) {
+                const FrameDev& fd = frames[f];
+                const double* qr = reinterpret_cast<const double*>(ws + fd.ws_qref);
+                bout[i] = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
+                bthr[i] = lowq_tau * (float)qr[0];
+                bqs[i] = (float)qr[1];
+                bflag[i] = reinterpret_cast<int*>(ws + fd.ws_lowq);
+            }
+        }
+    }
+    __syncthreads();
+    float q0 = 0.0f, q1 = 0.0f;
+    int cur = -1, curf = -1;                     // a block and the frame being summed (-1: padding)
+
+    auto flush = [&](int bi) {
+        const float t0 = q0 + __shfl_xor(q0, 32);
+        const float t1 = q1 + __shfl_xor(q1, 32);
+        const float v = ((lane < 32) ? t0 : t1) * bqs[bi];
+        const int l = base + lane;          // col tile lane/32, angle lane%32
+        const bool in = l < g.L;
+        if (in) bout[bi][l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
+        scan_lowq_collect(in && v < bthr[bi], bfr[bi], wave * kScanAnglesPerWave + lane, lq, bflag[bi]);
+    };
+
+    for (int t = it.t0; t < it.t1; ++t) {
+        halfx8 bh[S], bl[S];
+        const halfx8* src = embx + (t - it.t0) * kTile8 + lane;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            bh[s] = src[s * 64];
+            bl[s] = src[(S + s) * 64];
+        }
+        floatx16 a0 = {0.0f}, a1 = {0.0f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sh0[s], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sh1[s], a1, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sl0[s], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sl1[s], a1, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s], sh0[s], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s], sh1[s], a1, 0, 0, 0);
+        }
+        const int b0 = (t - it.t0) * 4;
+        const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
+        const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+            const int f = fbk[gq];
+            if (f != curf) {
+                if (curf >= 0) flush(cur);
+                cur = b0 + gq;
+                curf = f;
+                q0 = 0.0f;
+                q1 = 0.0f;
+            }
+            q0 += a0[4 * gq] * a0[4 * gq] + a0[4 * gq + 1] * a0[4 * gq + 1] +
+                  a0[4 * gq + 2] * a0[4 * gq + 2] + a0[4 * gq + 3] * a0[4 * gq + 3];
+            q1 += a1[4 * gq] * a1[4 * gq] + a1[4 * gq + 1] * a1[4 * gq + 1] +
+                  a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
+        }
+    }
+    if (curf >= 0) flush(cur);
+    __syncthreads();
+    scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
+}
+
+template <int M>
+hipError_t launch_split(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
+                        const FrameDev* frames, const int32_t* blkframe, const float* steer, char* ws, float* spec,
+                        int use_user, float tau, LowqList lq, hipStream_t s) {
+    const size_t lds = (size_t)max_tiles * 64 * M * sizeof(float);    // two FP16 parts per value
+    hipLaunchKernelGGL(scan_split16_kernel<M>, dim3(n_items), dim3(256), lds, s, items, groups, frames,
+                       blkframe, steer, ws, spec, use_user, tau, lq);
+    return hipGetLastError();
+}
+
 template <int M>
 hipError_t launch_m(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                     const FrameDev* frames, const int32_t* blkframe, const float* steer, char* ws, float* spec,
@@ -181,6 +341,29 @@ hipError_t launch_steer_table(const double* pos, int M, double start, double ste
     hipLaunchKernelGGL(steer_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, M, start, step,
                        L, Lpad, table);
     return hipGetLastError();
+}
+
+hipError_t launch_steer_table_split16(const double* pos, int M, double start, double step, int L, float* table,
+                                      hipStream_t s) {
+    const int Lpad = steer_table_rows(L);
+    const int64_t n = (int64_t)Lpad * M;
+    hipLaunchKernelGGL(steer_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, M, start, step,
+                       L, Lpad, reinterpret_cast<_Float16*>(table));
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_split16(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
+                               const FrameDev* frames, const int32_t* blkframe, const float* steer,
+                               char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if ((size_t)max_tiles * 64 * M * sizeof(float) > kScanLdsBytes) return hipErrorInvalidValue;
+    switch (M) {
+        case 8: return launch_split<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 16: return launch_split<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 32: return launch_split<32>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 64: return launch_split<64>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,

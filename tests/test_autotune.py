@@ -22,6 +22,7 @@ def test_signature_depends_on_shape_only():
     assert s == autotune.signature(arrays, grids, fb, "music", "c64")
     assert s != autotune.signature(arrays, grids, fa, "music", "bf16")
     assert s != autotune.signature(arrays, grids, fa, "mn", "c64")
+    assert s != autotune.signature(arrays, grids, fa, "music", "c64", "fp32")
     fc = [(0, 0, 4096, 3, 0, 4096, 0)] + fa[1:]                                           # another rank K
     assert s != autotune.signature(arrays, grids, fc, "music", "c64")
 

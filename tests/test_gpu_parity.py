@@ -156,14 +156,16 @@ def test_eigensolver_iteration_limit_sets_status():
         assert np.all(res["status"] & ST_EVD_NOT_CONVERGED), (method, res["status"])
 
 
+@pytest.mark.parametrize("kernel", ["split16", "fp32"])
 @pytest.mark.parametrize("alg", ["music", "ev", "mn", "phd"])
-def test_c2_frames_fp32_scan_parity(alg):
+def test_c2_frames_fp32_scan_parity(alg, kernel):
     # 12 frames of the 16-element workload at its full 18000-point grid (71 angle tiles, ragged
-    # last tile) and full 4096 snapshots.
+    # last tile) and full 4096 snapshots, on both C64 scan kernels (FP16 split, FP32 operands).
+    from paper_2007_14135_amd.api import Options
     fs = make_frames("c2", n_frames=12)
-    db, res = _run(fs, alg, "c64")
+    db, res = _run(fs, alg, "c64", options=Options(c64_scan=kernel))
     assert np.all(res["status"] == 0), res["status"]
-    _check_frames(fs, res, alg, 1e-4, 1e-8, "c2-" + alg)
+    _check_frames(fs, res, alg, 1e-4, 1e-8, "c2-%s-%s" % (alg, kernel))
 
 
 @pytest.mark.parametrize("alg", ["phd", "music", "ev", "mn"])
@@ -174,9 +176,11 @@ def test_c1_fp64_parity(alg):
     _check_frames(fs, res, alg, 1e-9, 1e-9, "c1-" + alg)
 
 
-def test_uneven_frames_chunking_and_groups():
+@pytest.mark.parametrize("kernel", ["split16", "fp32"])
+def test_uneven_frames_chunking_and_groups(kernel):
     # Mixed M, geometry, D and grid in one batch: several groups, several launches, ragged
-    # row chunks (K varies, rows padded to 8), M-bucketed peak kernels.
+    # row chunks (K varies, rows padded to 8), M-bucketed peak kernels; both C64 scan kernels.
+    from paper_2007_14135_amd.api import Options
     frames = []
     for i in range(24):
         fr = make_frame("c3", i, N=512)
@@ -184,9 +188,9 @@ def test_uneven_frames_chunking_and_groups():
             fr = make_frame("c3", i, N=512, grid_step=0.01)
         frames.append(fr)
     fs = pack_frames(frames, dtype=np.complex64)
-    db, res = _run(fs, "music", "c64", max_D=16)
+    db, res = _run(fs, "music", "c64", max_D=16, options=Options(c64_scan=kernel))
     assert np.all(res["status"] & 0x7 == 0), res["status"]
-    _check_frames(fs, res, "music", 1e-4, 1e-8, "c3-mixed")
+    _check_frames(fs, res, "music", 1e-4, 1e-8, "c3-mixed-" + kernel)
 
 
 def test_many_frames_one_group_multiple_chunks():
