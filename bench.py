@@ -1,12 +1,13 @@
 """Throughput benchmark of the DOA hot path on one MI355X.
 
 One step = one nssdoa_estimate call over the whole batch: covariance, FP64 eigensolve and
-noise-subspace matrix, FP32 matrix-core spectrum scan, FP64 low-Q re-evaluation and peak
+noise-subspace matrix, FP32-accuracy matrix-core spectrum scan (FP16 hi/lo split operands with FP32
+accumulation by default; --c64-scan fp32 for FP32 operands), FP64 low-Q re-evaluation and peak
 selection, for 256 synthetic frames of the 16-element workload (N = 4096 snapshots, D = 4,
 18000-point grid at 0.01 deg), MUSIC.  Snapshots are resident in HBM before the timed region.
 
-Prints one JSON line with the throughput (spectrum points/s), the roofline position of the
-scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
+Prints one JSON line with the throughput (spectrum points/s), the same step with the other C64
+scan kernel for comparison, the roofline position of the scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
 counter summary while the kernel source is unchanged), the FP64 oracle's throughput on the host
 cores over a bounded sample of the same frames, and, when trained proposal weights are present,
 the learned-proposal workload (8192 frames, 0.001 deg grid) run by the learned path and by the
@@ -29,11 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP16_MFMA_TFLOPS = 2516.6
 PEAK_HBM_GBS = 8000.0
 METRIC = "MUSIC spectrum points/s & frames/s at ≤0.01° peak err, learned vs full scan"
 WEIGHTS = os.path.join(ROOT, "paper_2007_14135_amd", "weights", "proposal_ula16.npy")
 SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")
+PMC_SUMMARY = {"split16": os.path.join(ROOT, "profiles", "scan_split16_c2_music_pmc.txt"),
+               "fp32": os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")}
+SCAN_KERNEL = {"split16": "scan_split16_kernel<16>", "fp32": "scan_f32_kernel<16>"}
 TUNE_CACHE = os.path.join(ROOT, "paper_2007_14135_amd", "tuning", "autotune_cache.json")
 
 
@@ -97,12 +101,12 @@ def make_frames_parallel(config, n):
     return pack_frames(frames, dtype=np.complex64)
 
 
-def scan_traffic(scan_rows):
+def scan_traffic(scan_rows, kernel):
     """HBM bytes per scan launch from the committed counter summary, or None when the summary is
     missing or was taken on another version of the scan kernel or another work-item size."""
     try:
         kv = {}
-        with open(PMC_SUMMARY) as fh:
+        with open(PMC_SUMMARY[kernel]) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -201,6 +205,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-frames", type=int, default=8192)
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
+    ap.add_argument("--c64-scan", default="split16", choices=["split16", "fp32"],
+                    help="matrix-core kernel of the FP32-accuracy scan (FP16 hi/lo split or FP32 operands)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="JSON cache of autotuner choices")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (the reference of the HBM "
@@ -237,9 +244,10 @@ def main():
     rows, tune_ms = 0, {}
     if not args.no_tune:
         rows, tune_ms = autotune.tune(arrays, grids, frames, fs.X_flat, args.alg, "c64", D,
-                                      cache_path=args.tune_cache or None)
+                                      cache_path=args.tune_cache or None,
+                                      options=Options(c64_scan=args.c64_scan))
     db = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
-                 options=Options(scan_rows=rows))
+                 options=Options(scan_rows=rows, c64_scan=args.c64_scan))
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -276,6 +284,33 @@ def main():
     achieved_tflops = scan_flops / scan_avg_s / 1e12
     points = F * L
     value = points / (ms_step / 1e3)
+    split = args.c64_scan == "split16"
+    peak = PEAK_FP16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
+    # matrix-core flops executed: the split forms each product from three FP16 products
+    mfma_flops = scan_flops * (3.0 if split else 1.0)
+
+    # the same step with the other C64 scan kernel (its own tuned work items), for comparison
+    other = None
+    if not args.no_compare:
+        okern = "fp32" if split else "split16"
+        orows = 0
+        if not args.no_tune:
+            orows, _ = autotune.tune(arrays, grids, frames, fs.X_flat, args.alg, "c64", D,
+                                     cache_path=args.tune_cache or None, options=Options(c64_scan=okern))
+        db2 = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
+                      options=Options(scan_rows=orows, c64_scan=okern), X_device=db.X)
+        oms = _timed(lambda: db2.run(stream), args.steps, args.warmup, stream)
+        db2.batch.set_timing(["scan"])
+        for _ in range(min(args.steps, 10)):
+            db2.run(stream)
+        osc, osn = db2.batch.stage_time("scan")
+        db2.batch.set_timing(False)
+        o_avg = osc / max(osn, 1)
+        o_peak = PEAK_FP16_MFMA_TFLOPS if okern == "split16" else PEAK_FP32_MFMA_TFLOPS
+        other = {"c64_scan": okern, "scan_rows": orows or 384, "value": points / (oms / 1e3), "ms_per_step": oms,
+                 "scan_kernel": SCAN_KERNEL[okern], "scan_avg_launch_ms": o_avg,
+                 "scan_roofline_frac": scan_flops / (o_avg / 1e3) / 1e12 / o_peak, "scan_peak_tflops": o_peak}
+        del db2
 
     out = {
         "metric": METRIC,
@@ -288,30 +323,34 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16x3-split/f32-acc" if split else "f32",
         "data": "synthetic",
         "frames_per_s": F / (ms_step / 1e3),
         "config": {
             "workload": "ULA M=16, D=4, N=4096 complex64 snapshots, SNR U[0,20] dB, 256 frames, "
                         "grid [-90,90) at 0.01 deg (L=18000), %s; FP64 covariance/eigensolve/refinement, "
-                        "FP32 matrix-core scan" % args.alg.upper(),
+                        "FP32-accuracy matrix-core scan (%s)" % (args.alg.upper(),
+                        "FP16 hi/lo split operands, FP32 accumulation" if split else "FP32 operands"),
             "frames": F, "M": M, "D": D, "N": fr0.N, "L": L, "alg": args.alg,
-            "scan_rows": rows or 384,
+            "scan_rows": rows or 384, "c64_scan": args.c64_scan,
         },
         "autotune": {"knob": "scan_rows", "chosen": rows or 384,
                      "scan_ms_by_candidate": {str(k): v for k, v in tune_ms.items()}},
         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "roofline": {
-            "kernel": "scan_f32_kernel<16>",
+            "kernel": SCAN_KERNEL[args.c64_scan],
             "bound": "mfma",
             "achieved": achieved_tflops,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": scan_traffic(rows or 384) if args.alg == "music" else None,
+            "frac": achieved_tflops / peak,
+            "traffic": scan_traffic(rows or 384, args.c64_scan) if args.alg == "music" else None,
             "algorithmic_flops_per_launch": scan_flops,
+            "mfma_flops_per_launch": mfma_flops,
+            "mfma_frac": mfma_flops / scan_avg_s / 1e12 / peak,
             "avg_launch_ms": scan_avg_s * 1e3,
         },
+        "other_c64_scan": other,
         "host_wall_s": wall,
         "status_nonzero_frames": int(np.count_nonzero(res["status"])),
     }

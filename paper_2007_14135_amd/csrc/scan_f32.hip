@@ -76,6 +76,14 @@ __global__ void steer_split_kernel(const double* __restrict__ pos, int M, double
     }
 }
 
+// Sum over the two 32-row halves of a column tile pair: lanes 0-31 return q0(l) + q0(l + 32) and
+// lanes 32-63 return q1(l - 32) + q1(l) (one v_permlane32_swap: the upper half of q0 trades
+// places with the lower half of q1).
+__device__ inline float halves_sum(float q0, float q1) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(q0), __float_as_uint(q1), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // The steering operand of lane h*32 + j for grid index l: M contiguous floats of the table.
 template <int M>
 __device__ inline void steering_load(const float* __restrict__ T, int l, int h, float* st) {
@@ -102,6 +110,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5;
     const int base = it.angle_tile * kScanAnglesPerWG + wave * kScanAnglesPerWave;
+    const int gL = g.L;
 
     float st0[M], st1[M];
     {
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
     __shared__ ScanLowq lq;
     __shared__ __align__(16) int bfr[kScanMaxBlocks];
     __shared__ float bthr[kScanMaxBlocks];
-    __shared__ float* bout[kScanMaxBlocks];
+    __shared__ int64_t bso[kScanMaxBlocks];
     __shared__ int* bflag[kScanMaxBlocks];
     constexpr int kTile4 = 64 * M / 4;                       // float4 per 32-row tile
     const int nblk = (it.t1 - it.t0) * 4;
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
             bfr[i] = f;
             if (f >= 0) {
                 const FrameDev& fd = frames[f];
-                bout[i] = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
+                bso[i] = use_user ? fd.spec_off_user : fd.spec_off_ws;
                 bthr[i] = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
                 bflag[i] = reinterpret_cast<int*>(ws + fd.ws_lowq);
             }
@@ -142,12 +151,10 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
     int cur = -1, curf = -1;                     // a block and the frame being summed (-1: padding)
 
     auto flush = [&](int bi) {
-        const float t0 = q0 + __shfl_xor(q0, 32);
-        const float t1 = q1 + __shfl_xor(q1, 32);
-        const float v = (lane < 32) ? t0 : t1;
+        const float v = halves_sum(q0, q1);
         const int l = base + lane;          // col tile lane/32, angle lane%32
-        const bool in = l < g.L;
-        if (in) bout[bi][l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
+        const bool in = l < gL;
+        if (in) spec[bso[bi] + l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
         scan_lowq_collect(in && v < bthr[bi], bfr[bi], wave * kScanAnglesPerWave + lane, lq, bflag[bi]);
     };
 
@@ -213,6 +220,7 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5;
     const int base = it.angle_tile * kScanAnglesPerWG + wave * kScanAnglesPerWave;
+    const int gL = g.L;
 
     halfx8 sh0[S], sl0[S], sh1[S], sl1[S];
     {
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     __shared__ __align__(16) int bfr[kScanMaxBlocks];
     __shared__ float bthr[kScanMaxBlocks];
     __shared__ float bqs[kScanMaxBlocks];
-    __shared__ float* bout[kScanMaxBlocks];
+    __shared__ int64_t bso[kScanMaxBlocks];
     __shared__ int* bflag[kScanMaxBlocks];
     constexpr int kTile8 = 2 * S * 64;                       // halfx8 per 32-row tile (both parts)
     const int nblk = (it.t1 - it.t0) * 4;
@@ -249,7 +257,7 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
             if (f >= 0) {
                 const FrameDev& fd = frames[f];
                 const double* qr = reinterpret_cast<const double*>(ws + fd.ws_qref);
-                bout[i] = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
+                bso[i] = use_user ? fd.spec_off_user : fd.spec_off_ws;
                 bthr[i] = lowq_tau * (float)qr[0];
                 bqs[i] = (float)qr[1];
                 bflag[i] = reinterpret_cast<int*>(ws + fd.ws_lowq);
@@ -261,12 +269,10 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     int cur = -1, curf = -1;                     // a block and the frame being summed (-1: padding)
 
     auto flush = [&](int bi) {
-        const float t0 = q0 + __shfl_xor(q0, 32);
-        const float t1 = q1 + __shfl_xor(q1, 32);
-        const float v = ((lane < 32) ? t0 : t1) * bqs[bi];
+        const float v = halves_sum(q0, q1) * bqs[bi];
         const int l = base + lane;          // col tile lane/32, angle lane%32
-        const bool in = l < g.L;
-        if (in) bout[bi][l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
+        const bool in = l < gL;
+        if (in) spec[bso[bi] + l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
         scan_lowq_collect(in && v < bthr[bi], bfr[bi], wave * kScanAnglesPerWave + lane, lq, bflag[bi]);
     };
 
