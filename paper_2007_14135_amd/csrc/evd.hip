@@ -196,18 +196,25 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
         const double pivmin = DBL_MIN * fmax(1.0, e2max);
         const double pad = 2.1 * (tnorm * eps * M + 2.0 * pivmin);
         // Sturm count at x: eigenvalues of T below x (the reciprocal to about 2^-48 suffices:
-        // the count is then exact for a matrix within a few 1e-15 ||T|| of T)
+        // the count is then exact for a matrix within a few 1e-15 ||T|| of T).  T is padded to
+        // MB rows with decoupled diagonal entries above every point counted at (4 ||T|| + 1),
+        // which add nothing to the count, so the chain runs without branches.
+        double dp[MB], e2[MB];
+        const double big = 4.0 * tnorm + 1.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            dp[i] = i < M ? d[i] : big;
+            e2[i] = (i > 0 && i < M) ? e[i - 1] * e[i - 1] : 0.0;
+        }
         auto sturm = [&](double x) {
-            double q = d[0] - x;
+            double q = dp[0] - x;
             q = fabs(q) < pivmin ? -pivmin : q;
             int cnt = q < 0.0;
 #pragma unroll
             for (int i = 1; i < MB; ++i) {
-                if (i < M) {
-                    q = (d[i] - x) - (e[i - 1] * e[i - 1]) * rcp_approx(q);
-                    q = fabs(q) < pivmin ? -pivmin : q;
-                    cnt += q < 0.0;
-                }
+                q = (dp[i] - x) - e2[i] * rcp_approx(q);
+                q = fabs(q) < pivmin ? -pivmin : q;
+                cnt += q < 0.0;
             }
             return cnt;
         };
