@@ -6,6 +6,10 @@ accumulation by default; --c64-scan fp32 for FP32 operands), FP64 low-Q re-evalu
 selection, for 256 synthetic frames of the 16-element workload (N = 4096 snapshots, D = 4,
 18000-point grid at 0.01 deg), MUSIC.  Snapshots are resident in HBM before the timed region.
 
+The timed steps keep --streams whole batches in flight (step k on stream k mod S, each stream
+with its own copy of the snapshots, its own workspace and outputs), as a serving loop would; a
+second, single-stream pass gives the latency of one batch and times the scan kernel alone.
+
 Prints one JSON line with the throughput (spectrum points/s), the same step with the other C64
 scan kernel for comparison, the roofline position of the scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
 counter summary while the kernel source is unchanged), the FP64 oracle's throughput on the host
@@ -208,6 +212,9 @@ def main():
     ap.add_argument("--c64-scan", default="split16", choices=["split16", "fp32"],
                     help="matrix-core kernel of the FP32-accuracy scan (FP16 hi/lo split or FP32 operands)")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
+                         "workspace and outputs (1 = one batch at a time)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="JSON cache of autotuner choices")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (the reference of the HBM "
@@ -249,28 +256,56 @@ def main():
     db = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
                  options=Options(scan_rows=rows, c64_scan=args.c64_scan))
     stream = torch.cuda.current_stream()
+    S = max(1, args.streams)
 
-    for _ in range(args.warmup):
-        db.run(stream)
+    def in_flight(kernel, rows_k, first):
+        """S batches of the same frames, each with its own snapshot copy, workspace and outputs."""
+        out = [first]
+        for _ in range(S - 1):
+            out.append(prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
+                               options=Options(scan_rows=rows_k, c64_scan=kernel), X_device=first.X.clone()))
+        return out
+
+    streams = [stream] + [torch.cuda.Stream() for _ in range(S - 1)]   # default priority
+
+    def run_steps(batches, k_steps):
+        fork = torch.cuda.Event()
+        fork.record(stream)
+        for s_ in streams[1:]:
+            s_.wait_event(fork)
+        for k in range(k_steps):
+            batches[k % S].run(streams[k % S])
+        for s_ in streams[1:]:
+            stream.wait_stream(s_)
+
+    dbs = in_flight(args.c64_scan, rows, db)
+    run_steps(dbs, max(args.warmup, S))
     torch.cuda.synchronize()
 
-    # timed region: HIP events around the scan launch only (its live average for the roofline)
-    db.batch.set_timing(["scan"])
+    # timed region: K steps, step k on stream k mod S (whole batches in flight)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        db.run(stream)
+    run_steps(dbs, args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
+    res = db.host_results()
+    for extra in dbs[1:]:                         # every in-flight copy computed the same results
+        r2 = extra.host_results()
+        assert np.array_equal(r2["npeaks"], res["npeaks"]) and np.array_equal(r2["status"], res["status"])
+    del dbs[1:]
+
+    # one batch at a time: latency per step and the scan kernel's roofline (HIP events around
+    # the scan launch on its stream, the GPU otherwise idle)
+    db.batch.set_timing(["scan"])
+    lat_ms = _timed(lambda: db.run(stream), args.steps, 1, stream)
     scan_ms, scan_n = db.batch.stage_time("scan")
     db.batch.set_timing(False)
-    res = db.host_results()
     # stage breakdown from a separate, untimed pass (events around every stage)
     db.batch.set_timing(True)
     for _ in range(min(args.steps, 10)):
@@ -299,7 +334,18 @@ def main():
                                      cache_path=args.tune_cache or None, options=Options(c64_scan=okern))
         db2 = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
                       options=Options(scan_rows=orows, c64_scan=okern), X_device=db.X)
-        oms = _timed(lambda: db2.run(stream), args.steps, args.warmup, stream)
+        dbs2 = in_flight(okern, orows, db2)
+        run_steps(dbs2, max(args.warmup, S))
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run_steps(dbs2, args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        oms = e0.elapsed_time(e1) / args.steps
+        del dbs2[1:]
+        olat = _timed(lambda: db2.run(stream), args.steps, 1, stream)
         db2.batch.set_timing(["scan"])
         for _ in range(min(args.steps, 10)):
             db2.run(stream)
@@ -308,6 +354,7 @@ def main():
         o_avg = osc / max(osn, 1)
         o_peak = PEAK_FP16_MFMA_TFLOPS if okern == "split16" else PEAK_FP32_MFMA_TFLOPS
         other = {"c64_scan": okern, "scan_rows": orows or 384, "value": points / (oms / 1e3), "ms_per_step": oms,
+                 "latency_ms_one_batch": olat,
                  "scan_kernel": SCAN_KERNEL[okern], "scan_avg_launch_ms": o_avg,
                  "scan_roofline_frac": scan_flops / (o_avg / 1e3) / 1e12 / o_peak, "scan_peak_tflops": o_peak}
         del db2
@@ -318,7 +365,7 @@ def main():
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": max(args.warmup, S),
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -326,6 +373,9 @@ def main():
         "dtype": "f16x3-split/f32-acc" if split else "f32",
         "data": "synthetic",
         "frames_per_s": F / (ms_step / 1e3),
+        "batches_in_flight": S,
+        "latency_ms_one_batch": lat_ms,
+        "value_one_batch_at_a_time": points / (lat_ms / 1e3),
         "config": {
             "workload": "ULA M=16, D=4, N=4096 complex64 snapshots, SNR U[0,20] dB, 256 frames, "
                         "grid [-90,90) at 0.01 deg (L=18000), %s; FP64 covariance/eigensolve/refinement, "
