@@ -155,7 +155,8 @@ typedef struct {
                                  (384 for C64, 4096 for BF16/F16), else a multiple of 32 in
                                  [32, 16384].  A tuning knob: it moves frames' rows within the
                                  32-row MFMA tiles, so FP32 spectra may change in their last
-                                 bits; peaks are re-picked in FP64                              */
+                                 bits; peaks are re-picked in FP64.  C64 work items hold at most
+                                 65536 / (8 M) rows with FP32 operands, 1024 with the FP16 split */
     int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_AUTO                            */
     int32_t c64_scan;         /* nssdoa_c64_scan: matrix-core kernel of the C64 scans; 0       */
 } nssdoa_options;

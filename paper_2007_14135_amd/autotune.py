@@ -21,9 +21,10 @@ import numpy as np
 
 # Revision of the scan kernels the cached choices were measured on; changing the kernels makes
 # old entries miss.
-KERNEL_REV = "scan-lds-4"
+KERNEL_REV = "scan-5"
 
 CANDIDATES = {"c64": (64, 96, 128, 160, 192, 256, 320, 384, 512),
+              "c64-split16": (128, 192, 256, 384, 512, 768, 1024),
               "bf16": (512, 1024, 2048, 4096, 8192, 16384),
               "f16": (512, 1024, 2048, 4096, 8192, 16384)}
 
@@ -100,7 +101,7 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
         return hit, {}
     timings = {}
     X_dev = None
-    for rows in (candidates or CANDIDATES[prec]):
+    for rows in (candidates or CANDIDATES["c64-split16" if prec == "c64" and kernel == "split16" else prec]):
         if options is None:
             opt = Options(scan_rows=int(rows))
         else:

@@ -379,9 +379,11 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         const size_t emb_elem = lp ? 2 : sizeof(float);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             GroupDev& gd = b->groups[g];
-            // the FP32 scan stages a work item's rows in LDS (8M bytes per row)
+            // the FP32 scan stages a work item's rows in LDS (8M bytes per row); the FP16 split
+            // scan keeps only its per-block tables there (kScanMaxBlocks 8-row blocks)
             const int chunk_rows = lp ? chunk_rows_req
-                                      : std::min(chunk_rows_req, (int)(kScanLdsBytes / (8 * gd.M)) / 32 * 32);
+                                 : b->split16 ? std::min(chunk_rows_req, kScanMaxBlocks * 8)
+                                              : std::min(chunk_rows_req, (int)(kScanLdsBytes / (8 * gd.M)) / 32 * 32);
             int row = 0, chunk_start = 0, chunk_frames = 0;
             std::vector<std::pair<int, int>> chunks;
             int last_f = -1;

@@ -237,7 +237,6 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         }
     }
 
-    extern __shared__ halfx8 embx[];
     __shared__ ScanLowq lq;
     __shared__ __align__(16) int bfr[kScanMaxBlocks];
     __shared__ float bthr[kScanMaxBlocks];
@@ -246,11 +245,18 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     __shared__ int* bflag[kScanMaxBlocks];
     constexpr int kTile8 = 2 * S * 64;                       // halfx8 per 32-row tile (both parts)
     const int nblk = (it.t1 - it.t0) * 4;
+    // B tiles: each wave reads them from global memory (L2) itself, one tile ahead
+    const halfx8* emb = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + lane;
+    halfx8 nh[S], nl[S];
+    if (it.t0 < it.t1) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            nh[s] = emb[(size_t)it.t0 * kTile8 + s * 64];
+            nl[s] = emb[(size_t)it.t0 * kTile8 + (S + s) * 64];
+        }
+    }
     if (threadIdx.x == 0) lq.n = 0;
     {
-        const halfx8* src = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + (size_t)it.t0 * kTile8;
-        const int n8 = (it.t1 - it.t0) * kTile8;
-        for (int i = threadIdx.x; i < n8; i += blockDim.x) embx[i] = src[i];
         for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
             const int f = blkframe[g.blk_off + it.t0 * 4 + i];
             bfr[i] = f;
@@ -278,11 +284,17 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
 
     for (int t = it.t0; t < it.t1; ++t) {
         halfx8 bh[S], bl[S];
-        const halfx8* src = embx + (t - it.t0) * kTile8 + lane;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            bh[s] = src[s * 64];
-            bl[s] = src[(S + s) * 64];
+            bh[s] = nh[s];
+            bl[s] = nl[s];
+        }
+        if (t + 1 < it.t1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                nh[s] = emb[(size_t)(t + 1) * kTile8 + s * 64];
+                nl[s] = emb[(size_t)(t + 1) * kTile8 + (S + s) * 64];
+            }
         }
         floatx16 a0 = {0.0f}, a1 = {0.0f};
 #pragma unroll
@@ -322,8 +334,8 @@ template <int M>
 hipError_t launch_split(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                         const FrameDev* frames, const int32_t* blkframe, const float* steer, char* ws, float* spec,
                         int use_user, float tau, LowqList lq, hipStream_t s) {
-    const size_t lds = (size_t)max_tiles * 64 * M * sizeof(float);    // two FP16 parts per value
-    hipLaunchKernelGGL(scan_split16_kernel<M>, dim3(n_items), dim3(256), lds, s, items, groups, frames,
+    (void)max_tiles;
+    hipLaunchKernelGGL(scan_split16_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
                        blkframe, steer, ws, spec, use_user, tau, lq);
     return hipGetLastError();
 }
@@ -362,7 +374,7 @@ hipError_t launch_scan_split16(int M, const ScanItem* items, int n_items, int ma
                                const FrameDev* frames, const int32_t* blkframe, const float* steer,
                                char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if ((size_t)max_tiles * 64 * M * sizeof(float) > kScanLdsBytes) return hipErrorInvalidValue;
+    if (max_tiles * 4 > kScanMaxBlocks) return hipErrorInvalidValue;
     switch (M) {
         case 8: return launch_split<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
         case 16: return launch_split<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
