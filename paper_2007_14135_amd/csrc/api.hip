@@ -725,14 +725,15 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     const uint32_t timing = capturing ? 0u : batch->timing;
     auto stage_begin = [&](int stage) -> nssdoa_status {
         if (!(timing & (1u << stage))) return NSSDOA_OK;
-        hipError_t e = hipEventCreate(&ev0);
+        // timing-only events: no system-scope fence (no cache writeback around the timed stage)
+        hipError_t e = hipEventCreateWithFlags(&ev0, hipEventDisableSystemFence);
         if (e == hipSuccess) e = hipEventRecord(ev0, s);
         return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "hipEventRecord");
     };
     auto stage_end = [&](int stage) -> nssdoa_status {
         if (!(timing & (1u << stage))) return NSSDOA_OK;
         hipEvent_t ev1;
-        hipError_t e = hipEventCreate(&ev1);
+        hipError_t e = hipEventCreateWithFlags(&ev1, hipEventDisableSystemFence);
         if (e == hipSuccess) e = hipEventRecord(ev1, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         batch->pending.push_back({stage, ev0, ev1});
