@@ -141,7 +141,7 @@ typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } n
  *                            cores (v_mfma_f32_32x32x16_f16); the neglected terms are below
  *                            2^-21 |a b|, the order of the FP32 accumulation error.  The default.
  *   NSSDOA_C64_SCAN_FP32:    FP32 operands on v_mfma_f32_32x32x2f32.
- * The windowed and learned estimators always use FP32 operands. */
+ * The windowed and learned estimators use the same kernel choice. */
 typedef enum { NSSDOA_C64_SCAN_SPLIT16 = 0, NSSDOA_C64_SCAN_FP32 = 1 } nssdoa_c64_scan;
 
 /* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */

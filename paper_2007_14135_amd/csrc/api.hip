@@ -656,7 +656,7 @@ int persistent_grid(int per_cu) {
 
 nssdoa_status check_windowed(nssdoa_batch batch, const WindowArgs& wa, int* n_feat, int* n_bins) {
     if (batch->prec != NSSDOA_C64)
-        return fail(NSSDOA_EUNSUPPORTED, "windowed estimation runs the FP32 scan: create the batch with NSSDOA_C64");
+        return fail(NSSDOA_EUNSUPPORTED, "windowed estimation runs the C64 scans: create the batch with NSSDOA_C64");
     const int M = batch->frames[0].M;
     for (const FrameDev& fd : batch->frames)
         if (fd.M != M) return fail(NSSDOA_EUNSUPPORTED, "windowed estimation needs one array size in the batch");
@@ -757,8 +757,8 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     ep.tol = opt.eig_tol;
     ep.max_iter = opt.eig_max_iter;
     ep.method = opt.eig_method;
-    // operand tiles of the scan: FP32 (the windowed scans always take these), FP16 split, BF16, FP16
-    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split16 && !wa ? 4 : 1)
+    // operand tiles of the scans: FP32, FP16 split, BF16, FP16
+    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split16 ? 4 : 1)
                                                          : batch->prec == NSSDOA_BF16 ? 2 : 3;
     for (auto& r : batch->peak_ranges) {
         e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
@@ -797,7 +797,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
 
         if ((st = stage_begin(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
-        e = launch_scan_windows(M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
+        e = launch_scan_windows(batch->split16, M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
                                 static_cast<float*>(spec), use_user, (float)opt.lowq_tau, persistent_grid(8), s);
         if (e != hipSuccess) return hip_fail(e, "windowed scan launch");
         if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;

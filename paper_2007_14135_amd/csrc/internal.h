@@ -515,7 +515,7 @@ hipError_t launch_features(const int32_t* flist, int n, const FrameDev* frames, 
 hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
                             double half_window, float threshold, char* ws, const LearnedLayout& lay,
                             uint32_t* status, hipStream_t s);
-hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+hipError_t launch_scan_windows(bool split16, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
                                const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);
 hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,

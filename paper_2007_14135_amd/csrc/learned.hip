@@ -11,9 +11,10 @@
 // prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan);
 // expand_kernel, one wave per frame: the frame's scan items and peak chunks written out at those
 //   offsets, so that the kernels below read their work item with one load.
-// scan_win_kernel<M>, grid-stride over 64-angle items, one wave per item: one frame's angles in
-//   one window, contracted on the FP32 matrix cores with the frame's own 8-row blocks of the
-//   packed B tiles (the operands, steering table and epilogue of the group scan).
+// scan_win_kernel<M, SPLIT>, grid-stride over 64-angle items, one wave per item: one frame's
+//   angles in one window, contracted on the matrix cores with the frame's own 8-row blocks of the
+//   packed B tiles (the operands, steering tables and epilogue of the group scans: FP32 operands,
+//   or FP16 split operands with three products per FP32-accuracy product).
 // lowq_win_kernel<MB>, grid-stride over 64-entry slices of the frames' low-Q lists: FP64
 //   re-evaluation of the listed points.
 // winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
@@ -28,6 +29,7 @@ namespace nssdoa {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 constexpr int kHaloW = 16;
 
 __device__ inline double qnan_d() { return __longlong_as_double(0x7ff8000000000000LL); }
@@ -223,13 +225,14 @@ __device__ inline void steering_load_w(const float* __restrict__ T, int l, int h
     }
 }
 
-template <int M>
+template <int M, bool SPLIT>
 __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restrict__ frames, int n_frames,
                                                        const GroupDev* __restrict__ groups,
                                                        const int32_t* __restrict__ blkframe,
                                                        const float* __restrict__ steer, char* __restrict__ ws,
                                                        LearnedLayout lay, float* __restrict__ spec, int use_user,
                                                        float lowq_tau) {
+    constexpr int S = M / 8;                     // 16-deep steps of the FP16 split
     const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
     const int* ioff = reinterpret_cast<const int*>(ws + lay.off_item_off);
     const int total = ioff[n_frames];
@@ -241,27 +244,10 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
         const int a0 = it.y & 0xFFFFFF, a1 = a0 + (it.y >> 24);
         const FrameDev& fr = frames[f];
         const GroupDev& g = groups[fr.group];
-        float st0[M], st1[M];
-        const float* T = steer + g.steer_off;
-        steering_load_w<M>(T, a0 + j, h, st0);
-        steering_load_w<M>(T, a0 + 32 + j, h, st1);
-        const float4* emb = reinterpret_cast<const float4*>(ws + g.ws_emb) + lane;   // [tile][M/4][64]
+        const double* qr = reinterpret_cast<const double*>(ws + fr.ws_qref);
         const int t0 = fr.emb_row0 >> 5, t1 = ((fr.emb_row0 + 2 * fr.K - 1) >> 5) + 1;
         float q0 = 0.0f, q1 = 0.0f;
-        for (int t = t0; t < t1; ++t) {
-            float b[M];
-            const float4* src = emb + (size_t)t * (16 * M);
-#pragma unroll
-            for (int v = 0; v < M / 4; ++v) {
-                const float4 x = src[v * 64];
-                b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
-            }
-            floatx16 acc0 = {0.0f}, acc1 = {0.0f};
-#pragma unroll
-            for (int s = 0; s < M; ++s) {
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st0[s], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s], st1[s], acc1, 0, 0, 0);
-            }
+        auto fold = [&](const floatx16& acc0, const floatx16& acc1, int t) {
             const int4 fb = reinterpret_cast<const int4*>(blkframe + g.blk_off)[t];
             const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
@@ -272,16 +258,71 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
                 q1 += acc1[4 * gq] * acc1[4 * gq] + acc1[4 * gq + 1] * acc1[4 * gq + 1] +
                       acc1[4 * gq + 2] * acc1[4 * gq + 2] + acc1[4 * gq + 3] * acc1[4 * gq + 3];
             }
+        };
+        if constexpr (SPLIT) {
+            halfx8 sh0[S], sl0[S], sh1[S], sl1[S];
+            const _Float16* T = reinterpret_cast<const _Float16*>(steer + g.steer_x16_off);
+            const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (a0 + j) + h) * M);
+            const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (a0 + 32 + j) + h) * M);
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) {
+                sh0[s2] = p0[s2];
+                sl0[s2] = p0[2 * S + s2];
+                sh1[s2] = p1[s2];
+                sl1[s2] = p1[2 * S + s2];
+            }
+            const halfx8* emb = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + lane;   // [tile][part][S][64]
+            for (int t = t0; t < t1; ++t) {
+                halfx8 bh[S], bl[S];
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) {
+                    bh[s2] = emb[((size_t)t * 2 * S + s2) * 64];
+                    bl[s2] = emb[((size_t)t * 2 * S + S + s2) * 64];
+                }
+                floatx16 acc0 = {0.0f}, acc1 = {0.0f};
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) {
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sh0[s2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sh1[s2], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sl0[s2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sl1[s2], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], sh0[s2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], sh1[s2], acc1, 0, 0, 0);
+                }
+                fold(acc0, acc1, t);
+            }
+        } else {
+            float st0[M], st1[M];
+            const float* T = steer + g.steer_off;
+            steering_load_w<M>(T, a0 + j, h, st0);
+            steering_load_w<M>(T, a0 + 32 + j, h, st1);
+            const float4* emb = reinterpret_cast<const float4*>(ws + g.ws_emb) + lane;   // [tile][M/4][64]
+            for (int t = t0; t < t1; ++t) {
+                float b[M];
+                const float4* src = emb + (size_t)t * (16 * M);
+#pragma unroll
+                for (int v = 0; v < M / 4; ++v) {
+                    const float4 x = src[v * 64];
+                    b[4 * v] = x.x; b[4 * v + 1] = x.y; b[4 * v + 2] = x.z; b[4 * v + 3] = x.w;
+                }
+                floatx16 acc0 = {0.0f}, acc1 = {0.0f};
+#pragma unroll
+                for (int s2 = 0; s2 < M; ++s2) {
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s2], st0[s2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b[s2], st1[s2], acc1, 0, 0, 0);
+                }
+                fold(acc0, acc1, t);
+            }
         }
         const float u0 = q0 + __shfl_xor(q0, 32), u1 = q1 + __shfl_xor(q1, 32);
-        const float v = (lane < 32) ? u0 : u1;
+        const float v = ((lane < 32) ? u0 : u1) * (SPLIT ? (float)qr[1] : 1.0f);
         const int l = a0 + lane;
         const bool in = l < a1;
         if (in) {
             float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
         }
-        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fr.ws_qref);
+        const float thr = lowq_tau * (float)qr[0];
         lowq_append(in && v < thr, l, reinterpret_cast<int*>(ws + fr.ws_lowq), fr.lowq_cap);
     }
 }
@@ -427,13 +468,17 @@ hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* s
     return hipGetLastError();
 }
 
-hipError_t launch_scan_windows(int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+hipError_t launch_scan_windows(bool split16, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
                                const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s) {
-#define NSSDOA_WIN_CASE(MM)                                                                             \
-    case MM:                                                                                         \
-        hipLaunchKernelGGL(scan_win_kernel<MM>, dim3(n_wg), dim3(256), 0, s, frames, n_frames, groups, \
-                           blkframe, steer, ws, lay, spec, use_user, lowq_tau);                        \
+#define NSSDOA_WIN_CASE(MM)                                                                                   \
+    case MM:                                                                                               \
+        if (split16)                                                                                       \
+            hipLaunchKernelGGL((scan_win_kernel<MM, true>), dim3(n_wg), dim3(256), 0, s, frames, n_frames,  \
+                               groups, blkframe, steer, ws, lay, spec, use_user, lowq_tau);                 \
+        else                                                                                               \
+            hipLaunchKernelGGL((scan_win_kernel<MM, false>), dim3(n_wg), dim3(256), 0, s, frames, n_frames, \
+                               groups, blkframe, steer, ws, lay, spec, use_user, lowq_tau);                 \
         return hipGetLastError();
     switch (M) {
         NSSDOA_WIN_CASE(8)
