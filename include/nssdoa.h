@@ -149,7 +149,7 @@ typedef struct {
     double eig_tol;           /* QL / Jacobi tolerance (see nssdoa_eig_method), (0, 1); 1e-15  */
     int32_t eig_max_iter;     /* QL iterations per eigenvalue / Jacobi sweeps, 1..1000; 30     */
     int32_t refine_halfwidth; /* FP64 re-evaluation window around each candidate peak, 1..16; 4 */
-    double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 2e-3 */
+    double lowq_tau;          /* C64: FP64 re-evaluation below lowq_tau * ||B||_F^2, >= 0; 5e-4 */
     int32_t extra_candidates; /* local maxima kept beyond D for the FP64 re-pick, 0..16; 4     */
     int32_t scan_rows;        /* rows of stacked B per matrix-core scan work item: 0 = default
                                  (384 for C64, 4096 for BF16/F16), else a multiple of 32 in

@@ -32,7 +32,7 @@ def _stream_handle(stream) -> Optional[int]:
 class Options:
     """Tunables of nssdoa_options (defaults as documented in the header)."""
 
-    def __init__(self, eig_tol=1e-15, eig_max_iter=30, refine_halfwidth=4, lowq_tau=2e-3,
+    def __init__(self, eig_tol=1e-15, eig_max_iter=30, refine_halfwidth=4, lowq_tau=5e-4,
                  extra_candidates=4, scan_rows=0, eig_method="auto", c64_scan="split16"):
         m = _abi.EIG_METHODS.get(eig_method, eig_method) if isinstance(eig_method, str) else int(eig_method)
         if isinstance(m, str):

@@ -143,7 +143,7 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     opt.eig_tol = 1e-15;
     opt.eig_max_iter = 30;
     opt.refine_halfwidth = 4;
-    opt.lowq_tau = 2e-3;
+    opt.lowq_tau = 5e-4;
     opt.extra_candidates = 4;
     opt.scan_rows = 0;
     opt.eig_method = NSSDOA_EIG_AUTO;
