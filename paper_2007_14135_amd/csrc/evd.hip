@@ -590,6 +590,32 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                 qref[1] = 1.0 / (sab * sab);
             }
         }
+        if (prm.write_emb == 4) {
+            // FP16 split: eight consecutive inner indices (one lane's 16-byte operand) per thread
+            typedef _Float16 halfx8v __attribute__((ext_vector_type(8)));
+            halfx8v* o8 = reinterpret_cast<halfx8v*>(ws + g.ws_emb);
+            for (int u = tid; u < rows * (inner / 8); u += bd) {
+                const int rl = u / (inner / 8), kk0 = (u - rl * (inner / 8)) * 8;
+                const int col = rl >> 1, re = kk0 < M, m0 = re ? kk0 : kk0 - M;
+                halfx8v hi8, lo8;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    double vd = 0.0;
+                    if (col < K) {
+                        const double2 bv = Bs[col * M + m0 + t];
+                        vd = (rl & 1) == 0 ? (re ? bv.x : bv.y) : (re ? -bv.y : bv.x);
+                    }
+                    vd *= bscale;
+                    const _Float16 hi = (_Float16)vd;
+                    hi8[t] = hi;
+                    lo8[t] = (_Float16)(vd - (double)hi);
+                }
+                const int r = fr.emb_row0 + rl, tile = r >> 5, i = r & 31;
+                const size_t o0 = ((size_t)tile * 2 * (M / 8) + (kk0 >> 4)) * 64 + ((kk0 >> 3) & 1) * 32 + i;
+                o8[o0] = hi8;
+                o8[o0 + (size_t)(M / 8) * 64] = lo8;
+            }
+        } else
         for (int e = tid; e < rows * inner; e += bd) {
             const int rl = e / inner, kk = e - rl * inner;
             const int col = rl >> 1;
@@ -605,20 +631,6 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                 const int h = kk & 1, s2 = kk >> 1;
                 reinterpret_cast<float*>(ws + g.ws_emb)[((size_t)tile * (M / 4) + (s2 >> 2)) * 256 +
                                                         (h * 32 + i) * 4 + (s2 & 3)] = v;
-            } else if (prm.write_emb == 4) {
-                double vd = 0.0;
-                if (col < K) {
-                    const double2 b = Bs[col * M + (kk < M ? kk : kk - M)];
-                    vd = (rl & 1) == 0 ? (kk < M ? b.x : b.y) : (kk < M ? -b.y : b.x);
-                }
-                vd *= bscale;
-                const _Float16 hi = (_Float16)vd;
-                const _Float16 lo = (_Float16)(vd - (double)hi);
-                const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
-                _Float16* o = reinterpret_cast<_Float16*>(ws + g.ws_emb);
-                const size_t o0 = (((size_t)tile * 2 * (M / 8) + s16) * 64 + h * 32 + i) * 8 + t;
-                o[o0] = hi;
-                o[o0 + (size_t)(M / 8) * 512] = lo;
             } else {
                 const int s16 = kk >> 4, h = (kk >> 3) & 1, t = kk & 7;
                 const size_t o = ((size_t)tile * 64 + h * 32 + i) * M + s16 * 8 + t;
