@@ -157,6 +157,95 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Broadcast of a double from position P of each aligned group of four lanes.
+template <int P>
+__device__ __forceinline__ double quad_bcast(double v) {
+    return dpp_f64<P * 0x55>(v);                 // quad_perm [P, P, P, P]
+}
+__device__ __forceinline__ double quad_bcast(double v, int p) {
+    return p == 0 ? quad_bcast<0>(v) : p == 1 ? quad_bcast<1>(v) : p == 2 ? quad_bcast<2>(v) : quad_bcast<3>(v);
+}
+
+// Householder reduction of the Hermitian A (LDS, row stride ld, M <= 16) to the real symmetric
+// tridiagonal T (dq, eq), with the reflectors in Hv (column k below row k, v_{k+1} = 1) and tau
+// in tq: the same steps as the LDS reduction in evd_ql_kernel, with the matrix in registers.
+// Lane l holds A[l >> 2][4 (l & 3) + t], t = 0..3; the reflector is broadcast within the
+// four-lane groups (rows) and gathered across them (columns).  One wave; A is not updated.
+__device__ void tridiag_regs(int M, const double2* A, int ld, double2* Hv, double* dq, double* eq, double2* tq) {
+    const int lane = threadIdx.x & 63, r = lane >> 2, q = lane & 3;
+    double2 a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        a[t] = (r < M && 4 * q + t < M) ? A[r * ld + 4 * q + t] : make_double2(0.0, 0.0);
+    auto col = [&](int kt) { return kt == 0 ? a[0] : kt == 1 ? a[1] : kt == 2 ? a[2] : a[3]; };
+    for (int k = 0; k < M - 1; ++k) {
+        const int kq = k >> 2;
+        const double2 x = col(k & 3);              // A[r][k] in the lanes (r, kq)
+        const double part = (q == kq && r > k + 1) ? fma(x.x, x.x, x.y * x.y) : 0.0;
+        const double xn2 = wave_sum(part);
+        const int sa = ((k + 1) << 2) | kq;
+        const double2 alpha = make_double2(readlane_f64(x.x, sa), readlane_f64(x.y, sa));
+        const double dk = readlane_f64(x.x, (k << 2) | kq);
+        double beta = alpha.x;
+        double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
+        if (xn2 > 0.0 || alpha.y != 0.0) {
+            beta = -copysign(sqrt(fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2))), alpha.x);
+            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            const double2 den = make_double2(alpha.x - beta, alpha.y);
+            const double dn2 = fma(den.x, den.x, den.y * den.y);
+            scl = make_double2(den.x / dn2, -den.y / dn2);
+        }
+        // v_r = 1 (r = k + 1), A[r][k] scl (r > k + 1), 0 (r <= k), in every lane of row r
+        const double2 xr = make_double2(quad_bcast(x.x, kq), quad_bcast(x.y, kq));
+        const double2 vr = (r == k + 1) ? make_double2(1.0, 0.0)
+                           : (r > k + 1 && r < M) ? cmul(xr, scl) : make_double2(0.0, 0.0);
+        if (q == 0 && r > k && r < M) Hv[r * ld + k] = vr;
+        if (lane == 0) {
+            dq[k] = dk;
+            eq[k] = beta;
+            tq[k] = tau;
+        }
+        if (tau.x == 0.0 && tau.y == 0.0) continue;      // uniform: H_k = I
+        // v at this lane's four columns
+        double2 vc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int sl = (4 * q + t) << 2;
+            vc[t] = make_double2(__shfl(vr.x, sl), __shfl(vr.y, sl));
+        }
+        // y = B v over the trailing block (v vanishes outside it), gamma = v^H y (real)
+        double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            y.x = fma(a[t].x, vc[t].x, fma(-a[t].y, vc[t].y, y.x));
+            y.y = fma(a[t].x, vc[t].y, fma(a[t].y, vc[t].x, y.y));
+        }
+        y.x = quad_sum(y.x);
+        y.y = quad_sum(y.y);
+        const double gam = wave_sum((q == 0 && r > k) ? fma(vr.x, y.x, vr.y * y.y) : 0.0);
+        const double h = 0.5 * fma(tau.x, tau.x, tau.y * tau.y) * gam;
+        const double2 wr = (r > k && r < M) ? csub(cmul(tau, y), cscale(h, vr)) : make_double2(0.0, 0.0);
+        double2 wc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int sl = (4 * q + t) << 2;
+            wc[t] = make_double2(__shfl(wr.x, sl), __shfl(wr.y, sl));
+        }
+        // B -= v w^H + w v^H
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double2 vj = vc[t], wj = wc[t];
+            a[t].x -= fma(vr.x, wj.x, vr.y * wj.y) + fma(wr.x, vj.x, wr.y * vj.y);
+            a[t].y -= fma(vr.y, wj.x, -vr.x * wj.y) + fma(wr.y, vj.x, -wr.x * vj.y);
+        }
+    }
+    const double dl = readlane_f64(col((M - 1) & 3).x, ((M - 1) << 2) | ((M - 1) >> 2));
+    if (lane == 0) {
+        dq[M - 1] = dl;
+        eq[M - 1] = 0.0;
+    }
+}
+
 // Deterministic pseudo-random start of inverse iteration, in [-1, 1).
 __device__ __forceinline__ double ii_start(int i, int j) {
     uint32_t h = (uint32_t)i * 0x9E3779B1u + (uint32_t)j * 0x85EBCA77u + 0x165667B1u;
@@ -865,10 +954,15 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
     uint32_t st = 0;
     // four lanes per matrix row (or column) in the parallel phases
     const int grp = tid >> 2, q = tid & 3, gstep = bd >> 2;
+    const bool bisect = prm.method == NSSDOA_EIG_AUTO && M <= kBisectMaxM && bd == 64;
+    if (!bad && bisect) {
+        tridiag_regs(M, A, ld, Hv, dq, eq, tq);
+        __syncthreads();
+    }
     if (!bad) {
         // T = Q^H R Q.  Step k reflects rows/columns k+1..M-1 so that column k below the
         // subdiagonal vanishes and the subdiagonal entry becomes the real beta.
-        for (int k = 0; k < M - 1; ++k) {
+        for (int k = 0; k < (bisect ? 0 : M - 1); ++k) {
             const int m = M - 1 - k;
             const double2* col = A + (k + 1) * ld + k;          // col[i * ld] = A[k+1+i][k]
             double part = 0.0;
@@ -939,12 +1033,11 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
             }
             __syncthreads();
         }
-        if (tid == 0) {
+        if (tid == 0 && !bisect) {
             dq[M - 1] = A[(M - 1) * ld + M - 1].x;
             eq[M - 1] = 0.0;
         }
         __syncthreads();
-        const bool bisect = prm.method == NSSDOA_EIG_AUTO && M <= kBisectMaxM && bd == 64;
         if (bisect) {
             tridiag_eig_bisect(M, dq, eq, A, ld, bcs);
         } else {
