@@ -88,6 +88,7 @@ struct nssdoa_batch_s {
     std::vector<std::pair<int, std::pair<int, int>>> peak_ranges;   // bucket M -> [begin, end)
     std::vector<PointItem> refine_items;        // (frame, chunk start), grouped like peak_list
     std::vector<std::pair<int, int>> refine_ranges;                 // per bucket [begin, end)
+    std::vector<int> peak_selcap;               // per bucket: candidate slots of its largest frame
     size_t ws_bytes = 0;
     int64_t ws_lowq_all = -1;                   // the scans' low-Q list (count, then cap entries)
     int32_t lowq_all_cap = 0;
@@ -468,6 +469,14 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         if ((int)b->peak_list.size() > begin) {
             b->peak_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
             b->refine_ranges.push_back({ibegin, (int)b->refine_items.size()});
+            // candidate slots per frame: (4096-point chunks + windows) x (D + extra), as ws_cand
+            int cap = 1;
+            for (int i = begin; i < (int)b->peak_list.size(); ++i) {
+                const FrameDev& fd = b->frames[b->peak_list[i]];
+                const int nch = (fd.L + kRefineChunk - 1) / kRefineChunk + kMaxWindows;
+                cap = std::max(cap, nch * (fd.D + plan->opt.extra_candidates));
+            }
+            b->peak_selcap.push_back(std::min(cap, kSelCap));
         }
     }
 
@@ -811,6 +820,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         pp.chunk_count = reinterpret_cast<const int32_t*>(ws + lay.off_chunks);
         pp.windows = reinterpret_cast<const int32_t*>(ws + lay.off_win);
         for (auto& r : batch->peak_ranges) {
+            pp.sel_cap = batch->peak_selcap[&r - &batch->peak_ranges[0]];
             e = launch_peaks(false, r.first, nullptr, 0, batch->d_plist + r.second.first,
                              r.second.second - r.second.first, batch->d_frames, batch->d_pos, batch->d_cis, ws, spec,
                              pp, peaks, npeaks, status, s);
@@ -856,6 +866,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
         const auto& r = batch->peak_ranges[i];
         const auto& ri = batch->refine_ranges[i];
+        pp.sel_cap = batch->peak_selcap[i];
         e = launch_peaks(c128, r.first, batch->d_refine + ri.first, ri.second - ri.first,
                          batch->d_plist + r.second.first, r.second.second - r.second.first,
                          batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);

@@ -101,7 +101,7 @@ struct PeakParams {
     int32_t max_D;              // peak slots per frame
     int32_t refine_lowq;        // 1 for FP32 spectra
     int32_t use_user_spec;      // spectrum lives in the caller's buffer
-    int32_t pad;
+    int32_t sel_cap;            // candidate slots of the launch's largest frame (<= kSelCap)
     // windowed estimation (both NULL otherwise): candidate chunks per frame, and the per-frame
     // window tables (kWinStride int32 each); grid points outside every window count as unknown
     const int32_t* chunk_count;

@@ -259,10 +259,13 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
                                                      nssdoa_peak* __restrict__ peaks,
                                                      int32_t* __restrict__ npeaks,
                                                      uint32_t* __restrict__ status) {
-    __shared__ double cval[kSelCap];
-    __shared__ int cidx[kSelCap];
-    __shared__ uint32_t cspan[kSelCap];
-    __shared__ int ord[kSelCap];
+    // candidate slots in dynamic LDS, sized for the launch's largest frame (prm.sel_cap): values,
+    // indices, plateau spans and the value order
+    extern __shared__ double sel_dyn[];
+    double* cval = sel_dyn;
+    int* cidx = reinterpret_cast<int*>(cval + prm.sel_cap);
+    uint32_t* cspan = reinterpret_cast<uint32_t*>(cidx + prm.sel_cap);
+    int* ord = reinterpret_cast<int*>(cspan + prm.sel_cap);
     __shared__ double buf[kSpanCap];
     __shared__ int sp_lo[kMaxBatch], sp_off[kMaxBatch + 1];
     __shared__ double fval[kMaxFinal];
@@ -488,9 +491,12 @@ hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (n_frames > 0)
-        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), 0, s, flist, frames, pos, cis, ws, p,
+    if (n_frames > 0) {
+        if (p.sel_cap < 1 || p.sel_cap > kSelCap) return hipErrorInvalidValue;
+        const size_t lds = (size_t)p.sel_cap * (sizeof(double) + 3 * sizeof(int));
+        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), lds, s, flist, frames, pos, cis, ws, p,
                            peaks, npeaks, status);
+    }
     return hipGetLastError();
 }
 
