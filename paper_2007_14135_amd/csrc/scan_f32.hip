@@ -1,5 +1,7 @@
-// Step-5 (Table 2): pseudo-spectrum scan P(theta_l) = 1 / ||B^H a(theta_l)||^2 in FP32 on the
-// matrix cores, for every frame of a group that shares one array geometry and one grid.
+// Step-5 (Table 2): pseudo-spectrum scan P(theta_l) = 1 / ||B^H a(theta_l)||^2 to FP32 accuracy on
+// the matrix cores, for every frame of a group that shares one array geometry and one grid:
+// scan_f32_kernel on FP32 operands, scan_split16_kernel (further down) on FP16 hi/lo parts of the
+// same FP32 operands.
 //
 // Real embedding: with a = ar + j ai and a column b of B,
 //   Re(b^H a) = br.ar + bi.ai,   Im(b^H a) = -bi.ar + br.ai,
@@ -196,8 +198,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
     scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
-// The FP16 split scan (C64 default): the same work items, LDS staging, per-frame reduction and
-// low-Q collection as scan_f32_kernel, on v_mfma_f32_32x32x16_f16.  Each FP32 product a b of the
+// The FP16 split scan (C64 default): the same work items, per-frame reduction and low-Q
+// collection as scan_f32_kernel, on v_mfma_f32_32x32x16_f16; each wave reads the B tiles from L2
+// itself, one tile ahead, instead of staging them in LDS.  Each FP32 product a b of the
 // real-embedded contraction is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b of the operands'
 // FP16 parts (B tiles scaled per frame by 2^e, steering by 2^13, both exact), accumulated in FP32;
 // the frame's Q is the sum of squares times its scale 2^-2e 2^-26 (qref[1]).
