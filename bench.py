@@ -201,7 +201,7 @@ def learned_leg(fs, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alg", default="music", choices=["music", "ev", "mn", "phd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
