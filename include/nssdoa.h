@@ -135,11 +135,13 @@ typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } n
 /* Matrix-core kernel of the C64 (FP32-accuracy) scans of Step-5 (Table 2).  Both form the
  * real-embedded product of the B tiles and the FP32 steering values and accumulate in FP32.
  *   NSSDOA_C64_SCAN_SPLIT16: every FP32 operand x is split into FP16 parts x = hi + lo + r with
- *                            |r| <= 2^-22 |x| (after an exact power-of-two scaling per frame and
- *                            per steering table that keeps the parts in the FP16 range), and a b
- *                            is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b on the FP16 matrix
- *                            cores (v_mfma_f32_32x32x16_f16); the neglected terms are below
- *                            2^-21 |a b|, the order of the FP32 accumulation error.  The default.
+ *                            |r| <= 2^-22 |x| + 2^-25 (2^-25: half the FP16 subnormal spacing),
+ *                            after an exact power-of-two scaling per frame (B) and per steering
+ *                            table that puts the largest magnitudes near 2^13, and a b is formed
+ *                            as hi_a hi_b + hi_a lo_b + lo_a hi_b on the FP16 matrix cores
+ *                            (v_mfma_f32_32x32x16_f16); the neglected terms are below
+ *                            2^-20 |a b| + 2^-25 (|a| + |b|), the order of the FP32 accumulation
+ *                            error of the sums they enter.  The default.
  *   NSSDOA_C64_SCAN_FP32:    FP32 operands on v_mfma_f32_32x32x2f32.
  * The windowed and learned estimators use the same kernel choice. */
 typedef enum { NSSDOA_C64_SCAN_SPLIT16 = 0, NSSDOA_C64_SCAN_FP32 = 1 } nssdoa_c64_scan;

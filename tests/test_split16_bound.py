@@ -1,0 +1,71 @@
+"""The FP16 split behind the default C64 scan, checked on the CPU with numpy's IEEE binary16.
+
+An FP32 operand x (after the exact power-of-two scaling that puts it in [2^-1, 2^13] in magnitude,
+as the eigen kernel does for B and the steering table for a) is split as hi = fp16(x),
+lo = fp16(x - hi); the matrix cores then form a b as hi_a hi_b + hi_a lo_b + lo_a hi_b.  The
+header of the library states the bounds |x - hi - lo| <= 2^-22 |x| + 2^-25 and a neglected part
+below 2^-20 |a b| + 2^-25 (|a| + |b|); this test checks them, and that the split dot product of a
+real-embedded steering vector with a unit-norm B column is as accurate as the FP32 dot product.
+"""
+
+import numpy as np
+
+
+def _split(x):
+    hi = x.astype(np.float16).astype(np.float64)
+    lo = (x - hi).astype(np.float16).astype(np.float64)
+    return hi, lo
+
+
+def test_split_residual_bound():
+    rng = np.random.default_rng(20071413)
+    # FP32 values over the scaled range of the operands
+    x = (rng.uniform(0.5, 1.0, 200000) * 2.0 ** rng.integers(-30, 13, 200000)).astype(np.float32).astype(np.float64)
+    x *= rng.choice([-1.0, 1.0], x.size)
+    hi, lo = _split(x)
+    r = np.abs(x - hi - lo)
+    assert np.all(r <= 2.0 ** -22 * np.abs(x) + 2.0 ** -25)
+    # above the FP16 normal range of lo the bound is relative alone
+    big = np.abs(x) >= 2.0 ** -2
+    assert np.all(r[big] <= 2.0 ** -22 * np.abs(x[big]))
+
+
+def test_three_product_bound():
+    rng = np.random.default_rng(7)
+    a = (rng.uniform(-1, 1, 100000) * 8192.0).astype(np.float32).astype(np.float64)
+    b = (rng.uniform(-1, 1, 100000) * 8192.0).astype(np.float32).astype(np.float64)
+    ha, la = _split(a)
+    hb, lb = _split(b)
+    p3 = ha * hb + ha * lb + la * hb            # each product exact in FP64
+    assert np.all(np.abs(a * b - p3) <= 2.0 ** -20 * np.abs(a * b) + 2.0 ** -25 * (np.abs(a) + np.abs(b)))
+
+
+def test_split_dot_matches_fp32_accuracy():
+    rng = np.random.default_rng(11)
+    M = 16
+    errs_split, errs_f32 = [], []
+    for _ in range(2000):
+        th = rng.uniform(-np.pi / 2, np.pi / 2)
+        ph = np.pi * np.arange(M) * np.sin(th)
+        a = np.concatenate([np.cos(ph), np.sin(ph)]).astype(np.float32).astype(np.float64)
+        bc = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+        bc /= np.linalg.norm(bc)
+        brow = np.concatenate([bc.real, bc.imag])
+        exact = float(np.dot(brow, a))
+        # split: steering scaled by 2^13, B by 2^e with its largest entry in [2^12, 2^13)
+        sb = 2.0 ** (12 - np.floor(np.log2(np.abs(brow).max())))
+        ha, la = _split(a * 8192.0)
+        hb, lb = _split(brow * sb)
+        acc = np.float32(0.0)
+        for k0 in range(0, 2 * M, 16):            # FP32 accumulation per 16-deep step
+            sl = slice(k0, k0 + 16)
+            acc = np.float32(acc + np.float32(np.sum(hb[sl] * ha[sl] + hb[sl] * la[sl] + lb[sl] * ha[sl])))
+        errs_split.append(abs(float(acc) / (8192.0 * sb) - exact))
+        acc32 = np.float32(0.0)
+        b32, a32 = brow.astype(np.float32), a.astype(np.float32)
+        for k in range(2 * M):
+            acc32 = np.float32(acc32 + b32[k] * a32[k])
+        errs_f32.append(abs(float(acc32) - exact))
+    # same order of error as FP32 operands (absolute, |b| = 1, |a_k| <= 1)
+    assert max(errs_split) < 4.0 * max(errs_f32)
+    assert max(errs_split) < 1e-6
