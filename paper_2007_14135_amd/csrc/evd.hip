@@ -257,8 +257,8 @@ __device__ __forceinline__ double ii_start(int i, int j) {
 
 // T from dq (diagonal) and eq (off-diagonal, eq[M-1] = 0).  Writes the eigenvalues in ascending
 // order to dq and eigenvector j as column j of Z (.x, row stride ld).  Every lane of the wave
-// calls it; cs: 64 ints of LDS.
-__device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2* Z, int ld, int* cs) {
+// calls it.
+__device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2* Z, int ld) {
     constexpr int MB = kBisectMaxM;
     constexpr double eps = 0x1p-52;
     const int lane = threadIdx.x & 63;
@@ -324,10 +324,9 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
         // multisection: lane j + 16 p counts at point p + 1 of 5 inside eigenvalue j's interval
         for (int it = 0; it < its; ++it) {
             const double w = hi - lo;
-            cs[lane] = sturm(lo + w * ((double)(p + 1) * 0.2));
-            wave_sync();
-            const int c0 = cs[j], c1 = cs[j + 16], c2 = cs[j + 32], c3 = cs[j + 48];
-            wave_sync();
+            const int cnt = sturm(lo + w * ((double)(p + 1) * 0.2));
+            const int c0 = __shfl(cnt, j), c1 = __shfl(cnt, j + 16), c2 = __shfl(cnt, j + 32),
+                      c3 = __shfl(cnt, j + 48);
             // the first point below which more than j eigenvalues lie bounds eigenvalue j above
             const int k = c0 > j ? 0 : c1 > j ? 1 : c2 > j ? 2 : c3 > j ? 3 : 4;
             const double nlo = k == 0 ? lo : lo + w * ((double)k * 0.2);
@@ -933,7 +932,6 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
     __shared__ double dq[64], eq[64];      // diagonal and off-diagonal of T (eq[i] couples i, i+1)
     __shared__ double2 tq[64];             // tau_k
     __shared__ double2 vb[64], wb[64];     // the current reflector v and the vector w of its update
-    __shared__ int bcs[64];                // Sturm counts of the bisection
     __shared__ int bad;
 
     const int fidx = flist[blockIdx.x];
@@ -1039,7 +1037,7 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
         }
         __syncthreads();
         if (bisect) {
-            tridiag_eig_bisect(M, dq, eq, A, ld, bcs);
+            tridiag_eig_bisect(M, dq, eq, A, ld);
         } else {
         for (int e = tid; e < Mp * Mp; e += bd) {
             const int i = e / Mp, j = e - i * Mp;
