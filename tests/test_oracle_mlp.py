@@ -1,5 +1,8 @@
 """Pins for the learned-proposal oracle: gradients by central differences, closed forms of the
-loss and of Adam's first step, feature invariances, bin labels and window arithmetic."""
+loss and of Adam (first step, every step of a constant gradient, every step of an alternating one,
+gradient-scale invariance), feature invariances, bin labels and window arithmetic.  The Adam pins
+are written as checks of a callable so that test_oracle_mutants.py can show that each of several
+planted mistakes fails one of them."""
 
 import numpy as np
 import pytest
@@ -59,6 +62,81 @@ def test_adam_first_step_closed_form():
         # bias-corrected first step: delta = -lr * g / (|g| + eps)
         assert np.allclose(W2 - W, -lr * gW / (np.abs(gW) + 1e-8), rtol=1e-12, atol=1e-18)
         assert np.allclose(b2 - b, -lr * gb / (np.abs(gb) + 1e-8), rtol=1e-12, atol=1e-18)
+
+
+B1, B2, EPS = 0.9, 0.999, 1e-8
+
+
+def _tree(rng):
+    """A small parameter-shaped list [(W, b)] of random values."""
+    return [(rng.normal(size=(3, 2)), rng.normal(size=3)), (rng.normal(size=(2, 3)), rng.normal(size=2))]
+
+
+def _zeros(tree):
+    return [(np.zeros_like(W), np.zeros_like(b)) for W, b in tree]
+
+
+def check_adam_constant_gradient(adam, steps=7, lr=1e-3):
+    """A constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias-corrected
+    moments are exactly g and g^2 and every step is -lr g / (|g| + eps): p_t = p_0 - t lr g / (|g| + eps)."""
+    rng = np.random.default_rng(11)
+    p0 = _tree(rng)
+    g = [(rng.normal(size=W.shape) * 10.0 ** rng.uniform(-4, 1, size=W.shape),
+          rng.normal(size=b.shape) * 10.0 ** rng.uniform(-4, 1, size=b.shape)) for W, b in p0]
+    p, m, v = p0, _zeros(p0), _zeros(p0)
+    for t in range(1, steps + 1):
+        p, m, v = adam(p, g, m, v, t, lr)
+        for (W, b), (W0, b0), (gW, gb) in zip(p, p0, g):
+            assert np.allclose(W, W0 - t * lr * gW / (np.abs(gW) + EPS), rtol=1e-12, atol=1e-15), t
+            assert np.allclose(b, b0 - t * lr * gb / (np.abs(gb) + EPS), rtol=1e-12, atol=1e-15), t
+
+
+def check_adam_alternating_gradient(adam, steps=8, lr=1e-2):
+    """g_t = (-1)^(t+1) g: v_t is as for a constant gradient, and the geometric series gives
+    m_t = (1 - b1) (-1)^(t+1) g (1 - (-b1)^t) / (1 + b1), so step t moves p by
+    -lr m_t / (1 - b1^t) / (|g| + eps)."""
+    rng = np.random.default_rng(12)
+    p0 = _tree(rng)
+    g = [(rng.normal(size=W.shape), rng.normal(size=b.shape)) for W, b in p0]
+    p, m, v = p0, _zeros(p0), _zeros(p0)
+    for t in range(1, steps + 1):
+        sgn = (-1.0) ** (t + 1)
+        gt = [(sgn * gW, sgn * gb) for gW, gb in g]
+        pn, m, v = adam(p, gt, m, v, t, lr)
+        coef = (1 - B1) * sgn * (1 - (-B1) ** t) / (1 + B1) / (1 - B1 ** t)
+        for (W, b), (Wn, bn), (gW, gb) in zip(p, pn, g):
+            assert np.allclose(Wn - W, -lr * coef * gW / (np.abs(gW) + EPS), rtol=1e-10, atol=1e-17), t
+            assert np.allclose(bn - b, -lr * coef * gb / (np.abs(gb) + EPS), rtol=1e-10, atol=1e-17), t
+        p = pn
+
+
+def check_adam_scale_invariance(adam, steps=5, lr=1e-3):
+    """With eps = 0 the update depends on the gradients only through their ratios: scaling every
+    gradient of a sequence by c > 0 leaves every step unchanged, and negating them negates it."""
+    rng = np.random.default_rng(13)
+    p0 = _tree(rng)
+    seq = [[(rng.normal(size=W.shape), rng.normal(size=b.shape)) for W, b in p0] for _ in range(steps)]
+    runs = {}
+    for c in (1.0, 1e-5, 3e4, -1.0):
+        p, m, v = p0, _zeros(p0), _zeros(p0)
+        for t, g in enumerate(seq, start=1):
+            p, m, v = adam(p, [(c * gW, c * gb) for gW, gb in g], m, v, t, lr, eps=0.0)
+        runs[c] = [x - x0 for layer, layer0 in zip(p, p0) for x, x0 in zip(layer, layer0)]
+    for c in (1e-5, 3e4, -1.0):
+        for d, d1 in zip(runs[c], runs[1.0]):
+            assert np.allclose(d, np.sign(c) * d1, rtol=1e-12, atol=1e-15), c
+
+
+def test_adam_constant_gradient_every_step():
+    check_adam_constant_gradient(mlp.adam_step)
+
+
+def test_adam_alternating_gradient_closed_form():
+    check_adam_alternating_gradient(mlp.adam_step)
+
+
+def test_adam_gradient_scale_invariance():
+    check_adam_scale_invariance(mlp.adam_step)
 
 
 def test_features_layout_and_invariance():
@@ -127,3 +205,24 @@ def test_bf16_mode_rounds_every_product_operand():
     for (gw_, gb_), (ew, eb) in zip(g, g64):
         rel = np.linalg.norm(gw_ - ew) / np.linalg.norm(ew)
         assert 0 < rel < 0.05
+
+
+def test_init_params_he_uniform():
+    # He-uniform: W_l (out x in) uniform on [-sqrt(6/in), sqrt(6/in)] (variance 2/in), zero biases,
+    # a function of the seed only
+    p = mlp.init_params(21)
+    assert [W.shape for W, _ in p] == [(512, 272), (512, 512), (180, 512)]
+    for (W, b), fin in zip(p, (272, 512, 512)):
+        lim = np.sqrt(6.0 / fin)
+        n = W.size
+        assert np.all(b == 0.0)
+        assert np.all(np.abs(W) <= lim) and np.abs(W).max() > lim * (1 - 20.0 / n)
+        assert abs(W.mean()) < 5 * lim / np.sqrt(3 * n)
+        assert abs(W.var() / (2.0 / fin) - 1) < 5 * np.sqrt(0.8 / n)
+        # uniform: each tenth of the interval holds a tenth of the values (5 sigma)
+        h, _ = np.histogram(W, bins=10, range=(-lim, lim))
+        assert np.all(np.abs(h - n / 10) < 5 * np.sqrt(n * 0.09))
+    q = mlp.init_params(21)
+    r = mlp.init_params(22)
+    assert all(np.array_equal(a[0], c[0]) for a, c in zip(p, q))
+    assert not np.array_equal(p[0][0], r[0][0])
