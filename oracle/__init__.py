@@ -24,5 +24,9 @@ from .doa import (  # noqa: F401
     select_peaks,
     estimate,
     estimate_windowed,
+    spectrum_factored_2d,
+    find_peaks_2d,
+    select_peaks_2d,
+    estimate_2d,
     percent_error,
 )

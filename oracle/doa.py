@@ -242,6 +242,76 @@ def estimate_windowed(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, wi
     return Estimate(R, lam, U, B, angles, Q, P, sel, angles[sel], allp)
 
 
+def spectrum_factored_2d(B: np.ndarray, pos: np.ndarray, az_deg, el_deg):
+    """Step-5 over a 2-D grid of Eq. 2's angle pairs: Q[j, i] = ||B^H a(theta_i, phi_j)||^2 with
+    theta the azimuth and phi the polar angle (phi = 90 deg is the horizontal plane), one row per
+    polar angle.  Returns (Q, P) of shape (len(el_deg), len(az_deg)), P = 1/max(Q, 1e-300)."""
+    rows = [spectrum_factored(B, pos, az_deg, float(ph))[0] for ph in np.atleast_1d(el_deg)]
+    Q = np.asarray(rows, dtype=np.float64)
+    return Q, 1.0 / np.maximum(Q, TINY_Q)
+
+
+def find_peaks_2d(P: np.ndarray, circular_az: bool = False) -> np.ndarray:
+    """Table 2 Step-6 findPeaks over a 2-D grid: linear (row-major) indices j * n_az + i of the
+    points that exceed their 8 neighbours, ascending.
+
+    Readings (the paper prints no rule): only neighbours inside the grid count, so edge rows and
+    columns can hold peaks (a planar array's spectrum is mirror-symmetric about phi = 90 deg, where
+    the paper's grids end); the azimuth axis wraps when circular, the polar axis never does.  Ties:
+    a point must be strictly greater than every neighbour that precedes it in row-major order, at
+    least equal to every neighbour that follows it, and strictly greater than at least one
+    neighbour, so a plateau is reported at its first point and a constant patch not at all.
+    """
+    P = np.asarray(P, dtype=np.float64)
+    E, A = P.shape
+    lin = np.arange(E * A).reshape(E, A)
+    ok = np.ones((E, A), dtype=bool)
+    above_one = np.zeros((E, A), dtype=bool)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if dj == 0 and di == 0:
+                continue
+            jj = np.arange(E)[:, None] + dj
+            ii = np.arange(A)[None, :] + di
+            if circular_az:
+                ii = ii % A
+            inside = (jj >= 0) & (jj < E) & (ii >= 0) & (ii < A)
+            jjc = np.clip(jj, 0, E - 1)
+            iic = np.clip(ii, 0, A - 1)
+            nb = P[jjc + 0 * iic, iic + 0 * jjc]
+            nidx = lin[jjc + 0 * iic, iic + 0 * jjc]
+            cond = np.where(nidx < lin, P > nb, P >= nb)
+            ok &= np.where(inside, cond, True)
+            above_one |= inside & (P > nb)
+    return np.flatnonzero((ok & above_one).ravel())
+
+
+def select_peaks_2d(P: np.ndarray, peaks: np.ndarray, D: int) -> np.ndarray:
+    """PeakSelection over a 2-D grid: the D largest by value, ties to the lower linear index."""
+    flat = np.asarray(P, dtype=np.float64).ravel()
+    return select_peaks(flat, peaks, D)
+
+
+def estimate_2d(X: np.ndarray, pos: np.ndarray, D: int, az_grid, el_grid, alg: str, *,
+                circular_az: bool = False) -> Estimate:
+    """Table 2, Steps 1-6 for one frame over a 2-D grid (azimuth x polar angle of Eq. 2).
+
+    ``az_grid`` and ``el_grid`` are (start, step, count) in degrees; Q and P have shape
+    (n_el, n_az); peak indices are row-major (j * n_az + i); ``peak_angles`` holds
+    (azimuth, polar angle) pairs."""
+    R = covariance(X)
+    lam, U = eig_desc(R)
+    B = noise_subspace_matrix(alg, lam, U, D)
+    az = grid_angles(*az_grid)
+    el = grid_angles(*el_grid)
+    Q, P = spectrum_factored_2d(B, pos, az, el)
+    allp = find_peaks_2d(P, circular_az)
+    sel = select_peaks_2d(P, allp, D)
+    A = len(az)
+    pairs = np.stack([az[sel % A], el[sel // A]], axis=1) if len(sel) else np.zeros((0, 2))
+    return Estimate(R, lam, U, B, (az, el), Q, P, sel, pairs, allp)
+
+
 def percent_error(y_meas: np.ndarray, y_true: np.ndarray) -> float:
     """Eq. 4: mean relative deviation in percent, 100/N * sum |y_meas - y_true| / |y_true|."""
     y_meas = np.asarray(y_meas, dtype=np.float64)

@@ -9,6 +9,7 @@ and in the HIP library, and neither imports the other.
 
 from .frames import (  # noqa: F401
     CONFIGS,
+    EL_GRIDS_2D,
     Frame,
     FrameSet,
     make_config,

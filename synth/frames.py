@@ -51,10 +51,16 @@ def uca_positions(M: int, radius: float) -> np.ndarray:
     return pos
 
 
-def _source_manifold(pos: np.ndarray, theta_deg: np.ndarray) -> np.ndarray:
-    """Array manifold A (M x D) for azimuth-plane sources (Eq. 2 with phi = 90 deg)."""
+def _source_manifold(pos: np.ndarray, theta_deg: np.ndarray, phi_deg=None) -> np.ndarray:
+    """Array manifold A (M x D) of Eq. 2: azimuth-plane sources (phi = 90 deg) unless polar
+    angles phi_deg (one per source) are given."""
     th = np.deg2rad(np.asarray(theta_deg, dtype=np.float64))
-    cyc = np.outer(pos[:, 0], np.sin(th)) + np.outer(pos[:, 1], np.cos(th))
+    if phi_deg is None:
+        cyc = np.outer(pos[:, 0], np.sin(th)) + np.outer(pos[:, 1], np.cos(th))
+    else:
+        ph = np.deg2rad(np.asarray(phi_deg, dtype=np.float64))
+        cyc = (np.outer(pos[:, 0], np.sin(th) * np.sin(ph)) + np.outer(pos[:, 1], np.cos(th) * np.sin(ph))
+               + np.outer(pos[:, 2], np.cos(ph)))
     return np.exp(2j * np.pi * cyc)
 
 
@@ -84,6 +90,7 @@ class Frame:
     snr_db: float
     sigma2: float
     angles_deg: np.ndarray     # (D,) true source azimuths
+    polar_deg: Optional[np.ndarray]  # (D,) true polar angles (phi of Eq. 2), None: all 90 deg
     grid_start: float          # scan grid theta_l = start + l * step, l = 0..L-1
     grid_step: float
     grid_L: int
@@ -149,6 +156,16 @@ def _c5(rng):
                 angle_lo=-70.0, angle_hi=70.0, gap=5.0, grid=_grid_for_step(0.001))
 
 
+def _c6(rng):
+    # the paper's test scenario (Section 5): 8-element UCA of radius 10 m at 15 MHz (0.5 lambda),
+    # two uncorrelated sources at 15 dB; snapshot count and directions are not given (readings:
+    # N = 1024, azimuths uniform in [0, 330] deg at least 30 deg apart, so also 30 deg apart across
+    # 0/360, polar angles uniform in [60, 90] deg); scanned over 0:1:359 deg of azimuth
+    M = 8
+    return dict(M=M, geometry="uca", pos=uca_positions(M, 0.5), D=2, N=1024, snr_db=15.0,
+                angle_lo=0.0, angle_hi=330.0, gap=30.0, polar=(60.0, 90.0), grid=(0.0, 1.0, 360))
+
+
 CONFIGS: Dict[str, Config] = {
     "c1": Config("c1", 0, 1, np.complex128, _c1,
                  "ULA M=8, D=2, N=1024, 10 dB, one frame, complex128, 0.1 deg grid"),
@@ -161,7 +178,16 @@ CONFIGS: Dict[str, Config] = {
                  "ULA M=64, D=8 (gap 1 deg), N=16384, 5 dB, 64 frames, complex64, 0.001 deg grid"),
     "c5": Config("c5", 4, 8192, np.complex64, _c5,
                  "ULA M=16, D U{1..4}, SNR U[-5,20] dB, N log-U[256,4096], 0.001 deg grid"),
+    "c6": Config("c6", 5, 1, np.complex64, _c6,
+                 "UCA M=8 radius 0.5 lambda, D=2 at polar angles U[60,90] deg, N=1024, 15 dB, complex64, "
+                 "azimuth 0:1:359 deg (2-D grids add polar angles)"),
 }
+
+# Polar-angle ranges of the 2-D scans of the paper's scenario (azimuth 0:1:359 x these), keyed by
+# their point count: 360 x 1 is the horizontal plane; the larger ranges extend it away from the
+# plane at 1 deg (reading: the paper names only the counts 1, 30, 60 and 90, and phi = 1..90 for
+# the largest).
+EL_GRIDS_2D = {1: (90.0, 1.0, 1), 30: (61.0, 1.0, 30), 60: (31.0, 1.0, 60), 90: (1.0, 1.0, 90)}
 
 
 def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
@@ -186,7 +212,8 @@ def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
         p["grid"] = _grid_for_step(grid_step)
     Mv, Dv, Nv = p["M"], p["D"], p["N"]
     angles = draw_angles(rng, Dv, p["angle_lo"], p["angle_hi"], p["gap"])
-    A = _source_manifold(p["pos"], angles)
+    polar = rng.uniform(p["polar"][0], p["polar"][1], size=Dv) if "polar" in p else None
+    A = _source_manifold(p["pos"], angles, polar)
     # complex draws built part by part (the same values as re + 1j * im, without temporaries):
     # S = (g1 + j g2) / sqrt(2), W = sqrt(sigma2) (g3 + j g4) / sqrt(2), in this draw order
     S = np.empty((Dv, Nv), dtype=np.complex128)
@@ -204,7 +231,7 @@ def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
     X = W.astype(cfg.dtype)
     g = p["grid"]
     return Frame(M=Mv, N=Nv, D=Dv, pos=p["pos"], geometry=p["geometry"], snr_db=p["snr_db"],
-                 sigma2=sigma2, angles_deg=angles, grid_start=g[0], grid_step=g[1], grid_L=g[2],
+                 sigma2=sigma2, angles_deg=angles, polar_deg=polar, grid_start=g[0], grid_step=g[1], grid_L=g[2],
                  X=X)
 
 
