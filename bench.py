@@ -42,7 +42,10 @@ SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
 PMC_SUMMARY = {"split16": os.path.join(ROOT, "profiles", "scan_split16_c2_music_pmc.txt"),
                "fp32": os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")}
 SCAN_KERNEL = {"split16": "scan_split16_kernel<16>", "fp32": "scan_f32_kernel<16>"}
+STAGE_KERNEL = {"covariance": "cov_mfma_kernel<float2, 1>", "eigen": "evd_ql_kernel", "scan": None}
 TUNE_CACHE = os.path.join(ROOT, "paper_2007_14135_amd", "tuning", "autotune_cache.json")
+PEAK_FP64_TFLOPS = 78.6
+HOST_WORKERS = 16          # host processes: the CPU share of one GPU on the measurement machine
 
 
 def _oracle_worker(args):
@@ -67,7 +70,7 @@ def _oracle_worker(args):
 def cpu_baseline(config, frame_ids, alg, L, repeats):
     import multiprocessing as mp
     cores = len(os.sched_getaffinity(0))
-    workers = max(1, min(cores, 16, len(frame_ids)))
+    workers = max(1, min(cores, HOST_WORKERS, len(frame_ids)))
     chunks = [frame_ids[i::workers] for i in range(workers)]
     with mp.get_context("fork").Pool(workers) as pool:
         res = pool.map(_oracle_worker, [(config, c, alg, repeats) for c in chunks])
@@ -79,9 +82,22 @@ def cpu_baseline(config, frame_ids, alg, L, repeats):
             peaks[i] = pk
     value = repeats * len(frame_ids) * L / wall
     return dict(value=value, unit="points/s", cores=workers, kind="oracle",
+                host_cores_in_affinity=cores, cpu_model=cpu_model(),
                 sample="all %d frames of the workload, %d passes, FP64 numpy/LAPACK oracle, covariance to peaks, "
-                       "one process per core with BLAS threads = 1; %.1f s of CPU work in %.1f s"
-                       % (len(frame_ids), repeats, cpu_s, wall)), peaks
+                       "one process per core with BLAS threads = 1 (%d worker processes: the host CPU share of "
+                       "one GPU; %d cores in this process's affinity); %.1f s of CPU work in %.1f s"
+                       % (len(frame_ids), repeats, workers, cores, cpu_s, wall)), peaks
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _frames_worker(args):
@@ -96,7 +112,7 @@ def make_frames_parallel(config, n):
     """Frames 0..n-1 of a configuration, drawn by a fork pool (before the GPU is touched)."""
     import multiprocessing as mp
     from synth.frames import pack_frames
-    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    workers = max(1, min(len(os.sched_getaffinity(0)), HOST_WORKERS))
     step = 256
     jobs = [(config, list(range(s, min(n, s + step)))) for s in range(0, n, step)]
     with mp.get_context("fork").Pool(workers) as pool:
@@ -158,12 +174,35 @@ def learned_leg(fs, steps, warmup):
     full = db.host_results()
     ms_learned = _timed(lambda: db.run_learned(net, 6, 1.0, 0.5, stream), steps * 4, warmup, stream)
     learned = db.host_results()
+    # honest ablation: a non-learned proposer on the device (MUSIC at 1 deg through the library, its
+    # peaks' bins scored 1 by a scatter, then the same windowed search of the fine grid)
+    coarse = prepare([fr0.pos], [(-89.5, 1.0, 180, 0)], frames, fs.X_flat, "music", "c64", 4, with_spectrum=False,
+                     device="cuda:0", X_device=db.X)
+    scores = torch.zeros(F, 180, dtype=torch.float32, device="cuda:0")
+    cidx = coarse.peaks.view(torch.int32).view(F, coarse.batch.max_D, 6)[:, :, 0]
+
+    def coarse_run():
+        coarse.run(stream)
+        scores.zero_()
+        scores.scatter_(1, cidx.clamp(min=0).long(), (cidx >= 0).float())
+        db.run_windowed(scores, 6, 1.0, 0.5, stream)
+
+    ms_coarse = _timed(coarse_run, steps * 4, warmup, stream)
+    coarse_res = db.host_results()
+    del coarse
     db.batch.set_timing(True)                      # stage breakdown: a separate, untimed pass
     for _ in range(3):
         db.run_learned(net, 6, 1.0, 0.5, stream)
     stages = {s: db.batch.stage_time(s) for s in ("covariance", "eigen", "proposal", "scan", "peaks")}
     db.batch.set_timing(False)
     fallback = (learned["status"] & nd.ST_FALLBACK_USED) != 0
+    miss_coarse = 0
+    for f in range(F):
+        nf, nc = int(full["npeaks"][f]), int(coarse_res["npeaks"][f])
+        a_full = np.sort(full["peaks"][f]["angle_deg"][:nf])
+        a_c = np.sort(coarse_res["peaks"][f]["angle_deg"][:nc])
+        if nf != nc or (nf and np.max(np.abs(a_full - a_c)) > 0.01 + 1e-9):
+            miss_coarse += 1
     miss = 0
     # RMSE over the sources of frames that report D peaks, matched in sorted order
     sq = {"full": [0.0, 0], "learned": [0.0, 0]}
@@ -181,7 +220,7 @@ def learned_leg(fs, steps, warmup):
     return {
         "workload": "ULA M=16, D U{1..4}, SNR U[-5,20] dB, N log-U[256,4096] complex64, %d frames, "
                     "grid [-90,90) at 0.001 deg (L=%d), MUSIC; learned: 6 windows of +-1 deg, "
-                    "full-scan fallback below score 0.5" % (F, L),
+                    "full-grid fallback below score 0.5 or when the windows hold fewer than D peaks" % (F, L),
         "frames": F,
         "frames_per_s_full": F / (ms_full / 1e3),
         "frames_per_s_learned": F / (ms_learned / 1e3),
@@ -195,7 +234,206 @@ def learned_leg(fs, steps, warmup):
         "rmse_deg_vs_truth_full": math.sqrt(sq["full"][0] / max(sq["full"][1], 1)),
         "rmse_deg_vs_truth_learned": math.sqrt(sq["learned"][0] / max(sq["learned"][1], 1)),
         "learned_stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "coarse_music_proposer": {
+            "how": "MUSIC at 1 deg through the library, its peaks' bins as scores (device scatter), then the "
+                   "same windowed search; everything on the device",
+            "ms_per_batch": ms_coarse, "frames_per_s": F / (ms_coarse / 1e3), "miss_rate_vs_full": miss_coarse / F,
+            "fallback_rate": float(np.mean((coarse_res["status"] & nd.ST_FALLBACK_USED) != 0)),
+            "learned_gain_over_it": ms_coarse / ms_learned},
     }
+
+
+def stage_rooflines(stage_ms, frames, alg, prec_scan_peak):
+    """Each stage of one step against the roofline of the unit it is bound by, with its own
+    algorithmic work (per frame f: covariance 8 M N bytes of complex64 snapshots read, eigensolve
+    12 M^3 FP64 flops, scan 8 M K L flops, peak search 4 L bytes of spectrum read)."""
+    cov_b = sum(8.0 * fr.M * fr.N for fr in frames)
+    eig_f = sum(12.0 * fr.M ** 3 for fr in frames)
+    scan_f = sum(8.0 * fr.M * (fr.M - fr.D if alg in ("music", "ev") else 1) * fr.grid_L for fr in frames)
+    peak_b = sum(4.0 * fr.grid_L for fr in frames)
+    out = {}
+    for name, work, unit, peak, bound, scale in (
+            ("covariance", cov_b, "GB/s", PEAK_HBM_GBS, "hbm", 1e9),
+            ("eigen", eig_f, "TFLOP/s", PEAK_FP64_TFLOPS, "alu", 1e12),
+            ("scan", scan_f, "TFLOP/s", prec_scan_peak, "mfma", 1e12),
+            ("peaks", peak_b, "GB/s", PEAK_HBM_GBS, "hbm", 1e9)):
+        ms = stage_ms.get(name)
+        if not ms:
+            continue
+        ach = work / (ms / 1e3) / scale
+        out[name] = {"ms": ms, "bound": bound, "work_per_launch": work, "achieved": ach, "peak": peak, "unit": unit,
+                     "frac": ach / peak}
+    return out
+
+
+def _oracle_peaks_worker(args):
+    """FP64 oracle over frames of a configuration: (index, peak angles, spectrum or None)."""
+    config, idx, alg, keep_spectrum = args
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from synth import make_frame
+    out = []
+    with threadpool_limits(1):
+        for i in idx:
+            fr = make_frame(config, i)
+            est = oracle.estimate(fr.X, fr.pos, fr.D, fr.grid, alg)
+            out.append((i, sorted(est.angles[est.peaks].tolist()), est.P if i in keep_spectrum else None))
+    return out
+
+
+def oracle_peaks_parallel(config, n, alg, keep_spectrum=()):
+    import multiprocessing as mp
+    workers = max(1, min(len(os.sched_getaffinity(0)), HOST_WORKERS, n))
+    jobs = [(config, list(range(w, n, workers)), alg, tuple(keep_spectrum)) for w in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_oracle_peaks_worker, jobs)
+    peaks, spectra = {}, {}
+    for part in parts:
+        for i, pk, P in part:
+            peaks[i] = pk
+            if P is not None:
+                spectra[i] = P
+    return peaks, spectra
+
+
+def _peak_errors(res, n_frames, opeaks):
+    worst, mism = 0.0, 0
+    for i in range(n_frames):
+        n = int(res["npeaks"][i])
+        g = sorted(res["peaks"][i]["angle_deg"][:n].tolist())
+        o = opeaks[i]
+        if len(g) != len(o):
+            mism += 1
+            continue
+        if n:
+            worst = max(worst, max(abs(a - b) for a, b in zip(g, o)))
+    return worst, mism
+
+
+def c1_leg(fs1, steps, warmup):
+    """The FP64 single-frame workload: latency of one estimate call per algorithm (eager call and
+    replay of the captured graph), and the peaks against the oracle."""
+    import torch
+    import oracle
+    from paper_2007_14135_amd.runner import prepare
+    fr = fs1.frames[0]
+    stream = torch.cuda.current_stream()
+    out = {"workload": "ULA M=8, D=2, N=1024 complex128 snapshots, 10 dB, one frame, grid [-90,90) at 0.1 deg "
+                       "(L=1800), FP64 throughout", "us_per_frame": {}, "us_per_frame_graph": {},
+           "peak_err_deg_vs_oracle": {}}
+    for alg in ("phd", "music", "ev", "mn"):
+        db = prepare([fr.pos], [(fr.grid_start, fr.grid_step, fr.grid_L, 0)],
+                     [(0, 0, fr.N, fr.D, int(fs1.x_off[0]), int(fs1.ld[0]))], fs1.X_flat, alg, "c128", fr.D,
+                     device="cuda:0")
+        out["us_per_frame"][alg] = 1e3 * _timed(lambda: db.run(stream), steps, warmup, stream)
+        g = db.capture()
+        out["us_per_frame_graph"][alg] = 1e3 * _timed(lambda: g.launch(stream), steps, warmup, stream)
+        res = db.host_results()
+        est = oracle.estimate(fr.X, fr.pos, fr.D, fr.grid, alg)
+        err, mism = _peak_errors(res, 1, {0: sorted(est.angles[est.peaks].tolist())})
+        out["peak_err_deg_vs_oracle"][alg] = err if not mism else None
+        g.close()
+        del db
+    return out
+
+
+def c3_leg(fs3, steps, warmup, tune_cache, kernel):
+    """The uneven workload: 4096 frames (M 8..64, ULA/UCA, uneven D, N, SNR, grid step) as one
+    graph launch with the autotuned scan work-item size."""
+    import torch
+    from paper_2007_14135_amd import autotune
+    from paper_2007_14135_amd.api import Options
+    from paper_2007_14135_amd.runner import prepare
+    arrays, grids, frames, amap, gmap = [], [], [], {}, {}
+    for f, fr in enumerate(fs3.frames):
+        ka = (fr.geometry, fr.M)
+        if ka not in amap:
+            amap[ka] = len(arrays)
+            arrays.append(fr.pos)
+        kg = fr.grid
+        if kg not in gmap:
+            gmap[kg] = len(grids)
+            grids.append((fr.grid_start, fr.grid_step, fr.grid_L, 0))
+        frames.append((amap[ka], gmap[kg], fr.N, fr.D, int(fs3.x_off[f]), int(fs3.ld[f])))
+    max_D = max(fr.D for fr in fs3.frames)
+    rows, _ = autotune.tune(arrays, grids, frames, fs3.X_flat, "music", "c64", max_D, cache_path=tune_cache or None,
+                            options=Options(c64_scan=kernel))
+    db = prepare(arrays, grids, frames, fs3.X_flat, "music", "c64", max_D, with_spectrum=False, device="cuda:0",
+                 options=Options(scan_rows=rows, c64_scan=kernel))
+    stream = torch.cuda.current_stream()
+    g = db.capture()
+    ms = _timed(lambda: g.launch(stream), steps, warmup, stream)
+    res = db.host_results()
+    db.batch.set_timing(True)
+    for _ in range(3):
+        db.run(stream)
+    stages = {s: db.batch.stage_time(s) for s in ("covariance", "eigen", "scan", "peaks")}
+    db.batch.set_timing(False)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    g.close()
+    F = len(fs3)
+    points = sum(fr.grid_L for fr in fs3.frames)
+    peak = PEAK_FP32_MFMA_TFLOPS if kernel == "fp32" else PEAK_FP16_MFMA_TFLOPS
+    return {"workload": "4096 uneven frames: M in {8,16,32,64}, ULA or UCA, D U{1..M/4}, N log-U[256,8192], "
+                        "SNR U[-5,20] dB, grid step in {0.1,0.01,0.002} deg over [-90,90), MUSIC, complex64; one "
+                        "graph launch, autotuned scan work items",
+            "frames": F, "points": points, "snapshot_bytes": int(fs3.X_flat.nbytes), "c64_scan": kernel,
+            "scan_rows": rows or 384, "ms_per_batch": ms, "frames_per_s": F / (ms / 1e3),
+            "points_per_s": points / (ms / 1e3), "stage_ms": stage_ms,
+            "stage_roofline": stage_rooflines(stage_ms, fs3.frames, "music", peak),
+            "status_nonzero_frames": int(np.count_nonzero(res["status"] & 0x7))}
+
+
+def c4_leg(fs4, steps, warmup, tune_cache, opeaks, ospectra):
+    """The precision workload (64 frames, M=64, 180000-point grid) with the BF16 and the FP16
+    scan: throughput, spectrum dB error against the FP64 oracle at every point of the frames the
+    oracle's spectra were kept for, and the peak error in degrees on every frame."""
+    import torch
+    from paper_2007_14135_amd import autotune
+    from paper_2007_14135_amd.runner import prepare
+    fr0 = fs4.frames[0]
+    arrays = [fr0.pos]
+    grids = [(fr0.grid_start, fr0.grid_step, fr0.grid_L, 0)]
+    frames = [(0, 0, fr.N, fr.D, int(fs4.x_off[f]), int(fs4.ld[f])) for f, fr in enumerate(fs4.frames)]
+    stream = torch.cuda.current_stream()
+    F, L = len(fs4), fr0.grid_L
+    K = fr0.M - fr0.D
+    out = {"workload": "ULA M=64, D=8 (gap >= 1 deg), N=16384 complex64 snapshots, 5 dB, 64 frames, grid "
+                       "[-90,90) at 0.001 deg (L=180000), MUSIC; 16-bit matrix-core scan with FP32 accumulation, "
+                       "FP64 eigensolve, FP64 re-evaluation of low-Q points and FP64 peak refinement",
+           "frames": F}
+    X_dev = None
+    for prec in ("bf16", "f16"):
+        rows, _ = autotune.tune(arrays, grids, frames, fs4.X_flat, "music", prec, fr0.D, cache_path=tune_cache or None)
+        from paper_2007_14135_amd.api import Options
+        db = prepare(arrays, grids, frames, fs4.X_flat, "music", prec, fr0.D, device="cuda:0", X_device=X_dev,
+                     options=Options(scan_rows=rows))
+        X_dev = db.X
+        ms = _timed(lambda: db.run(stream), steps, warmup, stream)
+        res = db.host_results()
+        db.batch.set_timing(True)
+        for _ in range(2):
+            db.run(stream)
+        stages = {s: db.batch.stage_time(s) for s in ("covariance", "eigen", "scan", "peaks")}
+        db.batch.set_timing(False)
+        stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+        err, mism = _peak_errors(res, F, opeaks)
+        dbe = []
+        for i, P in ospectra.items():
+            dbe.append(np.abs(10.0 * np.log10(res["spectra"][i].astype(np.float64) / P)))
+        dbe = np.concatenate(dbe) if dbe else np.zeros(1)
+        scan_s = stage_ms["scan"] / 1e3
+        out[prec] = {"scan_rows": rows, "ms_per_batch": ms, "frames_per_s": F / (ms / 1e3),
+                     "points_per_s": F * L / (ms / 1e3), "stage_ms": stage_ms,
+                     "scan_roofline": {"bound": "mfma", "achieved": 8.0 * fr0.M * K * L * F / scan_s / 1e12,
+                                       "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                       "frac": 8.0 * fr0.M * K * L * F / scan_s / 1e12 / PEAK_FP16_MFMA_TFLOPS},
+                     "db_err_vs_oracle": {"frames": sorted(ospectra), "median": float(np.median(dbe)),
+                                          "p99": float(np.percentile(dbe, 99)), "max": float(dbe.max())},
+                     "peak_err_deg_max_vs_oracle": err, "peak_count_mismatch_frames": mism,
+                     "status_nonzero_frames": int(np.count_nonzero(res["status"]))}
+        del db
+    return out
 
 
 def main():
@@ -209,8 +447,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-frames", type=int, default=8192)
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
-    ap.add_argument("--c64-scan", default="split16", choices=["split16", "fp32"],
-                    help="matrix-core kernel of the FP32-accuracy scan (FP16 hi/lo split or FP32 operands)")
+    ap.add_argument("--c64-scan", default="fp32", choices=["split16", "fp32"],
+                    help="matrix-core kernel of the complex64 scan (FP32 operands, or the FP16 hi/lo split)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the FP64 single-frame latency leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 4096-frame uneven-batch leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 16-bit precision leg")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
@@ -238,6 +479,12 @@ def main():
     fs5 = None
     if not args.no_learned and os.path.exists(WEIGHTS):
         fs5 = make_frames_parallel("c5", args.learned_frames)
+    fs1 = make_frames("c1") if not args.no_c1 else None
+    fs3 = make_frames_parallel("c3", 4096) if not args.no_c3 else None
+    fs4 = o4 = None
+    if not args.no_c4:
+        fs4 = make_frames_parallel("c4", 64)
+        o4 = oracle_peaks_parallel("c4", 64, "music", keep_spectrum=(0, 21, 42, 63))
 
     import torch
     from paper_2007_14135_amd import autotune
@@ -323,6 +570,10 @@ def main():
     peak = PEAK_FP16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
     # matrix-core flops executed: the split forms each product from three FP16 products
     mfma_flops = scan_flops * (3.0 if split else 1.0)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    stage_roof = stage_rooflines(stage_ms, fs.frames, args.alg, peak)
+    # the single-kernel stage that takes longest in one step (the peak stage is three kernels)
+    dominant = max(("covariance", "eigen", "scan"), key=lambda k: stage_ms[k])
 
     # the same step with the other C64 scan kernel (its own tuned work items), for comparison
     other = None
@@ -359,6 +610,27 @@ def main():
                  "scan_roofline_frac": scan_flops / (o_avg / 1e3) / 1e12 / o_peak, "scan_peak_tflops": o_peak}
         del db2
 
+    scan_roofline = {
+        "kernel": SCAN_KERNEL[args.c64_scan],
+        "bound": "mfma",
+        "achieved": achieved_tflops,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved_tflops / peak,
+        "traffic": scan_traffic(rows or 384, args.c64_scan) if args.alg == "music" else None,
+        "algorithmic_flops_per_launch": scan_flops,
+        "mfma_flops_per_launch": mfma_flops,
+        "mfma_frac": mfma_flops / scan_avg_s / 1e12 / peak,
+        "avg_launch_ms": scan_avg_s * 1e3,
+    }
+    if dominant == "scan":
+        roofline = scan_roofline
+    else:
+        # another stage dominates: its own kernel against its own unit, the scan's figures beside
+        sr = stage_roof[dominant]
+        roofline = {"kernel": STAGE_KERNEL[dominant], "bound": sr["bound"], "achieved": sr["achieved"],
+                    "peak": sr["peak"], "unit": sr["unit"], "frac": sr["frac"], "traffic": None,
+                    "avg_launch_ms": sr["ms"], "scan": scan_roofline}
     out = {
         "metric": METRIC,
         "value": value,
@@ -371,6 +643,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16x3-split/f32-acc" if split else "f32",
+        "dtype_note": ("complex64 snapshots; FP64 covariance accumulation, eigensolve, noise subspace and peak "
+                       "refinement; scan on FP32 operands with FP32 accumulation" if not split else
+                       "complex64 snapshots; FP64 covariance accumulation, eigensolve, noise subspace and peak "
+                       "refinement; scan on FP16 hi/lo parts of the FP32 operands (22-bit operands)"),
         "data": "synthetic",
         "frames_per_s": F / (ms_step / 1e3),
         "batches_in_flight": S,
@@ -386,20 +662,10 @@ def main():
         },
         "autotune": {"knob": "scan_rows", "chosen": rows or 384,
                      "scan_ms_by_candidate": {str(k): v for k, v in tune_ms.items()}},
-        "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
-        "roofline": {
-            "kernel": SCAN_KERNEL[args.c64_scan],
-            "bound": "mfma",
-            "achieved": achieved_tflops,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / peak,
-            "traffic": scan_traffic(rows or 384, args.c64_scan) if args.alg == "music" else None,
-            "algorithmic_flops_per_launch": scan_flops,
-            "mfma_flops_per_launch": mfma_flops,
-            "mfma_frac": mfma_flops / scan_avg_s / 1e12 / peak,
-            "avg_launch_ms": scan_avg_s * 1e3,
-        },
+        "stage_ms": stage_ms,
+        "stage_roofline": stage_roof,
+        "dominant_kernel_stage": dominant,
+        "roofline": roofline,
         "other_c64_scan": other,
         "host_wall_s": wall,
         "status_nonzero_frames": int(np.count_nonzero(res["status"])),
@@ -424,6 +690,15 @@ def main():
         del db
         torch.cuda.empty_cache()
         out["learned_vs_full"] = learned_leg(fs5, 3, 1)
+    if fs1 is not None:
+        out["c1_fp64_single_frame"] = c1_leg(fs1, 200, 10)
+    if fs3 is not None:
+        out["c3_uneven_batch"] = c3_leg(fs3, 5, 2, args.tune_cache, args.c64_scan)
+        del fs3
+        torch.cuda.empty_cache()
+    if fs4 is not None:
+        out["c4_precision"] = c4_leg(fs4, 5, 1, args.tune_cache, o4[0], o4[1])
+        torch.cuda.empty_cache()
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")

@@ -64,7 +64,11 @@ typedef enum { NSSDOA_PHD = 0, NSSDOA_MUSIC = 1, NSSDOA_EV = 2, NSSDOA_MN = 3 } 
  * BF16, F16: complex64 snapshots, scan operands rounded to bfloat16 / IEEE half on the matrix
  *       cores with FP32 accumulation; float spectrum.
  * For C64, BF16 and F16 every point whose scanned ||B^H a||^2 is below lowq_tau * ||B||_F^2 (the
- * neighbourhoods of the spectrum peaks) is re-evaluated in FP64 before the peak search. */
+ * neighbourhoods of the spectrum peaks) is re-evaluated in FP64 before the peak search.  For BF16
+ * and F16 the threshold is at least 12 E^2, E = c ||B||_F + e0 sqrt(K) with
+ * c = sqrt(2M) (2u + u^2 + (2M + 4) 2^-24), u = 2^-9 (BF16) or 2^-11 (F16), e0 = sqrt(2) M 2^-25
+ * (F16) or 0 (BF16): E bounds the error of the 16-bit B^H a, so every point where the relative
+ * bound 2E/sqrt(Q) + E^2/Q on the scanned Q reaches 1 is re-evaluated in FP64. */
 typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 } nssdoa_prec;
 
 /* Per-frame status bits written to status[] by nssdoa_estimate. */
@@ -75,7 +79,8 @@ typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 
 #define NSSDOA_ST_FEWER_PEAKS       0x8u  /* fewer than D local maxima; unused slots idx = -1      */
 #define NSSDOA_ST_PEAK_OVERFLOW     0x10u /* more local maxima than the candidate buffer holds     */
 #define NSSDOA_ST_FALLBACK_USED     0x20u /* windowed estimation scanned the whole grid (best score
-                                             below the threshold); informational                */
+                                             below the threshold, or the windows held fewer than D
+                                             peaks); informational                               */
 
 /* An array geometry: M elements at host positions pos_wl[3*m + {0,1,2}] = (x, y, z) in
  * wavelengths (Eq. 2).  The plan copies the positions; the caller may free them afterwards. */
@@ -317,7 +322,10 @@ nssdoa_status nssdoa_mlp_gradients(nssdoa_mlp mlp, float* host, size_t count);
  * step + 1e-9), clipped to [0, L), each operation rounded in FP64; overlapping or touching windows
  * merge.  If the frame's best score is below the threshold (or NaN) the frame falls back to one
  * window over its whole grid and gets NSSDOA_ST_FALLBACK_USED.  Windows never wrap around a
- * circular grid.
+ * circular grid.  A frame whose windows hold fewer than D peaks (a proposal that missed a source,
+ * or a peak whose plateau reaches a window's end) is searched again, on the device within the same
+ * call, with one window over its whole grid, and also gets NSSDOA_ST_FALLBACK_USED: its peaks are
+ * then those of the whole grid.
  * Within the windows everything is as in nssdoa_estimate (FP32 scan, FP64 re-evaluation of
  * low-Q points, FP64 re-pick around the candidates) except that spectrum values outside every
  * window are unknown: the first and last points of a window are never peaks, and a peak's

@@ -161,3 +161,31 @@ def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid
         else:
             merged.append((a, b))
     return merged
+
+
+def estimate_proposed(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, scores, topk: int,
+                      half_window_deg: float, threshold):
+    """Windowed estimation driven by per-bin scores, as the learned path runs it.
+
+    1. windows from the scores (proposal_windows, with the threshold's whole-grid fallback);
+    2. the windowed search (doa.estimate_windowed);
+    3. rescue: when the windows did not cover the whole grid by the threshold fallback and they
+       held fewer than D peaks (a proposal that missed a source, or a peak on a window's end), the
+       search runs again with one window over the whole grid.
+
+    Returns (estimate, fallback, rescued): fallback = the threshold sent the frame to the whole
+    grid; rescued = step 3 ran.  Not part of the paper: the rule makes the full scan the judge of
+    every frame whose windows cannot hold D peaks.
+    """
+    from .doa import estimate_windowed
+    start, step, L = grid
+    s = np.asarray(scores, dtype=np.float64)
+    wins = proposal_windows(s, topk, half_window_deg, start, step, L, threshold=threshold)
+    finite = s[~np.isnan(s)]
+    fallback = threshold is not None and not (finite.size and finite.max() >= threshold)
+    est = estimate_windowed(X, pos, D, grid, alg, wins)
+    rescued = False
+    if not fallback and len(est.peaks) < D and np.all(np.isfinite(est.R)):
+        est = estimate_windowed(X, pos, D, grid, alg, [(0, int(L))])
+        rescued = True
+    return est, fallback, rescued

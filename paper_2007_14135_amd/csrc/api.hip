@@ -651,6 +651,7 @@ size_t windowed_layout(const nssdoa_batch_s* b, int n_feat, int n_bins, LearnedL
     }
     lay->off_scan_items = (int64_t)off;  off = align_up(off + (size_t)n_scan * 8);
     lay->off_chunk_items = (int64_t)off; off = align_up(off + (size_t)n_chunk * 16);
+    lay->off_rescue = (int64_t)off;      off = align_up(off + F * sizeof(int32_t));
     return off;
 }
 
@@ -783,6 +784,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     pp.extra = opt.extra_candidates;
     pp.max_D = batch->max_D;
     pp.refine_lowq = c128 ? 0 : 1;
+    pp.lp_floor = batch->prec == NSSDOA_BF16 || batch->prec == NSSDOA_F16;
     pp.use_user_spec = use_user;
     // plateau depth of the peak candidates: above the relative error of the scanned spectrum
     // (FP32 and 16-bit scans after the FP64 re-evaluation of low-Q points; FP64 scan)
@@ -825,6 +827,30 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
                              r.second.second - r.second.first, batch->d_frames, batch->d_pos, batch->d_cis, ws, spec,
                              pp, peaks, npeaks, status, s);
             if (e != hipSuccess) return hip_fail(e, "peak launch");
+        }
+        // second pass: frames whose windows held fewer than D peaks, over their whole grid (the
+        // host enqueues it unconditionally; frames that need nothing get no work items)
+        int32_t* rescue = reinterpret_cast<int32_t*>(ws + lay.off_rescue);
+        for (auto& r : batch->peak_ranges) {
+            e = launch_rescue(batch->d_frames, batch->d_plist + r.second.first, r.second.second - r.second.first,
+                              npeaks, status, ws, lay, rescue + r.second.first, s);
+            if (e != hipSuccess) return hip_fail(e, "rescue launch");
+        }
+        e = launch_expand(batch->d_frames, F, ws, lay, s);
+        if (e == hipSuccess)
+            e = launch_scan_windows(batch->split16, M, batch->d_frames, F, batch->d_groups, batch->d_blk,
+                                    batch->d_steer, ws, lay, static_cast<float*>(spec), use_user,
+                                    (float)opt.lowq_tau, persistent_grid(8), s);
+        if (e == hipSuccess)
+            e = launch_window_peaks(bucket, batch->d_frames, F, batch->d_pos, batch->d_cis, ws, lay,
+                                    opt.extra_candidates, opt.lowq_tau, pp.plateau_rel, static_cast<float*>(spec),
+                                    use_user, persistent_grid(2), s);
+        if (e != hipSuccess) return hip_fail(e, "rescue scan launch");
+        for (auto& r : batch->peak_ranges) {
+            pp.sel_cap = batch->peak_selcap[&r - &batch->peak_ranges[0]];
+            e = launch_peaks(false, r.first, nullptr, 0, rescue + r.second.first, r.second.second - r.second.first,
+                             batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
+            if (e != hipSuccess) return hip_fail(e, "rescue peak launch");
         }
         return stage_end(NSSDOA_STAGE_PEAKS);
     }

@@ -591,7 +591,10 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         for (int e = tid; e < M; e += bd) evals[e] = nan;
         for (int e = tid; e < M * M; e += bd) evecs[e] = make_double2(nan, nan);
         for (int e = tid; e < M * K; e += bd) Bs[e] = make_double2(0.0, 0.0);
-        if (tid == 0) *qref = nan;
+        if (tid == 0) {
+            *qref = nan;
+            if (prm.write_emb == 2 || prm.write_emb == 3) qref[1] = nan;
+        }
     } else {
         if (tid < M) {
             const double li = lamv[tid * lstride];
@@ -646,7 +649,11 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         double q = 0.0;
         for (int e = tid; e < M * K; e += bd) q += Bs[e].x * Bs[e].x + Bs[e].y * Bs[e].y;
         q = block_sum(q, red);
-        if (tid == 0) *qref = q;
+        if (tid == 0) {
+            *qref = q;
+            // 16-bit scans: the Q below which a point is re-evaluated in FP64 at the least
+            if (prm.write_emb == 2 || prm.write_emb == 3) qref[1] = lp_lowq_floor(M, K, q, prm.write_emb == 3);
+        }
     }
     __syncthreads();
     for (int e = tid; e < M * K; e += bd) Bout[e] = Bs[e];

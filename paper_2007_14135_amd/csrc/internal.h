@@ -71,6 +71,22 @@ struct GroupDev {
 // of the FP32 table): hi = fp16(2^13 v), lo = fp16(2^13 v - hi).
 constexpr float kSplitSteerScale = 8192.0f;
 
+// Low-Q floor of the 16-bit scans.  With both operands rounded to 16 bits (unit roundoff u:
+// 2^-9 bfloat16, 2^-11 FP16), FP32 steering values and FP32 accumulation over 2M terms, each
+// y_k = b_k^H a is off by at most c ||b_k|| + e0, c = sqrt(2) sqrt(M) (2u + u^2 + (2M + 4) 2^-24),
+// e0 = sqrt(2) M 2^-25 (FP16 subnormals; 0 for bfloat16), so with S = ||B||_F^2 and K columns
+// E = c sqrt(S) + e0 sqrt(K) bounds the error of the vector B^H a and |dQ| <= 2 E sqrt(Q) + E^2.
+// That relative bound exceeds 1 exactly where Q < (1 + sqrt 2)^2 E^2; such a point scans to
+// Q_scan < (2 + sqrt 2)^2 E^2 < 12 E^2, so every point scanned below 12 E^2 is re-evaluated in
+// FP64 and the bound holds, with a relative error below 1, at every point that is not.
+__host__ __device__ inline double lp_lowq_floor(int M, int K, double S, bool f16) {
+    const double u = f16 ? 0x1p-11 : 0x1p-9;
+    const double c = sqrt(2.0 * M) * (2.0 * u + u * u + (2.0 * M + 4.0) * 0x1p-24);
+    const double e0 = f16 ? sqrt(2.0) * M * 0x1p-25 : 0.0;
+    const double E = c * sqrt(S) + e0 * sqrt((double)K);
+    return 12.0 * E * E;
+}
+
 // Steering table of a group for the FP32 scans: for grid index l (rounded up to whole 256-angle
 // tiles) and h = 0, 1, the M floats T[(2 l + h) M + k] are Re a_{2k+h}(theta_l) for k < M/2 and
 // Im a_{2(k-M/2)+h}(theta_l) for k >= M/2: the steering operand of MFMA lane h*32 + j for angle
@@ -100,6 +116,7 @@ struct PeakParams {
     int32_t extra;              // candidates beyond D
     int32_t max_D;              // peak slots per frame
     int32_t refine_lowq;        // 1 for FP32 spectra
+    int32_t lp_floor;           // 16-bit scans: the threshold is at least the frame's 16-bit floor
     int32_t use_user_spec;      // spectrum lives in the caller's buffer
     int32_t sel_cap;            // candidate slots of the launch's largest frame (<= kSelCap)
     // windowed estimation (both NULL otherwise): candidate chunks per frame, and the per-frame
@@ -123,6 +140,7 @@ struct LearnedLayout {
     int64_t off_lowq_off;
     int64_t off_scan_items;     // int2 {frame, first angle | angles << 24} per 64-angle scan item
     int64_t off_chunk_items;    // int4 {frame, first point, window start, window end} per chunk
+    int64_t off_rescue;         // n_frames int32: frames searched again over the whole grid, or -1
 };
 
 // Upper bounds of the windowed work lists of one frame (a fallback frame scans its whole grid).
@@ -515,6 +533,9 @@ hipError_t launch_features(const int32_t* flist, int n, const FrameDev* frames, 
 hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
                             double half_window, float threshold, char* ws, const LearnedLayout& lay,
                             uint32_t* status, hipStream_t s);
+hipError_t launch_rescue(const FrameDev* frames, const int32_t* frame_list, int n_list, const int32_t* npeaks,
+                         uint32_t* status, char* ws, const LearnedLayout& lay, int32_t* rescue, hipStream_t s);
+hipError_t launch_expand(const FrameDev* frames, int n_frames, char* ws, const LearnedLayout& lay, hipStream_t s);
 hipError_t launch_scan_windows(bool split16, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
                                const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);

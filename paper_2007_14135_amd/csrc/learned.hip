@@ -20,6 +20,10 @@
 // winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
 //   chunk: the chunk's best D + extra plateau winners to its candidate slots.  Values outside a
 //   window are unknown, so a window's end points are never peaks.
+// rescue_kernel, one thread per frame, after the peak selection: a frame whose windows held fewer
+//   than D peaks (a proposal that missed a source, or a peak whose plateau reaches a window end)
+//   gets one window over its whole grid and is searched again by the same kernels; every other
+//   frame gets no work in that second pass and keeps its peaks.
 #include <float.h>
 
 #include "nssdoa.h"
@@ -136,6 +140,33 @@ __global__ void lowq_count_kernel(const FrameDev* __restrict__ frames, int n_fra
         const FrameDev& fr = frames[f];
         const int n = min(*reinterpret_cast<const int*>(ws + fr.ws_lowq), fr.lowq_cap);
         reinterpret_cast<int*>(ws + lay.off_lowq)[f] = (n + 63) / 64;
+    }
+}
+
+__global__ void rescue_kernel(const FrameDev* __restrict__ frames, const int32_t* __restrict__ flist, int n_list,
+                              const int32_t* __restrict__ npeaks, uint32_t* __restrict__ status,
+                              char* __restrict__ ws, LearnedLayout lay, int32_t* __restrict__ rescue) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_list; i += gridDim.x * blockDim.x) {
+        const int f = flist[i];
+        const FrameDev& fr = frames[f];
+        const uint32_t st = status[f];
+        const bool again = !(st & (NSSDOA_ST_NONFINITE_INPUT | NSSDOA_ST_FALLBACK_USED)) && npeaks[f] < fr.D;
+        int* W = reinterpret_cast<int*>(ws + lay.off_win) + (size_t)f * kWinStride;
+        int items = 0, chunks = 0;
+        if (again) {
+            W[0] = 1;
+            W[1] = 0;
+            W[2] = fr.L;
+            items = (fr.L + kScanAnglesPerWave - 1) / kScanAnglesPerWave;
+            chunks = (fr.L + kRefineChunk - 1) / kRefineChunk;
+            status[f] = (st & ~(NSSDOA_ST_FEWER_PEAKS | NSSDOA_ST_PEAK_OVERFLOW)) | NSSDOA_ST_FALLBACK_USED;
+        } else {
+            W[0] = 0;
+        }
+        reinterpret_cast<int*>(ws + lay.off_items)[f] = items;
+        reinterpret_cast<int*>(ws + lay.off_chunks)[f] = chunks;
+        *reinterpret_cast<int*>(ws + fr.ws_lowq) = 0;      // the second pass's low-Q list
+        rescue[i] = again ? f : -1;
     }
 }
 
@@ -459,12 +490,25 @@ hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* s
                        half_window, threshold, ws, lay, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_expand(frames, n_frames, ws, lay, s);
+}
+
+hipError_t launch_expand(const FrameDev* frames, int n_frames, char* ws, const LearnedLayout& lay, hipStream_t s) {
     hipLaunchKernelGGL(prefix_kernel, dim3(1), dim3(1024), 0, s, n_frames,
                        reinterpret_cast<const int*>(ws + lay.off_items), reinterpret_cast<int*>(ws + lay.off_item_off),
                        reinterpret_cast<const int*>(ws + lay.off_chunks),
                        reinterpret_cast<int*>(ws + lay.off_chunk_off));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(expand_kernel, dim3((n_frames + 3) / 4), dim3(256), 0, s, frames, n_frames, ws, lay);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescue(const FrameDev* frames, const int32_t* frame_list, int n_list, const int32_t* npeaks,
+                         uint32_t* status, char* ws, const LearnedLayout& lay, int32_t* rescue, hipStream_t s) {
+    if (n_list <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rescue_kernel, dim3((n_list + 255) / 256), dim3(256), 0, s, frames, frame_list, n_list, npeaks,
+                       status, ws, lay, rescue);
     return hipGetLastError();
 }
 

@@ -132,7 +132,9 @@ __global__ __launch_bounds__(kLmThreads, 4) void localmax_kernel(const PointItem
     // false both ways).
     const uint32_t fst = status[f];
     const int overflow = prm.refine_lowq ? *reinterpret_cast<const int*>(ws + fr.ws_lowq) : 0;
-    const double qref = prm.refine_lowq ? *reinterpret_cast<const double*>(ws + fr.ws_qref) : 0.0;
+    const double* qrp = reinterpret_cast<const double*>(ws + fr.ws_qref);
+    const double qref = prm.refine_lowq ? qrp[0] : 0.0;
+    const double qfloor = prm.refine_lowq && prm.lp_floor ? qrp[1] : 0.0;
     constexpr int kPer = (kSpanMax + kLmThreads - 1) / kLmThreads;
     TS xs[kPer];
 #pragma unroll
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kLmThreads, 4) void localmax_kernel(const PointItem
     if (overflow) {
         // list the low-Q points (one LDS atomic per wave), then re-evaluate them in FP64, one per
         // thread; the halo gets the same rounded values the neighbouring chunk writes
-        const double pthr = 1.0 / (prm.lowq_tau * qref);
+        const double pthr = 1.0 / fmax(prm.lowq_tau * qref, qfloor);
         const int lane = tid & 63;
         for (int e0 = 0; e0 < span; e0 += blockDim.x) {
             const int e = e0 + tid;
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
     __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
 
     const int f = flist[blockIdx.x];
+    if (f < 0) return;                          // a frame with nothing to select (uniform)
     const FrameDev& fr = frames[f];
     const int tid = threadIdx.x;
     const int L = fr.L, D = fr.D;

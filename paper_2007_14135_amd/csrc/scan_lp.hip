@@ -8,6 +8,8 @@
 // j), so the per-frame reduction over 8-row blocks is the same as in the FP32 scan.
 // Steering values are formed as in the FP32 scan (phase in FP64, reduced, FP32 sincospi) and
 // rounded once to the operand type; embedded B tiles are rounded by the eigen kernel.
+// Points whose Q is below max(lowq_tau ||B||_F^2, the frame's 16-bit floor lp_lowq_floor, which
+// the eigen kernel stores after ||B||_F^2) go to the FP64 re-evaluation list.
 #include <float.h>
 
 #include "internal.h"
@@ -97,7 +99,8 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
             float* out = spec + (use_user ? fd.spec_off_user : fd.spec_off_ws);
             out[l] = 1.0f / fmaxf(v, FLT_MIN);
         }
-        const float thr = lowq_tau * (float)*reinterpret_cast<const double*>(ws + fd.ws_qref);
+        const double* qr = reinterpret_cast<const double*>(ws + fd.ws_qref);
+        const float thr = fmaxf(lowq_tau * (float)qr[0], (float)qr[1]);
         scan_lowq_collect(in && v < thr, f, wave * kScanAnglesPerWave + lane, lq,
                           reinterpret_cast<int*>(ws + fd.ws_lowq));
     };

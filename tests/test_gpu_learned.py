@@ -5,11 +5,14 @@ M=16, D in 1..4, N in 256..4096, SNR -5..20 dB, 0.001 deg grid) the learned path
 +-1 deg, full-grid fallback below score 0.5) is compared with the full scan on the same GPU:
   * a miss is a frame whose peaks differ from the full scan's by more than 0.01 deg (or in
     number); the full scan itself is at parity with the FP64 oracle (test_gpu_parity);
-  * the learned path must be faster than the full scan, with at most 3 % misses;
+  * the learned path must be faster than the full scan, with at most one missed frame in 1024
+    (frames whose windows hold fewer than D peaks are searched again over the whole grid on the
+    device, so a proposal that misses a source costs time, not accuracy);
   * without training (the same network at its initial weights) the windows are in the wrong
-    places: the miss rate is far higher, so the gain is the network's;
-  * a non-learned proposer (the library's own MUSIC scan at 1 deg, its D peaks as windows) is
-    reported beside it as the honest ablation.
+    places: the miss rate is far higher, or every frame falls back, so the gain is the network's;
+  * a non-learned proposer run entirely on the device (the library's own MUSIC scan at 1 deg,
+    its D peaks turned into bin scores by a scatter on the device, then the same windowed search)
+    is the honest ablation: the learned path must beat it in time at no more misses.
 """
 
 import os
@@ -79,7 +82,7 @@ def test_trained_network_beats_the_full_scan(setup):
     fb = float(np.mean((res["status"] & ST_FALLBACK) != 0))
     print("trained: %.3f ms vs full scan %.3f ms (gain %.2fx), miss rate %.4f, fallback %.4f"
           % (ms, ms_full, ms_full / ms, miss, fb), flush=True)
-    assert miss <= 0.03
+    assert miss * len(fs) <= 1
     assert ms < ms_full
 
 
@@ -98,31 +101,40 @@ def test_untrained_network_misses(setup):
     assert miss > 0.2 or ms > 0.5 * ms_full
 
 
-def test_coarse_scan_proposer_ablation(setup):
-    # non-learned proposal: the library's MUSIC at 1 deg (bin centres -89.5 + b), its D peaks
-    # become the windows (score 1 at each peak's bin, 0 elsewhere)
-    nd, fs, db, trained, full, ms_full = setup
+def coarse_proposer(fs, db):
+    """The non-learned proposal, on the device: MUSIC at 1 deg (bin centres -89.5 + b) through the
+    library, its peaks' bins scored 1 (others 0) by a scatter on the device, then the windowed
+    search of the fine grid with those scores."""
     from paper_2007_14135_amd.runner import prepare
     fr0 = fs.frames[0]
     frames = [(0, 0, fr.N, fr.D, int(fs.x_off[f]), int(fs.ld[f])) for f, fr in enumerate(fs.frames)]
-    coarse = prepare([fr0.pos], [(-89.5, 1.0, 180, 0)], frames, fs.X_flat, "music", "c64", 4, with_spectrum=False)
-    coarse.X = db.X
-    scores = torch.zeros(len(fs), 180, dtype=torch.float32, device="cuda")
+    coarse = prepare([fr0.pos], [(-89.5, 1.0, 180, 0)], frames, fs.X_flat, "music", "c64", 4, with_spectrum=False,
+                     X_device=db.X)
+    F = len(fs)
+    scores = torch.zeros(F, 180, dtype=torch.float32, device="cuda")
+    # peak records are 24 bytes: int32 idx, int32 reserved, double angle, double value
+    idx = coarse.peaks.view(torch.int32).view(F, coarse.batch.max_D, 6)[:, :, 0]
 
-    def propose_and_scan():
+    def run():
         coarse.run()
-        torch.cuda.synchronize()
-        r = coarse.host_results()
-        s = np.zeros((len(fs), 180), dtype=np.float32)
-        for f in range(len(fs)):
-            for j in range(int(r["npeaks"][f])):
-                s[f, int(r["peaks"][f]["idx"][j])] = 1.0
-        scores.copy_(torch.from_numpy(s))
+        scores.zero_()
+        scores.scatter_(1, idx.clamp(min=0).long(), (idx >= 0).float())
         db.run_windowed(scores, 6, 1.0, 0.5)
 
-    ms = _timed(propose_and_scan, reps=2)
+    return run
+
+
+def test_coarse_scan_proposer_ablation(setup):
+    nd, fs, db, trained, full, ms_full = setup
+    run = coarse_proposer(fs, db)
+    ms = _timed(run)
     res = db.host_results()
     miss = _miss_rate(fs, full, res)
     fb = float(np.mean((res["status"] & ST_FALLBACK) != 0))
-    print("coarse 1-deg MUSIC proposer: %.3f ms (host round trip included), miss rate %.4f, fallback %.4f"
-          % (ms, miss, fb), flush=True)
+    ms_l = _timed(lambda: db.run_learned(trained, 6, 1.0, 0.5))
+    res_l = db.host_results()
+    miss_l = _miss_rate(fs, full, res_l)
+    print("coarse 1-deg MUSIC proposer (on the device): %.3f ms, miss rate %.4f, fallback %.4f; learned %.3f ms, "
+          "miss rate %.4f" % (ms, miss, fb, ms_l, miss_l), flush=True)
+    assert ms_l < ms
+    assert miss_l <= miss + 1.0 / len(fs)

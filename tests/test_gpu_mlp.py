@@ -1,15 +1,17 @@
-"""GPU parity of the proposal network kernels against the MLP oracle.
+"""GPU parity of the proposal network kernels against the FP64 MLP oracle.
 
-The kernels round both operands of every matrix product to bfloat16 and accumulate in FP32.  The
-ReLU decisions of the network are taken on those values, so the parity comparison runs the
-oracle in its bfloat16-operand mode (the same roundings, FP64 products and sums): the remaining
-differences are FP32 accumulation and storage (K <= 512 terms: about 512 * 2^-24 relative), and
-the gates are, per layer, gradient-norm relative error <= 1e-3 with cosine >= 0.9999, and logits
-within 1e-4 (relative to the largest) in all but a few rows: a hidden value that lies within the
-FP32-vs-FP64 accumulation difference of a bfloat16 rounding boundary rounds the other way on one
-side (about 2^-24 / 2^-9 of the values), which moves that row's logits by up to one bfloat16
-step of that value times its weights.  Against the exact FP64 oracle the differences are bfloat16-sized and
-include ReLU decisions flipped by rounding; those are reported, with a cosine gate of 0.99.
+The kernels round both operands of every matrix product to bfloat16 (unit roundoff 2^-9) and
+accumulate in FP32.  Each product then carries a relative error of at most about 2^-8, and the
+errors of the K <= 512 products of a sum are independent with random signs, so a gradient
+component's relative error is of order 2^-8 only where its terms do not cancel; summed over a
+layer (hundreds of thousands of components) the error vector's norm stays near 2^-8 of the
+gradient's, i.e. a cosine of about 1 - 2^-17, plus the rare hidden units whose ReLU decision flips
+under the rounding.  The binding gates are those of the learned-proposal oracle step: per layer the
+gradient norm within 1e-2 relative and cosine >= 0.999 against the exact FP64 oracle, the logits
+within 3e-2 of the largest.  Adam is checked step by step, at t = 1..5, against the oracle's update
+applied to the kernels' own gradients and moments (FP32 arithmetic against FP64: a few ulps).  The
+oracle's bfloat16-operand mode (the same operand roundings in FP64) is printed beside the FP64
+figures as a diagnostic only: it shows how much of the difference is operand rounding.
 """
 
 import numpy as np
@@ -66,17 +68,63 @@ def test_gradients_match_oracle():
     torch.cuda.synchronize()
     lo16, grads16 = omlp.backward(params, X, Y, precision="bf16")
     lo, grads = omlp.backward(params, X, Y)
-    assert abs(float(loss.item()) - lo16) <= 1e-5 * lo16
+    assert abs(float(loss.item()) - lo) <= 1e-3 * lo
+    print("loss %.7f, FP64 oracle %.7f (bf16-operand oracle %.7f)" % (float(loss.item()), lo, lo16), flush=True)
     g = nd.unflatten_params(net.gradients().astype(np.float64), SIZES)
+    _gate_gradients(g, grads, grads16)
+
+
+def _gate_gradients(g, grads, grads16=None, tag=""):
     for li in range(3):
         for which, name in ((0, "W"), (1, "b")):
             a = g[li][which].ravel()
-            for ref, tag, rel_gate, cos_gate in ((grads16, "bf16-operand", 1e-3, 0.9999), (grads, "FP64", 5e-2, 0.99)):
-                b = ref[li][which].ravel()
-                rel = abs(np.linalg.norm(a) - np.linalg.norm(b)) / np.linalg.norm(b)
-                cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-                print("layer %d %s vs %s oracle: norm rel %.2e cos %.7f" % (li + 1, name, tag, rel, cos), flush=True)
-                assert rel <= rel_gate and cos >= cos_gate, (li, name, tag, rel, cos)
+            b = grads[li][which].ravel()
+            rel = abs(np.linalg.norm(a) - np.linalg.norm(b)) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            diag = ""
+            if grads16 is not None:
+                c = grads16[li][which].ravel()
+                diag = "; bf16-operand oracle (diagnostic): norm rel %.2e cos %.7f" % (
+                    abs(np.linalg.norm(a) - np.linalg.norm(c)) / np.linalg.norm(c),
+                    a @ c / (np.linalg.norm(a) * np.linalg.norm(c)))
+            print("%slayer %d %s vs FP64 oracle: norm rel %.2e cos %.7f%s" % (tag, li + 1, name, rel, cos, diag),
+                  flush=True)
+            assert rel <= 1e-2 and cos >= 0.999, (tag, li, name, rel, cos)
+
+
+def test_adam_steps_match_oracle():
+    # five training steps; at each one the gradients are gated against the FP64 oracle at the
+    # network's current parameters, and the update against the oracle's Adam step t applied to
+    # the kernels' gradients and moments (bias corrections 1 - beta^t change with t)
+    nd, net, params, X, Y = _setup(192, seed=11)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Yd = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lr = 2e-3
+    for t in range(1, 6):
+        p0, m0, v0, step0 = net.state()
+        assert step0 == t - 1
+        net.train_step(Xd, Yd, lr, loss)
+        torch.cuda.synchronize()
+        p1, m1, v1, step1 = net.state()
+        assert step1 == t
+        g = net.gradients().astype(np.float64)
+        P0 = nd.unflatten_params(p0.astype(np.float64), SIZES)
+        _, gref = omlp.backward(P0, X, Y)
+        _gate_gradients(nd.unflatten_params(g, SIZES), gref, tag="step %d: " % t)
+        G = nd.unflatten_params(g, SIZES)
+        Mo = nd.unflatten_params(m0.astype(np.float64), SIZES)
+        Vo = nd.unflatten_params(v0.astype(np.float64), SIZES)
+        pn, mn, vn = omlp.adam_step(P0, G, Mo, Vo, t, lr)
+        pe, me, ve = (nd.flatten_params(x) for x in (pn, mn, vn))
+        # FP32 moment updates: a few roundings of the two terms' magnitudes (m may cancel)
+        dm = np.abs(m1 - me) / (0.9 * np.abs(m0) + 0.1 * np.abs(g) + 1e-38)
+        dv = np.abs(v1 - ve) / (0.999 * np.abs(v0) + 0.001 * g * g + 1e-45)
+        # FP32 storage of p and the FP32 step (a value of magnitude <= lr / (1 - beta1^t) * ...)
+        dp = np.abs(p1 - pe) / (np.spacing(np.abs(pe).astype(np.float32)).astype(np.float64) + lr * 2.0 ** -20)
+        print("Adam step %d: max rel m %.2e, v %.2e; max |dp| %.2f ulp-units" % (t, dm.max(), dv.max(), dp.max()),
+              flush=True)
+        assert dm.max() <= 2.0 ** -20 and dv.max() <= 2.0 ** -20 and dp.max() <= 4.0, (t, dm.max(), dv.max(), dp.max())
 
 
 def test_adam_step_and_checkpoint_roundtrip():

@@ -121,3 +121,51 @@ def test_proposal_windows_with_fewer_finite_bins_than_topk():
     s[120] = -np.inf
     got = mlp.proposal_windows(s, 5, 0.5, -90.0, 0.01, 18000)
     assert got == [(4000, 4101), (10000, 10101), (12000, 12101)]   # centres -49.5, 10.5, 30.5
+
+
+def test_proposed_estimate_rescues_a_missed_source():
+    # scores that point at only one of two sources: the windows hold one peak, so the search runs
+    # again over the whole grid and equals the plain estimate (non-circular grid: a whole-grid
+    # window is the plain search)
+    pos, X = _frame(seed=3, th=(-31.3, 12.7))
+    grid = (-90.0, 0.01, 18000)
+    full = estimate(X, pos, 2, grid, "music")
+    s = np.full(180, -5.0)
+    s[int(np.floor(-31.3 + 90))] = 3.0
+    est, fb, rescued = mlp.estimate_proposed(X, pos, 2, grid, "music", s, 6, 1.0, 0.0)
+    assert not fb and rescued
+    assert np.array_equal(est.peaks, full.peaks) and np.array_equal(est.P, full.P)
+    # both sources scored: no rescue, the windowed search alone finds both
+    s[int(np.floor(12.7 + 90))] = 2.5
+    est2, fb2, rescued2 = mlp.estimate_proposed(X, pos, 2, grid, "music", s, 6, 1.0, 0.0)
+    assert not fb2 and not rescued2
+    assert sorted(est2.peaks) == sorted(full.peaks)
+    assert np.isnan(est2.P).sum() > 17000          # only the windows were scanned
+    # a peak on a window's end: the window [l0, p + 1) ends at the first source's peak index
+    p = int(full.peaks[np.argmin(full.angles[full.peaks])])
+    wins = [(p - 150, p + 1)]
+    w = estimate_windowed(X, pos, 2, grid, "music", wins)
+    assert p not in w.all_peaks
+
+
+def test_proposed_estimate_threshold_fallback_is_not_rescued():
+    # every score below the threshold: one whole-grid window, flagged as fallback, never rescued
+    pos, X = _frame(seed=4)
+    grid = (-90.0, 0.1, 1800)
+    s = np.full(180, -2.0)
+    est, fb, rescued = mlp.estimate_proposed(X, pos, 2, grid, "ev", s, 6, 1.0, 0.0)
+    assert fb and not rescued
+    full = estimate(X, pos, 2, grid, "ev")
+    assert np.array_equal(est.peaks, full.peaks)
+    # a frame whose whole spectrum has fewer than D peaks stays with fewer after the rescue: a
+    # 5-point grid 8..12 deg around one source at 10 deg; the window of bin 100 holds 10 and 11 deg
+    # only (no interior point), the whole grid one peak, at 10 deg
+    pos1, X1 = _frame(seed=5, th=(10.0,))
+    g1 = (8.0, 1.0, 5)
+    s1 = np.full(180, -5.0)
+    s1[100] = 4.0
+    assert mlp.proposal_windows(s1, 1, 1.0, *g1, threshold=0.0) == [(2, 4)]
+    e1, fb1, r1 = mlp.estimate_proposed(X1, pos1, 2, g1, "music", s1, 1, 1.0, 0.0)
+    f1 = estimate(X1, pos1, 2, g1, "music")
+    assert r1 and not fb1
+    assert list(e1.peaks) == list(f1.peaks) == [2]
