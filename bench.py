@@ -45,6 +45,7 @@ SCAN_KERNEL = {"split16": "scan_split16_kernel<16>", "fp32": "scan_f32_kernel<16
 STAGE_KERNEL = {"covariance": "cov_mfma_kernel<float2, 1>", "eigen": "evd_ql_kernel", "scan": None}
 TUNE_CACHE = os.path.join(ROOT, "paper_2007_14135_amd", "tuning", "autotune_cache.json")
 PEAK_FP64_TFLOPS = 78.6
+LEARNED_WINDOW_SCORE = 0.05  # windows beyond a frame's first D bins need sigmoid(logit) >= this
 HOST_WORKERS = 16          # host processes: the CPU share of one GPU on the measurement machine
 
 
@@ -172,27 +173,28 @@ def learned_leg(fs, steps, warmup):
     db._windowed_workspace(net)
     ms_full = _timed(lambda: db.run(stream), steps, warmup, stream)
     full = db.host_results()
-    ms_learned = _timed(lambda: db.run_learned(net, 6, 1.0, 0.5, stream), steps * 4, warmup, stream)
+    ms_learned = _timed(lambda: db.run_learned(net, 6, 1.0, 0.5, stream, window_score=LEARNED_WINDOW_SCORE, local_max_bins=True),
+                        steps * 4, warmup, stream)
     learned = db.host_results()
     # honest ablation: a non-learned proposer on the device (MUSIC at 1 deg through the library, its
     # peaks' bins scored 1 by a scatter, then the same windowed search of the fine grid)
     coarse = prepare([fr0.pos], [(-89.5, 1.0, 180, 0)], frames, fs.X_flat, "music", "c64", 4, with_spectrum=False,
                      device="cuda:0", X_device=db.X)
     scores = torch.zeros(F, 180, dtype=torch.float32, device="cuda:0")
-    cidx = coarse.peaks.view(torch.int32).view(F, coarse.batch.max_D, 6)[:, :, 0]
+    cidx = coarse.peaks.view(torch.int32).view(F, coarse.batch.max_D, 8)[:, :, 0]
 
     def coarse_run():
         coarse.run(stream)
         scores.zero_()
         scores.scatter_(1, cidx.clamp(min=0).long(), (cidx >= 0).float())
-        db.run_windowed(scores, 6, 1.0, 0.5, stream)
+        db.run_windowed(scores, 6, 1.0, 0.5, stream, window_floor=0.5)
 
     ms_coarse = _timed(coarse_run, steps * 4, warmup, stream)
     coarse_res = db.host_results()
     del coarse
     db.batch.set_timing(True)                      # stage breakdown: a separate, untimed pass
     for _ in range(3):
-        db.run_learned(net, 6, 1.0, 0.5, stream)
+        db.run_learned(net, 6, 1.0, 0.5, stream, window_score=LEARNED_WINDOW_SCORE, local_max_bins=True)
     stages = {s: db.batch.stage_time(s) for s in ("covariance", "eigen", "proposal", "scan", "peaks")}
     db.batch.set_timing(False)
     fallback = (learned["status"] & nd.ST_FALLBACK_USED) != 0
@@ -219,8 +221,10 @@ def learned_leg(fs, steps, warmup):
                 sq[key][1] += len(truth)
     return {
         "workload": "ULA M=16, D U{1..4}, SNR U[-5,20] dB, N log-U[256,4096] complex64, %d frames, "
-                    "grid [-90,90) at 0.001 deg (L=%d), MUSIC; learned: 6 windows of +-1 deg, "
-                    "full-grid fallback below score 0.5 or when the windows hold fewer than D peaks" % (F, L),
+                    "grid [-90,90) at 0.001 deg (L=%d), MUSIC; learned: windows of +-1 deg around the 6 best "
+                    "local maxima of the network's bin scores (beyond the first D only those scoring >= %.2f), "
+                    "full-grid fallback below score 0.5 or "
+                    "when the windows hold fewer than D peaks" % (F, L, LEARNED_WINDOW_SCORE),
         "frames": F,
         "frames_per_s_full": F / (ms_full / 1e3),
         "frames_per_s_learned": F / (ms_learned / 1e3),
@@ -333,6 +337,60 @@ def c1_leg(fs1, steps, warmup):
         err, mism = _peak_errors(res, 1, {0: sorted(est.angles[est.peaks].tolist())})
         out["peak_err_deg_vs_oracle"][alg] = err if not mism else None
         g.close()
+        del db
+    return out
+
+
+PAPER_TABLE10_MS = {1: 0.438, 30: 0.647, 60: 0.812, 90: 0.924}   # MUSIC end to end, GTX 1660 Ti, float32
+
+
+def c6_leg(fs6, steps, warmup):
+    """The paper's own experiment (Section 5, Tables 8 and 10): 8-element UCA of radius 0.5 lambda,
+    two sources at 15 dB, MUSIC over azimuth 0:1:359 deg x 1, 30, 60 or 90 polar angles, FP32-accuracy
+    scan (complex64) with FP64 eigensolve and peak refinement.  Per grid: the latency of one frame
+    (eager call and graph replay), the throughput of a batch of frames, and the peaks against the
+    oracle."""
+    import torch
+    import oracle
+    from synth import EL_GRIDS_2D
+    from paper_2007_14135_amd.runner import prepare
+    stream = torch.cuda.current_stream()
+    fr0 = fs6.frames[0]
+    F = len(fs6)
+    frames = [(0, 0, fr.N, fr.D, int(fs6.x_off[f]), int(fs6.ld[f])) for f, fr in enumerate(fs6.frames)]
+    out = {"workload": "UCA M=8 radius 0.5 lambda, D=2 uncorrelated sources at 15 dB (azimuth U[0,330] deg >= 30 "
+                       "deg apart, polar angle U[60,90] deg), N=1024 complex64 snapshots; MUSIC over azimuth 0:1:359 "
+                       "deg (circular) x n_polar polar angles at 1 deg; FP32-accuracy scan, FP64 eigensolve and peaks",
+           "batch_frames": F, "grids": {}}
+    for n_el, el in sorted(EL_GRIDS_2D.items()):
+        grid = (fr0.grid_start, fr0.grid_step, fr0.grid_L, 1) + tuple(el)
+        one = prepare([fr0.pos], [grid], frames[:1], fs6.X_flat, "music", "c64", 2, device="cuda:0")
+        us = 1e3 * _timed(lambda: one.run(stream), steps, warmup, stream)
+        g = one.capture()
+        us_g = 1e3 * _timed(lambda: g.launch(stream), steps, warmup, stream)
+        g.close()
+        del one
+        db = prepare([fr0.pos], [grid], frames, fs6.X_flat, "music", "c64", 2, device="cuda:0")
+        ms_b = _timed(lambda: db.run(stream), max(10, steps // 10), warmup, stream)
+        res = db.host_results()
+        err, mism = 0.0, 0
+        for f in range(min(F, 16)):
+            fr = fs6.frames[f]
+            est = oracle.estimate_2d(fr.X, fr.pos, fr.D, fr.grid, el, "music", circular_az=True)
+            n = int(res["npeaks"][f])
+            got = sorted(zip(res["peaks"][f]["angle_deg"][:n].tolist(), res["peaks"][f]["polar_deg"][:n].tolist()))
+            ref = sorted(map(tuple, est.peak_angles.tolist()))
+            if len(got) != len(ref):
+                mism += 1
+                continue
+            for a, b in zip(got, ref):
+                err = max(err, abs(a[0] - b[0]), abs(a[1] - b[1]))
+        pts = fr0.grid_L * el[2]
+        out["grids"]["360x%d" % n_el] = {
+            "points": pts, "us_per_frame": us, "us_per_frame_graph": us_g,
+            "batch_ms": ms_b, "frames_per_s_batched": F / (ms_b / 1e3), "points_per_s_batched": F * pts / (ms_b / 1e3),
+            "peak_err_deg_vs_oracle": err, "peak_count_mismatch_frames": mism, "oracle_frames_checked": min(F, 16),
+            "paper_table10_ms_gtx1660ti_context": PAPER_TABLE10_MS[n_el]}
         del db
     return out
 
@@ -452,6 +510,7 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="skip the FP64 single-frame latency leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096-frame uneven-batch leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 16-bit precision leg")
+    ap.add_argument("--no-2d", action="store_true", help="skip the paper's 2-D (azimuth x polar angle) leg")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
@@ -480,6 +539,7 @@ def main():
     if not args.no_learned and os.path.exists(WEIGHTS):
         fs5 = make_frames_parallel("c5", args.learned_frames)
     fs1 = make_frames("c1") if not args.no_c1 else None
+    fs6 = make_frames("c6", n_frames=256) if not args.no_2d else None
     fs3 = make_frames_parallel("c3", 4096) if not args.no_c3 else None
     fs4 = o4 = None
     if not args.no_c4:
@@ -692,6 +752,8 @@ def main():
         out["learned_vs_full"] = learned_leg(fs5, 3, 1)
     if fs1 is not None:
         out["c1_fp64_single_frame"] = c1_leg(fs1, 200, 10)
+    if fs6 is not None:
+        out["paper_2d_uca8"] = c6_leg(fs6, 200, 10)
     if fs3 is not None:
         out["c3_uneven_batch"] = c3_leg(fs3, 5, 2, args.tune_cache, args.c64_scan)
         del fs3

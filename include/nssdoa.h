@@ -66,7 +66,7 @@ typedef enum { NSSDOA_PHD = 0, NSSDOA_MUSIC = 1, NSSDOA_EV = 2, NSSDOA_MN = 3 } 
  * For C64, BF16 and F16 every point whose scanned ||B^H a||^2 is below lowq_tau * ||B||_F^2 (the
  * neighbourhoods of the spectrum peaks) is re-evaluated in FP64 before the peak search.  For BF16
  * and F16 the threshold is at least 12 E^2, E = c ||B||_F + e0 sqrt(K) with
- * c = sqrt(2M) (2u + u^2 + (2M + 4) 2^-24), u = 2^-9 (BF16) or 2^-11 (F16), e0 = sqrt(2) M 2^-25
+ * c = sqrt(2M) (2u + u^2 + (2M + 4) 2^-24), u = 2^-8 (BF16) or 2^-11 (F16), e0 = sqrt(2) M 2^-25
  * (F16) or 0 (BF16): E bounds the error of the 16-bit B^H a, so every point where the relative
  * bound 2E/sqrt(Q) + E^2/Q on the scanned Q reaches 1 is re-evaluated in FP64. */
 typedef enum { NSSDOA_C128 = 0, NSSDOA_C64 = 1, NSSDOA_BF16 = 2, NSSDOA_F16 = 3 } nssdoa_prec;
@@ -90,15 +90,31 @@ typedef struct {
     const double* pos_wl; /* host, 3*M doubles                                                 */
 } nssdoa_array;
 
-/* A uniform azimuth scan grid (the AngleSer of Table 2, Step-5): theta_l = start_deg +
- * l * step_deg for l = 0..L-1, each computed from l in FP64.  circular != 0 makes the first and
- * last points neighbours for the peak search (a full 360 deg grid); otherwise neither end can be
- * a peak. */
+/* A uniform scan grid (the AngleSer of Table 2, Step-5).
+ * 1-D (n_polar = 0): azimuths theta_l = start_deg + l * step_deg for l = 0..L-1, each computed
+ *   from l in FP64, in the horizontal plane (phi = 90 deg of Eq. 2, taken as sin phi = 1 and
+ *   cos phi = 0 exactly).  circular != 0 makes the first and last points neighbours for the peak
+ *   search (a full 360 deg grid); otherwise neither end can be a peak.
+ * 2-D (n_polar >= 1): the L azimuths above times n_polar polar angles phi_j = polar_start_deg +
+ *   j * polar_step_deg (Eq. 2's phi, measured from +z; 90 deg is the horizontal plane), the
+ *   azimuth x elevation scans of the paper's experiments (Section 5, Tables 8 and 10).  A frame's
+ *   spectrum then holds L * n_polar values, row-major with one row per polar angle: point
+ *   j * L + i is (theta_i, phi_j).  Peaks are the points above their 8 neighbours inside the
+ *   grid: strictly above each neighbour that precedes them in that order, at least equal to
+ *   each one that follows, and strictly above at least one (a plateau is reported at its first
+ *   point; grid edges can hold peaks); the azimuth axis wraps when circular != 0, the polar axis
+ *   never does.  2-D grids are supported with NSSDOA_C64 and NSSDOA_C128 by nssdoa_estimate and
+ *   graph capture (EUNSUPPORTED otherwise). */
 typedef struct {
     double start_deg;
     double step_deg;      /* > 0                                                               */
-    int32_t L;            /* >= 3                                                              */
+    int32_t L;            /* azimuth points, >= 3                                              */
     int32_t circular;
+    double polar_start_deg;  /* 2-D grids: first polar angle, finite                          */
+    double polar_step_deg;   /* 2-D grids: > 0                                                */
+    int32_t n_polar;      /* 0: 1-D grid; 1..4096: polar angles of a 2-D grid; L * n_polar <=
+                             2^24                                                              */
+    int32_t reserved;     /* must be 0                                                         */
 } nssdoa_grid;
 
 /* One frame of snapshots.  X_N of Eq. 3 is M x N with one column per snapshot; it is stored
@@ -115,12 +131,13 @@ typedef struct {
     int64_t spec_off;     /* >= 0                                                              */
 } nssdoa_frame;
 
-/* One selected peak (Table 2, Step-6): grid index, its angle and the FP64 spectrum value. */
+/* One selected peak (Table 2, Step-6): grid index, its direction and the FP64 spectrum value. */
 typedef struct {
-    int32_t idx;          /* grid index, or -1 for an unused slot                              */
+    int32_t idx;          /* grid index (j * L + i on a 2-D grid), or -1 for an unused slot    */
     int32_t reserved;
-    double angle_deg;     /* start + idx * step, NaN for an unused slot                        */
+    double angle_deg;     /* azimuth theta, NaN for an unused slot                             */
     double value;         /* P at idx evaluated in FP64, NaN for an unused slot                */
+    double polar_deg;     /* polar angle phi: 90 on a 1-D grid, NaN for an unused slot         */
 } nssdoa_peak;
 
 /* Hermitian eigensolver of Step-2 (Table 2).  All run in FP64 with one workgroup per frame and
@@ -317,7 +334,10 @@ nssdoa_status nssdoa_mlp_gradients(nssdoa_mlp mlp, float* host, size_t count);
  *
  * Bins: n_bins bins of width w = 180 / n_bins deg; bin b covers [-90 + b w, -90 + (b+1) w) and its
  * centre is c_b = -90 + (b + 1/2) w.  Per frame the topk best scores (ties to the lower bin; NaN
- * never chosen) give windows [c_b - half_window_deg, c_b + half_window_deg], snapped inward to the
+ * never chosen; after the frame's first D bins only those scoring at least the window floor; with
+ * local_max_bins != 0 only local maxima of the score curve: a bin above its left neighbour whose run
+ * of equal scores ends lower or at the last bin, NaN counting as -inf) give
+ * windows [c_b - half_window_deg, c_b + half_window_deg], snapped inward to the
  * frame's grid: grid indices ceil((c_b - hw - start) / step - 1e-9) .. floor((c_b + hw - start) /
  * step + 1e-9), clipped to [0, L), each operation rounded in FP64; overlapping or touching windows
  * merge.  If the frame's best score is below the threshold (or NaN) the frame falls back to one
@@ -344,26 +364,30 @@ nssdoa_status nssdoa_mlp_gradients(nssdoa_mlp mlp, float* host, size_t count);
 nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes);
 
 /* Windowed estimation with caller scores: scores is device [n_frames][n_bins] float, row f for
- * frame f; a frame falls back to the full grid when its best score < score_threshold.  The other
- * arguments are those of nssdoa_estimate. */
+ * frame f; a frame falls back to the full grid when its best score < score_threshold; a chosen bin
+ * beyond the frame's first D gets a window only when its score >= window_floor (-INFINITY: every
+ * one of the topk; EINVAL if NaN).  The other arguments are those of nssdoa_estimate. */
 nssdoa_status nssdoa_estimate_windowed(nssdoa_batch batch, const void* X, size_t x_elems, const float* scores,
                                        int32_t n_bins, int32_t topk, double half_window_deg,
-                                       float score_threshold, void* spectrum, size_t spectrum_elems,
-                                       nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
-                                       void* workspace, size_t workspace_bytes, void* stream);
+                                       float score_threshold, float window_floor, int32_t local_max_bins,
+                                       void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks,
+                                       int32_t* npeaks, uint32_t* status, void* workspace, size_t workspace_bytes,
+                                       void* stream);
 
 /* Windowed estimation with the learned proposal: per frame the features (upper triangle i <= j
  * of R * M / trace(R), row-major, real and imaginary parts interleaved: M (M + 1) values, which
  * must equal the network's input size) go through the network; its outputs are the bin logits
  * (n_bins = the network's output size).  A frame falls back to the full grid when
  * sigmoid(best logit) < fallback_score, i.e. best logit < log(p / (1 - p)); fallback_score in
- * [0, 1] (0: never, 1: always).  The network's activation buffers are reused, so two calls that
- * use one network must not overlap. */
+ * [0, 1] (0: never, 1: always).  A chosen bin beyond the frame's first D gets a window only when
+ * sigmoid(its logit) >= window_score, in [0, 1] (0: every one of the topk); local_max_bins as for
+ * nssdoa_estimate_windowed, on the logits.  The network's
+ * activation buffers are reused, so two calls that use one network must not overlap. */
 nssdoa_status nssdoa_estimate_learned(nssdoa_batch batch, nssdoa_mlp mlp, const void* X, size_t x_elems,
                                       int32_t topk, double half_window_deg, double fallback_score,
-                                      void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks,
-                                      int32_t* npeaks, uint32_t* status, void* workspace,
-                                      size_t workspace_bytes, void* stream);
+                                      double window_score, int32_t local_max_bins, void* spectrum,
+                                      size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                      uint32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Static description of a status code, and the last failure message on this thread. */
 const char* nssdoa_status_string(nssdoa_status status);

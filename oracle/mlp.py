@@ -126,8 +126,29 @@ def bin_labels(angles_deg, n_bins: int = N_BINS) -> np.ndarray:
     return y
 
 
+def score_peaks(scores: np.ndarray) -> np.ndarray:
+    """Bins that are local maxima of the score curve: NaN counts as -inf; bin b qualifies when it
+    is above its left neighbour (or is bin 0) and the run of scores equal to it that starts at b
+    ends in a lower score or at the last bin (a plateau qualifies at its first bin).  NaN bins
+    never qualify."""
+    s = np.asarray(scores, dtype=np.float64)
+    v = np.where(np.isnan(s), -np.inf, s)
+    n = len(v)
+    out = []
+    for b in range(n):
+        if np.isnan(s[b]) or (b > 0 and not v[b] > v[b - 1]):
+            continue
+        e = b
+        while e + 1 < n and v[e + 1] == v[b]:
+            e += 1
+        if e + 1 == n or v[e + 1] < v[b]:
+            out.append(b)
+    return np.asarray(out, dtype=np.int64)
+
+
 def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid_start: float,
-                     grid_step: float, L: int, threshold=None):
+                     grid_step: float, L: int, threshold=None, n_sure: int = 0, floor=None,
+                     local_max: bool = False):
     """Index ranges [l0, l1) of a grid covered by +-half_window around the centres of the topk
     best bins, merged where they overlap or touch, ascending.
 
@@ -135,13 +156,21 @@ def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid
     and its centre is -90 + (b + 1/2) w.  NaN scores are never chosen; ties go to the lower bin.
     A window is snapped inward to the grid (a 1e-9 step guard absorbs the rounding of the
     division) and clipped to [0, L); empty windows are dropped.  With a threshold, a frame whose
-    best score is below it (or has no non-NaN score) gets the whole grid [(0, L)] instead.
+    best score is below it (or has no non-NaN score) gets the whole grid [(0, L)] instead.  With a
+    floor, the first n_sure of the chosen bins (the frame's source count) are kept whatever their
+    score and the later ones only if their score is at least the floor.  With local_max, only the
+    bins of score_peaks are eligible (the best score, for the threshold, is the same).
     """
     s = np.asarray(scores, dtype=np.float64)
     n_bins = len(s)
     eligible = [b for b in range(n_bins) if not np.isnan(s[b])]
+    if local_max:
+        eligible = [int(b) for b in score_peaks(s)]
     order = sorted(eligible, key=lambda b: (-s[b], b))[:topk]
     best = s[order[0]] if order else -np.inf
+    if floor is not None:
+        # bins after the first n_sure (the source count) need a score of at least `floor`
+        order = [b for r, b in enumerate(order) if r < n_sure or s[b] >= floor]
     if threshold is not None and not (best >= threshold):
         return [(0, int(L))]
     width = 180.0 / n_bins
@@ -164,10 +193,12 @@ def proposal_windows(scores: np.ndarray, topk: int, half_window_deg: float, grid
 
 
 def estimate_proposed(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, scores, topk: int,
-                      half_window_deg: float, threshold):
+                      half_window_deg: float, threshold, floor=None, local_max: bool = False):
     """Windowed estimation driven by per-bin scores, as the learned path runs it.
 
-    1. windows from the scores (proposal_windows, with the threshold's whole-grid fallback);
+    1. windows from the scores (proposal_windows, with the threshold's whole-grid fallback; bins
+       beyond the first D need a score of at least `floor` when one is given; with local_max only
+       local maxima of the score curve are chosen);
     2. the windowed search (doa.estimate_windowed);
     3. rescue: when the windows did not cover the whole grid by the threshold fallback and they
        held fewer than D peaks (a proposal that missed a source, or a peak on a window's end), the
@@ -180,7 +211,8 @@ def estimate_proposed(X: np.ndarray, pos: np.ndarray, D: int, grid, alg: str, sc
     from .doa import estimate_windowed
     start, step, L = grid
     s = np.asarray(scores, dtype=np.float64)
-    wins = proposal_windows(s, topk, half_window_deg, start, step, L, threshold=threshold)
+    wins = proposal_windows(s, topk, half_window_deg, start, step, L, threshold=threshold, n_sure=D, floor=floor,
+                            local_max=local_max)
     finite = s[~np.isnan(s)]
     fallback = threshold is not None and not (finite.size and finite.max() >= threshold)
     est = estimate_windowed(X, pos, D, grid, alg, wins)

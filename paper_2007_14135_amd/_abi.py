@@ -34,7 +34,9 @@ class Array(ctypes.Structure):
 
 class Grid(ctypes.Structure):
     _fields_ = [("start_deg", ctypes.c_double), ("step_deg", ctypes.c_double),
-                ("L", ctypes.c_int32), ("circular", ctypes.c_int32)]
+                ("L", ctypes.c_int32), ("circular", ctypes.c_int32),
+                ("polar_start_deg", ctypes.c_double), ("polar_step_deg", ctypes.c_double),
+                ("n_polar", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -45,7 +47,7 @@ class Frame(ctypes.Structure):
 
 class Peak(ctypes.Structure):
     _fields_ = [("idx", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("angle_deg", ctypes.c_double), ("value", ctypes.c_double)]
+                ("angle_deg", ctypes.c_double), ("value", ctypes.c_double), ("polar_deg", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -59,8 +61,10 @@ EIG_METHODS = {"auto": 0, "ql": 1, "jacobi": 2}
 C64_SCANS = {"split16": 0, "fp32": 1}
 
 
-PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8")])
-assert PEAK_DTYPE.itemsize == ctypes.sizeof(Peak) == 24
+PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8"),
+                       ("polar_deg", "<f8")])
+assert PEAK_DTYPE.itemsize == ctypes.sizeof(Peak) == 32
+assert ctypes.sizeof(Grid) == 48
 
 _P = ctypes.c_void_p
 _SIGNATURES = {
@@ -91,9 +95,11 @@ _SIGNATURES = {
     "nssdoa_graph_launch": [_P, _P],
     "nssdoa_graph_destroy": [_P],
     "nssdoa_estimate_windowed": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                 ctypes.c_float, _P, ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                                 ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P,
+                                 _P, ctypes.c_size_t, _P],
     "nssdoa_estimate_learned": [_P, _P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                _P, ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                                ctypes.c_double, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P,
+                                ctypes.c_size_t, _P],
 }
 
 _lib = None

@@ -43,8 +43,15 @@ class Options:
         self.c = _abi.Options(eig_tol, eig_max_iter, refine_halfwidth, lowq_tau, extra_candidates, scan_rows, m, k)
 
 
+def grid_points(g: tuple) -> int:
+    """Grid points of a grid tuple: L, or L * n_polar for a 2-D grid."""
+    return int(g[2]) * (int(g[6]) if len(g) > 4 and int(g[6]) > 0 else 1)
+
+
 class Plan:
-    """Array geometries (positions in wavelengths, shape (M, 3)) and azimuth scan grids."""
+    """Array geometries (positions in wavelengths, shape (M, 3)) and scan grids: (start, step, L,
+    circular) for azimuth grids, (start, step, L, circular, polar_start, polar_step, n_polar) for
+    azimuth x polar-angle grids."""
 
     def __init__(self, arrays: Sequence[np.ndarray], grids: Sequence[tuple], options: Optional[Options] = None):
         lib = _abi.load()
@@ -56,7 +63,10 @@ class Plan:
         for i, g in enumerate(grids):
             start, step, L = g[0], g[1], g[2]
             circ = g[3] if len(g) > 3 else 0
-            grd[i] = _abi.Grid(float(start), float(step), int(L), int(circ))
+            if len(g) > 4:     # 2-D: (start, step, L, circular, polar_start, polar_step, n_polar)
+                grd[i] = _abi.Grid(float(start), float(step), int(L), int(circ), float(g[4]), float(g[5]), int(g[6]), 0)
+            else:
+                grd[i] = _abi.Grid(float(start), float(step), int(L), int(circ), 0.0, 0.0, 0, 0)
         h = ctypes.c_void_p()
         opt = ctypes.byref(options.c) if options is not None else None
         _abi.check(lib.nssdoa_plan_create(ctypes.byref(h), arr, len(self._pos), grd, len(grids), opt),
@@ -143,26 +153,31 @@ class Batch:
         return int(n.value)
 
     def estimate_windowed(self, X, scores, topk: int, half_window_deg: float, score_threshold: float,
-                          spectrum, peaks, npeaks, status, workspace, stream=None) -> None:
+                          spectrum, peaks, npeaks, status, workspace, stream=None,
+                          window_floor: float = float("-inf"), local_max_bins: bool = False) -> None:
         """Windowed estimation with caller scores (device float [n_frames][n_bins])."""
         lib = _abi.load()
         ws_bytes = workspace.numel() * workspace.element_size()
         s_elems = spectrum.numel() if spectrum is not None else 0
         _abi.check(lib.nssdoa_estimate_windowed(self.handle, _ptr(X), X.numel() // 2, _ptr(scores),
                                                 int(scores.shape[1]), int(topk), float(half_window_deg),
-                                                float(score_threshold), _ptr(spectrum), s_elems, _ptr(peaks),
+                                                float(score_threshold), float(window_floor),
+                                                int(bool(local_max_bins)), _ptr(spectrum),
+                                                s_elems, _ptr(peaks),
                                                 _ptr(npeaks), _ptr(status), _ptr(workspace), ws_bytes,
                                                 _stream_handle(stream)),
                    "nssdoa_estimate_windowed")
 
     def estimate_learned(self, mlp: "MLP", X, topk: int, half_window_deg: float, fallback_score: float,
-                         spectrum, peaks, npeaks, status, workspace, stream=None) -> None:
+                         spectrum, peaks, npeaks, status, workspace, stream=None, window_score: float = 0.0,
+                         local_max_bins: bool = False) -> None:
         """Windowed estimation with the learned proposal network."""
         lib = _abi.load()
         ws_bytes = workspace.numel() * workspace.element_size()
         s_elems = spectrum.numel() if spectrum is not None else 0
         _abi.check(lib.nssdoa_estimate_learned(self.handle, mlp.handle, _ptr(X), X.numel() // 2, int(topk),
-                                               float(half_window_deg), float(fallback_score), _ptr(spectrum),
+                                               float(half_window_deg), float(fallback_score), float(window_score),
+                                               int(bool(local_max_bins)), _ptr(spectrum),
                                                s_elems, _ptr(peaks), _ptr(npeaks), _ptr(status), _ptr(workspace),
                                                ws_bytes, _stream_handle(stream)),
                    "nssdoa_estimate_learned")

@@ -15,6 +15,7 @@
 
 using namespace nssdoa;
 
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -44,6 +45,11 @@ nssdoa_status hip_fail(hipError_t e, const char* what) {
                 hipGetErrorString(e));
 }
 
+// Grid points of a grid: L azimuths, times n_polar polar angles for a 2-D grid.
+inline int64_t grid_points(const nssdoa_grid& g) { return (int64_t)g.L * std::max(1, g.n_polar); }
+constexpr int64_t kMaxGrid2dPoints = (int64_t)1 << 24;
+constexpr int kMaxPolar = 4096;
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 inline int round_up(int v, int a) { return (v + a - 1) / a * a; }
@@ -54,6 +60,7 @@ constexpr int kCovTargetItems = 2048;
 constexpr int64_t kLowqListMax = 1 << 22;     // entries of a batch's low-Q list
 constexpr int kLowqRefineGrid = 1024;         // workgroups of the low-Q re-evaluation
 constexpr double kPlateauRelScan = 1e-4;   // > the FP32 scan's relative error above the low-Q cut
+
 
 }  // namespace
 
@@ -89,6 +96,10 @@ struct nssdoa_batch_s {
     std::vector<PointItem> refine_items;        // (frame, chunk start), grouped like peak_list
     std::vector<std::pair<int, int>> refine_ranges;                 // per bucket [begin, end)
     std::vector<int> peak_selcap;               // per bucket: candidate slots of its largest frame
+    // 2-D grids: frames (in peak_list, after the 1-D ones) and 256-point items (in refine_items)
+    std::vector<std::pair<int, std::pair<int, int>>> p2d_ranges;    // bucket M -> [begin, end) of peak_list
+    std::vector<std::pair<int, int>> p2d_iranges;                   // per bucket [begin, end) of refine_items
+    bool any2d = false;
     size_t ws_bytes = 0;
     int64_t ws_lowq_all = -1;                   // the scans' low-Q list (count, then cap entries)
     int32_t lowq_all_cap = 0;
@@ -199,6 +210,22 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
             delete p;
             return fail(NSSDOA_EINVAL, "grid %d: step must be finite and > 0", g);
         }
+        if (gr.reserved != 0 || gr.n_polar < 0 || gr.n_polar > kMaxPolar) {
+            delete p;
+            return fail(NSSDOA_EINVAL, "grid %d: n_polar=%d outside [0, %d] or nonzero reserved", g, gr.n_polar,
+                        kMaxPolar);
+        }
+        if (gr.n_polar > 0) {
+            if (!(gr.polar_step_deg > 0.0) || !isfinite(gr.polar_step_deg) || !isfinite(gr.polar_start_deg)) {
+                delete p;
+                return fail(NSSDOA_EINVAL, "grid %d: polar step must be finite and > 0", g);
+            }
+            if (grid_points(gr) > kMaxGrid2dPoints) {
+                delete p;
+                return fail(NSSDOA_EINVAL, "grid %d: %lld points exceed the 2-D grid limit of %lld", g,
+                            (long long)grid_points(gr), (long long)kMaxGrid2dPoints);
+            }
+        }
         p->grids.push_back(gr);
     }
     p->opt = opt;
@@ -250,7 +277,10 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         if (fr.D > max_D) return fail(NSSDOA_EINVAL, "frame %d: D=%d > max_D=%d", f, fr.D, max_D);
         if (fr.ldx < fr.N) return fail(NSSDOA_EINVAL, "frame %d: ldx < N", f);
         if (fr.x_off < 0 || fr.spec_off < 0) return fail(NSSDOA_EINVAL, "frame %d: negative offset", f);
-        {
+        if (plan->grids[fr.grid_id].n_polar > 0) {
+            if (prec != NSSDOA_C64 && prec != NSSDOA_C128)
+                return fail(NSSDOA_EUNSUPPORTED, "frame %d: 2-D grids need NSSDOA_C64 or NSSDOA_C128", f);
+        } else {
             const int64_t L = plan->grids[fr.grid_id].L;
             const int64_t slots = (L + kRefineChunk - 1) / kRefineChunk * (fr.D + plan->opt.extra_candidates);
             if (slots > kSelCap)
@@ -295,10 +325,14 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             memset(&gd, 0, sizeof(gd));
             const nssdoa_grid& gr = plan->grids[in.grid_id];
             gd.M = plan->M[in.array_id];
-            gd.L = gr.L;
+            gd.L = (int32_t)grid_points(gr);
             gd.pos_off = pos_off[in.array_id];
             gd.grid_start = gr.start_deg;
             gd.grid_step = gr.step_deg;
+            gd.is2d = gr.n_polar > 0;
+            gd.n_az = gr.L;
+            gd.el_start = gr.n_polar > 0 ? gr.polar_start_deg : 90.0;
+            gd.el_step = gr.n_polar > 0 ? gr.polar_step_deg : 0.0;
             b->groups.push_back(gd);
             gframes.emplace_back();
         } else {
@@ -318,13 +352,17 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.spec_off_user = in.spec_off;
         fd.grid_start = gr.start_deg;
         fd.grid_step = gr.step_deg;
-        fd.L = gr.L;
+        fd.L = (int32_t)grid_points(gr);
         fd.circular = gr.circular ? 1 : 0;
+        fd.is2d = gr.n_polar > 0;
+        fd.n_az = gr.L;
+        fd.el_start = gr.n_polar > 0 ? gr.polar_start_deg : 90.0;
+        fd.el_step = gr.n_polar > 0 ? gr.polar_step_deg : 0.0;
         fd.pos_off = pos_off[in.array_id];
         fd.alg = (int32_t)alg;
         b->max_M = std::max(b->max_M, fd.M);
         b->x_extent = std::max(b->x_extent, (size_t)(in.x_off + (int64_t)(fd.M - 1) * in.ldx + in.N));
-        b->spec_extent = std::max(b->spec_extent, (size_t)(in.spec_off + gr.L));
+        b->spec_extent = std::max(b->spec_extent, (size_t)(in.spec_off + grid_points(gr)));
     }
 
     // covariance chunks over snapshots
@@ -351,7 +389,11 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         fd.ws_qref = (int64_t)off;    off = align_up(off + 16);   // ||B||_F^2, then the FP16 split Q scale
         // candidate chunks: one per 4096 grid points, plus one per window of windowed estimation
         const int n_chunks = (fd.L + kRefineChunk - 1) / kRefineChunk + kMaxWindows;
-        fd.ws_cand = (int64_t)off;    off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
+        fd.ws_cand = (int64_t)off;
+        if (fd.is2d)   // the FP64 peak map of a 2-D grid
+            off = align_up(off + (size_t)fd.L * sizeof(double));
+        else
+            off = align_up(off + (size_t)n_chunks * (fd.D + plan->opt.extra_candidates) * 16);
         if (prec != NSSDOA_C128) {
             // low-Q list: room for an eighth of the grid (at least 256 points); a frame with more
             // low-Q points re-evaluates them in its local-maximum pass instead
@@ -462,7 +504,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         for (int f = 0; f < n_frames; ++f) {
             const int M = b->frames[f].M;
             const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
-            if (bucket != mb) continue;
+            if (bucket != mb || b->frames[f].is2d) continue;
             b->peak_list.push_back(f);
             for (int l0 = 0; l0 < b->frames[f].L; l0 += kRefineChunk) b->refine_items.push_back({f, l0});
         }
@@ -477,6 +519,22 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
                 cap = std::max(cap, nch * (fd.D + plan->opt.extra_candidates));
             }
             b->peak_selcap.push_back(std::min(cap, kSelCap));
+        }
+    }
+    for (int mb : {8, 16, 32, 64}) {
+        const int begin = (int)b->peak_list.size();
+        const int ibegin = (int)b->refine_items.size();
+        for (int f = 0; f < n_frames; ++f) {
+            const int M = b->frames[f].M;
+            const int bucket = M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64;
+            if (bucket != mb || !b->frames[f].is2d) continue;
+            b->peak_list.push_back(f);
+            for (int l0 = 0; l0 < b->frames[f].L; l0 += kPeak2dItem) b->refine_items.push_back({f, l0});
+        }
+        if ((int)b->peak_list.size() > begin) {
+            b->p2d_ranges.push_back({mb, {begin, (int)b->peak_list.size()}});
+            b->p2d_iranges.push_back({ibegin, (int)b->refine_items.size()});
+            b->any2d = true;
         }
     }
 
@@ -540,11 +598,9 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     // steering tables of the FP32 scans, computed once per batch on the device
     for (const GroupDev& gd : b->groups) {
         if (gd.steer_off < 0) continue;
-        e = launch_steer_table(b->d_pos + gd.pos_off, gd.M, gd.grid_start, gd.grid_step, gd.L,
-                               b->d_steer + gd.steer_off, nullptr);
+        e = launch_steer_table(b->d_pos + gd.pos_off, gd, b->d_steer + gd.steer_off, nullptr);
         if (e == hipSuccess && gd.steer_x16_off >= 0)
-            e = launch_steer_table_split16(b->d_pos + gd.pos_off, gd.M, gd.grid_start, gd.grid_step, gd.L,
-                                           b->d_steer + gd.steer_x16_off, nullptr);
+            e = launch_steer_table_split16(b->d_pos + gd.pos_off, gd, b->d_steer + gd.steer_x16_off, nullptr);
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -630,6 +686,8 @@ struct WindowArgs {
     int32_t topk;
     double half_window;
     float threshold;
+    float floor;               // bins beyond a frame's first D need at least this score
+    int32_t local_max;         // only local maxima of the score curve are eligible
 };
 
 size_t windowed_layout(const nssdoa_batch_s* b, int n_feat, int n_bins, LearnedLayout* lay) {
@@ -667,6 +725,7 @@ int persistent_grid(int per_cu) {
 nssdoa_status check_windowed(nssdoa_batch batch, const WindowArgs& wa, int* n_feat, int* n_bins) {
     if (batch->prec != NSSDOA_C64)
         return fail(NSSDOA_EUNSUPPORTED, "windowed estimation runs the C64 scans: create the batch with NSSDOA_C64");
+    if (batch->any2d) return fail(NSSDOA_EUNSUPPORTED, "windowed estimation scans 1-D grids only");
     const int M = batch->frames[0].M;
     for (const FrameDev& fd : batch->frames)
         if (fd.M != M) return fail(NSSDOA_EUNSUPPORTED, "windowed estimation needs one array size in the batch");
@@ -770,10 +829,12 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     // operand tiles of the scans: FP32, FP16 split, BF16, FP16
     ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split16 ? 4 : 1)
                                                          : batch->prec == NSSDOA_BF16 ? 2 : 3;
-    for (auto& r : batch->peak_ranges) {
-        e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
-                       batch->d_frames, batch->d_groups, ws, status, s);
-        if (e != hipSuccess) return hip_fail(e, "eigen launch");
+    for (const auto* ranges : {&batch->peak_ranges, &batch->p2d_ranges}) {
+        for (auto& r : *ranges) {
+            e = launch_evd(batch->d_plist + r.second.first, r.second.second - r.second.first, r.first, ep,
+                           batch->d_frames, batch->d_groups, ws, status, s);
+            if (e != hipSuccess) return hip_fail(e, "eigen launch");
+        }
     }
     if ((st = stage_end(NSSDOA_STAGE_EIGEN)) != NSSDOA_OK) return st;
 
@@ -802,7 +863,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
             if (e != hipSuccess) return hip_fail(e, "proposal network launch");
             scores = logits;
         }
-        e = launch_proposals(batch->d_frames, F, scores, n_bins, wa->topk, wa->half_window, wa->threshold, ws, lay,
+        e = launch_proposals(batch->d_frames, F, scores, n_bins, wa->topk, wa->half_window, wa->threshold, wa->floor, wa->local_max, ws, lay,
                              status, s);
         if (e != hipSuccess) return hip_fail(e, "proposal launch");
         if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
@@ -898,6 +959,14 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
                          batch->d_frames, batch->d_pos, batch->d_cis, ws, spec, pp, peaks, npeaks, status, s);
         if (e != hipSuccess) return hip_fail(e, "peak launch");
     }
+    for (size_t i = 0; i < batch->p2d_ranges.size(); ++i) {
+        const auto& r = batch->p2d_ranges[i];
+        const auto& ri = batch->p2d_iranges[i];
+        e = launch_peaks2d(c128, r.first, batch->d_refine + ri.first, ri.second - ri.first,
+                           batch->d_plist + r.second.first, r.second.second - r.second.first, batch->d_frames,
+                           batch->d_pos, batch->d_cis, ws, spec, use_user, batch->max_D, peaks, npeaks, status, s);
+        if (e != hipSuccess) return hip_fail(e, "2-D peak launch");
+    }
     return stage_end(NSSDOA_STAGE_PEAKS);
 }
 
@@ -924,24 +993,29 @@ nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp,
 
 nssdoa_status nssdoa_estimate_windowed(nssdoa_batch batch, const void* X, size_t x_elems, const float* scores,
                                        int32_t n_bins, int32_t topk, double half_window_deg, float score_threshold,
-                                       void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
-                                       uint32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
-    WindowArgs wa{nullptr, scores, n_bins, topk, half_window_deg, score_threshold};
+                                       float window_floor, int32_t local_max_bins, void* spectrum,
+                                       size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+    if (window_floor != window_floor) return fail(NSSDOA_EINVAL, "window_floor is NaN");
+    WindowArgs wa{nullptr, scores, n_bins, topk, half_window_deg, score_threshold, window_floor, local_max_bins != 0};
     return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
                          workspace_bytes, stream, &wa);
 }
 
 nssdoa_status nssdoa_estimate_learned(nssdoa_batch batch, nssdoa_mlp mlp, const void* X, size_t x_elems,
                                       int32_t topk, double half_window_deg, double fallback_score,
-                                      void* spectrum, size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
-                                      uint32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+                                      double window_score, int32_t local_max_bins, void* spectrum,
+                                      size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
     if (!mlp) return fail(NSSDOA_EINVAL, "mlp is NULL");
     if (!(fallback_score >= 0.0 && fallback_score <= 1.0))
         return fail(NSSDOA_EINVAL, "fallback_score must be in [0, 1]");
+    if (!(window_score >= 0.0 && window_score <= 1.0))
+        return fail(NSSDOA_EINVAL, "window_score must be in [0, 1]");
     // sigmoid(z) < p  <=>  z < log(p / (1 - p))
-    const double thr = fallback_score == 0.0 ? -INFINITY : fallback_score == 1.0 ? INFINITY
-                                             : log(fallback_score) - log1p(-fallback_score);
-    WindowArgs wa{mlp, nullptr, 0, topk, half_window_deg, (float)thr};
+    auto logit = [](double p) { return p == 0.0 ? -INFINITY : p == 1.0 ? INFINITY : log(p) - log1p(-p); };
+    WindowArgs wa{mlp, nullptr, 0, topk, half_window_deg, (float)logit(fallback_score), (float)logit(window_score),
+                  local_max_bins != 0};
     return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
                          workspace_bytes, stream, &wa);
 }

@@ -45,11 +45,14 @@ struct FrameDev {
                                 // scan keeps a count and the list there; the full scans keep only a
                                 // flag, set when a work item's LDS list of low-Q points overflowed
     double grid_start, grid_step;
-    int32_t L, circular;
+    int32_t L, circular;        // L: grid points of the frame (n_az * n_polar for a 2-D grid)
     int32_t pos_off;            // offset (doubles) of this frame's 3*M positions
     int32_t alg;
     int32_t lowq_cap;           // capacity of the low-Q list (a multiple of 256)
-    int32_t pad2;
+    int32_t is2d;               // 2-D grid: azimuth x polar angle, row-major (one row per polar angle)
+    int32_t n_az;               // azimuth points per row (L for a 1-D grid)
+    int32_t pad3;
+    double el_start, el_step;   // 2-D grid: polar angle phi_j = el_start + j * el_step
 };
 
 // Frames that share an array geometry and a scan grid: their spectra are one GEMM.
@@ -62,6 +65,8 @@ struct GroupDev {
     int32_t pad;
     int64_t steer_off;          // FP32 scans: float offset of the group's steering table, else -1
     int64_t steer_x16_off;      // FP16 split scan: float offset of the group's split table, else -1
+    int32_t is2d, n_az;         // as in FrameDev
+    double el_start, el_step;
 };
 
 // Split steering table of a group for the FP16 split scan (same rows as the FP32 table, same
@@ -72,15 +77,15 @@ struct GroupDev {
 constexpr float kSplitSteerScale = 8192.0f;
 
 // Low-Q floor of the 16-bit scans.  With both operands rounded to 16 bits (unit roundoff u:
-// 2^-9 bfloat16, 2^-11 FP16), FP32 steering values and FP32 accumulation over 2M terms, each
-// y_k = b_k^H a is off by at most c ||b_k|| + e0, c = sqrt(2) sqrt(M) (2u + u^2 + (2M + 4) 2^-24),
+// 2^-8 bfloat16, 2^-11 FP16, from their 8 and 11 significant bits), FP32 steering values and
+// FP32 accumulation over 2M terms, each y_k = b_k^H a is off by at most c ||b_k|| + e0, c = sqrt(2) sqrt(M) (2u + u^2 + (2M + 4) 2^-24),
 // e0 = sqrt(2) M 2^-25 (FP16 subnormals; 0 for bfloat16), so with S = ||B||_F^2 and K columns
 // E = c sqrt(S) + e0 sqrt(K) bounds the error of the vector B^H a and |dQ| <= 2 E sqrt(Q) + E^2.
 // That relative bound exceeds 1 exactly where Q < (1 + sqrt 2)^2 E^2; such a point scans to
 // Q_scan < (2 + sqrt 2)^2 E^2 < 12 E^2, so every point scanned below 12 E^2 is re-evaluated in
 // FP64 and the bound holds, with a relative error below 1, at every point that is not.
 __host__ __device__ inline double lp_lowq_floor(int M, int K, double S, bool f16) {
-    const double u = f16 ? 0x1p-11 : 0x1p-9;
+    const double u = f16 ? 0x1p-11 : 0x1p-8;
     const double c = sqrt(2.0 * M) * (2.0 * u + u * u + (2.0 * M + 4.0) * 0x1p-24);
     const double e0 = f16 ? sqrt(2.0) * M * 0x1p-25 : 0.0;
     const double E = c * sqrt(S) + e0 * sqrt((double)K);
@@ -155,6 +160,37 @@ __device__ inline double grid_angle(double start, double step, int l) {
     return start + prod;
 }
 
+// Direction of grid index l as the three factors of Eq. 2's phase: the phase of element m in
+// cycles is x_m u + y_m v + z_m w.  A 1-D grid lies in the horizontal plane (phi = 90 deg, taken
+// as sin phi = 1 and cos phi = 0 exactly): u = sin theta, v = cos theta, w = 0.  A 2-D grid is
+// row-major, l = j n_az + i: theta_i = start + i step, phi_j = el_start + j el_step, and
+// u = sin theta sin phi, v = cos theta sin phi, w = cos phi.  Any descriptor with the FrameDev /
+// GroupDev grid fields works.
+struct Dir3 { double u, v, w; };
+
+template <typename G>
+__device__ inline Dir3 grid_dir(const G& g, int l) {
+    Dir3 d;
+    if (!g.is2d) {
+        sincos(grid_angle(g.grid_start, g.grid_step, l) * kDeg2Rad, &d.u, &d.v);
+        d.w = 0.0;
+        return d;
+    }
+    const int j = l / g.n_az, i = l - j * g.n_az;
+    double sth, cth, sph, cph;
+    sincos(grid_angle(g.grid_start, g.grid_step, i) * kDeg2Rad, &sth, &cth);
+    sincos(grid_angle(g.el_start, g.el_step, j) * kDeg2Rad, &sph, &cph);
+    d.u = sth * sph;
+    d.v = cth * sph;
+    d.w = cph;
+    return d;
+}
+
+// Phase of element m in cycles for direction d (positions: x, y, z in wavelengths).
+__device__ __forceinline__ double phase_cycles(const double* __restrict__ pm, const Dir3& d) {
+    return fma(pm[2], d.w, fma(pm[0], d.u, pm[1] * d.v));
+}
+
 constexpr int kCisTable = 257;   // exp(j 2 pi k / 256) for k = -128..128
 
 // exp(j 2 pi r) in FP64 for |r| <= 1/2: r = k/256 + d with |d| <= 1/512; exp(j 2 pi k/256) comes
@@ -176,22 +212,20 @@ __device__ __forceinline__ double2 cis2pi(double r, const double2* __restrict__ 
     return make_double2(t.x * c - t.y * s, fma(t.x, s, t.y * c));
 }
 
-// ||B^H a(theta)||^2 in FP64 for one direction (Eq. 2 with phi = 90 deg, Table 3 Step-4 in
-// factored form).  B is M x K complex128, column-major.  The phase in cycles is reduced to
-// [-1/2, 1/2] before exp(j 2 pi .) so that its rounding does not grow with the aperture.
+// ||B^H a(d)||^2 in FP64 for one direction d (Eq. 2, Table 3 Step-4 in factored form).  B is
+// M x K complex128, column-major.  The phase in cycles is reduced to [-1/2, 1/2] before
+// exp(j 2 pi .) so that its rounding does not grow with the aperture.
 template <int MB>
 __device__ __forceinline__ double q64_eval(const double* __restrict__ pos, int M, int K,
-                                           const double2* __restrict__ B, double theta_deg,
+                                           const double2* __restrict__ B, const Dir3& d,
                                            const double2* __restrict__ cis) {
-    double sth, cth;
-    sincos(theta_deg * kDeg2Rad, &sth, &cth);
     double ar[MB], ai[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         ar[m] = 0.0;
         ai[m] = 0.0;
         if (m < M) {
-            const double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
+            const double c = phase_cycles(pos + 3 * m, d);
             const double2 a = cis2pi(c - rint(c), cis);
             ar[m] = a.x;
             ai[m] = a.y;
@@ -237,13 +271,11 @@ __device__ __forceinline__ double q64_eval(const double* __restrict__ pos, int M
 // with a butterfly.  Every lane of the wave must call it; the result is in all 16 lanes.
 template <int MB>
 __device__ __forceinline__ double q64_group(const double* __restrict__ pos, int M, int K,
-                                            const double2* __restrict__ B, double theta_deg,
+                                            const double2* __restrict__ B, const Dir3& d,
                                             const double2* __restrict__ cis, double2* a) {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
-    double sth, cth;
-    sincos(theta_deg * kDeg2Rad, &sth, &cth);
     for (int m = j; m < M; m += 16) {
-        const double c = pos[3 * m] * sth + pos[3 * m + 1] * cth;
+        const double c = phase_cycles(pos + 3 * m, d);
         a[g * MB + m] = cis2pi(c - rint(c), cis);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -487,10 +519,8 @@ hipError_t launch_cov(bool c128, int max_M, const CovItem* items, int n_items, c
 hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s);
-hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
-                              hipStream_t s);
-hipError_t launch_steer_table_split16(const double* pos, int M, double start, double step, int L, float* table,
-                                      hipStream_t s);
+hipError_t launch_steer_table(const double* pos, const GroupDev& g, float* table, hipStream_t s);
+hipError_t launch_steer_table_split16(const double* pos, const GroupDev& g, float* table, hipStream_t s);
 constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
 constexpr int kScanMaxBlocks = kScanLdsBytes / (64 * 8 * 4) * 4;   // 8-row blocks of one, M >= 8
 // Low-Q list of a batch: an int count (reset by the covariance launch), then cap (frame, index).
@@ -518,6 +548,13 @@ hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_it
                         int n_frames, const FrameDev* frames, const double* pos, const double2* cis, char* ws,
                         void* spec, const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
                         hipStream_t s);
+// 2-D grids: items of 256 points of the frames in flist (one M bucket), then one selection per
+// frame; each frame's ws_cand region holds an FP64 peak map of L doubles.
+constexpr int kPeak2dItem = 256;
+hipError_t launch_peaks2d(bool f64, int bucket_M, const PointItem* items, int n_items, const int32_t* flist,
+                          int n_frames, const FrameDev* frames, const double* pos, const double2* cis, char* ws,
+                          const void* spec, int use_user, int max_D, nssdoa_peak* peaks, int32_t* npeaks,
+                          uint32_t* status, hipStream_t s);
 
 hipError_t launch_gemm_bf16(int M, int N, int K, const float* A, int64_t sam, int64_t sak, int relu_in_a,
                             const float* B, int64_t sbk, int64_t sbn, int relu_in_b, float alpha,
@@ -531,8 +568,8 @@ hipError_t launch_features(const int32_t* flist, int n, const FrameDev* frames, 
                            int nfeat, hipStream_t s);
 
 hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
-                            double half_window, float threshold, char* ws, const LearnedLayout& lay,
-                            uint32_t* status, hipStream_t s);
+                            double half_window, float threshold, float floor, int local_max, char* ws,
+                            const LearnedLayout& lay, uint32_t* status, hipStream_t s);
 hipError_t launch_rescue(const FrameDev* frames, const int32_t* frame_list, int n_list, const int32_t* npeaks,
                          uint32_t* status, char* ws, const LearnedLayout& lay, int32_t* rescue, hipStream_t s);
 hipError_t launch_expand(const FrameDev* frames, int n_frames, char* ws, const LearnedLayout& lay, hipStream_t s);

@@ -4,8 +4,9 @@
 // device, so the host issues the whole sequence without waiting for it.
 //
 // proposal_kernel, one wave per frame: bin b covers [-90 + b w, -90 + (b+1) w) deg with
-//   w = 180 / n_bins.  The topk best bins (ties to the lower bin) give windows centre +- half
-//   width, snapped to the frame's grid, sorted and merged.  A frame whose best score is below
+//   w = 180 / n_bins.  The topk best bins (ties to the lower bin; after the first D of them only
+//   those scoring at least the floor; optionally only local maxima of the score curve) give
+//   windows centre +- half width, snapped to the frame's grid, sorted and merged.  A frame whose best score is below
 //   the threshold falls back to one window over its whole grid.  It also counts the frame's
 //   64-angle scan items and 4096-point peak chunks.
 // prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan);
@@ -52,8 +53,8 @@ __device__ inline void window_of_bin(int b, double width, double hw, double star
 
 __global__ __launch_bounds__(64) void proposal_kernel(const FrameDev* __restrict__ frames, int n_frames,
                                                       const float* __restrict__ scores, int n_bins, int topk,
-                                                      double half_window, float threshold,
-                                                      char* __restrict__ ws, LearnedLayout lay,
+                                                      double half_window, float threshold, float floor,
+                                                      int local_max, char* __restrict__ ws, LearnedLayout lay,
                                                       uint32_t* __restrict__ status) {
     const int f = blockIdx.x;
     if (f >= n_frames) return;
@@ -64,6 +65,31 @@ __global__ __launch_bounds__(64) void proposal_kernel(const FrameDev* __restrict
     const float* z = scores + (size_t)f * n_bins;
     for (int b = lane; b < n_bins; b += 64) sc[b] = z[b];
     __syncthreads();
+    if (local_max) {
+        // only local maxima of the score curve stay eligible (NaN counts as -inf): above the left
+        // neighbour, and the run of equal scores starting here ends lower or at the last bin;
+        // every other bin becomes NaN.  The best score is a local maximum, so the threshold test
+        // is unchanged.
+        constexpr int kPer = kMaxBins / 64;
+        float keep[kPer];
+        auto val = [&](int b) { const float x = sc[b]; return x == x ? x : -INFINITY; };
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int b = lane + 64 * k;
+            keep[k] = __int_as_float(0x7fc00000);
+            if (b >= n_bins || sc[b] != sc[b]) continue;
+            const float v = sc[b];
+            if (b > 0 && !(v > val(b - 1))) continue;
+            int e = b;
+            while (e + 1 < n_bins && val(e + 1) == v) ++e;
+            if (e + 1 == n_bins || val(e + 1) < v) keep[k] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (lane + 64 * k < n_bins) sc[lane + 64 * k] = keep[k];
+        __syncthreads();
+    }
     // best score (the fallback test) and the topk best bins; NaN scores never win
     float best = -INFINITY;
     int nch = 0;
@@ -79,6 +105,7 @@ __global__ __launch_bounds__(64) void proposal_kernel(const FrameDev* __restrict
         }
         if (r == 0) best = v;
         if (bi >= n_bins) break;          // uniform: every lane holds the reduced value
+        if (r >= fr.D && !(v >= floor)) break;   // bins beyond the source count need the floor
         if (lane == 0) {
             chosen[nch] = bi;
             sc[bi] = __int_as_float(0x7fc00000);   // NaN: never chosen again
@@ -377,7 +404,7 @@ __global__ __launch_bounds__(256) void lowq_win_kernel(const FrameDev* __restric
         const int l = list[1 + i];
         const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
         const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
-                                      grid_angle(fr.grid_start, fr.grid_step, l), cis);
+                                      grid_dir(fr, l), cis);
         float* P = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
         P[l] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
     }
@@ -433,7 +460,7 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
                 const int e = rlist[i];
                 const int l = c0 - kHaloW + e;
                 const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
-                                              grid_angle(fr.grid_start, fr.grid_step, l), cis);
+                                              grid_dir(fr, l), cis);
                 const double x = 1.0 / fmax(Q, (double)FLT_MIN);
                 v[e] = x;
                 if (e >= kHaloW && e < kHaloW + nown) P[l] = (float)x;
@@ -484,10 +511,10 @@ __global__ __launch_bounds__(256) void winpeaks_kernel(const FrameDev* __restric
 }  // namespace
 
 hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* scores, int n_bins, int topk,
-                            double half_window, float threshold, char* ws, const LearnedLayout& lay,
-                            uint32_t* status, hipStream_t s) {
+                            double half_window, float threshold, float floor, int local_max, char* ws,
+                            const LearnedLayout& lay, uint32_t* status, hipStream_t s) {
     hipLaunchKernelGGL(proposal_kernel, dim3(n_frames), dim3(64), 0, s, frames, n_frames, scores, n_bins, topk,
-                       half_window, threshold, ws, lay, status);
+                       half_window, threshold, floor, local_max, ws, lay, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_expand(frames, n_frames, ws, lay, s);

@@ -124,14 +124,17 @@ __global__ void loss_finish_kernel(int rows, int cols, const float* __restrict__
     *loss = (float)(s / ((double)rows * (double)cols));
 }
 
-// Adam with bias correction; t counts from 1.
+// Adam with bias correction; t counts from 1.  a1 = 1 - b1, a2 = 1 - b2 and the bias corrections
+// c1 = 1 - b1^t, c2 = 1 - b2^t come from the host, formed in FP64 and rounded once: formed in FP32
+// from the rounded b2 = 0.999f they would carry a relative error near 5e-5 (cancellation).
 __global__ void adam_kernel(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+                            float* __restrict__ v, float lr, float b1, float b2, float a1, float a2, float eps,
+                            float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + a1 * gi;
+    const float vi = b2 * v[i] + a2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -190,9 +193,10 @@ hipError_t launch_bce(int rows, int cols, const float* Z, const float* Y, float*
 }
 
 hipError_t launch_adam(int n, float* p, const float* g, float* m, float* v, float lr, int t, hipStream_t s) {
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
-    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, p, g, m, v, lr, b1, b2, 1e-8f, c1, c2);
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)t)), c2 = (float)(1.0 - pow(b2, (double)t));
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, p, g, m, v, lr, (float)b1, (float)b2,
+                       (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
     return hipGetLastError();
 }
 

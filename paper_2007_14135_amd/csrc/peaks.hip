@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void lowq_refine_kernel(LowqList lq, const Fra
         const int2 e = lq.list[i];
         const FrameDev& fr = frames[e.x];
         const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, reinterpret_cast<const double2*>(ws + fr.ws_B),
-                                      grid_angle(fr.grid_start, fr.grid_step, e.y), cis);
+                                      grid_dir(fr, e.y), cis);
         float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
         out[e.y] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
     }
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kLmThreads, 4) void localmax_kernel(const PointItem
             const int e = rlist[i];
             int l = l0 - kHalo + e;
             if (l < 0 || l >= L) l = ((l % L) + L) % L;
-            const double Q = q64_eval<MB>(ps, fr.M, fr.K, B, grid_angle(fr.grid_start, fr.grid_step, l), cis);
+            const double Q = q64_eval<MB>(ps, fr.M, fr.K, B, grid_dir(fr, l), cis);
             const TS x = (TS)(1.0 / fmax(Q, (double)FLT_MIN));
             v[e] = x;
             if (e >= kHalo && e < kHalo + nown) P[l] = x;
@@ -292,6 +292,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
             out[r].reserved = 0;
             out[r].angle_deg = qnan();
             out[r].value = qnan();
+            out[r].polar_deg = qnan();
         }
         if (tid == 0) {
             npeaks[f] = 0;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
             bool inside = valid && (circ || (l >= 0 && l < L));
             if (inside && W) inside = in_windows(W, l);
             const double Q = q64_group<MB>(ps, fr.M, fr.K, B,
-                                           grid_angle(fr.grid_start, fr.grid_step, inside ? l : 0), cis, a);
+                                           grid_dir(fr, inside ? l : 0), cis, a);
             if (valid && j == 0) buf[e] = inside ? 1.0 / fmax(Q, 1e-300) : qnan();
         }
         __syncthreads();
@@ -465,11 +466,13 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
             out[r].reserved = 0;
             out[r].angle_deg = grid_angle(fr.grid_start, fr.grid_step, fidx[i]);
             out[r].value = fval[i];
+            out[r].polar_deg = 90.0;
         } else {
             out[r].idx = -1;
             out[r].reserved = 0;
             out[r].angle_deg = qnan();
             out[r].value = qnan();
+            out[r].polar_deg = qnan();
         }
     }
     if (tid == 0) {

@@ -35,16 +35,14 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 // One thread per (angle, element): a_m(theta_l) into the group's steering table (see internal.h).
-__global__ void steer_table_kernel(const double* __restrict__ pos, int M, double start, double step, int L,
-                                   int Lpad, float* __restrict__ T) {
+__global__ void steer_table_kernel(const double* __restrict__ pos, GroupDev g, int Lpad, float* __restrict__ T) {
+    const int M = g.M;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Lpad * M) return;
     const int l = t / M, m = t - l * M;
     float s = 0.0f, co = 0.0f;
-    if (l < L) {
-        double sth, cth;
-        sincos(grid_angle(start, step, l) * kDeg2Rad, &sth, &cth);
-        const double c = fma(pos[3 * m], sth, pos[3 * m + 1] * cth);   // cycles, phi = 90 deg
+    if (l < g.L) {
+        const double c = phase_cycles(pos + 3 * m, grid_dir(g, l));   // cycles
         sincospif((float)(2.0 * (c - rint(c))), &s, &co);
     }
     const int h = m & 1, j = m >> 1;
@@ -54,16 +52,14 @@ __global__ void steer_table_kernel(const double* __restrict__ pos, int M, double
 
 // One thread per (angle, element): the FP16 split steering table (layout in internal.h) from the
 // same FP32 values as steer_table_kernel.
-__global__ void steer_split_kernel(const double* __restrict__ pos, int M, double start, double step, int L,
-                                   int Lpad, _Float16* __restrict__ T) {
+__global__ void steer_split_kernel(const double* __restrict__ pos, GroupDev g, int Lpad, _Float16* __restrict__ T) {
+    const int M = g.M;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Lpad * M) return;
     const int l = t / M, m = t - l * M;
     float s = 0.0f, co = 0.0f;
-    if (l < L) {
-        double sth, cth;
-        sincos(grid_angle(start, step, l) * kDeg2Rad, &sth, &cth);
-        const double c = fma(pos[3 * m], sth, pos[3 * m + 1] * cth);   // cycles, phi = 90 deg
+    if (l < g.L) {
+        const double c = phase_cycles(pos + 3 * m, grid_dir(g, l));   // cycles
         sincospif((float)(2.0 * (c - rint(c))), &s, &co);
     }
 #pragma unroll
@@ -355,21 +351,18 @@ hipError_t launch_m(const ScanItem* items, int n_items, int max_tiles, const Gro
 
 }  // namespace
 
-hipError_t launch_steer_table(const double* pos, int M, double start, double step, int L, float* table,
-                              hipStream_t s) {
-    const int Lpad = steer_table_rows(L);
-    const int64_t n = (int64_t)Lpad * M;
-    hipLaunchKernelGGL(steer_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, M, start, step,
-                       L, Lpad, table);
+hipError_t launch_steer_table(const double* pos, const GroupDev& g, float* table, hipStream_t s) {
+    const int Lpad = steer_table_rows(g.L);
+    const int64_t n = (int64_t)Lpad * g.M;
+    hipLaunchKernelGGL(steer_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, g, Lpad, table);
     return hipGetLastError();
 }
 
-hipError_t launch_steer_table_split16(const double* pos, int M, double start, double step, int L, float* table,
-                                      hipStream_t s) {
-    const int Lpad = steer_table_rows(L);
-    const int64_t n = (int64_t)Lpad * M;
-    hipLaunchKernelGGL(steer_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, M, start, step,
-                       L, Lpad, reinterpret_cast<_Float16*>(table));
+hipError_t launch_steer_table_split16(const double* pos, const GroupDev& g, float* table, hipStream_t s) {
+    const int Lpad = steer_table_rows(g.L);
+    const int64_t n = (int64_t)Lpad * g.M;
+    hipLaunchKernelGGL(steer_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, g, Lpad,
+                       reinterpret_cast<_Float16*>(table));
     return hipGetLastError();
 }
 

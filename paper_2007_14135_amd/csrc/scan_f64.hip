@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void scan_f64_kernel(const PointItem* __restri
     if (l >= fr.L) return;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
     const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, B,
-                                  grid_angle(fr.grid_start, fr.grid_step, l), cis);
+                                  grid_dir(fr, l), cis);
     double* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
     out[l] = 1.0 / fmax(Q, 1e-300);
 }

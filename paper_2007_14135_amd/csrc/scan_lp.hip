@@ -35,18 +35,16 @@ __device__ inline floatx16 mfma16(halfx8 a, halfx8 b, floatx16 c) {
 // Steering operand of one lane for one 32-angle column tile: inner k = 16s + 8h + t is Re a_k for
 // k < M and Im a_(k-M) otherwise.
 template <int M, typename T>
-__device__ inline void steering16(const double* __restrict__ p, double th, int h,
+__device__ inline void steering16(const double* __restrict__ p, const Dir3& d, int h,
                                   typename Vec8<T>::type* st) {
     constexpr int S = M / 8;
-    double sth, cth;
-    sincos(th * kDeg2Rad, &sth, &cth);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int k = 16 * s + 8 * h + t;
             const int m = k < M ? k : k - M;
-            const double c = p[3 * m] * sth + p[3 * m + 1] * cth;   // cycles, phi = 90 deg
+            const double c = phase_cycles(p + 3 * m, d);   // cycles
             float sn, cs;
             sincospif((float)(2.0 * (c - rint(c))), &sn, &cs);
             st[s][t] = (T)(k < M ? cs : sn);
@@ -76,8 +74,8 @@ __global__ __launch_bounds__(256) void scan_lp_kernel(const ScanItem* __restrict
     {
         const double* p = pos + g.pos_off;
         const int j = lane & 31;
-        steering16<M, T>(p, grid_angle(g.grid_start, g.grid_step, base + j), h, st0);
-        steering16<M, T>(p, grid_angle(g.grid_start, g.grid_step, base + 32 + j), h, st1);
+        steering16<M, T>(p, grid_dir(g, base + j), h, st0);
+        steering16<M, T>(p, grid_dir(g, base + 32 + j), h, st1);
     }
 
     const V* emb = reinterpret_cast<const V*>(ws + g.ws_emb) + (size_t)lane * S;

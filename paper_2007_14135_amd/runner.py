@@ -11,7 +11,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from .api import Batch, Options, Plan, decode_peaks
+from .api import Batch, Options, Plan, decode_peaks, grid_points
 
 
 @dataclasses.dataclass
@@ -20,7 +20,7 @@ class DeviceBatch:
     batch: Batch
     X: object            # torch tensor (flat complex64/complex128 viewed as float)
     spectrum: object     # torch tensor or None
-    peaks: object        # torch uint8 tensor, n * max_D * 24 bytes
+    peaks: object        # torch uint8 tensor, n * max_D * 32 bytes
     npeaks: object       # torch int32
     status: object       # torch int32 (uint32 bits)
     workspace: object    # torch uint8
@@ -40,17 +40,21 @@ class DeviceBatch:
         if self.workspace.numel() < need:
             self.workspace = torch.empty(need, dtype=torch.uint8, device=self.workspace.device)
 
-    def run_windowed(self, scores, topk: int, half_window_deg: float, score_threshold: float, stream=None):
+    def run_windowed(self, scores, topk: int, half_window_deg: float, score_threshold: float, stream=None,
+                     window_floor: float = float("-inf"), local_max_bins: bool = False):
         """Windowed estimation with caller scores (device float tensor [n_frames][n_bins])."""
         self._windowed_workspace()
         self.batch.estimate_windowed(self.X, scores, topk, half_window_deg, score_threshold, self.spectrum,
-                                     self.peaks, self.npeaks, self.status, self.workspace, stream)
+                                     self.peaks, self.npeaks, self.status, self.workspace, stream,
+                                     window_floor=window_floor, local_max_bins=local_max_bins)
 
-    def run_learned(self, mlp, topk: int, half_window_deg: float, fallback_score: float, stream=None):
+    def run_learned(self, mlp, topk: int, half_window_deg: float, fallback_score: float, stream=None,
+                    window_score: float = 0.0, local_max_bins: bool = False):
         """Windowed estimation with the learned proposal network."""
         self._windowed_workspace(mlp)
         self.batch.estimate_learned(mlp, self.X, topk, half_window_deg, fallback_score, self.spectrum,
-                                    self.peaks, self.npeaks, self.status, self.workspace, stream)
+                                    self.peaks, self.npeaks, self.status, self.workspace, stream,
+                                    window_score=window_score, local_max_bins=local_max_bins)
 
     def host_results(self):
         import torch
@@ -83,7 +87,7 @@ def prepare(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequen
     spec_off, spec_len, full = [], [], []
     off = 0
     for f in frames:
-        L = int(grids[f[1]][2])
+        L = grid_points(grids[f[1]])
         spec_off.append(off)
         spec_len.append(L)
         full.append(tuple(f[:6]) + (off,))

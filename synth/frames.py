@@ -90,11 +90,11 @@ class Frame:
     snr_db: float
     sigma2: float
     angles_deg: np.ndarray     # (D,) true source azimuths
-    polar_deg: Optional[np.ndarray]  # (D,) true polar angles (phi of Eq. 2), None: all 90 deg
     grid_start: float          # scan grid theta_l = start + l * step, l = 0..L-1
     grid_step: float
     grid_L: int
     X: np.ndarray              # (M, N) complex64 or complex128, element-major
+    polar_deg: Optional[np.ndarray] = None  # (D,) true polar angles (phi of Eq. 2), None: all 90 deg
 
     @property
     def grid(self):

@@ -50,6 +50,11 @@ def _ula(M):
     ([_ula(8)], [(-90, -0.1, 1800)], "step<0"),
     ([_ula(8)], [(-90, float("nan"), 1800)], "step nan"),
     ([np.full((8, 3), np.inf)], [(-90, 0.1, 1800)], "non-finite positions"),
+    ([_ula(8)], [(0, 1.0, 360, 1, 1.0, 0.0, 90)], "2-D polar step 0"),
+    ([_ula(8)], [(0, 1.0, 360, 1, float("nan"), 1.0, 90)], "2-D polar start nan"),
+    ([_ula(8)], [(0, 1.0, 360, 1, 1.0, 1.0, -1)], "n_polar < 0"),
+    ([_ula(8)], [(0, 1.0, 360, 1, 1.0, 1.0, 4097)], "n_polar > 4096"),
+    ([_ula(8)], [(0, 0.001, 360000, 1, 1.0, 0.01, 4096)], "2-D grid beyond 2^24 points"),
 ])
 def test_plan_rejects_invalid(arrays, grids, msg):
     with pytest.raises(nd.NssdoaError) as e:
@@ -106,3 +111,19 @@ def test_null_handles_rejected():
 
 def test_plan_accepts_scan_rows():
     nd.Plan([_ula(8)], [(-90, 0.1, 1800)], nd.Options(scan_rows=1024)).close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_2d_grids_need_c64_or_c128(prec):
+    # azimuth x polar-angle grids run on the FP32-accuracy and FP64 scans only
+    plan = nd.Plan([_ula(8)], [(0, 1.0, 360, 1, 61.0, 1.0, 30)])
+    with pytest.raises(nd.NssdoaError) as e:
+        nd.Batch(plan, "music", prec, [(0, 0, 1024, 2, 0, 1024, 0)], 4)
+    assert e.value.status == _abi.EUNSUPPORTED
+
+
+def test_2d_grid_struct_layout():
+    # the C struct: start, step, L, circular, polar start, polar step, n_polar, reserved
+    assert ctypes.sizeof(_abi.Grid) == 48 and _abi.Grid.n_polar.offset == 40
+    assert _abi.PEAK_DTYPE.itemsize == 32 and _abi.PEAK_DTYPE.fields["polar_deg"][1] == 24
+    nd.Plan([_ula(8)], [(0, 1.0, 360, 1, 1.0, 1.0, 90), (-90, 0.1, 1800)]).close()

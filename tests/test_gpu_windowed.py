@@ -36,13 +36,15 @@ def _bin_of(angle):
     return int(np.clip(np.floor(angle + 90.0), 0, 179))
 
 
-def _check(fs, db, res, scores, topk, hw, thr, alg, tag):
+def _check(fs, db, res, scores, topk, hw, thr, alg, tag, floor=None, local_max=False):
     worst, ties, n_rescued = 0.0, 0, 0
     for f, fr in enumerate(fs.frames):
         est, fallback, rescued = omlp.estimate_proposed(fr.X, fr.pos, fr.D, fr.grid, alg,
-                                                        scores[f].astype(np.float64), topk, hw, float(thr))
+                                                        scores[f].astype(np.float64), topk, hw, float(thr),
+                                                        floor=floor, local_max=local_max)
         wins = "whole grid" if fallback or rescued else omlp.proposal_windows(
-            scores[f].astype(np.float64), topk, hw, fr.grid_start, fr.grid_step, fr.grid_L, threshold=float(thr))
+            scores[f].astype(np.float64), topk, hw, fr.grid_start, fr.grid_step, fr.grid_L, threshold=float(thr),
+            n_sure=fr.D, floor=floor, local_max=local_max)
         n_rescued += int(rescued)
         P = res["spectra"][f].astype(np.float64)
         written = ~np.isnan(P)
@@ -109,6 +111,35 @@ def test_windowed_matches_oracle_designed_cases():
     db.run_windowed(sd, 6, 1.0, 0.0)
     res = db.host_results()
     _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 designed")
+
+
+def test_windowed_window_floor():
+    # the designed scores with a window floor of 1.2: after each frame's first D bins only bins
+    # scoring at least 1.2 get windows (case 1's neighbour bins and case 3's edge bins stay, case
+    # 0's weaker source bins beyond D do not exist, random bins drop out)
+    fs = make_frames("c2", n_frames=12, N=2048, start=40)
+    db = _prepare(fs)
+    scores = _designed_scores(fs, 9)
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(scores, device="cuda"), 6, 1.0, 0.0, window_floor=1.2)
+    res = db.host_results()
+    _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 floor 1.2", floor=1.2)
+
+
+def test_windowed_local_max_bins():
+    # the designed scores with only local maxima of each frame's score curve eligible: merging
+    # neighbours (case 1) collapse to one bin, the equal-score plateau (case 4) keeps its first bin,
+    # NaN bins (case 3) count as -inf; with a floor too on half of the frames' second call
+    fs = make_frames("c2", n_frames=12, N=2048, start=60)
+    db = _prepare(fs)
+    scores = _designed_scores(fs, 13)
+    for floor in (None, 0.8):
+        db.spectrum.fill_(float("nan"))
+        db.run_windowed(torch.tensor(scores, device="cuda"), 6, 1.0, 0.0,
+                        window_floor=float("-inf") if floor is None else floor, local_max_bins=True)
+        res = db.host_results()
+        _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 local-max bins, floor %s" % floor,
+               floor=floor, local_max=True)
 
 
 @pytest.mark.parametrize("alg", ["music", "ev", "mn", "phd"])
@@ -195,6 +226,20 @@ def test_learned_equals_windowed_with_network_scores():
     spec_l = [s.copy() for s in res_l["spectra"]]
     db.spectrum.fill_(float("nan"))
     db.run_windowed(logits, 6, 1.0, 0.0)                 # sigmoid(z) < 0.5  <=>  z < 0
+    res_w = db.host_results()
+    assert np.array_equal(res_l["npeaks"], res_w["npeaks"])
+    assert np.array_equal(res_l["status"], res_w["status"])
+    assert res_l["peaks"].tobytes() == res_w["peaks"].tobytes()
+    for a, b in zip(spec_l, res_w["spectra"]):
+        assert np.array_equal(a, b, equal_nan=True)
+    # the same with local-maximum bins and a window score of 0.3 (a logit floor of log(0.3 / 0.7))
+    import math
+    db.spectrum.fill_(float("nan"))
+    db.run_learned(net, 6, 1.0, 0.5, window_score=0.3, local_max_bins=True)
+    res_l = db.host_results()
+    spec_l = [s.copy() for s in res_l["spectra"]]
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(logits, 6, 1.0, 0.0, window_floor=math.log(0.3) - math.log1p(-0.3), local_max_bins=True)
     res_w = db.host_results()
     assert np.array_equal(res_l["npeaks"], res_w["npeaks"])
     assert np.array_equal(res_l["status"], res_w["status"])

@@ -226,3 +226,26 @@ def test_init_params_he_uniform():
     r = mlp.init_params(22)
     assert all(np.array_equal(a[0], c[0]) for a, c in zip(p, q))
     assert not np.array_equal(p[0][0], r[0][0])
+
+
+def test_bf16_operand_gradients_within_the_rounding_bound():
+    # The oracle's bfloat16-operand mode is one admissible rounding of every GEMM operand, so its
+    # gradients must lie inside the probabilistic bound the GPU gradients are gated with; a bound
+    # that wrongly drops a propagation term (here: the layer-2 decision uncertainty) fails.
+    from mlp_bounds import gradient_bounds
+    for seed, B in ((5, 257), (3, 64)):
+        params = mlp.init_params(seed)
+        rng = np.random.default_rng(seed)
+        X = rng.normal(0, 1, size=(B, 272))
+        Y = (rng.uniform(size=(B, 180)) < 0.02).astype(np.float64)
+        bounds, risk = gradient_bounds(params, X, Y)
+        _, g64 = mlp.backward(params, X, Y)
+        _, g16 = mlp.backward(params, X, Y, precision="bf16")
+        assert 0.0 < risk[0] < 0.1 and 0.0 < risk[1] < 0.1
+        worst = 0.0
+        for li in range(3):
+            for w in range(2):
+                worst = max(worst, float(np.max(np.abs(g16[li][w] - g64[li][w]) / bounds[li][w])))
+        assert worst < 1.0, (seed, worst)
+        # the bound is not vacuous for the output layer: well below the gradient itself
+        assert np.median(bounds[2][0] / (np.abs(g64[2][0]) + 1e-300)) < 0.1

@@ -114,6 +114,25 @@ def test_proposal_windows_threshold_nan_and_bin_width():
     assert mlp.proposal_windows(s, 1, 1.0, 20.0, 0.01, 1000) == []
 
 
+def test_proposal_windows_floor_keeps_the_first_n_sure_bins():
+    # scores 3 > 2 > 1 > 0.5 > 0.2 at bins 10, 50, 90, 130, 170 (centres -79.5, -39.5, 0.5, 40.5, 80.5)
+    s = np.full(180, -5.0)
+    for b, v in ((10, 3.0), (50, 2.0), (90, 1.0), (130, 0.5), (170, 0.2)):
+        s[b] = v
+    args = (5, 0.5, -90.0, 0.01, 18000)
+    win = {10: (1000, 1101), 50: (5000, 5101), 90: (9000, 9101), 130: (13000, 13101), 170: (17000, 17101)}
+    assert mlp.proposal_windows(s, *args) == [win[b] for b in (10, 50, 90, 130, 170)]
+    # floor 0.75: the first two bins always, then only the one at score 1
+    assert mlp.proposal_windows(s, *args, n_sure=2, floor=0.75) == [win[b] for b in (10, 50, 90)]
+    # the first n_sure bins stay even below the floor
+    assert mlp.proposal_windows(s, *args, n_sure=4, floor=10.0) == [win[b] for b in (10, 50, 90, 130)]
+    assert mlp.proposal_windows(s, *args, n_sure=0, floor=10.0) == []
+    # a floor at or below every chosen score changes nothing; topk still caps the count
+    assert mlp.proposal_windows(s, 3, 0.5, -90.0, 0.01, 18000, n_sure=1, floor=-5.0) == [win[b] for b in (10, 50, 90)]
+    # the threshold's whole-grid fallback is unaffected by the floor
+    assert mlp.proposal_windows(s, *args, threshold=4.0, n_sure=1, floor=0.0) == [(0, 18000)]
+
+
 def test_proposal_windows_with_fewer_finite_bins_than_topk():
     # -inf scores stay eligible (lowest first by bin), NaN never; no bin is chosen twice
     s = np.full(180, np.nan)
@@ -169,3 +188,49 @@ def test_proposed_estimate_threshold_fallback_is_not_rescued():
     f1 = estimate(X1, pos1, 2, g1, "music")
     assert r1 and not fb1
     assert list(e1.peaks) == list(f1.peaks) == [2]
+
+
+def test_score_peaks_brute_force_and_cases():
+    # hand cases: plateau at its first bin, a shoulder plateau that rises is no peak, ends count,
+    # NaN is -inf and never a peak itself
+    assert mlp.score_peaks(np.array([0.0, 2.0, 2.0, 1.0, 3.0])).tolist() == [1, 4]
+    assert mlp.score_peaks(np.array([1.0, 2.0, 2.0, 3.0, 0.0])).tolist() == [3]
+    assert mlp.score_peaks(np.array([5.0, 1.0, 1.0, 1.0])).tolist() == [0]
+    assert mlp.score_peaks(np.array([1.0, 1.0, 1.0])).tolist() == [0]
+    assert mlp.score_peaks(np.array([np.nan, 1.0, np.nan, 0.5])).tolist() == [1, 3]
+    assert mlp.score_peaks(np.array([-np.inf, -np.inf, 0.0])).tolist() == [2]
+    # brute force: a bin is a peak iff it is not NaN and no bin of its maximal equal run has a
+    # larger neighbour, and the bin before the run (if any) is smaller
+    rng = np.random.default_rng(3)
+    for trial in range(300):
+        s = rng.integers(0, 4, size=rng.integers(1, 12)).astype(np.float64)
+        s[rng.uniform(size=len(s)) < 0.15] = np.nan
+        v = np.where(np.isnan(s), -np.inf, s)
+        ref = []
+        for b in range(len(s)):
+            if np.isnan(s[b]) or (b > 0 and v[b - 1] >= v[b]):
+                continue
+            e = b
+            while e + 1 < len(s) and v[e + 1] == v[b]:
+                e += 1
+            if e + 1 < len(s) and v[e + 1] > v[b]:
+                continue
+            ref.append(b)
+        assert mlp.score_peaks(s).tolist() == ref, (trial, s)
+
+
+def test_proposal_windows_local_max_bins():
+    # a source's bin and both its neighbours score high: only the best of the three gets a window;
+    # the threshold test still uses the best score
+    s = np.full(180, -4.0)
+    s[99], s[100], s[101] = 2.5, 3.0, 2.8          # centres 9.5, 10.5, 11.5
+    s[40] = 1.0
+    args = (3, 1.0, -90.0, 0.01, 18000)
+    # top 3 bins without the rule: the source's three, merged into one 3-degree window
+    assert mlp.proposal_windows(s, *args) == [(9850, 10251)]
+    # with it: the source's best bin and the next local maximum (bin 40)
+    assert mlp.proposal_windows(s, *args, local_max=True) == [(3950, 4151), (9950, 10151)]
+    got = mlp.proposal_windows(s, 2, 1.0, -90.0, 0.01, 18000, local_max=True)
+    assert got == [(3950, 4151), (9950, 10151)]
+    assert mlp.proposal_windows(s, 2, 1.0, -90.0, 0.01, 18000, threshold=3.0, local_max=True) == got
+    assert mlp.proposal_windows(s, 2, 1.0, -90.0, 0.01, 18000, threshold=3.1, local_max=True) == [(0, 18000)]

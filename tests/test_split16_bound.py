@@ -69,3 +69,19 @@ def test_split_dot_matches_fp32_accuracy():
     # same order of error as FP32 operands (absolute, |b| = 1, |a_k| <= 1)
     assert max(errs_split) < 4.0 * max(errs_f32)
     assert max(errs_split) < 1e-6
+
+
+def test_unit_roundoffs_of_the_16_bit_formats():
+    # The 16-bit scan bounds use u = 2^-8 for bfloat16 (8 significant bits) and 2^-11 for IEEE
+    # half (11 significant bits): the largest relative rounding error of FP32 values reaches each
+    # (just above a power of two) and never exceeds it.  Conversions: torch's bfloat16 and numpy's
+    # binary16, both round to nearest even.
+    import torch
+    rng = np.random.default_rng(7)
+    x = (rng.uniform(1.0, 2.0, 400000) * 2.0 ** rng.integers(-10, 10, 400000)).astype(np.float32)
+    xb = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    rb = np.abs(xb - x) / np.abs(x)
+    assert rb.max() <= 2.0 ** -8 and rb.max() > 0.99 * 2.0 ** -8
+    xh = x.astype(np.float16).astype(np.float64)
+    rh = np.abs(xh - x) / np.abs(x)
+    assert rh.max() <= 2.0 ** -11 and rh.max() > 0.99 * 2.0 ** -11
