@@ -103,8 +103,8 @@ typedef struct {
  *   grid: strictly above each neighbour that precedes them in that order, at least equal to
  *   each one that follows, and strictly above at least one (a plateau is reported at its first
  *   point; grid edges can hold peaks); the azimuth axis wraps when circular != 0, the polar axis
- *   never does.  2-D grids are supported with NSSDOA_C64 and NSSDOA_C128 by nssdoa_estimate and
- *   graph capture (EUNSUPPORTED otherwise). */
+ *   never does.  2-D grids are supported with NSSDOA_C64 and NSSDOA_C128 by nssdoa_estimate,
+ *   nssdoa_estimate_noalloc and graph capture (EUNSUPPORTED otherwise). */
 typedef struct {
     double start_deg;
     double step_deg;      /* > 0                                                               */
@@ -263,6 +263,25 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
                               size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
                               uint32_t* status, void* workspace, size_t workspace_bytes,
                               void* stream);
+
+/* nssdoa_estimate without a caller workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is one array of the library's code object per device,
+ * of nssdoa_noalloc_workspace_limit bytes (64 MiB), held by every device the library runs on
+ * until the process ends; its address on a device is looked up by the first nssdoa_batch_create
+ * (or nssdoa_estimate_noalloc) call made with that device current.  The call itself allocates
+ * nothing (no hipMalloc, no events) and computes exactly what nssdoa_estimate computes with the
+ * same arguments.  Every call on one device shares that device's array, which keeps the last
+ * call's contents: two calls that may overlap on one device (different streams, or different
+ * host threads) race on it and must be serialised by the caller.  Stage timing does not apply.
+ * EINVAL: as nssdoa_estimate, or a batch whose workspace (nssdoa_workspace_size) exceeds the
+ * array; EDEVICE: the array's address could not be obtained. */
+nssdoa_status nssdoa_estimate_noalloc(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                                      size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks,
+                                      uint32_t* status, void* stream);
+
+/* Size in bytes of the workspace array of nssdoa_estimate_noalloc. */
+nssdoa_status nssdoa_noalloc_workspace_limit(size_t* bytes);
 
 /* Graph capture: record the launch sequence of one nssdoa_estimate call with these arguments
  * (validated as for nssdoa_estimate) into a HIP graph, captured on a stream of the library's own.

@@ -78,6 +78,8 @@ _SIGNATURES = {
     "nssdoa_workspace_offset": [_P, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "nssdoa_estimate": [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, _P, _P,
                         ctypes.c_size_t, _P],
+    "nssdoa_estimate_noalloc": [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, _P, _P],
+    "nssdoa_noalloc_workspace_limit": [ctypes.POINTER(ctypes.c_size_t)],
     "nssdoa_set_timing": [_P, ctypes.c_int32],
     "nssdoa_stage_time": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64)],

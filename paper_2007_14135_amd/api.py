@@ -146,6 +146,14 @@ class Batch:
                                        _stream_handle(stream)),
                    "nssdoa_estimate")
 
+    def estimate_noalloc(self, X, spectrum, peaks, npeaks, status, stream=None) -> None:
+        """nssdoa_estimate on the library's own per-device workspace array (no allocation)."""
+        lib = _abi.load()
+        s_elems = spectrum.numel() if spectrum is not None else 0
+        _abi.check(lib.nssdoa_estimate_noalloc(self.handle, _ptr(X), X.numel() // 2, _ptr(spectrum), s_elems,
+                                               _ptr(peaks), _ptr(npeaks), _ptr(status), _stream_handle(stream)),
+                   "nssdoa_estimate_noalloc")
+
     def windowed_workspace_size(self, mlp: Optional["MLP"] = None) -> int:
         n = ctypes.c_size_t()
         _abi.check(_abi.load().nssdoa_windowed_workspace_size(self.handle, mlp.handle if mlp is not None else None,
@@ -202,6 +210,13 @@ class Batch:
         _abi.check(_abi.load().nssdoa_stage_time(self.handle, _abi.STAGES[stage], ctypes.byref(ms), ctypes.byref(n)),
                    "nssdoa_stage_time")
         return float(ms.value), int(n.value)
+
+
+def noalloc_workspace_limit() -> int:
+    """Bytes of the workspace array nssdoa_estimate_noalloc uses."""
+    n = ctypes.c_size_t()
+    _abi.check(_abi.load().nssdoa_noalloc_workspace_limit(ctypes.byref(n)), "nssdoa_noalloc_workspace_limit")
+    return int(n.value)
 
 
 class Graph:

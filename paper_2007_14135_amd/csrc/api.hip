@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,15 @@
 
 using namespace nssdoa;
 
+// Workspace of nssdoa_estimate_noalloc: one array per device in the library's code object, so
+// that call needs no allocation.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is a stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device, looked up once per device and kept in g_scratch_addr.
+static constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
 
 namespace {
 
@@ -43,6 +53,26 @@ namespace {
 nssdoa_status hip_fail(hipError_t e, const char* what) {
     return fail(e == hipErrorOutOfMemory ? NSSDOA_ENOMEM : NSSDOA_EDEVICE, "%s: %s", what,
                 hipGetErrorString(e));
+}
+
+// Device address of the no-allocation workspace on the current device (looked up on the first
+// call for that device, then cached).
+nssdoa_status scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(NSSDOA_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+            return fail(NSSDOA_EDEVICE, "scratch array at an unaligned address");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return NSSDOA_OK;
 }
 
 // Grid points of a grid: L azimuths, times n_polar polar angles for a 2-D grid.
@@ -573,6 +603,13 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         }
         put(o_cis, cis.data(), cis.size() * sizeof(double2));
     }
+    // set-up of nssdoa_estimate_noalloc on this device: the address of its workspace array
+    void* scratch_ws = nullptr;
+    nssdoa_status sst = scratch_address(&scratch_ws);
+    if (sst != NSSDOA_OK) {
+        delete b;
+        return sst;
+    }
     hipError_t e = hipMalloc((void**)&b->dev, total);
     if (e != hipSuccess) {
         delete b;
@@ -980,6 +1017,27 @@ nssdoa_status nssdoa_estimate(nssdoa_batch batch, const void* X, size_t x_elems,
                               void* stream) {
     return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, workspace,
                          workspace_bytes, stream, nullptr);
+}
+
+nssdoa_status nssdoa_estimate_noalloc(nssdoa_batch batch, const void* X, size_t x_elems, void* spectrum,
+                                      size_t spectrum_elems, nssdoa_peak* peaks, int32_t* npeaks, uint32_t* status,
+                                      void* stream) {
+    if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
+    if (batch->ws_bytes > kNoallocScratchBytes)
+        return fail(NSSDOA_EINVAL, "the batch needs %zu bytes of workspace, the no-allocation workspace holds %zu",
+                    batch->ws_bytes, kNoallocScratchBytes);
+    void* ws = nullptr;
+    nssdoa_status st = scratch_address(&ws);
+    if (st != NSSDOA_OK) return st;
+    // no stage timing here: its events are created per call
+    return estimate_impl(batch, X, x_elems, spectrum, spectrum_elems, peaks, npeaks, status, ws,
+                         kNoallocScratchBytes, stream, nullptr, true);
+}
+
+nssdoa_status nssdoa_noalloc_workspace_limit(size_t* bytes) {
+    if (!bytes) return fail(NSSDOA_EINVAL, "NULL argument");
+    *bytes = kNoallocScratchBytes;
+    return NSSDOA_OK;
 }
 
 nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes) {

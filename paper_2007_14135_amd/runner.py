@@ -30,6 +30,10 @@ class DeviceBatch:
     def run(self, stream=None):
         self.batch.estimate(self.X, self.spectrum, self.peaks, self.npeaks, self.status, self.workspace, stream)
 
+    def run_noalloc(self, stream=None):
+        """The same estimate on the library's per-device workspace array (no allocation)."""
+        self.batch.estimate_noalloc(self.X, self.spectrum, self.peaks, self.npeaks, self.status, stream)
+
     def capture(self):
         """A graph of nssdoa_estimate on this batch's buffers (replay with .launch(stream))."""
         return self.batch.graph(self.X, self.spectrum, self.peaks, self.npeaks, self.status, self.workspace)

@@ -104,6 +104,9 @@ def test_null_handles_rejected():
     n = ctypes.c_size_t()
     assert lib.nssdoa_workspace_size(None, ctypes.byref(n)) == _abi.EINVAL
     assert lib.nssdoa_estimate(None, None, 0, None, 0, None, None, None, None, 0, None) == _abi.EINVAL
+    assert lib.nssdoa_estimate_noalloc(None, None, 0, None, 0, None, None, None, None) == _abi.EINVAL
+    assert lib.nssdoa_noalloc_workspace_limit(None) == _abi.EINVAL
+    assert lib.nssdoa_noalloc_workspace_limit(ctypes.byref(n)) == _abi.OK and n.value == 64 << 20
     assert lib.nssdoa_plan_destroy(None) == _abi.OK
     assert lib.nssdoa_batch_destroy(None) == _abi.OK
     assert lib.nssdoa_plan_create(None, None, 0, None, 0, None) == _abi.EINVAL
