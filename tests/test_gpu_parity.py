@@ -82,6 +82,28 @@ def test_covariance_bit_exact_integer_snapshots():
         assert np.array_equal(R, exp), (f, np.max(np.abs(R - exp)))
 
 
+@pytest.mark.parametrize("sizes", [[(8, 1000), (16, 4097), (16, 257), (8, 1), (16, 63), (16, 64), (8, 65)],
+                                   [(8, 1), (8, 4096), (8, 129), (8, 700)]])
+def test_covariance_bit_exact_on_the_vector_kernel(sizes):
+    # batches with M <= 16 (complex64) accumulate on the FP64 vector ALUs: the same exact sums
+    rng = np.random.default_rng(12)
+    frames = []
+    for M, N in sizes:
+        X = integer_snapshots(rng, M, N)
+        frames.append(Frame(M=M, N=N, D=1, pos=ula_positions(M), geometry="ula", snr_db=0.0, sigma2=1.0,
+                            angles_deg=np.zeros(1), grid_start=-90.0, grid_step=1.0, grid_L=180, X=X))
+    fs = pack_frames(frames, dtype=np.complex64)
+    db, res = _run(fs, "music", "c64")
+    from paper_2007_14135_amd import WS_COV
+    for f, fr in enumerate(frames):
+        R = db.workspace_array(WS_COV, f, fr.M * fr.M, np.complex128).reshape(fr.M, fr.M)
+        Xi = fr.X.astype(np.complex128)
+        Sre = np.rint((Xi @ Xi.conj().T).real).astype(np.int64)
+        Sim = np.rint((Xi @ Xi.conj().T).imag).astype(np.int64)
+        exp = Sre.astype(np.float64) / fr.N + 1j * (Sim.astype(np.float64) / fr.N)
+        assert np.array_equal(R, exp), (f, np.max(np.abs(R - exp)))
+
+
 def test_eigendecomposition_matches_oracle():
     from paper_2007_14135_amd import WS_EVALS, WS_EVECS, WS_COV
     fs = make_frames("c2", n_frames=6, N=1024)
