@@ -395,6 +395,57 @@ def c6_leg(fs6, steps, warmup):
     return out
 
 
+def streaming_leg(fs, db, n_batches=24, depth=3):
+    """Snapshots that arrive in pinned host memory (the continuously working system of Section 5.3
+    with the pinned buffers of Table 9's third step): each 256-frame batch copied in, estimated and
+    its peaks copied out through a pipeline of `depth` slots.  Reported: the PCIe-inclusive rate,
+    and the copy-in and estimate times of one batch alone (their maximum bounds the pipelined time
+    per batch when they overlap)."""
+    import time as _t
+    import torch
+    import paper_2007_14135_amd as nd
+    F = len(fs)
+    n_host = 4                                   # host batches cycled through (same frames)
+    Xs = [torch.from_numpy(np.ascontiguousarray(fs.X_flat).view(np.float32).copy()).pin_memory()
+          for _ in range(n_host)]
+    outs = [(torch.empty(F * db.batch.max_D * 32, dtype=torch.uint8).pin_memory(),
+             torch.empty(F, dtype=torch.int32).pin_memory(), torch.empty(F, dtype=torch.int32).pin_memory())
+            for _ in range(n_host)]
+    stream = torch.cuda.current_stream()
+    # copy-in alone and estimate alone
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(8):
+        db.X.copy_(Xs[k % n_host], non_blocking=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = ev0.elapsed_time(ev1) / 8
+    comp_ms = _timed(lambda: db.run(stream), 20, 3, stream)
+    pipe = nd.Pipeline(db.batch, depth)
+    for k in range(depth):                       # warm the slots
+        pipe.wait(pipe.submit(Xs[k % n_host], *outs[k % n_host]))
+    t0 = _t.perf_counter()
+    tickets = []
+    for k in range(n_batches):
+        if k >= n_host:
+            pipe.wait(tickets[k - n_host])      # that host buffer's previous results are in
+        tickets.append(pipe.submit(Xs[k % n_host], *outs[k % n_host]))
+    for t in tickets[-n_host:]:
+        pipe.wait(t)
+    wall = _t.perf_counter() - t0
+    pipe.close()
+    ms = 1e3 * wall / n_batches
+    same = all(np.array_equal(o[1].numpy(), outs[0][1].numpy()) for o in outs)
+    x_bytes = Xs[0].numel() * 4
+    return {"how": "256-frame batches in pinned host memory through nssdoa_pipeline (%d slots): copy-in, estimate, "
+                   "copy-out of peaks; host wall clock over %d batches" % (depth, n_batches),
+            "ms_per_batch": ms, "frames_per_s_pcie_inclusive": F / (ms / 1e3),
+            "points_per_s_pcie_inclusive": F * fs.frames[0].grid_L / (ms / 1e3),
+            "copy_in_ms_alone": h2d_ms, "copy_in_GBps": x_bytes / (h2d_ms / 1e3) / 1e9,
+            "estimate_ms_alone": comp_ms, "overlap_bound_ms": max(h2d_ms, comp_ms),
+            "results_equal_across_batches": bool(same)}
+
+
 def c3_leg(fs3, steps, warmup, tune_cache, kernel):
     """The uneven workload: 4096 frames (M 8..64, ULA/UCA, uneven D, N, SNR, grid step) as one
     graph launch with the autotuned scan work-item size."""
@@ -511,6 +562,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096-frame uneven-batch leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 16-bit precision leg")
     ap.add_argument("--no-2d", action="store_true", help="skip the paper's 2-D (azimuth x polar angle) leg")
+    ap.add_argument("--no-stream", action="store_true", help="skip the pinned-host streaming pipeline leg")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
@@ -746,6 +798,8 @@ def main():
             worst = max(worst, max(abs(a - b) for a, b in zip(gang, oang)))
         out["peak_err_deg_max_vs_oracle"] = worst
         out["peak_count_mismatch_frames"] = mism
+    if not args.no_stream:
+        out["streaming_pcie"] = streaming_leg(fs, db)
     if fs5 is not None:
         del db
         torch.cuda.empty_cache()

@@ -235,7 +235,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* batch, nssdoa_plan plan, nssdoa_
                                   int32_t max_D);
 
 /* Free a batch (waits for nothing: the caller must not destroy a batch whose work is in flight).
- * ESTATE while graphs captured from it exist.  NULL is accepted and ignored. */
+ * ESTATE while graphs captured from it or pipelines built on it exist.  NULL is accepted and
+ * ignored. */
 nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch);
 
 /* Bytes of device workspace nssdoa_estimate needs for this batch. */
@@ -297,6 +298,32 @@ nssdoa_status nssdoa_graph_create(nssdoa_graph* graph, nssdoa_batch batch, const
 nssdoa_status nssdoa_graph_launch(nssdoa_graph graph, void* stream);
 nssdoa_status nssdoa_graph_destroy(nssdoa_graph graph);
 
+/* Streaming pipeline (the continuously working system of Section 5.3, with the pinned host
+ * buffers of Table 9's third step): batches of snapshots that arrive in host memory, laid out as
+ * the batch's frames address them, each copied to the device, estimated and its results copied
+ * back on one of `depth` slots.  A slot owns a stream, device copies of X, the workspace and the
+ * outputs, and a completion event, so the copy-in of one batch overlaps the estimate of the one
+ * before and the copy-out of the one before that.  Host buffers should be pinned (hipHostMalloc,
+ * or a torch tensor with pin_memory): from pageable memory the copies are staged by the runtime
+ * and do not overlap.
+ * create: EINVAL for depth outside [1, 8]; allocates the slots (ENOMEM/EDEVICE on failure).  The
+ *   batch must outlive the pipeline (nssdoa_batch_destroy returns ESTATE while it exists).
+ * submit: waits on the host until the slot it takes (slots in turn) has finished its previous
+ *   batch, enqueues copy-in of X_host (the batch's x extent), the estimate, and copy-out of the
+ *   peaks, peak counts and status (and of the spectrum into spectrum_host unless it is NULL:
+ *   nssdoa_estimate's spectrum layout, frames at their spec_off), and returns a ticket.  The host
+ *   buffers of a submission must not be touched until nssdoa_pipeline_wait(ticket) returns.
+ * wait: blocks until the ticket's results are in its host buffers.  EINVAL for a ticket never
+ *   issued.
+ * destroy: waits for every slot, then frees them. */
+typedef struct nssdoa_pipeline_s* nssdoa_pipeline;
+nssdoa_status nssdoa_pipeline_create(nssdoa_pipeline* pipeline, nssdoa_batch batch, int32_t depth);
+nssdoa_status nssdoa_pipeline_submit(nssdoa_pipeline pipeline, const void* X_host, void* spectrum_host,
+                                     nssdoa_peak* peaks_host, int32_t* npeaks_host, uint32_t* status_host,
+                                     int64_t* ticket);
+nssdoa_status nssdoa_pipeline_wait(nssdoa_pipeline pipeline, int64_t ticket);
+nssdoa_status nssdoa_pipeline_destroy(nssdoa_pipeline pipeline);
+
 /* Per-stage device timing.  stage_mask selects stages (bit 1 << NSSDOA_STAGE_*; 0 = off, -1 =
  * all); while set, nssdoa_estimate records HIP events around those stages on its stream (each
  * pair costs a few microseconds of stream time).  nssdoa_stage_time waits for them and returns
@@ -315,7 +342,11 @@ nssdoa_status nssdoa_stage_time(nssdoa_batch batch, nssdoa_stage stage, double* 
 typedef struct nssdoa_mlp_s* nssdoa_mlp;
 
 /* Allocate a network with zero parameters and zero Adam state; max_batch bounds the rows of
- * forward and training calls (activation buffers are sized for it).
+ * forward and training calls (activation buffers are sized for it).  The activation buffers
+ * belong to the network object and every call that runs it (nssdoa_mlp_forward,
+ * nssdoa_mlp_train_step, nssdoa_estimate_learned) reuses them: calls that use one network must
+ * not overlap (one stream at a time, or the caller orders them); give each concurrent stream
+ * its own network (nssdoa_mlp_save / nssdoa_mlp_load copy one).
  * EINVAL: NULL mlp, a size outside [1, 65536], max_batch outside [1, 2^20]. */
 nssdoa_status nssdoa_mlp_create(nssdoa_mlp* mlp, int32_t in, int32_t width, int32_t out, int32_t max_batch);
 nssdoa_status nssdoa_mlp_destroy(nssdoa_mlp mlp);
@@ -332,6 +363,17 @@ nssdoa_status nssdoa_mlp_param_count(nssdoa_mlp mlp, size_t* count);
  * them). */
 nssdoa_status nssdoa_mlp_save(nssdoa_mlp mlp, void* blob, size_t* bytes);
 nssdoa_status nssdoa_mlp_load(nssdoa_mlp mlp, const void* blob, size_t bytes);
+
+/* Proposal features of every frame of a batch, as nssdoa_estimate_learned computes them: the
+ * upper triangle i <= j of R * M / trace(R), row-major, real and imaginary parts interleaved
+ * (M (M + 1) FP32 values per frame; the trace summed in index order and the scale M / trace
+ * formed in FP64, each product rounded to FP32), from the covariances R (Eq. 3) that the last
+ * nssdoa_estimate (or _noalloc: then pass nothing else) left in `workspace`; enqueued on `stream`,
+ * so it must follow that call on the same stream.  feats: device [n_frames][n_feat] float.
+ * EINVAL: NULL pointers, a workspace smaller than nssdoa_workspace_size or not 256-byte aligned,
+ * n_feat != M (M + 1); EUNSUPPORTED: frames of different M. */
+nssdoa_status nssdoa_features(nssdoa_batch batch, const void* workspace, size_t workspace_bytes, float* feats,
+                              int32_t n_feat, void* stream);
 
 /* Logits of `batch` feature rows: feats device [batch][in] FP32, logits device [batch][out]. */
 nssdoa_status nssdoa_mlp_forward(nssdoa_mlp mlp, const float* feats, int32_t batch, float* logits,

@@ -10,4 +10,4 @@ from ._abi import (  # noqa: F401
     ST_FALLBACK_USED,
     WS_COV, WS_EVALS, WS_EVECS, WS_B, WS_QREF, WS_SPECTRUM,
 )
-from .api import MLP, Batch, Options, Plan, decode_peaks, flatten_params, unflatten_params  # noqa: F401
+from .api import MLP, Batch, Options, Pipeline, Plan, decode_peaks, flatten_params, unflatten_params  # noqa: F401

@@ -92,9 +92,14 @@ _SIGNATURES = {
     "nssdoa_mlp_train_step": [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P],
     "nssdoa_mlp_gradients": [_P, _P, ctypes.c_size_t],
     "nssdoa_windowed_workspace_size": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "nssdoa_features": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, _P],
     "nssdoa_graph_create": [ctypes.POINTER(_P), _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, _P, _P,
                             ctypes.c_size_t],
     "nssdoa_graph_launch": [_P, _P],
+    "nssdoa_pipeline_create": [ctypes.POINTER(_P), _P, ctypes.c_int32],
+    "nssdoa_pipeline_submit": [_P, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)],
+    "nssdoa_pipeline_wait": [_P, ctypes.c_int64],
+    "nssdoa_pipeline_destroy": [_P],
     "nssdoa_graph_destroy": [_P],
     "nssdoa_estimate_windowed": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P,

@@ -154,6 +154,13 @@ class Batch:
                                                _ptr(peaks), _ptr(npeaks), _ptr(status), _stream_handle(stream)),
                    "nssdoa_estimate_noalloc")
 
+    def features(self, workspace, feats, stream=None) -> None:
+        """Proposal features (device float [n_frames][M(M+1)]) of the covariances the last estimate
+        on this workspace computed."""
+        _abi.check(_abi.load().nssdoa_features(self.handle, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                               _ptr(feats), int(feats.shape[1]), _stream_handle(stream)),
+                   "nssdoa_features")
+
     def windowed_workspace_size(self, mlp: Optional["MLP"] = None) -> int:
         n = ctypes.c_size_t()
         _abi.check(_abi.load().nssdoa_windowed_workspace_size(self.handle, mlp.handle if mlp is not None else None,
@@ -245,6 +252,41 @@ class Graph:
         try:
             if getattr(self, "handle", None):
                 _abi.load().nssdoa_graph_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """nssdoa_pipeline: batches of host snapshots copied in, estimated and copied out on `depth`
+    slots.  Host buffers are tensors (pinned for overlapping copies); a submission's buffers must
+    stay untouched until wait(ticket) returns."""
+
+    def __init__(self, batch: Batch, depth: int):
+        h = ctypes.c_void_p()
+        _abi.check(_abi.load().nssdoa_pipeline_create(ctypes.byref(h), batch.handle, int(depth)),
+                   "nssdoa_pipeline_create")
+        self.handle = h
+        self.batch = batch
+
+    def submit(self, X_host, peaks_host, npeaks_host, status_host, spectrum_host=None) -> int:
+        t = ctypes.c_int64()
+        _abi.check(_abi.load().nssdoa_pipeline_submit(self.handle, _ptr(X_host), _ptr(spectrum_host), _ptr(peaks_host),
+                                                      _ptr(npeaks_host), _ptr(status_host), ctypes.byref(t)),
+                   "nssdoa_pipeline_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int) -> None:
+        _abi.check(_abi.load().nssdoa_pipeline_wait(self.handle, int(ticket)), "nssdoa_pipeline_wait")
+
+    def close(self):
+        if self.handle:
+            _abi.check(_abi.load().nssdoa_pipeline_destroy(self.handle), "nssdoa_pipeline_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                _abi.load().nssdoa_pipeline_destroy(self.handle)
         except Exception:
             pass
 

@@ -150,7 +150,7 @@ struct nssdoa_batch_s {
     double2* d_cis = nullptr;
     float* d_steer = nullptr;                   // steering tables of the C64 scans (batch-owned)
     bool split16 = false;                       // C64 scans on FP16 split operands
-    int live_graphs = 0;
+    int live_graphs = 0;                        // graphs and pipelines that use the batch
     // timing
     uint32_t timing = 0;                        // stages with HIP events (bit 1 << stage)
     std::vector<StageEvents> pending;
@@ -273,7 +273,8 @@ nssdoa_status nssdoa_plan_destroy(nssdoa_plan plan) {
 
 nssdoa_status nssdoa_batch_destroy(nssdoa_batch batch) {
     if (!batch) return NSSDOA_OK;
-    if (batch->live_graphs > 0) return fail(NSSDOA_ESTATE, "batch still has %d live graphs", batch->live_graphs);
+    if (batch->live_graphs > 0)
+        return fail(NSSDOA_ESTATE, "batch still has %d live graphs or pipelines", batch->live_graphs);
     for (auto& e : batch->pending) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -1040,6 +1041,22 @@ nssdoa_status nssdoa_noalloc_workspace_limit(size_t* bytes) {
     return NSSDOA_OK;
 }
 
+nssdoa_status nssdoa_features(nssdoa_batch batch, const void* workspace, size_t workspace_bytes, float* feats,
+                              int32_t n_feat, void* stream) {
+    if (!batch || !workspace || !feats) return fail(NSSDOA_EINVAL, "NULL batch, workspace or feats");
+    if (workspace_bytes < batch->ws_bytes)
+        return fail(NSSDOA_EINVAL, "workspace of %zu bytes < required %zu", workspace_bytes, batch->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(NSSDOA_EINVAL, "workspace must be 256-byte aligned");
+    const int M = batch->frames[0].M;
+    for (const FrameDev& fd : batch->frames)
+        if (fd.M != M) return fail(NSSDOA_EUNSUPPORTED, "features need one array size in the batch");
+    if (n_feat != M * (M + 1)) return fail(NSSDOA_EINVAL, "n_feat=%d, the features of M=%d hold %d", n_feat, M, M * (M + 1));
+    hipError_t e = launch_features(nullptr, batch->n_frames, batch->d_frames,
+                                   static_cast<const char*>(workspace), feats, n_feat, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "features launch");
+}
+
 nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes) {
     if (!batch || !bytes) return fail(NSSDOA_EINVAL, "NULL argument");
     int32_t in = 0, width = 0, out = 0, mb = 0;
@@ -1136,6 +1153,125 @@ nssdoa_status nssdoa_graph_destroy(nssdoa_graph graph) {
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->batch) graph->batch->live_graphs--;
     delete graph;
+    return NSSDOA_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Streaming pipeline: batches of snapshots arriving in host memory, each copied in, estimated and
+// its results copied out on one of `depth` slots; every slot has its own stream, device buffers
+// and completion event, so the copy-in of one batch overlaps the estimate of the previous one and
+// the copy-out of the one before.
+struct PipeSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    char* dev = nullptr;                 // X, workspace, spectrum, peaks, npeaks, status
+    void* X = nullptr;
+    void* ws = nullptr;
+    void* spec = nullptr;
+    nssdoa_peak* peaks = nullptr;
+    int32_t* npeaks = nullptr;
+    uint32_t* status = nullptr;
+    int64_t ticket = -1;                 // last submission on this slot, -1 if none
+};
+
+struct nssdoa_pipeline_s {
+    nssdoa_batch batch = nullptr;
+    std::vector<PipeSlot> slots;
+    int64_t next = 0;
+    size_t x_bytes = 0, ws_bytes = 0, spec_bytes = 0, peak_bytes = 0;
+};
+
+static void pipeline_free(nssdoa_pipeline pl) {
+    for (PipeSlot& sl : pl->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.dev) (void)hipFree(sl.dev);
+    }
+    if (pl->batch) pl->batch->live_graphs--;
+    delete pl;
+}
+
+nssdoa_status nssdoa_pipeline_create(nssdoa_pipeline* out, nssdoa_batch batch, int32_t depth) {
+    if (!out) return fail(NSSDOA_EINVAL, "pipeline is NULL");
+    *out = nullptr;
+    if (!batch) return fail(NSSDOA_EINVAL, "batch is NULL");
+    if (depth < 1 || depth > 8) return fail(NSSDOA_EINVAL, "depth=%d outside [1, 8]", depth);
+    auto* pl = new (std::nothrow) nssdoa_pipeline_s();
+    if (!pl) return fail(NSSDOA_ENOMEM, "host allocation failed");
+    pl->batch = batch;
+    batch->live_graphs++;                // the batch must outlive the pipeline
+    const size_t celem = batch->prec == NSSDOA_C128 ? 16 : 8;
+    pl->x_bytes = align_up(batch->x_extent * celem);
+    pl->ws_bytes = align_up(batch->ws_bytes);
+    pl->spec_bytes = align_up(batch->spec_extent * batch->spec_elem);
+    pl->peak_bytes = align_up((size_t)batch->n_frames * batch->max_D * sizeof(nssdoa_peak));
+    const size_t small = align_up((size_t)batch->n_frames * 4);
+    const size_t total = pl->x_bytes + pl->ws_bytes + pl->spec_bytes + pl->peak_bytes + 2 * small;
+    pl->slots.resize(depth);
+    for (PipeSlot& sl : pl->slots) {
+        hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc((void**)&sl.dev, total);
+        if (e != hipSuccess) {
+            pipeline_free(pl);
+            return hip_fail(e, "pipeline slot");
+        }
+        char* p = sl.dev;
+        sl.X = p;                                       p += pl->x_bytes;
+        sl.ws = p;                                      p += pl->ws_bytes;
+        sl.spec = p;                                    p += pl->spec_bytes;
+        sl.peaks = reinterpret_cast<nssdoa_peak*>(p);   p += pl->peak_bytes;
+        sl.npeaks = reinterpret_cast<int32_t*>(p);      p += small;
+        sl.status = reinterpret_cast<uint32_t*>(p);
+    }
+    *out = pl;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_pipeline_submit(nssdoa_pipeline pl, const void* X_host, void* spectrum_host, nssdoa_peak* peaks_host,
+                                     int32_t* npeaks_host, uint32_t* status_host, int64_t* ticket) {
+    if (!pl || !X_host || !peaks_host || !npeaks_host || !status_host || !ticket)
+        return fail(NSSDOA_EINVAL, "NULL pipeline, X, peaks, npeaks, status or ticket");
+    PipeSlot& sl = pl->slots[pl->next % (int64_t)pl->slots.size()];
+    hipError_t e = hipSuccess;
+    if (sl.ticket >= 0) {
+        e = hipEventSynchronize(sl.done);             // the slot's previous batch has finished
+        if (e != hipSuccess) return hip_fail(e, "pipeline wait");
+    }
+    nssdoa_batch b = pl->batch;
+    const size_t celem = b->prec == NSSDOA_C128 ? 16 : 8;
+    e = hipMemcpyAsync(sl.X, X_host, b->x_extent * celem, hipMemcpyHostToDevice, sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "pipeline copy-in");
+    nssdoa_status st = estimate_impl(b, sl.X, b->x_extent, spectrum_host ? sl.spec : nullptr,
+                                     pl->spec_bytes / b->spec_elem, sl.peaks, sl.npeaks, sl.status, sl.ws, pl->ws_bytes,
+                                     sl.stream, nullptr, true);
+    if (st != NSSDOA_OK) return st;
+    const size_t n = (size_t)b->n_frames;
+    e = hipMemcpyAsync(peaks_host, sl.peaks, n * b->max_D * sizeof(nssdoa_peak), hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(npeaks_host, sl.npeaks, n * 4, hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(status_host, sl.status, n * 4, hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess && spectrum_host)
+        e = hipMemcpyAsync(spectrum_host, sl.spec, b->spec_extent * b->spec_elem, hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "pipeline copy-out");
+    sl.ticket = pl->next++;
+    *ticket = sl.ticket;
+    return NSSDOA_OK;
+}
+
+nssdoa_status nssdoa_pipeline_wait(nssdoa_pipeline pl, int64_t ticket) {
+    if (!pl) return fail(NSSDOA_EINVAL, "pipeline is NULL");
+    if (ticket < 0 || ticket >= pl->next) return fail(NSSDOA_EINVAL, "ticket %lld was never issued", (long long)ticket);
+    const PipeSlot& sl = pl->slots[ticket % (int64_t)pl->slots.size()];
+    if (sl.ticket != ticket) return NSSDOA_OK;         // its slot was reused, which waited for it
+    hipError_t e = hipEventSynchronize(sl.done);
+    return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "pipeline wait");
+}
+
+nssdoa_status nssdoa_pipeline_destroy(nssdoa_pipeline pl) {
+    if (!pl) return NSSDOA_OK;
+    pipeline_free(pl);
     return NSSDOA_OK;
 }
 

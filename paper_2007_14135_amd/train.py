@@ -4,12 +4,14 @@ Data: frames of the learned-proposal workload (ULA M = 16 at half-wavelength spa
 1..4, SNR uniform in [-5, 20] dB, N log-uniform in [256, 4096], angles in [-70, 70] deg at least
 5 deg apart) drawn by the seeded generator from frame indices that the evaluation batch never
 uses (evaluation takes frames 0..8191; training starts at TRAIN_FIRST_FRAME).
-Inputs: the covariance features the learned path computes on the device, upper triangle i <= j of
-R M / trace(R) with real and imaginary parts interleaved (272 values at M = 16).
-Labels: multi-hot 1-degree bins (bin b covers [-90 + b, -89 + b) deg) of the D peaks of the
-library's own MUSIC scan of R at 0.1 deg (method-matched: the windows must contain the peaks the
-full scan would report).  The scan is run on a 16 x 16 snapshot block R^(1/2) sqrt(16), whose
-sample covariance is R, so that only R-sized data crosses process and device boundaries.
+Every quantity derived from the snapshots comes from the library, on the device, as the learned
+path computes it at inference: per chunk of frames the snapshots go through nssdoa_estimate
+(MUSIC at 0.1 deg: covariance, eigensolve, scan, peaks), then nssdoa_features reads the same
+covariances.
+Inputs: the covariance features, upper triangle i <= j of R M / trace(R) with real and imaginary
+parts interleaved (272 values at M = 16).
+Labels: multi-hot 1-degree bins (bin b covers [-90 + b, -89 + b) deg) of the D peaks of that MUSIC
+scan (method-matched: the windows must contain the peaks the full scan would report).
 Optimiser: Adam (beta 0.9 / 0.999, eps 1e-8) on mean binary cross-entropy in
 nssdoa_mlp_train_step, minibatches in a seeded order, cosine learning-rate decay.  The blob of
 nssdoa_mlp_save (parameters and Adam state) is written after every epoch; --resume continues
@@ -36,62 +38,18 @@ TRAIN_FIRST_FRAME = 1_000_000
 LABEL_GRID = (-90.0, 0.1, 1800)
 
 
-def covariance_features(R: np.ndarray) -> np.ndarray:
-    """Features of one covariance, computed as the device does: the trace summed in index order,
-    scale M / trace in FP64, products rounded to FP32."""
-    m = R.shape[0]
-    t = 0.0
-    for i in range(m):
-        t += float(R[i, i].real)
-    trs = m / t
-    iu, ju = np.triu_indices(m)
-    v = R[iu, ju]
-    out = np.empty(2 * len(v), dtype=np.float32)
-    out[0::2] = (v.real * trs).astype(np.float32)
-    out[1::2] = (v.imag * trs).astype(np.float32)
-    return out
-
-
 def _generate(args):
-    """Frames [start, start + count) of the learned-proposal workload -> features, 16 x 16 snapshot
-    blocks with the frame's covariance, source counts."""
+    """Frames [start, start + count) of the learned-proposal workload: their snapshots packed back
+    to back (complex64), per-frame offsets and snapshot counts, and source counts."""
     start, count = args
     from threadpoolctl import threadpool_limits
     from synth import make_frame
-    feats = np.empty((count, N_FEAT), dtype=np.float32)
-    blocks = np.empty((count, M, M), dtype=np.complex64)
-    D = np.empty(count, dtype=np.int32)
+    from synth.frames import pack_frames
     with threadpool_limits(1):
-        for k in range(count):
-            fr = make_frame("c5", start + k)
-            X = fr.X.astype(np.complex128)
-            R = X @ X.conj().T / fr.N
-            feats[k] = covariance_features(R)
-            w, V = np.linalg.eigh(R)
-            blocks[k] = ((V * np.sqrt(np.maximum(w, 0.0))) @ V.conj().T * math.sqrt(M)).astype(np.complex64)
-            D[k] = fr.D
-    return start, feats, blocks, D
-
-
-def generate(first: int, n: int, workers: int, chunk: int = 2048, log=print):
-    """Features, snapshot blocks and source counts of n frames, generated by a fork pool (before
-    anything touches the GPU)."""
-    feats = np.empty((n, N_FEAT), dtype=np.float32)
-    blocks = np.empty((n, M, M), dtype=np.complex64)
-    D = np.empty(n, dtype=np.int32)
-    jobs = [(first + s, min(chunk, n - s)) for s in range(0, n, chunk)]
-    t0 = time.time()
-    done = 0
-    with mp.get_context("fork").Pool(workers) as pool:
-        for start, f, b, d in pool.imap_unordered(_generate, jobs):
-            o = start - first
-            feats[o:o + len(d)] = f
-            blocks[o:o + len(d)] = b
-            D[o:o + len(d)] = d
-            done += len(d)
-            if done % (chunk * 32) < chunk or done == n:
-                log("generated %d / %d frames (%.0f s)" % (done, n, time.time() - t0))
-    return feats, blocks, D
+        fs = pack_frames([make_frame("c5", start + k) for k in range(count)], dtype=np.complex64)
+    N = np.array([fr.N for fr in fs.frames], dtype=np.int32)
+    D = np.array([fr.D for fr in fs.frames], dtype=np.int32)
+    return start, fs.X_flat, fs.x_off, N, D
 
 
 def ula_positions(m: int) -> np.ndarray:
@@ -100,35 +58,44 @@ def ula_positions(m: int) -> np.ndarray:
     return pos
 
 
-def music_labels(blocks: np.ndarray, D: np.ndarray, batch_frames: int = 8192, log=print) -> np.ndarray:
-    """Multi-hot bin labels from the library's MUSIC scan at 0.1 deg of each block's covariance."""
+def generate(first: int, n: int, workers: int, chunk: int = 1024, log=print):
+    """Features and MUSIC bin labels of n frames: a fork pool draws the snapshots (before anything
+    touches the GPU in this process's children), the library turns each chunk into features and
+    labels on the device."""
     import torch
     from . import api, _abi
     plan = api.Plan([ula_positions(M)], [LABEL_GRID + (0,)])
-    n = len(D)
     labels = np.zeros((n, N_BINS), dtype=np.float32)
+    D_all = np.empty(n, dtype=np.int32)
+    jobs = [(first + s, min(chunk, n - s)) for s in range(0, n, chunk)]
     t0 = time.time()
-    for s in range(0, n, batch_frames):
-        e = min(n, s + batch_frames)
-        frames = [(0, 0, M, int(D[i]), (i - s) * M * M, M, 0) for i in range(s, e)]
-        b = api.Batch(plan, "music", "c64", frames, 4)
-        X = torch.from_numpy(np.ascontiguousarray(blocks[s:e]).reshape(-1).view(np.float32)).cuda()
-        peaks = torch.empty((e - s) * 4 * _abi.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-        npk = torch.empty(e - s, dtype=torch.int32, device="cuda")
-        st = torch.empty(e - s, dtype=torch.int32, device="cuda")
-        ws = torch.empty(b.workspace_size(), dtype=torch.uint8, device="cuda")
-        b.estimate(X, None, peaks, npk, st, ws)
-        pk = api.decode_peaks(peaks.cpu().numpy(), e - s, 4)
-        cnt = npk.cpu().numpy()
-        for r in range(e - s):
-            for j in range(int(cnt[r])):
-                a = float(pk[r, j]["angle_deg"])
-                labels[s + r, int(min(max(math.floor(a + 90.0), 0), N_BINS - 1))] = 1.0
-        b.close()
-        if (s // batch_frames) % 16 == 0 or e == n:
-            log("labelled %d / %d frames (%.0f s)" % (e, n, time.time() - t0))
+    done = 0
+    with mp.get_context("fork").Pool(workers) as pool:     # forked before this process touches the GPU
+        feats = torch.empty((n, N_FEAT), dtype=torch.float32, device="cuda")
+        for start, X_flat, x_off, N, D in pool.imap_unordered(_generate, jobs):
+            o, c = start - first, len(D)
+            frames = [(0, 0, int(N[k]), int(D[k]), int(x_off[k]), int(N[k]), 0) for k in range(c)]
+            b = api.Batch(plan, "music", "c64", frames, 4)
+            X = torch.from_numpy(np.ascontiguousarray(X_flat).view(np.float32)).cuda()
+            peaks = torch.empty(c * 4 * _abi.PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+            npk = torch.empty(c, dtype=torch.int32, device="cuda")
+            st = torch.empty(c, dtype=torch.int32, device="cuda")
+            ws = torch.empty(b.workspace_size(), dtype=torch.uint8, device="cuda")
+            b.estimate(X, None, peaks, npk, st, ws)
+            b.features(ws, feats[o:o + c])
+            pk = api.decode_peaks(peaks.cpu().numpy(), c, 4)
+            cnt = npk.cpu().numpy()
+            for r in range(c):
+                for j in range(int(cnt[r])):
+                    a = float(pk[r, j]["angle_deg"])
+                    labels[o + r, int(min(max(math.floor(a + 90.0), 0), N_BINS - 1))] = 1.0
+            D_all[o:o + c] = D
+            b.close()
+            done += c
+            if done % (chunk * 64) < chunk or done == n:
+                log("features and labels of %d / %d frames (%.0f s)" % (done, n, time.time() - t0))
     plan.close()
-    return labels
+    return feats, labels, D_all
 
 
 def window_recall(logits: np.ndarray, labels: np.ndarray, topk: int = 6) -> float:
@@ -146,14 +113,11 @@ def window_recall(logits: np.ndarray, labels: np.ndarray, topk: int = 6) -> floa
 def train(args) -> dict:
     log = lambda s: print(s, flush=True)  # noqa: E731
     workers = args.workers or min(16, len(os.sched_getaffinity(0)))
-    feats, blocks, D = generate(args.first_frame, args.frames, workers, log=log)
     import torch
-    from . import api, _abi
-    labels = music_labels(blocks, D, log=log)
-    del blocks
+    from . import api
+    Xd, labels, D = generate(args.first_frame, args.frames, workers, log=log)
     n_val = max(1024, args.frames // 100)
     n_tr = args.frames - n_val
-    Xd = torch.from_numpy(feats).cuda()
     Yd = torch.from_numpy(labels).cuda()
     net = api.MLP(N_FEAT, WIDTH, N_BINS, max_batch=max(args.batch, 1024))
     if args.resume:

@@ -198,3 +198,43 @@ def test_training_reduces_loss_on_a_small_batch():
         losses.append(float(loss.item()))
     print("overfit: loss %.4f -> %.4f" % (losses[0], losses[-1]), flush=True)
     assert losses[-1] < 0.2 * losses[0]
+
+
+def test_features_entry_point_against_the_oracle():
+    # nssdoa_features after nssdoa_estimate: the proposal features of the covariances the estimate
+    # computed, against the oracle's features of its own FP64 covariance (FP32 rounding of each
+    # value, so within 2^-22 relative)
+    from paper_2007_14135_amd.runner import prepare
+    from synth import make_frames
+    import oracle
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fs = make_frames("c5", n_frames=24, start=500)
+    fr0 = fs.frames[0]
+    frames = [(0, 0, fr.N, fr.D, int(fs.x_off[f]), int(fs.ld[f])) for f, fr in enumerate(fs.frames)]
+    db = prepare([fr0.pos], [(-90.0, 0.1, 1800, 0)], frames, fs.X_flat, "music", "c64", 4)
+    db.run()
+    feats = torch.empty(len(fs), 272, dtype=torch.float32, device="cuda")
+    db.batch.features(db.workspace, feats)
+    got = feats.cpu().numpy().astype(np.float64)
+    for f, fr in enumerate(fs.frames):
+        ref = omlp.features(oracle.covariance(fr.X))
+        assert np.all(np.abs(got[f] - ref) <= 2.0 ** -22 * np.abs(ref) + 1e-12), f
+    from paper_2007_14135_amd import _abi
+    with pytest.raises(_abi.NssdoaError):
+        db.batch.features(db.workspace, torch.empty(len(fs), 270, dtype=torch.float32, device="cuda"))
+
+
+def test_training_pipeline_runs_on_the_library(tmp_path):
+    # the trainer end to end on 3072 frames: snapshots -> library estimate + features -> labels ->
+    # one epoch of nssdoa_mlp_train_step; finite losses, weights and metadata written
+    from paper_2007_14135_amd import train as tr
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    out = str(tmp_path / "w.npy")
+    meta = tr.train(tr.argparse.Namespace(frames=3072, first_frame=tr.TRAIN_FIRST_FRAME + 7, epochs=1, batch=256,
+                                          lr=1e-3, lr_min=1e-4, seed=3, workers=4, out=out, checkpoint="", resume=""))
+    h = meta["history"][-1]
+    assert np.isfinite(h["train_loss"]) and np.isfinite(h["val_loss"]) and 0.0 <= h["val_recall6"] <= 1.0
+    w = np.load(out, allow_pickle=False)
+    assert w.shape == (272 * 512 + 512 + 512 * 512 + 512 + 180 * 512 + 180,) and np.all(np.isfinite(w))
