@@ -446,6 +446,33 @@ def streaming_leg(fs, db, n_batches=24, depth=3):
             "results_equal_across_batches": bool(same)}
 
 
+def scan_forms_leg(fs, db, opeaks_frames=8):
+    """Alternative Step-5 forms on the benchmark batch (plain FP32 on the vector ALUs, no FP64
+    re-evaluation): kernel time per form, and the largest relative error of Q against the oracle
+    near the nulls (Q < 5e-4 ||B||_F^2) and elsewhere over the first frames."""
+    import torch
+    import oracle
+    stream = torch.cuda.current_stream()
+    db.run(stream)
+    out = {"how": "nssdoa_scan_form after the estimate: factored ||B^H a||^2, Table 2's a^H C a, and the "
+                  "complement ||a||^2 - ||E_s^H a||^2; FP32, every grid point, %d frames against the oracle"
+                  % opeaks_frames}
+    ests = [oracle.estimate(fr.X, fr.pos, fr.D, fr.grid, "music") for fr in fs.frames[:opeaks_frames]]
+    for form in ("factored", "quadratic", "complement"):
+        spec = torch.empty_like(db.spectrum)
+        ms = _timed(lambda: db.batch.scan_form(form, db.workspace, spec, stream), 20, 2, stream)
+        P = spec.cpu().numpy().astype(np.float64)
+        low, rest = 0.0, 0.0
+        for f, est in enumerate(ests):
+            L = fs.frames[f].grid_L
+            rel = np.abs(1.0 / P[db.spec_off[f]:db.spec_off[f] + L] - est.Q) / est.Q
+            m = est.Q < 5e-4 * np.sum(np.abs(est.B) ** 2)
+            low = max(low, float(rel[m].max()) if m.any() else 0.0)
+            rest = max(rest, float(rel[~m].max()))
+        out[form] = {"kernel_ms": ms, "max_rel_err_Q_near_nulls": low, "max_rel_err_Q_elsewhere": rest}
+    return out
+
+
 def c3_leg(fs3, steps, warmup, tune_cache, kernel):
     """The uneven workload: 4096 frames (M 8..64, ULA/UCA, uneven D, N, SNR, grid step) as one
     graph launch with the autotuned scan work-item size."""
@@ -563,6 +590,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 16-bit precision leg")
     ap.add_argument("--no-2d", action="store_true", help="skip the paper's 2-D (azimuth x polar angle) leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the pinned-host streaming pipeline leg")
+    ap.add_argument("--no-forms", action="store_true", help="skip the alternative scan-form ablation leg")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
@@ -800,6 +828,8 @@ def main():
         out["peak_count_mismatch_frames"] = mism
     if not args.no_stream:
         out["streaming_pcie"] = streaming_leg(fs, db)
+    if not args.no_forms and args.alg == "music":
+        out["scan_forms_ablation"] = scan_forms_leg(fs, db)
     if fs5 is not None:
         del db
         torch.cuda.empty_cache()

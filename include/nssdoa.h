@@ -375,6 +375,22 @@ nssdoa_status nssdoa_mlp_load(nssdoa_mlp mlp, const void* blob, size_t bytes);
 nssdoa_status nssdoa_features(nssdoa_batch batch, const void* workspace, size_t workspace_bytes, float* feats,
                               int32_t n_feat, void* stream);
 
+/* Alternative forms of the Step-5 scan, as measured ablations of the factored form: after
+ * nssdoa_estimate on `workspace`, the spectrum of every frame again, in plain FP32 on the vector
+ * ALUs and without the FP64 re-evaluation of low-Q points, with Q formed as
+ *   NSSDOA_FORM_FACTORED:   ||B^H a||^2 (the library's form, a sum of squares);
+ *   NSSDOA_FORM_QUADRATIC:  Re a^H C a, C = B B^H formed in FP64 then rounded to FP32 (Table 2
+ *                           Step-5 as printed: M^2 terms that cancel down to Q near a null);
+ *   NSSDOA_FORM_COMPLEMENT: ||a||^2 - ||E_s^H a||^2 with the D signal eigenvectors (MUSIC only).
+ * P = 1 / max(Q, FLT_MIN) is written to `spectrum` (float) at each frame's spec_off; steering
+ * vectors are FP32 values of phases reduced in FP64.  Peaks are not searched.
+ * EINVAL: NULL pointers, an unknown form, a workspace or spectrum smaller than the batch needs;
+ * EUNSUPPORTED: a batch that is not NSSDOA_C64, has 2-D grids or M > 32, or the complement form
+ * for another method than MUSIC. */
+typedef enum { NSSDOA_FORM_FACTORED = 0, NSSDOA_FORM_QUADRATIC = 1, NSSDOA_FORM_COMPLEMENT = 2 } nssdoa_scan_form_kind;
+nssdoa_status nssdoa_scan_form(nssdoa_batch batch, int32_t form, const void* workspace, size_t workspace_bytes,
+                               float* spectrum, size_t spectrum_elems, void* stream);
+
 /* Logits of `batch` feature rows: feats device [batch][in] FP32, logits device [batch][out]. */
 nssdoa_status nssdoa_mlp_forward(nssdoa_mlp mlp, const float* feats, int32_t batch, float* logits,
                                  void* stream);

@@ -59,6 +59,7 @@ class Options(ctypes.Structure):
 
 EIG_METHODS = {"auto": 0, "ql": 1, "jacobi": 2}
 C64_SCANS = {"split16": 0, "fp32": 1}
+SCAN_FORMS = {"factored": 0, "quadratic": 1, "complement": 2}
 
 
 PEAK_DTYPE = np.dtype([("idx", "<i4"), ("reserved", "<i4"), ("angle_deg", "<f8"), ("value", "<f8"),
@@ -93,6 +94,7 @@ _SIGNATURES = {
     "nssdoa_mlp_gradients": [_P, _P, ctypes.c_size_t],
     "nssdoa_windowed_workspace_size": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
     "nssdoa_features": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, _P],
+    "nssdoa_scan_form": [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P],
     "nssdoa_graph_create": [ctypes.POINTER(_P), _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, _P, _P, _P,
                             ctypes.c_size_t],
     "nssdoa_graph_launch": [_P, _P],

@@ -161,6 +161,14 @@ class Batch:
                                                _ptr(feats), int(feats.shape[1]), _stream_handle(stream)),
                    "nssdoa_features")
 
+    def scan_form(self, form: str, workspace, spectrum, stream=None) -> None:
+        """Rescan the frames of the last estimate on this workspace with an alternative Step-5 form
+        (plain FP32, no FP64 re-evaluation): 'factored', 'quadratic' or 'complement'."""
+        _abi.check(_abi.load().nssdoa_scan_form(self.handle, _abi.SCAN_FORMS[form], _ptr(workspace),
+                                                workspace.numel() * workspace.element_size(), _ptr(spectrum),
+                                                spectrum.numel(), _stream_handle(stream)),
+                   "nssdoa_scan_form")
+
     def windowed_workspace_size(self, mlp: Optional["MLP"] = None) -> int:
         n = ctypes.c_size_t()
         _abi.check(_abi.load().nssdoa_windowed_workspace_size(self.handle, mlp.handle if mlp is not None else None,

@@ -1057,6 +1057,32 @@ nssdoa_status nssdoa_features(nssdoa_batch batch, const void* workspace, size_t 
     return e == hipSuccess ? NSSDOA_OK : hip_fail(e, "features launch");
 }
 
+nssdoa_status nssdoa_scan_form(nssdoa_batch batch, int32_t form, const void* workspace, size_t workspace_bytes,
+                               float* spectrum, size_t spectrum_elems, void* stream) {
+    if (!batch || !workspace || !spectrum) return fail(NSSDOA_EINVAL, "NULL batch, workspace or spectrum");
+    if (form != NSSDOA_FORM_FACTORED && form != NSSDOA_FORM_QUADRATIC && form != NSSDOA_FORM_COMPLEMENT)
+        return fail(NSSDOA_EINVAL, "unknown scan form %d", form);
+    if (batch->prec != NSSDOA_C64) return fail(NSSDOA_EUNSUPPORTED, "scan forms run on NSSDOA_C64 batches");
+    if (batch->any2d || batch->max_M > 32)
+        return fail(NSSDOA_EUNSUPPORTED, "scan forms run on 1-D grids with M <= 32");
+    if (form == NSSDOA_FORM_COMPLEMENT && batch->alg != NSSDOA_MUSIC)
+        return fail(NSSDOA_EUNSUPPORTED, "the complement form is the MUSIC matrix I - E_s E_s^H");
+    if (workspace_bytes < batch->ws_bytes)
+        return fail(NSSDOA_EINVAL, "workspace of %zu bytes < required %zu", workspace_bytes, batch->ws_bytes);
+    if (spectrum_elems < batch->spec_extent)
+        return fail(NSSDOA_EINVAL, "spectrum holds %zu elements, the frames address %zu", spectrum_elems,
+                    batch->spec_extent);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (size_t i = 0; i < batch->peak_ranges.size(); ++i) {
+        const auto& ri = batch->refine_ranges[i];
+        hipError_t e = launch_scan_form(batch->peak_ranges[i].first, batch->d_refine + ri.first, ri.second - ri.first,
+                                        batch->d_frames, batch->d_pos, static_cast<const char*>(workspace), form,
+                                        spectrum, s);
+        if (e != hipSuccess) return hip_fail(e, "scan form launch");
+    }
+    return NSSDOA_OK;
+}
+
 nssdoa_status nssdoa_windowed_workspace_size(nssdoa_batch batch, nssdoa_mlp mlp, size_t* bytes) {
     if (!batch || !bytes) return fail(NSSDOA_EINVAL, "NULL argument");
     int32_t in = 0, width = 0, out = 0, mb = 0;

@@ -548,6 +548,9 @@ hipError_t launch_peaks(bool f64, int bucket_M, const PointItem* items, int n_it
                         int n_frames, const FrameDev* frames, const double* pos, const double2* cis, char* ws,
                         void* spec, const PeakParams& p, void* peaks, int32_t* npeaks, uint32_t* status,
                         hipStream_t s);
+hipError_t launch_scan_form(int bucket_M, const PointItem* items, int n_items, const FrameDev* frames,
+                            const double* pos, const char* ws, int form, float* spec, hipStream_t s);
+
 // 2-D grids: items of 256 points of the frames in flist (one M bucket), then one selection per
 // frame; each frame's ws_cand region holds an FP64 peak map of L doubles.
 constexpr int kPeak2dItem = 256;
