@@ -473,6 +473,75 @@ def scan_forms_leg(fs, db, opeaks_frames=8):
     return out
 
 
+PAPER_TABLE7_MS = {8: {"matlab_svd": 0.018, "eigen_jacobisvd": 0.112, "cusolver_gesvdj": 390.279},
+                   64: {"matlab_svd": 0.836, "eigen_jacobisvd": 29.910, "cusolver_gesvdj": 386.242},
+                   512: {"matlab_svd": 64.283, "eigen_jacobisvd": 18651.0}}
+
+
+def eigensolver_leg(sizes=(8, 16, 32, 64), n_batch=256):
+    """The eigensolver study of Section 5.2 (Tables 6 and 7) for Step-2 on the covariances of the
+    method's frames: each of the library's FP64 Hermitian solvers (bisection + inverse iteration,
+    implicit QL, cyclic Jacobi) at M = 8..64, the latency of one matrix and the time per matrix in
+    a batch (HIP events around the eigen stage, which also adds the chunk partial covariances and
+    builds B), with the Eq. 5 residual ||R - U diag(lambda) U^H|| and ||U^H U - I|| of every matrix
+    read back; host LAPACK (numpy eigh, one thread) beside it at 8, 64 and 512."""
+    import time as _t
+    import torch
+    from threadpoolctl import threadpool_limits
+    from paper_2007_14135_amd import WS_COV, WS_EVALS, WS_EVECS
+    from paper_2007_14135_amd.api import Options
+    from paper_2007_14135_amd.runner import prepare
+    from synth import make_frames
+    stream = torch.cuda.current_stream()
+    out = {"how": "covariances of ULA frames (D = 4, N = 1024, SNR U[0,20] dB, 1 deg grid); eigen stage timed with "
+                  "HIP events; residuals in FP64 on the host from the solver's own output; Frobenius norms relative "
+                  "to ||R||_F", "gpu": {}, "host_lapack": {}, "paper_table7_ms_context": PAPER_TABLE7_MS}
+    for M in sizes:
+        fs = make_frames("c2", n_frames=n_batch, M=M, N=1024, grid_step=1.0, start=2000)
+        fr0 = fs.frames[0]
+        frames = [(0, 0, fr.N, fr.D, int(fs.x_off[f]), int(fs.ld[f])) for f, fr in enumerate(fs.frames)]
+        for meth in (((("bisect", "auto"),) if M <= 16 else ()) + (("ql", "ql"), ("jacobi", "jacobi"))):
+            name, opt = meth
+            res_max = orth_max = 0.0
+            times = {}
+            for n in (1, n_batch):
+                db = prepare([fr0.pos], [(fr0.grid_start, fr0.grid_step, fr0.grid_L, 0)], frames[:n], fs.X_flat,
+                             "music", "c64", 4, options=Options(eig_method=opt), device="cuda:0")
+                db.run(stream)
+                db.batch.set_timing(["eigen"])
+                for _ in range(20):
+                    db.run(stream)
+                ms, k = db.batch.stage_time("eigen")
+                db.batch.set_timing(False)
+                times[n] = ms / k
+                if n == n_batch:
+                    torch.cuda.synchronize()
+                    for f in range(0, n, 8):
+                        R = db.workspace_array(WS_COV, f, M * M, np.complex128).reshape(M, M)
+                        lam = db.workspace_array(WS_EVALS, f, M, np.float64)
+                        U = db.workspace_array(WS_EVECS, f, M * M, np.complex128).reshape(M, M)
+                        res_max = max(res_max, float(np.linalg.norm(R - (U * lam) @ U.conj().T) / np.linalg.norm(R)))
+                        orth_max = max(orth_max, float(np.linalg.norm(U.conj().T @ U - np.eye(M))))
+                del db
+            out["gpu"]["%s_M%d" % (name, M)] = {"ms_one_matrix": times[1], "us_per_matrix_in_batch_of_%d" % n_batch:
+                                                1e3 * times[n_batch] / n_batch, "eq5_residual_rel_max": res_max,
+                                                "orthogonality_max": orth_max}
+    rng = np.random.default_rng(7)
+    with threadpool_limits(1):
+        for M in (8, 64, 512):
+            Xh = (rng.standard_normal((M, 4 * M)) + 1j * rng.standard_normal((M, 4 * M))) / np.sqrt(2.0)
+            R = Xh @ Xh.conj().T / (4 * M)
+            reps = max(3, int(2000 / M))
+            t0 = _t.perf_counter()
+            for _ in range(reps):
+                lam, U = np.linalg.eigh(R)
+            ms = 1e3 * (_t.perf_counter() - t0) / reps
+            out["host_lapack"]["M%d" % M] = {"ms_one_matrix": ms,
+                                            "eq5_residual_rel": float(np.linalg.norm(R - (U * lam) @ U.conj().T)
+                                                                      / np.linalg.norm(R))}
+    return out
+
+
 def c3_leg(fs3, steps, warmup, tune_cache, kernel):
     """The uneven workload: 4096 frames (M 8..64, ULA/UCA, uneven D, N, SNR, grid step) as one
     graph launch with the autotuned scan work-item size."""
@@ -591,6 +660,7 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the paper's 2-D (azimuth x polar angle) leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the pinned-host streaming pipeline leg")
     ap.add_argument("--no-forms", action="store_true", help="skip the alternative scan-form ablation leg")
+    ap.add_argument("--no-eig", action="store_true", help="skip the eigensolver study leg")
     ap.add_argument("--no-compare", action="store_true", help="skip the step with the other C64 scan kernel")
     ap.add_argument("--streams", type=int, default=4,
                     help="batches in flight: step k runs on stream k mod S with its own copy of the snapshots, "
@@ -830,6 +900,8 @@ def main():
         out["streaming_pcie"] = streaming_leg(fs, db)
     if not args.no_forms and args.alg == "music":
         out["scan_forms_ablation"] = scan_forms_leg(fs, db)
+    if not args.no_eig:
+        out["eigensolver_study"] = eigensolver_leg()
     if fs5 is not None:
         del db
         torch.cuda.empty_cache()
