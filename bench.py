@@ -1,8 +1,9 @@
 """Throughput benchmark of the DOA hot path on one MI355X.
 
 One step = one nssdoa_estimate call over the whole batch: covariance, FP64 eigensolve and
-noise-subspace matrix, FP32-accuracy matrix-core spectrum scan (FP16 hi/lo split operands with FP32
-accumulation by default; --c64-scan fp32 for FP32 operands), FP64 low-Q re-evaluation and peak
+noise-subspace matrix, FP32-accuracy matrix-core spectrum scan (by default FP16 split operands of
+three parts, which reproduce every FP32 operand, with FP32 accumulation; --c64-scan fp32 for FP32
+operands, split16 for two parts), FP64 low-Q re-evaluation and peak
 selection, for 256 synthetic frames of the 16-element workload (N = 4096 snapshots, D = 4,
 18000-point grid at 0.01 deg), MUSIC.  Snapshots are resident in HBM before the timed region.
 
@@ -11,7 +12,7 @@ with its own copy of the snapshots, its own workspace and outputs), as a serving
 second, single-stream pass gives the latency of one batch and times the scan kernel alone.
 
 Prints one JSON line with the throughput (spectrum points/s), the same step with the other C64
-scan kernel for comparison, the roofline position of the scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
+scan kernels for comparison, the roofline position of the scan kernel (timed live with HIP events on the launch stream; HBM traffic from the committed
 counter summary while the kernel source is unchanged), the FP64 oracle's throughput on the host
 cores over a bounded sample of the same frames, and, when trained proposal weights are present,
 the learned-proposal workload (8192 frames, 0.001 deg grid) run by the learned path and by the
@@ -40,8 +41,15 @@ METRIC = "MUSIC spectrum points/s & frames/s at ≤0.01° peak err, learned vs f
 WEIGHTS = os.path.join(ROOT, "paper_2007_14135_amd", "weights", "proposal_ula16.npy")
 SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
 PMC_SUMMARY = {"split16": os.path.join(ROOT, "profiles", "scan_split16_c2_music_pmc.txt"),
-               "fp32": os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt")}
-SCAN_KERNEL = {"split16": "scan_split16_kernel<16>", "fp32": "scan_f32_kernel<16>"}
+               "fp32": os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt"),
+               "split3": os.path.join(ROOT, "profiles", "scan_split3_c2_music_pmc.txt")}
+SCAN_KERNEL = {"split16": "scan_split16_kernel<16, 2>", "fp32": "scan_f32_kernel<16>",
+               "split3": "scan_split16_kernel<16, 3>"}
+MFMA_PRODUCTS = {"split16": 3.0, "fp32": 1.0, "split3": 6.0}   # matrix-core products per FP32-accuracy product
+SCAN_DESC = {"fp32": "FP32 operands, FP32 accumulation",
+             "split16": "FP16 split operands of two parts (22-bit operands), FP32 accumulation",
+             "split3": "FP16 split operands of three parts (33-bit operands, every FP32 operand reproduced), "
+                       "six products per FP32-accuracy product, FP32 accumulation"}
 STAGE_KERNEL = {"covariance": "cov_mfma_kernel<float2, 1>", "eigen": "evd_ql_kernel", "scan": None}
 TUNE_CACHE = os.path.join(ROOT, "paper_2007_14135_amd", "tuning", "autotune_cache.json")
 PEAK_FP64_TFLOPS = 78.6
@@ -652,8 +660,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-frames", type=int, default=8192)
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (default work items)")
-    ap.add_argument("--c64-scan", default="fp32", choices=["split16", "fp32"],
-                    help="matrix-core kernel of the complex64 scan (FP32 operands, or the FP16 hi/lo split)")
+    ap.add_argument("--c64-scan", default="split3", choices=["split16", "fp32", "split3"],
+                    help="matrix-core kernel of the complex64 scan (FP32 operands, or FP16 split operands of two or "
+                         "three parts)")
     ap.add_argument("--no-c1", action="store_true", help="skip the FP64 single-frame latency leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096-frame uneven-batch leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 16-bit precision leg")
@@ -776,49 +785,56 @@ def main():
     achieved_tflops = scan_flops / scan_avg_s / 1e12
     points = F * L
     value = points / (ms_step / 1e3)
-    split = args.c64_scan == "split16"
+    split = args.c64_scan != "fp32"
     peak = PEAK_FP16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
-    # matrix-core flops executed: the split forms each product from three FP16 products
-    mfma_flops = scan_flops * (3.0 if split else 1.0)
+    # matrix-core flops executed: a split forms each FP32-accuracy product from 3 or 6 FP16 products
+    mfma_flops = scan_flops * MFMA_PRODUCTS[args.c64_scan]
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
     stage_roof = stage_rooflines(stage_ms, fs.frames, args.alg, peak)
     # the single-kernel stage that takes longest in one step (the peak stage is three kernels)
     dominant = max(("covariance", "eigen", "scan"), key=lambda k: stage_ms[k])
 
-    # the same step with the other C64 scan kernel (its own tuned work items), for comparison
+    # the same step with the other C64 scan kernels (their own tuned work items), for comparison
     other = None
     if not args.no_compare:
-        okern = "fp32" if split else "split16"
-        orows = 0
-        if not args.no_tune:
-            orows, _ = autotune.tune(arrays, grids, frames, fs.X_flat, args.alg, "c64", D,
-                                     cache_path=args.tune_cache or None, options=Options(c64_scan=okern))
-        db2 = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
-                      options=Options(scan_rows=orows, c64_scan=okern), X_device=db.X)
-        dbs2 = in_flight(okern, orows, db2)
-        run_steps(dbs2, max(args.warmup, S))
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        run_steps(dbs2, args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        oms = e0.elapsed_time(e1) / args.steps
-        del dbs2[1:]
-        olat = _timed(lambda: db2.run(stream), args.steps, 1, stream)
-        db2.batch.set_timing(["scan"])
-        for _ in range(min(args.steps, 10)):
-            db2.run(stream)
-        osc, osn = db2.batch.stage_time("scan")
-        db2.batch.set_timing(False)
-        o_avg = osc / max(osn, 1)
-        o_peak = PEAK_FP16_MFMA_TFLOPS if okern == "split16" else PEAK_FP32_MFMA_TFLOPS
-        other = {"c64_scan": okern, "scan_rows": orows or 384, "value": points / (oms / 1e3), "ms_per_step": oms,
-                 "latency_ms_one_batch": olat,
-                 "scan_kernel": SCAN_KERNEL[okern], "scan_avg_launch_ms": o_avg,
-                 "scan_roofline_frac": scan_flops / (o_avg / 1e3) / 1e12 / o_peak, "scan_peak_tflops": o_peak}
-        del db2
+        other = {}
+        for okern in [k for k in ("fp32", "split16", "split3") if k != args.c64_scan]:
+            orows = 0
+            if not args.no_tune:
+                orows, _ = autotune.tune(arrays, grids, frames, fs.X_flat, args.alg, "c64", D,
+                                         cache_path=args.tune_cache or None, options=Options(c64_scan=okern))
+            db2 = prepare(arrays, grids, frames, fs.X_flat, args.alg, "c64", D, device="cuda:0",
+                          options=Options(scan_rows=orows, c64_scan=okern), X_device=db.X)
+            dbs2 = in_flight(okern, orows, db2)
+            run_steps(dbs2, max(args.warmup, S))
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run_steps(dbs2, args.steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            oms = e0.elapsed_time(e1) / args.steps
+            del dbs2[1:]
+            olat = _timed(lambda: db2.run(stream), args.steps, 1, stream)
+            db2.batch.set_timing(["scan"])
+            for _ in range(min(args.steps, 10)):
+                db2.run(stream)
+            osc, osn = db2.batch.stage_time("scan")
+            db2.batch.set_timing(False)
+            o_avg = osc / max(osn, 1)
+            o_peak = PEAK_FP32_MFMA_TFLOPS if okern == "fp32" else PEAK_FP16_MFMA_TFLOPS
+            ores = db2.host_results()
+            other[okern] = {"scan_rows": orows or 384, "value": points / (oms / 1e3), "ms_per_step": oms,
+                            "latency_ms_one_batch": olat, "scan_kernel": SCAN_KERNEL[okern],
+                            "scan_avg_launch_ms": o_avg,
+                            "scan_roofline_frac": scan_flops / (o_avg / 1e3) / 1e12 / o_peak,
+                            "scan_mfma_frac": scan_flops * MFMA_PRODUCTS[okern] / (o_avg / 1e3) / 1e12 / o_peak,
+                            "scan_peak_tflops": o_peak,
+                            "peaks_equal_headline": bool(np.array_equal(ores["npeaks"], res["npeaks"]) and all(
+                                np.array_equal(ores["peaks"][i]["idx"][:n], res["peaks"][i]["idx"][:n])
+                                for i, n in enumerate(res["npeaks"])))}
+            del db2
 
     scan_roofline = {
         "kernel": SCAN_KERNEL[args.c64_scan],
@@ -852,11 +868,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16x3-split/f32-acc" if split else "f32",
-        "dtype_note": ("complex64 snapshots; FP64 covariance accumulation, eigensolve, noise subspace and peak "
-                       "refinement; scan on FP32 operands with FP32 accumulation" if not split else
-                       "complex64 snapshots; FP64 covariance accumulation, eigensolve, noise subspace and peak "
-                       "refinement; scan on FP16 hi/lo parts of the FP32 operands (22-bit operands)"),
+        "dtype": "f16x2-split/f32-acc" if args.c64_scan == "split16" else "f32",
+        "dtype_note": "complex64 snapshots; FP64 covariance accumulation, eigensolve, noise subspace and peak "
+                      "refinement; scan: " + SCAN_DESC[args.c64_scan],
         "data": "synthetic",
         "frames_per_s": F / (ms_step / 1e3),
         "batches_in_flight": S,
@@ -865,8 +879,7 @@ def main():
         "config": {
             "workload": "ULA M=16, D=4, N=4096 complex64 snapshots, SNR U[0,20] dB, 256 frames, "
                         "grid [-90,90) at 0.01 deg (L=18000), %s; FP64 covariance/eigensolve/refinement, "
-                        "FP32-accuracy matrix-core scan (%s)" % (args.alg.upper(),
-                        "FP16 hi/lo split operands, FP32 accumulation" if split else "FP32 operands"),
+                        "FP32-accuracy matrix-core scan (%s)" % (args.alg.upper(), SCAN_DESC[args.c64_scan]),
             "frames": F, "M": M, "D": D, "N": fr0.N, "L": L, "alg": args.alg,
             "scan_rows": rows or 384, "c64_scan": args.c64_scan,
         },
@@ -876,7 +889,7 @@ def main():
         "stage_roofline": stage_roof,
         "dominant_kernel_stage": dominant,
         "roofline": roofline,
-        "other_c64_scan": other,
+        "other_c64_scans": other,
         "host_wall_s": wall,
         "status_nonzero_frames": int(np.count_nonzero(res["status"])),
     }

@@ -154,7 +154,7 @@ typedef struct {
  * Eigenvalue errors of AUTO and QL are of the order of eps ||R||. */
 typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } nssdoa_eig_method;
 
-/* Matrix-core kernel of the C64 (FP32-accuracy) scans of Step-5 (Table 2).  Both form the
+/* Matrix-core kernel of the C64 (FP32-accuracy) scans of Step-5 (Table 2).  All three form the
  * real-embedded product of the B tiles and the FP32 steering values and accumulate in FP32.
  *   NSSDOA_C64_SCAN_SPLIT16: every FP32 operand x is split into FP16 parts x = hi + lo + r with
  *                            |r| <= 2^-22 |x| + 2^-25 (2^-25: half the FP16 subnormal spacing),
@@ -163,10 +163,20 @@ typedef enum { NSSDOA_EIG_AUTO = 0, NSSDOA_EIG_QL = 1, NSSDOA_EIG_JACOBI = 2 } n
  *                            as hi_a hi_b + hi_a lo_b + lo_a hi_b on the FP16 matrix cores
  *                            (v_mfma_f32_32x32x16_f16); the neglected terms are below
  *                            2^-20 |a b| + 2^-25 (|a| + |b|), the order of the FP32 accumulation
- *                            error of the sums they enter.  The default.
+ *                            error of the sums they enter: 22-bit operands, the fastest.
  *   NSSDOA_C64_SCAN_FP32:    FP32 operands on v_mfma_f32_32x32x2f32.
+ *   NSSDOA_C64_SCAN_SPLIT16X3: three FP16 parts per operand, x = hi + mid + lo + r (each part the
+ *                            FP16 rounding of what the earlier parts leave): 33 significant bits,
+ *                            so after the same power-of-two scaling every FP32 steering value is
+ *                            reproduced exactly where |2^13 v| >= 1/2 and to within 2^-25 below,
+ *                            and B (split from its FP64 values) to within 2^-33 |x| + 2^-25, both
+ *                            below the FP32 rounding the FP32-operand kernel applies to them; a b
+ *                            is formed from the six products of parts whose orders add up to at
+ *                            most two (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid; the dropped
+ *                            ones are below 2^-33 |a b|), accumulated in FP32 on the FP16 matrix
+ *                            cores.  At least as accurate as the FP32-operand kernel.  The default.
  * The windowed and learned estimators use the same kernel choice. */
-typedef enum { NSSDOA_C64_SCAN_SPLIT16 = 0, NSSDOA_C64_SCAN_FP32 = 1 } nssdoa_c64_scan;
+typedef enum { NSSDOA_C64_SCAN_SPLIT16X3 = 0, NSSDOA_C64_SCAN_FP32 = 1, NSSDOA_C64_SCAN_SPLIT16 = 2 } nssdoa_c64_scan;
 
 /* Tunables; pass NULL to nssdoa_plan_create for the defaults given here. */
 typedef struct {
@@ -180,9 +190,10 @@ typedef struct {
                                  [32, 16384].  A tuning knob: it moves frames' rows within the
                                  32-row MFMA tiles, so FP32 spectra may change in their last
                                  bits; peaks are re-picked in FP64.  C64 work items hold at most
-                                 65536 / (8 M) rows with FP32 operands, 1024 with the FP16 split */
+                                 65536 / (8 M) rows with FP32 operands, 1024 with FP16 split ones */
     int32_t eig_method;       /* nssdoa_eig_method; NSSDOA_EIG_AUTO                            */
-    int32_t c64_scan;         /* nssdoa_c64_scan: matrix-core kernel of the C64 scans; 0       */
+    int32_t c64_scan;         /* nssdoa_c64_scan: matrix-core kernel of the C64 scans;
+                                 NSSDOA_C64_SCAN_SPLIT16X3 (0)                                  */
 } nssdoa_options;
 
 typedef struct nssdoa_plan_s* nssdoa_plan;

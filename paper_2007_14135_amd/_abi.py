@@ -58,7 +58,7 @@ class Options(ctypes.Structure):
 
 
 EIG_METHODS = {"auto": 0, "ql": 1, "jacobi": 2}
-C64_SCANS = {"split16": 0, "fp32": 1}
+C64_SCANS = {"split3": 0, "fp32": 1, "split16": 2}
 SCAN_FORMS = {"factored": 0, "quadratic": 1, "complement": 2}
 
 

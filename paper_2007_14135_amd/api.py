@@ -33,7 +33,7 @@ class Options:
     """Tunables of nssdoa_options (defaults as documented in the header)."""
 
     def __init__(self, eig_tol=1e-15, eig_max_iter=30, refine_halfwidth=4, lowq_tau=5e-4,
-                 extra_candidates=4, scan_rows=0, eig_method="auto", c64_scan="split16"):
+                 extra_candidates=4, scan_rows=0, eig_method="auto", c64_scan="split3"):
         m = _abi.EIG_METHODS.get(eig_method, eig_method) if isinstance(eig_method, str) else int(eig_method)
         if isinstance(m, str):
             raise ValueError("eig_method must be one of %s" % sorted(_abi.EIG_METHODS))

@@ -21,16 +21,17 @@ import numpy as np
 
 # Revision of the scan kernels the cached choices were measured on; changing the kernels makes
 # old entries miss.
-KERNEL_REV = "scan-5"
+KERNEL_REV = "scan-6"
 
 CANDIDATES = {"c64": (64, 96, 128, 160, 192, 256, 320, 384, 512),
               "c64-split16": (128, 192, 256, 384, 512, 768, 1024),
+              "c64-split3": (128, 192, 256, 384, 512, 768, 1024),
               "bf16": (512, 1024, 2048, 4096, 8192, 16384),
               "f16": (512, 1024, 2048, 4096, 8192, 16384)}
 
 
 def signature(arrays: Sequence[np.ndarray], grids: Sequence[tuple], frames: Sequence[tuple], alg: str,
-              prec: str, kernel: str = "split16") -> str:
+              prec: str, kernel: str = "split3") -> str:
     """A digest of what the scan schedule depends on: per (array, grid) group its M, its L and
     the multiset of noise-subspace ranks K of its frames, plus the algorithm, the precision and
     the C64 scan kernel."""
@@ -93,7 +94,7 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
     if prec == "c128":
         return 0, {}
     dev = device_name()
-    kernel = "split16" if options is None or options.c.c64_scan == 0 else "fp32"
+    kernel = {0: "split3", 1: "fp32", 2: "split16"}[0 if options is None else int(options.c.c64_scan)]
     sig = signature(arrays, grids, frames, alg, prec, kernel)
     cache = Cache(cache_path)
     hit = cache.get(dev, sig)
@@ -101,7 +102,7 @@ def tune(arrays, grids, frames, X_flat, alg: str, prec: str, max_D: int, *, cand
         return hit, {}
     timings = {}
     X_dev = None
-    for rows in (candidates or CANDIDATES["c64-split16" if prec == "c64" and kernel == "split16" else prec]):
+    for rows in (candidates or CANDIDATES["c64-" + kernel if prec == "c64" and kernel != "fp32" else prec]):
         if options is None:
             opt = Options(scan_rows=int(rows))
         else:

@@ -149,7 +149,7 @@ struct nssdoa_batch_s {
     PointItem* d_refine = nullptr;
     double2* d_cis = nullptr;
     float* d_steer = nullptr;                   // steering tables of the C64 scans (batch-owned)
-    bool split16 = false;                       // C64 scans on FP16 split operands
+    int split_parts = 0;                        // C64 scans on FP16 split operands of 2 or 3 parts (0: FP32)
     int live_graphs = 0;                        // graphs and pipelines that use the batch
     // timing
     uint32_t timing = 0;                        // stages with HIP events (bit 1 << stage)
@@ -189,7 +189,7 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
     opt.extra_candidates = 4;
     opt.scan_rows = 0;
     opt.eig_method = NSSDOA_EIG_AUTO;
-    opt.c64_scan = NSSDOA_C64_SCAN_SPLIT16;
+    opt.c64_scan = NSSDOA_C64_SCAN_SPLIT16X3;
     if (options) {
         opt = *options;
         if (!(opt.eig_tol > 0.0 && opt.eig_tol < 1.0))
@@ -206,8 +206,9 @@ nssdoa_status nssdoa_plan_create(nssdoa_plan* plan, const nssdoa_array* arrays, 
             return fail(NSSDOA_EINVAL, "extra_candidates must be in [0, 16]");
         if (opt.scan_rows != 0 && (opt.scan_rows < 32 || opt.scan_rows > 16384 || opt.scan_rows % 32 != 0))
             return fail(NSSDOA_EINVAL, "scan_rows must be 0 or a multiple of 32 in [32, 16384]");
-        if (opt.c64_scan != NSSDOA_C64_SCAN_SPLIT16 && opt.c64_scan != NSSDOA_C64_SCAN_FP32)
-            return fail(NSSDOA_EINVAL, "c64_scan must be NSSDOA_C64_SCAN_SPLIT16 or NSSDOA_C64_SCAN_FP32");
+        if (opt.c64_scan != NSSDOA_C64_SCAN_SPLIT16 && opt.c64_scan != NSSDOA_C64_SCAN_FP32 &&
+            opt.c64_scan != NSSDOA_C64_SCAN_SPLIT16X3)
+            return fail(NSSDOA_EINVAL, "c64_scan must be NSSDOA_C64_SCAN_SPLIT16X3, _FP32 or _SPLIT16");
     }
     auto* p = new (std::nothrow) nssdoa_plan_s();
     if (!p) return fail(NSSDOA_ENOMEM, "host allocation failed");
@@ -331,7 +332,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
     b->n_frames = n_frames;
     b->max_D = max_D;
     b->spec_elem = prec == NSSDOA_C128 ? sizeof(double) : sizeof(float);
-    b->split16 = prec == NSSDOA_C64 && plan->opt.c64_scan == NSSDOA_C64_SCAN_SPLIT16;
+    b->split_parts = prec != NSSDOA_C64 ? 0 : plan->opt.c64_scan == NSSDOA_C64_SCAN_SPLIT16 ? 2
+                   : plan->opt.c64_scan == NSSDOA_C64_SCAN_SPLIT16X3 ? 3 : 0;
 
     // positions table (one copy per array)
     std::vector<int> pos_off(n_arr);
@@ -450,13 +452,14 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         // per work item at a cost comparable to 64 tiles of their MFMA work, so they take
         // longer chunks
         const int chunk_rows_req = plan->opt.scan_rows > 0 ? plan->opt.scan_rows : lp ? kChunkRowsLP : kChunkRows;
-        const size_t emb_elem = lp ? 2 : sizeof(float);
+        // bytes per operand value: 16-bit, FP32, or P FP16 parts
+        const size_t emb_elem = lp ? 2 : b->split_parts ? 2 * b->split_parts : sizeof(float);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             GroupDev& gd = b->groups[g];
             // the FP32 scan stages a work item's rows in LDS (8M bytes per row); the FP16 split
             // scan keeps only its per-block tables there (kScanMaxBlocks 8-row blocks)
             const int chunk_rows = lp ? chunk_rows_req
-                                 : b->split16 ? std::min(chunk_rows_req, kScanMaxBlocks * 8)
+                                 : b->split_parts ? std::min(chunk_rows_req, kScanMaxBlocks * 8)
                                               : std::min(chunk_rows_req, (int)(kScanLdsBytes / (8 * gd.M)) / 32 * 32);
             int row = 0, chunk_start = 0, chunk_frames = 0;
             std::vector<std::pair<int, int>> chunks;
@@ -493,9 +496,9 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             if (!lp) {
                 gd.steer_off = steer_floats;
                 steer_floats += (steer_table_floats(gd.M, gd.L) + 63) / 64 * 64;
-                if (b->split16) {   // the split table holds as many bytes as the FP32 one
+                if (b->split_parts) {   // P FP16 parts: P / 2 times the bytes of the FP32 table
                     gd.steer_x16_off = steer_floats;
-                    steer_floats += (steer_table_floats(gd.M, gd.L) + 63) / 64 * 64;
+                    steer_floats += (steer_table_floats(gd.M, gd.L) * b->split_parts / 2 + 63) / 64 * 64;
                 }
             }
             const int n_at = (gd.L + kScanAnglesPerWG - 1) / kScanAnglesPerWG;
@@ -638,7 +641,8 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
         if (gd.steer_off < 0) continue;
         e = launch_steer_table(b->d_pos + gd.pos_off, gd, b->d_steer + gd.steer_off, nullptr);
         if (e == hipSuccess && gd.steer_x16_off >= 0)
-            e = launch_steer_table_split16(b->d_pos + gd.pos_off, gd, b->d_steer + gd.steer_x16_off, nullptr);
+            e = launch_steer_table_split16(b->split_parts, b->d_pos + gd.pos_off, gd, b->d_steer + gd.steer_x16_off,
+                                           nullptr);
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -865,7 +869,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
     ep.max_iter = opt.eig_max_iter;
     ep.method = opt.eig_method;
     // operand tiles of the scans: FP32, FP16 split, BF16, FP16
-    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split16 ? 4 : 1)
+    ep.write_emb = c128 ? 0 : batch->prec == NSSDOA_C64 ? (batch->split_parts == 3 ? 5 : batch->split_parts ? 4 : 1)
                                                          : batch->prec == NSSDOA_BF16 ? 2 : 3;
     for (const auto* ranges : {&batch->peak_ranges, &batch->p2d_ranges}) {
         for (auto& r : *ranges) {
@@ -907,7 +911,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if ((st = stage_end(NSSDOA_STAGE_PROPOSAL)) != NSSDOA_OK) return st;
 
         if ((st = stage_begin(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
-        e = launch_scan_windows(batch->split16, M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
+        e = launch_scan_windows(batch->split_parts, M, batch->d_frames, F, batch->d_groups, batch->d_blk, batch->d_steer, ws, lay,
                                 static_cast<float*>(spec), use_user, (float)opt.lowq_tau, persistent_grid(8), s);
         if (e != hipSuccess) return hip_fail(e, "windowed scan launch");
         if ((st = stage_end(NSSDOA_STAGE_SCAN)) != NSSDOA_OK) return st;
@@ -937,7 +941,7 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         }
         e = launch_expand(batch->d_frames, F, ws, lay, s);
         if (e == hipSuccess)
-            e = launch_scan_windows(batch->split16, M, batch->d_frames, F, batch->d_groups, batch->d_blk,
+            e = launch_scan_windows(batch->split_parts, M, batch->d_frames, F, batch->d_groups, batch->d_blk,
                                     batch->d_steer, ws, lay, static_cast<float*>(spec), use_user,
                                     (float)opt.lowq_tau, persistent_grid(8), s);
         if (e == hipSuccess)
@@ -961,8 +965,8 @@ nssdoa_status estimate_impl(nssdoa_batch batch, const void* X, size_t x_elems, v
         if (e != hipSuccess) return hip_fail(e, "FP64 scan launch");
     } else {
         for (auto& r : batch->scan_ranges) {
-            if (batch->prec == NSSDOA_C64 && batch->split16)
-                e = launch_scan_split16(r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
+            if (batch->prec == NSSDOA_C64 && batch->split_parts)
+                e = launch_scan_split16(batch->split_parts, r.first, batch->d_scan + r.second.first, r.second.second - r.second.first,
                                         batch->scan_max_tiles[&r - &batch->scan_ranges[0]],
                                         batch->d_groups, batch->d_frames, batch->d_blk, batch->d_steer, ws,
                                         static_cast<float*>(spec), use_user, (float)opt.lowq_tau, lql, s);

@@ -675,7 +675,7 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         const GroupDev& g = groups[fr.group];
         const int rows = fr.emb_rows, inner = 2 * M;
         double bscale = 1.0;
-        if (prm.write_emb == 4) {
+        if (prm.write_emb >= 4) {
             double mx = 0.0;
             for (int e = tid; e < M * K; e += bd) mx = fmax(mx, fmax(fabs(Bs[e].x), fabs(Bs[e].y)));
             mx = block_max(mx, red);
@@ -685,14 +685,16 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                 qref[1] = 1.0 / (sab * sab);
             }
         }
-        if (prm.write_emb == 4) {
-            // FP16 split: eight consecutive inner indices (one lane's 16-byte operand) per thread
+        if (prm.write_emb >= 4) {
+            // FP16 split of P parts from the FP64 values: part p = fp16(x_p), x_(p+1) = x_p - part p
+            // (exact in FP64); eight consecutive inner indices (one lane's 16-byte operand) per thread
             typedef _Float16 halfx8v __attribute__((ext_vector_type(8)));
             halfx8v* o8 = reinterpret_cast<halfx8v*>(ws + g.ws_emb);
+            const int P = prm.write_emb == 5 ? 3 : 2;
             for (int u = tid; u < rows * (inner / 8); u += bd) {
                 const int rl = u / (inner / 8), kk0 = (u - rl * (inner / 8)) * 8;
                 const int col = rl >> 1, re = kk0 < M, m0 = re ? kk0 : kk0 - M;
-                halfx8v hi8, lo8;
+                halfx8v part8[3];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     double vd = 0.0;
@@ -701,14 +703,16 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                         vd = (rl & 1) == 0 ? (re ? bv.x : bv.y) : (re ? -bv.y : bv.x);
                     }
                     vd *= bscale;
-                    const _Float16 hi = (_Float16)vd;
-                    hi8[t] = hi;
-                    lo8[t] = (_Float16)(vd - (double)hi);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const _Float16 x = (_Float16)vd;
+                        part8[q][t] = x;
+                        vd -= (double)x;
+                    }
                 }
                 const int r = fr.emb_row0 + rl, tile = r >> 5, i = r & 31;
-                const size_t o0 = ((size_t)tile * 2 * (M / 8) + (kk0 >> 4)) * 64 + ((kk0 >> 3) & 1) * 32 + i;
-                o8[o0] = hi8;
-                o8[o0 + (size_t)(M / 8) * 64] = lo8;
+                const size_t o0 = ((size_t)tile * P * (M / 8) + (kk0 >> 4)) * 64 + ((kk0 >> 3) & 1) * 32 + i;
+                for (int q = 0; q < P; ++q) o8[o0 + (size_t)q * (M / 8) * 64] = part8[q];
             }
         } else
         for (int e = tid; e < rows * inner; e += bd) {

@@ -69,11 +69,11 @@ struct GroupDev {
     double el_start, el_step;
 };
 
-// Split steering table of a group for the FP16 split scan (same rows as the FP32 table, same
-// bytes): for grid index l, part p (0: hi, 1: lo) and h = 0, 1, the M halves at
-// ((4 l + 2 p + h) M + 8 s + t) hold part p of 2^13 v for the inner index k = 16 s + 8 h + t of
+// Split steering table of a group for the FP16 split scans of P parts (P = 2: the bytes of the
+// FP32 table; P = 3: 1.5 times them): for grid index l, part p < P and h = 0, 1, the M halves at
+// ((2 P l + 2 p + h) M + 8 s + t) hold part p of 2^13 v for the inner index k = 16 s + 8 h + t of
 // the real-embedded steering vector (v = Re a_k for k < M, Im a_(k-M) otherwise, the FP32 value
-// of the FP32 table): hi = fp16(2^13 v), lo = fp16(2^13 v - hi).
+// of the FP32 table): x_0 = 2^13 v, part p = fp16(x_p), x_(p+1) = x_p - part p (exact in FP32).
 constexpr float kSplitSteerScale = 8192.0f;
 
 // Low-Q floor of the 16-bit scans.  With both operands rounded to 16 bits (unit roundoff u:
@@ -112,7 +112,8 @@ struct EvdParams {
     double tol;
     int32_t max_iter;           // Jacobi: sweeps; QL: iterations per eigenvalue
     int32_t method;             // nssdoa_eig_method
-    int32_t write_emb;          // packed B tiles for the scan: 0 none, 1 FP32, 2 BF16, 3 FP16
+    int32_t write_emb;          // packed B tiles for the scan: 0 none, 1 FP32, 2 BF16, 3 FP16,
+                                // 4 FP16 split of 2 parts, 5 FP16 split of 3 parts
 };
 
 struct PeakParams {
@@ -520,7 +521,7 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
                       const FrameDev* frames, const GroupDev* groups, char* ws, uint32_t* status,
                       hipStream_t s);
 hipError_t launch_steer_table(const double* pos, const GroupDev& g, float* table, hipStream_t s);
-hipError_t launch_steer_table_split16(const double* pos, const GroupDev& g, float* table, hipStream_t s);
+hipError_t launch_steer_table_split16(int parts, const double* pos, const GroupDev& g, float* table, hipStream_t s);
 constexpr size_t kScanLdsBytes = 65536;            // B tiles of one FP32 scan work item in LDS
 constexpr int kScanMaxBlocks = kScanLdsBytes / (64 * 8 * 4) * 4;   // 8-row blocks of one, M >= 8
 // Low-Q list of a batch: an int count (reset by the covariance launch), then cap (frame, index).
@@ -532,9 +533,10 @@ struct LowqList {
 hipError_t launch_scan_f32(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
                            const FrameDev* frames, const int32_t* blkframe, const float* steer,
                            char* ws, float* spec, int use_user_spec, float lowq_tau, LowqList lq, hipStream_t s);
-hipError_t launch_scan_split16(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
-                               const FrameDev* frames, const int32_t* blkframe, const float* steer,
-                               char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s);
+hipError_t launch_scan_split16(int parts, int M, const ScanItem* items, int n_items, int max_tiles,
+                               const GroupDev* groups, const FrameDev* frames, const int32_t* blkframe,
+                               const float* steer, char* ws, float* spec, int use_user, float tau, LowqList lq,
+                               hipStream_t s);
 hipError_t launch_scan_lp(bool f16, int M, const ScanItem* items, int n_items, const GroupDev* groups,
                           const FrameDev* frames, const int32_t* blkframe, const double* pos, char* ws,
                           float* spec, int use_user, float lowq_tau, LowqList lq, hipStream_t s);
@@ -576,7 +578,7 @@ hipError_t launch_proposals(const FrameDev* frames, int n_frames, const float* s
 hipError_t launch_rescue(const FrameDev* frames, const int32_t* frame_list, int n_list, const int32_t* npeaks,
                          uint32_t* status, char* ws, const LearnedLayout& lay, int32_t* rescue, hipStream_t s);
 hipError_t launch_expand(const FrameDev* frames, int n_frames, char* ws, const LearnedLayout& lay, hipStream_t s);
-hipError_t launch_scan_windows(bool split16, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+hipError_t launch_scan_windows(int parts, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
                                const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s);
 hipError_t launch_window_peaks(int bucket_M, const FrameDev* frames, int n_frames, const double* pos,

@@ -12,10 +12,10 @@
 // prefix_kernel, one workgroup: exclusive prefix sums of per-frame counts (a block scan);
 // expand_kernel, one wave per frame: the frame's scan items and peak chunks written out at those
 //   offsets, so that the kernels below read their work item with one load.
-// scan_win_kernel<M, SPLIT>, grid-stride over 64-angle items, one wave per item: one frame's
+// scan_win_kernel<M, PARTS>, grid-stride over 64-angle items, one wave per item: one frame's
 //   angles in one window, contracted on the matrix cores with the frame's own 8-row blocks of the
 //   packed B tiles (the operands, steering tables and epilogue of the group scans: FP32 operands,
-//   or FP16 split operands with three products per FP32-accuracy product).
+//   or FP16 split operands of 2 or 3 parts with 3 or 6 products per FP32-accuracy product).
 // lowq_win_kernel<MB>, grid-stride over 64-entry slices of the frames' low-Q lists: FP64
 //   re-evaluation of the listed points.
 // winpeaks_kernel<MB>, grid-stride over 4096-point chunks of the windows, one workgroup per
@@ -283,7 +283,22 @@ __device__ inline void steering_load_w(const float* __restrict__ T, int l, int h
     }
 }
 
-template <int M, bool SPLIT>
+// FP32-accuracy products of the split parts kept (see scan_split16_kernel): P = 2 or 3.
+template <int P>
+__device__ __forceinline__ void win_split_mfma(const halfx8* bp, const halfx8* s0, const halfx8* s1, floatx16& a0,
+                                               floatx16& a1) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (i + j <= P - 1) {
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bp[i], s0[j], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bp[i], s1[j], a1, 0, 0, 0);
+            }
+}
+
+// PARTS: 0 = FP32 operands, 2 or 3 = FP16 split operands of that many parts
+template <int M, int PARTS>
 __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restrict__ frames, int n_frames,
                                                        const GroupDev* __restrict__ groups,
                                                        const int32_t* __restrict__ blkframe,
@@ -317,36 +332,29 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
                       acc1[4 * gq + 2] * acc1[4 * gq + 2] + acc1[4 * gq + 3] * acc1[4 * gq + 3];
             }
         };
-        if constexpr (SPLIT) {
-            halfx8 sh0[S], sl0[S], sh1[S], sl1[S];
+        if constexpr (PARTS > 0) {
+            constexpr int P = PARTS;
+            halfx8 st0[S][P], st1[S][P];
             const _Float16* T = reinterpret_cast<const _Float16*>(steer + g.steer_x16_off);
-            const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (a0 + j) + h) * M);
-            const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (a0 + 32 + j) + h) * M);
+            const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)2 * P * (a0 + j) + h) * M);
+            const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)2 * P * (a0 + 32 + j) + h) * M);
 #pragma unroll
-            for (int s2 = 0; s2 < S; ++s2) {
-                sh0[s2] = p0[s2];
-                sl0[s2] = p0[2 * S + s2];
-                sh1[s2] = p1[s2];
-                sl1[s2] = p1[2 * S + s2];
-            }
+            for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    st0[s2][q] = p0[2 * S * q + s2];
+                    st1[s2][q] = p1[2 * S * q + s2];
+                }
             const halfx8* emb = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + lane;   // [tile][part][S][64]
             for (int t = t0; t < t1; ++t) {
-                halfx8 bh[S], bl[S];
+                halfx8 bp[S][P];
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) {
-                    bh[s2] = emb[((size_t)t * 2 * S + s2) * 64];
-                    bl[s2] = emb[((size_t)t * 2 * S + S + s2) * 64];
-                }
+                for (int s2 = 0; s2 < S; ++s2)
+#pragma unroll
+                    for (int q = 0; q < P; ++q) bp[s2][q] = emb[((size_t)t * P * S + q * S + s2) * 64];
                 floatx16 acc0 = {0.0f}, acc1 = {0.0f};
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) {
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sh0[s2], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sh1[s2], acc1, 0, 0, 0);
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sl0[s2], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s2], sl1[s2], acc1, 0, 0, 0);
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], sh0[s2], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s2], sh1[s2], acc1, 0, 0, 0);
-                }
+                for (int s2 = 0; s2 < S; ++s2) win_split_mfma<P>(bp[s2], st0[s2], st1[s2], acc0, acc1);
                 fold(acc0, acc1, t);
             }
         } else {
@@ -373,7 +381,7 @@ __global__ __launch_bounds__(256) void scan_win_kernel(const FrameDev* __restric
             }
         }
         const float u0 = q0 + __shfl_xor(q0, 32), u1 = q1 + __shfl_xor(q1, 32);
-        const float v = ((lane < 32) ? u0 : u1) * (SPLIT ? (float)qr[1] : 1.0f);
+        const float v = ((lane < 32) ? u0 : u1) * (PARTS > 0 ? (float)qr[1] : 1.0f);
         const int l = a0 + lane;
         const bool in = l < a1;
         if (in) {
@@ -539,16 +547,19 @@ hipError_t launch_rescue(const FrameDev* frames, const int32_t* frame_list, int 
     return hipGetLastError();
 }
 
-hipError_t launch_scan_windows(bool split16, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
+hipError_t launch_scan_windows(int parts, int M, const FrameDev* frames, int n_frames, const GroupDev* groups,
                                const int32_t* blkframe, const float* steer, char* ws, const LearnedLayout& lay,
                                float* spec, int use_user, float lowq_tau, int n_wg, hipStream_t s) {
 #define NSSDOA_WIN_CASE(MM)                                                                                   \
     case MM:                                                                                               \
-        if (split16)                                                                                       \
-            hipLaunchKernelGGL((scan_win_kernel<MM, true>), dim3(n_wg), dim3(256), 0, s, frames, n_frames,  \
+        if (parts == 3)                                                                                    \
+            hipLaunchKernelGGL((scan_win_kernel<MM, 3>), dim3(n_wg), dim3(256), 0, s, frames, n_frames,     \
+                               groups, blkframe, steer, ws, lay, spec, use_user, lowq_tau);                 \
+        else if (parts == 2)                                                                               \
+            hipLaunchKernelGGL((scan_win_kernel<MM, 2>), dim3(n_wg), dim3(256), 0, s, frames, n_frames,     \
                                groups, blkframe, steer, ws, lay, spec, use_user, lowq_tau);                 \
         else                                                                                               \
-            hipLaunchKernelGGL((scan_win_kernel<MM, false>), dim3(n_wg), dim3(256), 0, s, frames, n_frames, \
+            hipLaunchKernelGGL((scan_win_kernel<MM, 0>), dim3(n_wg), dim3(256), 0, s, frames, n_frames,     \
                                groups, blkframe, steer, ws, lay, spec, use_user, lowq_tau);                 \
         return hipGetLastError();
     switch (M) {

@@ -50,8 +50,9 @@ __global__ void steer_table_kernel(const double* __restrict__ pos, GroupDev g, i
     T[(size_t)(2 * l + h) * M + M / 2 + j] = s;
 }
 
-// One thread per (angle, element): the FP16 split steering table (layout in internal.h) from the
-// same FP32 values as steer_table_kernel.
+// One thread per (angle, element): the FP16 split steering table of P parts (layout in
+// internal.h) from the same FP32 values as steer_table_kernel.
+template <int P>
 __global__ void steer_split_kernel(const double* __restrict__ pos, GroupDev g, int Lpad, _Float16* __restrict__ T) {
     const int M = g.M;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,14 +64,16 @@ __global__ void steer_split_kernel(const double* __restrict__ pos, GroupDev g, i
         sincospif((float)(2.0 * (c - rint(c))), &s, &co);
     }
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {   // inner k = m (Re a_m) and k = M + m (Im a_m)
-        const int k = part == 0 ? m : M + m;
-        const float v = (part == 0 ? co : s) * kSplitSteerScale;   // exact: a power of two
-        const _Float16 hi = (_Float16)v;
-        const _Float16 lo = (_Float16)(v - (float)hi);               // v - hi is exact in FP32
+    for (int c = 0; c < 2; ++c) {            // inner k = m (Re a_m) and k = M + m (Im a_m)
+        const int k = c == 0 ? m : M + m;
+        float v = (c == 0 ? co : s) * kSplitSteerScale;             // exact: a power of two
         const int s16 = k >> 4, h = (k >> 3) & 1, tt = k & 7;
-        T[((size_t)4 * l + h) * M + 8 * s16 + tt] = hi;
-        T[((size_t)4 * l + 2 + h) * M + 8 * s16 + tt] = lo;
+#pragma unroll
+        for (int part = 0; part < P; ++part) {
+            const _Float16 x = (_Float16)v;
+            v -= (float)x;                                           // exact in FP32
+            T[((size_t)2 * P * l + 2 * part + h) * M + 8 * s16 + tt] = x;
+        }
     }
 }
 
@@ -203,7 +206,23 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 // Operand layout (D[i][j] += sum_k A[i][k] B[k][j], k < 16 per step s): lane h*32+i holds
 // A[i][16s + 8h .. 16s + 8h + 7] (B rows) and lane h*32+j holds B[16s + 8h .. +7][j] (steering);
 // the result layout is that of the FP32 32x32 instruction.
-template <int M>
+// Products of the parts that the split keeps: with P = 2, hi hi + hi lo + lo hi; with P = 3,
+// every pair of parts whose orders add up to at most 2 (hi hi, hi mid, mid hi, hi lo, lo hi,
+// mid mid), so the dropped products are below 2^-33 of |a b| (their orders add up to 3 or more).
+template <int P>
+__device__ __forceinline__ void split_mfma(const halfx8* bp, const halfx8* s0, const halfx8* s1, floatx16& a0,
+                                           floatx16& a1) {
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (i + j <= P - 1) {
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bp[i], s0[j], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bp[i], s1[j], a1, 0, 0, 0);
+            }
+}
+
+template <int M, int P>
 __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __restrict__ items,
                                                            const GroupDev* __restrict__ groups,
                                                            const FrameDev* __restrict__ frames,
@@ -221,19 +240,19 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     const int base = it.angle_tile * kScanAnglesPerWG + wave * kScanAnglesPerWave;
     const int gL = g.L;
 
-    halfx8 sh0[S], sl0[S], sh1[S], sl1[S];
+    halfx8 st0[S][P], st1[S][P];             // steering parts of the two column tiles
     {
         const _Float16* T = reinterpret_cast<const _Float16*>(steer + g.steer_x16_off);
         const int j = lane & 31;
-        const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (base + j) + h) * M);
-        const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)4 * (base + 32 + j) + h) * M);
+        const halfx8* p0 = reinterpret_cast<const halfx8*>(T + ((size_t)2 * P * (base + j) + h) * M);
+        const halfx8* p1 = reinterpret_cast<const halfx8*>(T + ((size_t)2 * P * (base + 32 + j) + h) * M);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            sh0[s] = p0[s];
-            sl0[s] = p0[2 * S + s];          // part 1 is 2M halves further
-            sh1[s] = p1[s];
-            sl1[s] = p1[2 * S + s];
-        }
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                st0[s][q] = p0[2 * S * q + s];   // part q is 2qM halves further
+                st1[s][q] = p1[2 * S * q + s];
+            }
     }
 
     __shared__ ScanLowq lq;
@@ -242,17 +261,16 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     __shared__ float bqs[kScanMaxBlocks];
     __shared__ int64_t bso[kScanMaxBlocks];
     __shared__ int* bflag[kScanMaxBlocks];
-    constexpr int kTile8 = 2 * S * 64;                       // halfx8 per 32-row tile (both parts)
+    constexpr int kTile8 = P * S * 64;                       // halfx8 per 32-row tile (all parts)
     const int nblk = (it.t1 - it.t0) * 4;
     // B tiles: each wave reads them from global memory (L2) itself, one tile ahead
     const halfx8* emb = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + lane;
-    halfx8 nh[S], nl[S];
+    halfx8 nb[S][P];
     if (it.t0 < it.t1) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            nh[s] = emb[(size_t)it.t0 * kTile8 + s * 64];
-            nl[s] = emb[(size_t)it.t0 * kTile8 + (S + s) * 64];
-        }
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)it.t0 * kTile8 + (q * S + s) * 64];
     }
     if (threadIdx.x == 0) lq.n = 0;
     {
@@ -282,29 +300,20 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     };
 
     for (int t = it.t0; t < it.t1; ++t) {
-        halfx8 bh[S], bl[S];
+        halfx8 bp[S][P];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            bh[s] = nh[s];
-            bl[s] = nl[s];
-        }
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int q = 0; q < P; ++q) bp[s][q] = nb[s][q];
         if (t + 1 < it.t1) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                nh[s] = emb[(size_t)(t + 1) * kTile8 + s * 64];
-                nl[s] = emb[(size_t)(t + 1) * kTile8 + (S + s) * 64];
-            }
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)(t + 1) * kTile8 + (q * S + s) * 64];
         }
         floatx16 a0 = {0.0f}, a1 = {0.0f};
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sh0[s], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sh1[s], a1, 0, 0, 0);
-            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sl0[s], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bh[s], sl1[s], a1, 0, 0, 0);
-            a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s], sh0[s], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bl[s], sh1[s], a1, 0, 0, 0);
-        }
+        for (int s = 0; s < S; ++s) split_mfma<P>(bp[s], st0[s], st1[s], a0, a1);
         const int b0 = (t - it.t0) * 4;
         const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
         const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
@@ -330,12 +339,15 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
 }
 
 template <int M>
-hipError_t launch_split(const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
+hipError_t launch_split(int parts, const ScanItem* items, int n_items, const GroupDev* groups,
                         const FrameDev* frames, const int32_t* blkframe, const float* steer, char* ws, float* spec,
                         int use_user, float tau, LowqList lq, hipStream_t s) {
-    (void)max_tiles;
-    hipLaunchKernelGGL(scan_split16_kernel<M>, dim3(n_items), dim3(256), 0, s, items, groups, frames,
-                       blkframe, steer, ws, spec, use_user, tau, lq);
+    if (parts == 3)
+        hipLaunchKernelGGL((scan_split16_kernel<M, 3>), dim3(n_items), dim3(256), 0, s, items, groups, frames,
+                           blkframe, steer, ws, spec, use_user, tau, lq);
+    else
+        hipLaunchKernelGGL((scan_split16_kernel<M, 2>), dim3(n_items), dim3(256), 0, s, items, groups, frames,
+                           blkframe, steer, ws, spec, use_user, tau, lq);
     return hipGetLastError();
 }
 
@@ -358,24 +370,29 @@ hipError_t launch_steer_table(const double* pos, const GroupDev& g, float* table
     return hipGetLastError();
 }
 
-hipError_t launch_steer_table_split16(const double* pos, const GroupDev& g, float* table, hipStream_t s) {
+hipError_t launch_steer_table_split16(int parts, const double* pos, const GroupDev& g, float* table, hipStream_t s) {
     const int Lpad = steer_table_rows(g.L);
     const int64_t n = (int64_t)Lpad * g.M;
-    hipLaunchKernelGGL(steer_split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, g, Lpad,
-                       reinterpret_cast<_Float16*>(table));
+    if (parts == 3)
+        hipLaunchKernelGGL(steer_split_kernel<3>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, g, Lpad,
+                           reinterpret_cast<_Float16*>(table));
+    else
+        hipLaunchKernelGGL(steer_split_kernel<2>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, g, Lpad,
+                           reinterpret_cast<_Float16*>(table));
     return hipGetLastError();
 }
 
-hipError_t launch_scan_split16(int M, const ScanItem* items, int n_items, int max_tiles, const GroupDev* groups,
-                               const FrameDev* frames, const int32_t* blkframe, const float* steer,
-                               char* ws, float* spec, int use_user, float tau, LowqList lq, hipStream_t s) {
+hipError_t launch_scan_split16(int parts, int M, const ScanItem* items, int n_items, int max_tiles,
+                               const GroupDev* groups, const FrameDev* frames, const int32_t* blkframe,
+                               const float* steer, char* ws, float* spec, int use_user, float tau, LowqList lq,
+                               hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (max_tiles * 4 > kScanMaxBlocks) return hipErrorInvalidValue;
+    if (max_tiles * 4 > kScanMaxBlocks || (parts != 2 && parts != 3)) return hipErrorInvalidValue;
     switch (M) {
-        case 8: return launch_split<8>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
-        case 16: return launch_split<16>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
-        case 32: return launch_split<32>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
-        case 64: return launch_split<64>(items, n_items, max_tiles, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 8: return launch_split<8>(parts, items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 16: return launch_split<16>(parts, items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 32: return launch_split<32>(parts, items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
+        case 64: return launch_split<64>(parts, items, n_items, groups, frames, blkframe, steer, ws, spec, use_user, tau, lq, s);
         default: return hipErrorInvalidValue;
     }
 }

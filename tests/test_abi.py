@@ -62,7 +62,7 @@ def test_plan_rejects_invalid(arrays, grids, msg):
     assert e.value.status == _abi.EINVAL, msg
 
 
-@pytest.mark.parametrize("kw", [dict(eig_tol=0.0), dict(eig_max_iter=0), dict(eig_method=3), dict(c64_scan=2), dict(refine_halfwidth=0),
+@pytest.mark.parametrize("kw", [dict(eig_tol=0.0), dict(eig_max_iter=0), dict(eig_method=3), dict(c64_scan=3), dict(refine_halfwidth=0),
                                 dict(refine_halfwidth=17), dict(lowq_tau=-1.0), dict(extra_candidates=17),
                                 dict(scan_rows=16), dict(scan_rows=100), dict(scan_rows=32768)])
 def test_plan_rejects_bad_options(kw):

@@ -178,16 +178,41 @@ def test_eigensolver_iteration_limit_sets_status():
         assert np.all(res["status"] & ST_EVD_NOT_CONVERGED), (method, res["status"])
 
 
-@pytest.mark.parametrize("kernel", ["split16", "fp32"])
+@pytest.mark.parametrize("kernel", ["split16", "fp32", "split3"])
 @pytest.mark.parametrize("alg", ["music", "ev", "mn", "phd"])
 def test_c2_frames_fp32_scan_parity(alg, kernel):
     # 12 frames of the 16-element workload at its full 18000-point grid (71 angle tiles, ragged
-    # last tile) and full 4096 snapshots, on both C64 scan kernels (FP16 split, FP32 operands).
+    # last tile) and full 4096 snapshots, on the three C64 scan kernels (FP16 split of two parts,
+    # FP32 operands, FP16 split of three parts).
     from paper_2007_14135_amd.api import Options
     fs = make_frames("c2", n_frames=12)
     db, res = _run(fs, alg, "c64", options=Options(c64_scan=kernel))
     assert np.all(res["status"] == 0), res["status"]
     _check_frames(fs, res, alg, 1e-4, 1e-8, "c2-%s-%s" % (alg, kernel))
+
+
+@pytest.mark.parametrize("alg", ["music", "phd"])
+def test_three_part_split_at_least_as_accurate_as_fp32_operands(alg):
+    # the FP16 split of three parts against the FP32-operand kernel on the same 12 frames: the
+    # relative spectrum error against the oracle at the points the scan writes unrefined (Q above
+    # the FP64 re-evaluation threshold), worst case and 99th percentile
+    from paper_2007_14135_amd.api import Options
+    fs = make_frames("c2", n_frames=12, start=100)
+    errs = {}
+    for kernel in ("fp32", "split3"):
+        db, res = _run(fs, alg, "c64", options=Options(c64_scan=kernel))
+        e = []
+        for f, fr in enumerate(fs.frames):
+            est = oracle_frame(fr, alg)
+            keep = est.Q >= 5e-4 * np.sum(np.abs(est.B) ** 2)
+            e.append(spectrum_rel_err(res["spectra"][f], est)[keep])
+        e = np.concatenate(e)
+        errs[kernel] = (float(e.max()), float(np.percentile(e, 99)), float(e.mean()))
+    print("unrefined points, relative error max / p99 / mean: FP32 operands %.2e / %.2e / %.2e, "
+          "three-part split %.2e / %.2e / %.2e" % (errs["fp32"] + errs["split3"]), flush=True)
+    assert errs["split3"][0] <= 1.25 * errs["fp32"][0]
+    assert errs["split3"][1] <= 1.25 * errs["fp32"][1]
+    assert errs["split3"][2] <= 1.25 * errs["fp32"][2]
 
 
 @pytest.mark.parametrize("alg", ["phd", "music", "ev", "mn"])
@@ -198,7 +223,7 @@ def test_c1_fp64_parity(alg):
     _check_frames(fs, res, alg, 1e-9, 1e-9, "c1-" + alg)
 
 
-@pytest.mark.parametrize("kernel", ["split16", "fp32"])
+@pytest.mark.parametrize("kernel", ["split16", "fp32", "split3"])
 def test_uneven_frames_chunking_and_groups(kernel):
     # Mixed M, geometry, D and grid in one batch: several groups, several launches, ragged
     # row chunks (K varies, rows padded to 8), M-bucketed peak kernels; both C64 scan kernels.

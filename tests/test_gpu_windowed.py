@@ -24,12 +24,12 @@ ST_FALLBACK = 0x20
 ST_FEWER = 0x8
 
 
-def _prepare(fs, alg="music", max_D=4):
+def _prepare(fs, alg="music", max_D=4, options=None):
     from paper_2007_14135_amd.runner import prepare
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     arrays, grids, frames, X = frameset_inputs(fs)
-    return prepare(arrays, grids, frames, X, alg, "c64", max_D)
+    return prepare(arrays, grids, frames, X, alg, "c64", max_D, options=options)
 
 
 def _bin_of(angle):
@@ -111,6 +111,19 @@ def test_windowed_matches_oracle_designed_cases():
     db.run_windowed(sd, 6, 1.0, 0.0)
     res = db.host_results()
     _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 designed")
+
+
+@pytest.mark.parametrize("kernel", ["fp32", "split3"])
+def test_windowed_other_scan_kernels(kernel):
+    # the windowed scan on FP32 operands and on the three-part FP16 split
+    from paper_2007_14135_amd.api import Options
+    fs = make_frames("c2", n_frames=12, N=2048, start=80)
+    db = _prepare(fs, options=Options(c64_scan=kernel))
+    scores = _designed_scores(fs, 21)
+    db.spectrum.fill_(float("nan"))
+    db.run_windowed(torch.tensor(scores, device="cuda"), 6, 1.0, 0.0)
+    res = db.host_results()
+    _check(fs, db, res, scores, 6, 1.0, 0.0, "music", "windowed c2 " + kernel)
 
 
 def test_windowed_window_floor():

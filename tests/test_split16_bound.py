@@ -85,3 +85,86 @@ def test_unit_roundoffs_of_the_16_bit_formats():
     xh = x.astype(np.float16).astype(np.float64)
     rh = np.abs(xh - x) / np.abs(x)
     assert rh.max() <= 2.0 ** -11 and rh.max() > 0.99 * 2.0 ** -11
+
+
+def _split3(x):
+    parts = []
+    r = np.asarray(x, dtype=np.float64)
+    for _ in range(3):
+        p = r.astype(np.float16).astype(np.float64)
+        parts.append(p)
+        r = r - p                                 # exact in FP64
+    return parts
+
+
+def test_three_part_split_reproduces_fp32_operands():
+    # Steering values: FP32 v scaled by 2^13.  Three FP16 parts hold 33 significant bits, so every
+    # scaled FP32 value of magnitude >= 1/2 is reproduced exactly; below, the remainder is under half
+    # the FP16 subnormal spacing, 2^-25.  B from FP64: residual <= 2^-33 |x| + 2^-25.
+    rng = np.random.default_rng(20071413)
+    v = (rng.uniform(0.5, 1.0, 300000) * 2.0 ** rng.integers(-40, 1, 300000)).astype(np.float32)
+    v *= rng.choice(np.array([-1.0, 1.0], dtype=np.float32), v.size)
+    x = v.astype(np.float64) * 8192.0
+    h, m, l = _split3(x)
+    r = np.abs(x - h - m - l)
+    big = np.abs(x) >= 0.5
+    assert np.all(r[big] == 0.0)
+    assert np.all(r <= 2.0 ** -25)
+    # from FP64 values in the scaled range of B
+    y = rng.uniform(0.5, 1.0, 300000) * 2.0 ** rng.integers(-30, 13, 300000) * rng.choice([-1.0, 1.0], 300000)
+    h, m, l = _split3(y)
+    assert np.all(np.abs(y - h - m - l) <= 2.0 ** -33 * np.abs(y) + 2.0 ** -25)
+    # at the scale of a B column (largest component in [2^12, 2^13)) that is far below the FP32
+    # rounding the FP32-operand kernel applies to the same values: worst residual 2^-20 against
+    # FP32's 2^-13 near the top of the range, and a mean 100 times smaller
+    f32err = np.abs(y.astype(np.float32).astype(np.float64) - y)
+    res = np.abs(y - h - m - l)
+    assert res.max() <= 2.0 ** -20 and f32err.max() >= 2.0 ** -14
+    assert res.mean() < 1e-2 * f32err.mean()
+
+
+def test_six_product_bound():
+    # products of the parts whose orders add up to at most two; the dropped ones are below
+    # 2^-33 |a b| plus the subnormal terms 2^-25 (|a| + |b|)
+    rng = np.random.default_rng(9)
+    a = (rng.uniform(-1, 1, 200000) * 8192.0).astype(np.float32).astype(np.float64)
+    b = rng.uniform(-1, 1, 200000) * 8192.0
+    pa, pb = _split3(a), _split3(b)
+    p6 = sum(pa[i] * pb[j] for i in range(3) for j in range(3) if i + j <= 2)
+    exact = np.array([float(np.longdouble(ai) * np.longdouble(bi)) for ai, bi in zip(a[:2000], b[:2000])])
+    bound = 2.0 ** -33 * np.abs(a * b) + 2.0 ** -25 * (np.abs(a) + np.abs(b))
+    assert np.all(np.abs(exact - p6[:2000]) <= bound[:2000] + 2.0 ** -52 * np.abs(exact))
+    # a b reconstructed from the kept products is as close to a b as FP32 can represent it
+    assert np.all(np.abs(a * b - p6) <= 2.0 ** -30 * np.abs(a * b) + 2.0 ** -24 * (np.abs(a) + np.abs(b)))
+
+
+def test_three_part_split_dot_at_least_fp32_accurate():
+    # the scan's dot product on three-part operands (six products per step, FP32 accumulation of
+    # 16-deep steps) against FP32 operands, on real-embedded steering vectors and unit B columns
+    rng = np.random.default_rng(13)
+    M = 16
+    e6, e32 = [], []
+    for _ in range(2000):
+        th = rng.uniform(-np.pi / 2, np.pi / 2)
+        ph = np.pi * np.arange(M) * np.sin(th)
+        a = np.concatenate([np.cos(ph), np.sin(ph)]).astype(np.float32).astype(np.float64)
+        bc = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+        bc /= np.linalg.norm(bc)
+        brow = np.concatenate([bc.real, bc.imag])
+        exact = float(np.dot(brow, a))
+        sb = 2.0 ** (12 - np.floor(np.log2(np.abs(brow).max())))
+        pa, pb = _split3(a * 8192.0), _split3(brow * sb)
+        acc = np.float32(0.0)
+        for k0 in range(0, 2 * M, 16):
+            sl = slice(k0, k0 + 16)
+            for i in range(3):
+                for j in range(3):
+                    if i + j <= 2:
+                        acc = np.float32(acc + np.float32(np.sum(pb[i][sl] * pa[j][sl])))
+        e6.append(abs(float(acc) / (8192.0 * sb) - exact))
+        acc32 = np.float32(0.0)
+        b32, a32 = brow.astype(np.float32), a.astype(np.float32)
+        for k in range(2 * M):
+            acc32 = np.float32(acc32 + b32[k] * a32[k])
+        e32.append(abs(float(acc32) - exact))
+    assert max(e6) <= 1.5 * max(e32) and np.mean(e6) <= 1.5 * np.mean(e32)
