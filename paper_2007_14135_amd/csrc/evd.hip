@@ -2,9 +2,12 @@
 // noise-subspace matrix B with C = B B^H.
 //
 // One workgroup per frame.  The workgroup first adds the frame's partial covariances in chunk
-// order and divides by N (Eq. 3).  Two eigensolvers:
+// order and divides by N (Eq. 3).  Three eigensolvers:
 //
-// * Householder + implicit QL (default).  R is reduced to a real symmetric tridiagonal matrix
+// * For M <= 16 (the default there): one wave per frame, Householder reduction with the matrix
+//   and the unitary factor in registers, Sturm-count multisection for the eigenvalues and
+//   inverse iteration for the eigenvectors (described before evd_small_kernel).
+// * Householder + implicit QL (the default for M > 16).  R is reduced to a real symmetric tridiagonal matrix
 //   T = Q^H R Q with Q = H_0 H_1 ... H_{M-2}, H_k = I - tau_k v_k v_k^H chosen so that H_k^H maps
 //   the part of column k below the diagonal onto a real multiple of its first unit vector (the
 //   two-sided update of the trailing block is the rank-2 form A -= v w^H + w v^H,
@@ -95,6 +98,20 @@ __device__ __forceinline__ double rcp_approx(double x) {
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// x rounded to the nearest FP16 value (ties to even): x is first rounded to FP32 with round to
+// odd (truncated, and the last bit set when inexact), which keeps 13 bits beyond FP16's 11, so
+// the hardware's round to nearest from FP32 then rounds as if from x itself.
+__device__ __forceinline__ _Float16 f64_to_f16(double x) {
+    const float f = (float)x;
+    const double back = (double)f;
+    uint32_t u = __float_as_uint(f);
+    if (back != x) {
+        if (fabs(back) > fabs(x)) u -= 1u;     // rounded away from zero: step back toward it
+        u |= 1u;
+    }
+    return (_Float16)__uint_as_float(u);
+}
+
 // Cross-lane moves of doubles (two 32-bit DPP moves or lane reads).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -137,19 +154,38 @@ __device__ inline double block_sum_fast(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tridiagonal eigenpairs by bisection and inverse iteration (M <= kBisectMaxM, one wave).  The
-// eigenvalues are found together: a coarse pass counts eigenvalues below 64 points across the
-// Gershgorin interval (Sturm counts: the number of negative pivots of T - x I, each pivot floored
-// at pivmin in magnitude), then multisection: lane j + 16 p counts at point p + 1 of 5 equally
-// spaced points inside eigenvalue j's current interval, so every iteration shrinks each interval
-// fivefold; the number of iterations is fixed by the interval and the tolerance
-// 2 eps ||T|| + 4 pivmin.  Lane j then solves (T - lambda_j I) x = b three times by
-// LU with partial pivoting (a zero pivot is replaced by eps ||T||) from a pseudo-random start,
-// the vectors are orthonormalised by modified Gram-Schmidt within clusters of close eigenvalues,
-// solved once more and orthonormalised again (the second solve removes what the first
-// orthonormalisation mixed in from far eigenvectors when a cluster's vectors were nearly
-// dependent).
-constexpr int kBisectMaxM = 16;
+// The default eigensolver for M <= kSmallM (evd_small_kernel): four waves per frame, one per SIMD
+// of the compute unit, thread t owning entry (t / 16, t % 16) of the matrices.
+//   1. R = (sum of the chunk partials, in chunk order) / N (load_covariance).
+//   2. Householder reduction T = Q^H R Q with R and Q one entry per thread.  H_k = I - tau_k u_k
+//      u_k^H maps column k below the diagonal onto a real multiple beta_k of its first unit
+//      vector; the reflector is kept unnormalised, u = (alpha - beta, x), tau = (beta - alpha) /
+//      (beta |alpha - beta|^2) (the usual v = u / (alpha - beta) with tau (beta - alpha) / beta).
+//      The sixteen threads of row k form it from row k alone (column k is its conjugate): the
+//      norm by a reduction within their row of lanes, beta and 1/beta from one reciprocal square
+//      root; u goes to LDS.  Every thread then forms its row's part of y = A u and z = Q u (row
+//      reductions), y goes to LDS for the columns and the waves' parts of gamma = u^H y meet in
+//      LDS; the trailing block takes the rank-2 update A -= u w^H + w u^H with w = tau y -
+//      |tau|^2 gamma / 2 u, and Q <- Q H_k = Q - tau z u^H, so V = Q Z needs no separate
+//      back-transformation.  Two barriers per step.
+//   3. Eigenvalues of T by Sturm counts: the number of eigenvalues below x is the number of
+//      sign changes along the leading principal minors p_i of T - x I, whose three-term
+//      recurrence needs no division (T is scaled by a power of two to a norm in [1/2, 1), the
+//      minors are rescaled by powers of two every fourth row, and a minor that vanishes is
+//      replaced by -2^-60 times its predecessor: a negative pivot far below rounding).  A coarse
+//      pass counts at 256 points across the Gershgorin interval, then 17-section: the sixteen
+//      lanes of eigenvalue j count at the sixteen inner points of its interval, down to
+//      2 eps ||T||.
+//   4. Eigenvectors of T by inverse iteration (one wave): lane j solves (T - lambda_j I) x = b
+//      twice by LU with partial pivoting (a zero pivot is replaced by eps ||T||) from a
+//      pseudo-random start, and the vectors are orthonormalised by modified Gram-Schmidt within
+//      clusters of close eigenvalues.  If that moved some vector towards another by more than
+//      16 eps ||T|| / |lambda_j - lambda_k| (nearly dependent vectors of a tight cluster, where
+//      the projection mixes in what the solves had not yet removed), every vector is solved
+//      once more and orthonormalised again.
+//   5. V = Q Z; ranking, B and the scan operands as for the other solvers.
+constexpr int kSmallM = 16;
+constexpr int kSmallThreads = kSmallM * kSmallM;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -157,93 +193,175 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Broadcast of a double from position P of each aligned group of four lanes.
-template <int P>
-__device__ __forceinline__ double quad_bcast(double v) {
-    return dpp_f64<P * 0x55>(v);                 // quad_perm [P, P, P, P]
-}
-__device__ __forceinline__ double quad_bcast(double v, int p) {
-    return p == 0 ? quad_bcast<0>(v) : p == 1 ? quad_bcast<1>(v) : p == 2 ? quad_bcast<2>(v) : quad_bcast<3>(v);
+// Sum over each aligned row of 16 lanes, in all 16 (the row must be active).
+__device__ __forceinline__ double row16_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_f64<kDppRowHalfMirror>(v);
+    return v + dpp_f64<kDppRowMirror>(v);
 }
 
-// Householder reduction of the Hermitian A (LDS, row stride ld, M <= 16) to the real symmetric
-// tridiagonal T (dq, eq), with the reflectors in Hv (column k below row k, v_{k+1} = 1) and tau
-// in tq: the same steps as the LDS reduction in evd_ql_kernel, with the matrix in registers.
-// Lane l holds A[l >> 2][4 (l & 3) + t], t = 0..3; the reflector is broadcast within the
-// four-lane groups (rows) and gathered across them (columns).  One wave; A is not updated.
-__device__ void tridiag_regs(int M, const double2* A, int ld, double2* Hv, double* dq, double* eq, double2* tq) {
-    const int lane = threadIdx.x & 63, r = lane >> 2, q = lane & 3;
-    double2 a[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        a[t] = (r < M && 4 * q + t < M) ? A[r * ld + 4 * q + t] : make_double2(0.0, 0.0);
-    auto col = [&](int kt) { return kt == 0 ? a[0] : kt == 1 ? a[1] : kt == 2 ? a[2] : a[3]; };
+// Step 2 (see above).  A: R in LDS (row stride ld); on return the thread holds Q[r][c] in qm,
+// T is in dq (diagonal) and eq (off-diagonal, eq[M-1] = 0).  ubuf, ybuf: 16 entries; sc: two
+// complex scalars; gpart: one double per wave.
+__device__ void tridiag_block(int M, const double2* A, int ld, double* dq, double* eq, double2* ubuf, double2* ybuf,
+                              double2* sc, double* gpart, double2& qm) {
+    const int tid = threadIdx.x, r = tid >> 4, c = tid & 15, lane = tid & 63;
+    double2 a = (r < M && c < M) ? A[r * ld + c] : make_double2(0.0, 0.0);
+    qm = make_double2((r == c && r < M) ? 1.0 : 0.0, 0.0);
     for (int k = 0; k < M - 1; ++k) {
-        const int kq = k >> 2;
-        const double2 x = col(k & 3);              // A[r][k] in the lanes (r, kq)
-        const double part = (q == kq && r > k + 1) ? fma(x.x, x.x, x.y * x.y) : 0.0;
-        const double xn2 = wave_sum(part);
-        const int sa = ((k + 1) << 2) | kq;
-        const double2 alpha = make_double2(readlane_f64(x.x, sa), readlane_f64(x.y, sa));
-        const double dk = readlane_f64(x.x, (k << 2) | kq);
-        double beta = alpha.x;
-        double2 tau = make_double2(0.0, 0.0), scl = make_double2(0.0, 0.0);
-        if (xn2 > 0.0 || alpha.y != 0.0) {
-            beta = -copysign(sqrt(fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2))), alpha.x);
-            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-            const double2 den = make_double2(alpha.x - beta, alpha.y);
-            const double dn2 = fma(den.x, den.x, den.y * den.y);
-            scl = make_double2(den.x / dn2, -den.y / dn2);
+        if (r == k) {
+            // the sixteen lanes of row k: ||A[k][k+2:]||^2, alpha = A[k+1][k] = conj(A[k][k+1])
+            const double xn2 = row16_sum(c > k + 1 ? fma(a.x, a.x, a.y * a.y) : 0.0);
+            const int l0 = 16 * (k & 3);             // row k: lanes l0 .. l0 + 15 of wave k / 4
+            const double2 alpha = make_double2(readlane_f64(a.x, l0 + k + 1), -readlane_f64(a.y, l0 + k + 1));
+            const double dk = readlane_f64(a.x, l0 + k);
+            double beta = alpha.x;
+            double2 tau = make_double2(0.0, 0.0), u1 = make_double2(0.0, 0.0);
+            if (xn2 > 0.0 || alpha.y != 0.0) {
+                const double s2 = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2));
+                const double rs = rsq_full(s2);
+                beta = -copysign(s2 * rs, alpha.x);
+                u1 = make_double2(alpha.x - beta, alpha.y);
+                const double rt = rcp64(beta * fma(u1.x, u1.x, u1.y * u1.y));
+                tau = make_double2((beta - alpha.x) * rt, -alpha.y * rt);
+            }
+            // u_{k+1} = alpha - beta, u_c = A[c][k] = conj(A[k][c]) for c > k + 1, 0 elsewhere
+            ubuf[c] = (c == k + 1) ? u1 : (c > k + 1 && c < M) ? cconj(a) : make_double2(0.0, 0.0);
+            if (c == 0) {
+                sc[0] = tau;
+                dq[k] = dk;
+                eq[k] = beta;
+            }
         }
-        // v_r = 1 (r = k + 1), A[r][k] scl (r > k + 1), 0 (r <= k), in every lane of row r
-        const double2 xr = make_double2(quad_bcast(x.x, kq), quad_bcast(x.y, kq));
-        const double2 vr = (r == k + 1) ? make_double2(1.0, 0.0)
-                           : (r > k + 1 && r < M) ? cmul(xr, scl) : make_double2(0.0, 0.0);
-        if (q == 0 && r > k && r < M) Hv[r * ld + k] = vr;
-        if (lane == 0) {
-            dq[k] = dk;
-            eq[k] = beta;
-            tq[k] = tau;
-        }
+        __syncthreads();
+        const double2 tau = sc[0];
         if (tau.x == 0.0 && tau.y == 0.0) continue;      // uniform: H_k = I
-        // v at this lane's four columns
-        double2 vc[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int sl = (4 * q + t) << 2;
-            vc[t] = make_double2(__shfl(vr.x, sl), __shfl(vr.y, sl));
-        }
-        // y = B v over the trailing block (v vanishes outside it), gamma = v^H y (real)
-        double2 y = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            y.x = fma(a[t].x, vc[t].x, fma(-a[t].y, vc[t].y, y.x));
-            y.y = fma(a[t].x, vc[t].y, fma(a[t].y, vc[t].x, y.y));
-        }
-        y.x = quad_sum(y.x);
-        y.y = quad_sum(y.y);
-        const double gam = wave_sum((q == 0 && r > k) ? fma(vr.x, y.x, vr.y * y.y) : 0.0);
+        const double2 ur = ubuf[r], uc = ubuf[c];
+        // row parts of y = A u and z = Q u
+        double2 y = make_double2(fma(a.x, uc.x, -a.y * uc.y), fma(a.x, uc.y, a.y * uc.x));
+        double2 z = make_double2(fma(qm.x, uc.x, -qm.y * uc.y), fma(qm.x, uc.y, qm.y * uc.x));
+        y.x = row16_sum(y.x);
+        y.y = row16_sum(y.y);
+        z.x = row16_sum(z.x);
+        z.y = row16_sum(z.y);
+        if (c == 0) ybuf[r] = y;
+        // gamma = sum over rows r > k of Re(conj(u_r) y_r): the wave's four rows, then the waves
+        double g = (r > k) ? fma(ur.x, y.x, ur.y * y.y) : 0.0;
+        g = (readlane_f64(g, 0) + readlane_f64(g, 16)) + (readlane_f64(g, 32) + readlane_f64(g, 48));
+        if (lane == 0) gpart[tid >> 6] = g;
+        __syncthreads();
+        const double gam = (gpart[0] + gpart[1]) + (gpart[2] + gpart[3]);
         const double h = 0.5 * fma(tau.x, tau.x, tau.y * tau.y) * gam;
-        const double2 wr = (r > k && r < M) ? csub(cmul(tau, y), cscale(h, vr)) : make_double2(0.0, 0.0);
-        double2 wc[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int sl = (4 * q + t) << 2;
-            wc[t] = make_double2(__shfl(wr.x, sl), __shfl(wr.y, sl));
-        }
-        // B -= v w^H + w v^H
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double2 vj = vc[t], wj = wc[t];
-            a[t].x -= fma(vr.x, wj.x, vr.y * wj.y) + fma(wr.x, vj.x, wr.y * vj.y);
-            a[t].y -= fma(vr.y, wj.x, -vr.x * wj.y) + fma(wr.y, vj.x, -wr.x * vj.y);
-        }
+        const double2 yc = ybuf[c];
+        const double2 wr = (r > k && r < M) ? csub(cmul(tau, y), cscale(h, ur)) : make_double2(0.0, 0.0);
+        const double2 wc = (c > k && c < M) ? csub(cmul(tau, yc), cscale(h, uc)) : make_double2(0.0, 0.0);
+        const double2 tz = cmul(tau, z);
+        // A -= u w^H + w u^H;  Q -= (tau Q u) u^H
+        a.x -= fma(ur.x, wc.x, ur.y * wc.y) + fma(wr.x, uc.x, wr.y * uc.y);
+        a.y -= fma(ur.y, wc.x, -ur.x * wc.y) + fma(wr.y, uc.x, -wr.x * uc.y);
+        qm.x -= fma(tz.x, uc.x, tz.y * uc.y);
+        qm.y -= fma(tz.y, uc.x, -tz.x * uc.y);
     }
-    const double dl = readlane_f64(col((M - 1) & 3).x, ((M - 1) << 2) | ((M - 1) >> 2));
-    if (lane == 0) {
-        dq[M - 1] = dl;
+    if (r == M - 1 && c == M - 1) {
+        dq[M - 1] = a.x;
         eq[M - 1] = 0.0;
     }
+}
+
+// Eigenvalues of T below x: sign changes along p_0 = 1, p_{i+1} = (dp_i - x) p_i - e2_i p_{i-1}
+// (dp: scaled diagonal padded with decoupled rows above every point counted, e2_i: squared
+// scaled coupling of rows i - 1 and i, e2_0 = 0).
+__device__ __forceinline__ int sturm_count(const double (&dp)[kSmallM], const double (&e2)[kSmallM], double x) {
+    double p0 = 0.0, p1 = 1.0;
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kSmallM; ++i) {
+        double pn = fma(dp[i] - x, p1, -e2[i] * p0);
+        pn = pn != 0.0 ? pn : -0x1p-60 * p1;
+        cnt += (pn < 0.0) != (p1 < 0.0);
+        p0 = p1;
+        p1 = pn;
+        if ((i & 3) == 3) {
+            const int ex = __builtin_amdgcn_frexp_exp(p1);
+            p1 = __builtin_amdgcn_ldexp(p1, -ex);
+            p0 = __builtin_amdgcn_ldexp(p0, -ex);
+        }
+    }
+    return cnt;
+}
+
+// Step 3, all four waves: eigenvalue j of T (ascending, j < M) to lamv[j]; returns the
+// Gershgorin bound tnorm of ||T|| (0 when T = 0: every eigenvalue is then 0).  first: 64 ints.
+__device__ double eigvals_block(int M, const double (&d)[kSmallM], const double (&e)[kSmallM], double* lamv,
+                                int* first) {
+    constexpr int MB = kSmallM;
+    constexpr double eps = 0x1p-52;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int grp = lane >> 4, p = lane & 15, j = 4 * wv + grp;
+    double gl = INFINITY, gu = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        if (i < M) {
+            const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+            gl = fmin(gl, d[i] - r);
+            gu = fmax(gu, d[i] + r);
+        }
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    if (!(tnorm > 0.0)) {
+        if (tid < M) lamv[tid] = 0.0;
+        return 0.0;
+    }
+    // scale by 2^-ex: ||T|| bound in [1/2, 1); rows beyond M sit at 4, above every point
+    const int ex = __builtin_amdgcn_frexp_exp(tnorm);
+    double dp[MB], e2[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        dp[i] = i < M ? __builtin_amdgcn_ldexp(d[i], -ex) : 4.0;
+        const double es = (i > 0 && i < M) ? __builtin_amdgcn_ldexp(e[i - 1], -ex) : 0.0;
+        e2[i] = es * es;
+    }
+    const double tn = __builtin_amdgcn_ldexp(tnorm, -ex);
+    const double pad = 2.1 * (tn * eps * M + 0x1p-57);
+    const double tol = 2.0 * eps * tn + 0x1p-58;
+    // coarse pass: thread t counts at the point t + 1 of 257 across the Gershgorin interval;
+    // eigenvalue j lies above the last point below which at most j eigenvalues lie
+    const double g0 = __builtin_amdgcn_ldexp(gl, -ex) - pad;
+    const double gw = (__builtin_amdgcn_ldexp(gu, -ex) + pad) - g0;
+    constexpr double kInv257 = 1.0 / 257.0;
+    const int cc = sturm_count(dp, e2, g0 + gw * ((double)(tid + 1) * kInv257));
+    for (int jj = 0; jj < M; ++jj) {
+        const unsigned long long bal = __ballot(cc > jj);
+        if (lane == jj) first[wv * 16 + jj] = bal ? __builtin_ctzll(bal) : 64;
+    }
+    __syncthreads();
+    int kf = 256;
+    if (j < M) {
+#pragma unroll
+        for (int w = 3; w >= 0; --w) {
+            const int f = first[w * 16 + j];
+            kf = f < 64 ? 64 * w + f : kf;
+        }
+    }
+    double lo = kf == 0 ? g0 : g0 + gw * ((double)kf * kInv257);
+    double hi = kf == 256 ? g0 + gw : g0 + gw * ((double)(kf + 1) * kInv257);
+    const int its = min(64, max(1, (int)ceil(log2(gw * kInv257 / tol) / log2(17.0)) + 1));
+    // 17-section: lane p of eigenvalue j's row of lanes counts at point p + 1 of 17
+    constexpr double kInv17 = 1.0 / 17.0;
+    for (int it = 0; it < its; ++it) {
+        const double w = hi - lo;
+        const int cnt = sturm_count(dp, e2, lo + w * ((double)(p + 1) * kInv17));
+        // the first point below which more than j eigenvalues lie bounds eigenvalue j above
+        const unsigned long long bal = __ballot(cnt > j);
+        const uint32_t bits = (uint32_t)(bal >> (16 * grp)) & 0xFFFFu;
+        const int k = bits ? __builtin_ctz(bits) : 16;
+        const double nlo = k == 0 ? lo : lo + w * ((double)k * kInv17);
+        const double nhi = k == 16 ? hi : lo + w * ((double)(k + 1) * kInv17);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (p == 0 && j < M) lamv[j] = __builtin_amdgcn_ldexp(0.5 * (lo + hi), ex);
+    return tnorm;
 }
 
 // Deterministic pseudo-random start of inverse iteration, in [-1, 1).
@@ -255,88 +373,13 @@ __device__ __forceinline__ double ii_start(int i, int j) {
     return (double)h * 0x1p-31 - 1.0;
 }
 
-// T from dq (diagonal) and eq (off-diagonal, eq[M-1] = 0).  Writes the eigenvalues in ascending
-// order to dq and eigenvector j as column j of Z (.x, row stride ld).  Every lane of the wave
-// calls it.
-__device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2* Z, int ld) {
-    constexpr int MB = kBisectMaxM;
+// Step 4: eigenvector j of T (for eigenvalue lam in lane j < M) as column j of Zs (row-major,
+// kSmallM columns).  Every lane of one wave calls it.
+__device__ void tridiag_eigvecs(int M, const double (&d)[kSmallM], const double (&e)[kSmallM], double lam,
+                                double tnorm, double* Zs) {
+    constexpr int MB = kSmallM;
     constexpr double eps = 0x1p-52;
     const int lane = threadIdx.x & 63;
-    const int j = lane & 15, p = lane >> 4;
-    double d[MB], e[MB];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        d[i] = i < M ? dq[i] : 0.0;
-        e[i] = i < M - 1 ? eq[i] : 0.0;
-    }
-    double gl = INFINITY, gu = -INFINITY, e2max = 0.0;
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        if (i < M) {
-            const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
-            gl = fmin(gl, d[i] - r);
-            gu = fmax(gu, d[i] + r);
-            e2max = fmax(e2max, e[i] * e[i]);
-        }
-    }
-    const double tnorm = fmax(fabs(gl), fabs(gu));
-    double lam = 0.0;
-    if (tnorm > 0.0) {
-        const double pivmin = DBL_MIN * fmax(1.0, e2max);
-        const double pad = 2.1 * (tnorm * eps * M + 2.0 * pivmin);
-        // Sturm count at x: eigenvalues of T below x (the reciprocal to about 2^-48 suffices:
-        // the count is then exact for a matrix within a few 1e-15 ||T|| of T).  T is padded to
-        // MB rows with decoupled diagonal entries above every point counted at (4 ||T|| + 1),
-        // which add nothing to the count, so the chain runs without branches.
-        double dp[MB], e2[MB];
-        const double big = 4.0 * tnorm + 1.0;
-#pragma unroll
-        for (int i = 0; i < MB; ++i) {
-            dp[i] = i < M ? d[i] : big;
-            e2[i] = (i > 0 && i < M) ? e[i - 1] * e[i - 1] : 0.0;
-        }
-        auto sturm = [&](double x) {
-            double q = dp[0] - x;
-            q = fabs(q) < pivmin ? -pivmin : q;
-            int cnt = q < 0.0;
-#pragma unroll
-            for (int i = 1; i < MB; ++i) {
-                q = (dp[i] - x) - e2[i] * rcp_approx(q);
-                q = fabs(q) < pivmin ? -pivmin : q;
-                cnt += q < 0.0;
-            }
-            return cnt;
-        };
-        // coarse pass: lane k counts at the point k + 1 of 65 across the Gershgorin interval, and
-        // each eigenvalue takes the first point above which it lies
-        const double g0 = gl - pad, gw = (gu + pad) - g0;
-        const int c = sturm(g0 + gw * ((double)(lane + 1) * (1.0 / 65.0)));
-        int kf = 64;
-        for (int jj = 0; jj < M; ++jj) {
-            const unsigned long long bal = __ballot(c > jj);
-            const int k = bal ? __builtin_ctzll(bal) : 64;
-            kf = (j == jj) ? k : kf;
-        }
-        double lo = kf == 0 ? g0 : g0 + gw * ((double)kf * (1.0 / 65.0));
-        double hi = kf == 64 ? g0 + gw : g0 + gw * ((double)(kf + 1) * (1.0 / 65.0));
-        const double tol = 2.0 * eps * tnorm + 4.0 * pivmin;
-        const int its = min(64, max(1, (int)ceil(log2(gw * (1.0 / 65.0) / tol) / log2(5.0)) + 1));
-        // multisection: lane j + 16 p counts at point p + 1 of 5 inside eigenvalue j's interval
-        for (int it = 0; it < its; ++it) {
-            const double w = hi - lo;
-            const int cnt = sturm(lo + w * ((double)(p + 1) * 0.2));
-            const int c0 = __shfl(cnt, j), c1 = __shfl(cnt, j + 16), c2 = __shfl(cnt, j + 32),
-                      c3 = __shfl(cnt, j + 48);
-            // the first point below which more than j eigenvalues lie bounds eigenvalue j above
-            const int k = c0 > j ? 0 : c1 > j ? 1 : c2 > j ? 2 : c3 > j ? 3 : 4;
-            const double nlo = k == 0 ? lo : lo + w * ((double)k * 0.2);
-            const double nhi = k == 4 ? hi : lo + w * ((double)(k + 1) * 0.2);
-            lo = nlo;
-            hi = nhi;
-        }
-        lam = 0.5 * (lo + hi);
-    }
-
     double z[MB];
 #pragma unroll
     for (int i = 0; i < MB; ++i) z[i] = (tnorm == 0.0 && i == lane) ? 1.0 : 0.0;
@@ -420,23 +463,34 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
         const double lam_next = __shfl_down(lam, 1);
         const unsigned long long cend =
             __ballot(lane < M && (lane == M - 1 || lam_next - lam > 1e-3 * tnorm)) | (1ull << (M - 1));
-        // modified Gram-Schmidt within each cluster, in lane order
+        // modified Gram-Schmidt within each cluster, in lane order.  mix: the largest
+        // |<z_k, z_j>| |lambda_j - lambda_k| removed from this lane's vector (the change of its
+        // eigen-residual); weak: a vector whose norm fell below 1/sqrt(2) before normalisation
+        // (it was nearly dependent on the ones before it)
+        double mix = 0.0;
+        bool weak = false;
         auto mgs = [&]() {
             for (int k = 0; k < M; ++k) {
                 if ((cend >> k) & 1ull) {            // last of its cluster: only normalised
-                    if (lane == k) normalise(z);
+                    if (lane == k) {
+                        weak |= dot(z, z) < 0.5;
+                        normalise(z);
+                    }
                     continue;
                 }
                 const int ce = k + 2 + __builtin_ctzll(cend >> (k + 1));   // cluster end, exclusive
                 double zk[MB];
 #pragma unroll
                 for (int i = 0; i < MB; ++i) zk[i] = readlane_f64(z[i], k);
+                const double lk = readlane_f64(lam, k);
+                weak |= dot(zk, zk) < 0.5;
                 normalise(zk);
                 if (lane == k) {
 #pragma unroll
                     for (int i = 0; i < MB; ++i) z[i] = zk[i];
                 } else if (lane > k && lane < ce) {
                     const double dt = dot(zk, z);
+                    mix = fmax(mix, fabs(dt) * fabs(lam - lk));
 #pragma unroll
                     for (int i = 0; i < MB; ++i) z[i] = fma(-dt, zk[i], z[i]);
                 }
@@ -447,21 +501,21 @@ __device__ void tridiag_eig_bisect(int M, double* dq, const double* eq, double2*
             for (int i = 0; i < MB; ++i) z[i] = i < M ? ii_start(i, lane) : 0.0;
             solve(z);
             solve(z);
-            solve(z);
             normalise(z);
         }
         mgs();
-        if (lane < M) {
-            solve(z);
-            normalise(z);
+        if (__ballot(lane < M && (weak || mix > 16.0 * epsp))) {
+            if (lane < M) {
+                solve(z);
+                normalise(z);
+            }
+            mgs();
         }
-        mgs();
     }
     if (lane < M) {
-        dq[lane] = lam;
 #pragma unroll
         for (int i = 0; i < MB; ++i)
-            if (i < M) Z[i * ld + lane] = make_double2(z[i], 0.0);
+            if (i < M) Zs[i * MB + lane] = z[i];
     }
 }
 
@@ -705,7 +759,7 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
                     vd *= bscale;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        const _Float16 x = (_Float16)vd;
+                        const _Float16 x = f64_to_f16(vd);
                         part8[q][t] = x;
                         vd -= (double)x;
                     }
@@ -963,15 +1017,10 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
     uint32_t st = 0;
     // four lanes per matrix row (or column) in the parallel phases
     const int grp = tid >> 2, q = tid & 3, gstep = bd >> 2;
-    const bool bisect = prm.method == NSSDOA_EIG_AUTO && M <= kBisectMaxM && bd == 64;
-    if (!bad && bisect) {
-        tridiag_regs(M, A, ld, Hv, dq, eq, tq);
-        __syncthreads();
-    }
     if (!bad) {
         // T = Q^H R Q.  Step k reflects rows/columns k+1..M-1 so that column k below the
         // subdiagonal vanishes and the subdiagonal entry becomes the real beta.
-        for (int k = 0; k < (bisect ? 0 : M - 1); ++k) {
+        for (int k = 0; k < M - 1; ++k) {
             const int m = M - 1 - k;
             const double2* col = A + (k + 1) * ld + k;          // col[i * ld] = A[k+1+i][k]
             double part = 0.0;
@@ -1042,14 +1091,11 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
             }
             __syncthreads();
         }
-        if (tid == 0 && !bisect) {
+        if (tid == 0) {
             dq[M - 1] = A[(M - 1) * ld + M - 1].x;
             eq[M - 1] = 0.0;
         }
         __syncthreads();
-        if (bisect) {
-            tridiag_eig_bisect(M, dq, eq, A, ld);
-        } else {
         for (int e = tid; e < Mp * Mp; e += bd) {
             const int i = e / Mp, j = e - i * Mp;
             A[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);      // Z = I
@@ -1129,7 +1175,6 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
             }
             dq[lane] = dl;
         }
-        }
         __syncthreads();
 
         // V = H_0 (H_1 (... H_{M-2} Z)); H_k Z = Z - tau_k v_k (v_k^H Z).  Four lanes own one
@@ -1159,6 +1204,69 @@ __global__ __launch_bounds__(256) void evd_ql_kernel(const int32_t* __restrict__
     finish_frame(fr, fidx, prm, groups, ws, status, dq, 1, A, ld, Hv, bad, st, perm, lam, red);
 }
 
+// The default solver for M <= kSmallM: four waves per frame (see the description of steps 1-5
+// above).  LDS: R and then Q and V (row stride kSmallM + 1), Z, B.
+__global__ __launch_bounds__(kSmallThreads) void evd_small_kernel(const int32_t* __restrict__ flist,
+                                                                  const FrameDev* __restrict__ frames, EvdParams prm,
+                                                                  const GroupDev* __restrict__ groups,
+                                                                  char* __restrict__ ws,
+                                                                  uint32_t* __restrict__ status) {
+    constexpr int MB = kSmallM, ld = kSmallM + 1;
+    __shared__ double2 As[MB * ld];
+    __shared__ double2 Bs[MB * MB];
+    __shared__ double Zs[MB * MB];
+    __shared__ double2 ubuf[MB], ybuf[MB], sc[2];
+    __shared__ double dq[MB], eq[MB], lamv[MB], gpart[4];
+    __shared__ int first[64];
+    __shared__ int perm[64];
+    __shared__ double red[32];
+    __shared__ double lam[64];
+    __shared__ int bad;
+
+    const int fidx = flist[blockIdx.x];
+    const FrameDev& fr = frames[fidx];
+    const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
+    const int M = fr.M;
+    if (tid == 0) {
+        bad = 0;
+        if (prm.write_emb) *reinterpret_cast<int*>(ws + fr.ws_lowq) = 0;   // low-Q list of the scan
+    }
+    __syncthreads();
+    load_covariance(fr, ws, As, ld, MB, &bad);
+    __syncthreads();
+    if (!bad) {
+        double2 qm;
+        tridiag_block(M, As, ld, dq, eq, ubuf, ybuf, sc, gpart, qm);
+        __syncthreads();
+        // Q over R (R is no longer read)
+        if (r < M && c < M) As[r * ld + c] = qm;
+        double d[MB], e[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            d[i] = i < M ? dq[i] : 0.0;
+            e[i] = i < M - 1 ? eq[i] : 0.0;
+        }
+        const double tnorm = eigvals_block(M, d, e, lamv, first);
+        __syncthreads();
+        if (tid < 64) tridiag_eigvecs(M, d, e, tid < M ? lamv[tid] : 0.0, tnorm, Zs);
+        __syncthreads();
+        // V = Q Z (Z real), over Q
+        double2 v = make_double2(0.0, 0.0);
+        if (r < M && c < M) {
+            for (int i = 0; i < M; ++i) {
+                const double2 qi = As[r * ld + i];
+                const double zt = Zs[i * MB + c];
+                v.x = fma(qi.x, zt, v.x);
+                v.y = fma(qi.y, zt, v.y);
+            }
+        }
+        __syncthreads();
+        if (r < M && c < M) As[r * ld + c] = v;
+        __syncthreads();
+    }
+    finish_frame(fr, fidx, prm, groups, ws, status, lamv, 1, As, ld, Bs, bad, 0u, perm, lam, red);
+}
+
 }  // namespace
 
 hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const EvdParams& p,
@@ -1167,6 +1275,11 @@ hipError_t launch_evd(const int32_t* frame_list, int n_frames, int max_M, const 
     if (n_frames <= 0) return hipSuccess;
     if (max_M < 2 || max_M > 64) return hipErrorInvalidValue;
     const int Mp = max_M + (max_M & 1);
+    if (p.method == NSSDOA_EIG_AUTO && max_M <= kSmallM) {
+        hipLaunchKernelGGL(evd_small_kernel, dim3(n_frames), dim3(kSmallThreads), 0, s, frame_list, frames, p, groups,
+                           ws, status);
+        return hipGetLastError();
+    }
     if (p.method != NSSDOA_EIG_JACOBI) {
         const int threads = max_M <= 16 ? 64 : max_M <= 32 ? 128 : 256;
         const size_t lds = (size_t)2 * Mp * (Mp + 1) * sizeof(double2);
