@@ -140,6 +140,34 @@ __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_f64<kDppRowMirror>(v);
     return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
+// Maximum over the 64 lanes of a fully active wave; every lane gets the same value.
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_f64<kDppQuadXor1>(v));
+    v = fmax(v, dpp_f64<kDppQuadXor2>(v));
+    v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
+    v = fmax(v, dpp_f64<kDppRowMirror>(v));
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+// Block-wide sum of q and maximum of mx over fully active waves, in one LDS exchange (red: two
+// doubles per wave).
+__device__ inline void block_sum_max(double& q, double& mx, double* red) {
+    q = wave_sum(q);
+    mx = wave_max(mx);
+    const int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * (threadIdx.x >> 6)] = q;
+        red[2 * (threadIdx.x >> 6) + 1] = mx;
+    }
+    __syncthreads();
+    q = red[0];
+    mx = red[1];
+    for (int w = 1; w < nw; ++w) {
+        q += red[2 * w];
+        mx = fmax(mx, red[2 * w + 1]);
+    }
+    __syncthreads();
+}
 // Block-wide sum of fully active waves: wave sums, then (with several waves) one LDS pass.
 __device__ inline double block_sum_fast(double v, double* red) {
     v = wave_sum(v);
@@ -373,10 +401,13 @@ __device__ __forceinline__ double ii_start(int i, int j) {
     return (double)h * 0x1p-31 - 1.0;
 }
 
-// Step 4: eigenvector j of T (for eigenvalue lam in lane j < M) as column j of Zs (row-major,
-// kSmallM columns).  Every lane of one wave calls it.
+// Step 4, one wave (every lane calls it), for eigenvalue lam in lane j < M.  With finish false:
+// the two solves from the pseudo-random start, normalised, as row j of Zr (row stride
+// kSmallM + 1), and the cluster index of eigenvalue j in cid[j].  With finish true: from those
+// rows, Gram-Schmidt within clusters and, where needed, one more solve and Gram-Schmidt;
+// eigenvector j as column j of Zs (row-major, kSmallM columns).
 __device__ void tridiag_eigvecs(int M, const double (&d)[kSmallM], const double (&e)[kSmallM], double lam,
-                                double tnorm, double* Zs) {
+                                double tnorm, double* Zr, double* Zs, double* bk, int* cid, bool finish) {
     constexpr int MB = kSmallM;
     constexpr double eps = 0x1p-52;
     const int lane = threadIdx.x & 63;
@@ -463,59 +494,119 @@ __device__ void tridiag_eigvecs(int M, const double (&d)[kSmallM], const double 
         const double lam_next = __shfl_down(lam, 1);
         const unsigned long long cend =
             __ballot(lane < M && (lane == M - 1 || lam_next - lam > 1e-3 * tnorm)) | (1ull << (M - 1));
-        // modified Gram-Schmidt within each cluster, in lane order.  mix: the largest
-        // |<z_k, z_j>| |lambda_j - lambda_k| removed from this lane's vector (the change of its
+        // Modified Gram-Schmidt within each cluster, in lane order, with four lanes per vector:
+        // lane 4 j + g holds components 4 g .. 4 g + 3 of vector j (moved there through Zs, one
+        // row per vector); the pivot vector reaches every lane through LDS (bk).  mix: the
+        // largest |<z_k, z_j>| |lambda_j - lambda_k| removed from vector j (the change of its
         // eigen-residual); weak: a vector whose norm fell below 1/sqrt(2) before normalisation
-        // (it was nearly dependent on the ones before it)
+        // (it was nearly dependent on the ones before it).
+        const int jq = lane >> 2, g = lane & 3;
+        const double lamq = __shfl(lam, jq);
+        double zq[4];
         double mix = 0.0;
         bool weak = false;
+        auto to_quads = [&]() {
+            if (lane < M) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i) Zr[lane * (MB + 1) + i] = z[i];
+            }
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < 4; ++t) zq[t] = Zr[jq * (MB + 1) + 4 * g + t];
+            wave_sync();
+        };
+        auto from_quads = [&]() {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Zr[jq * (MB + 1) + 4 * g + t] = zq[t];
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < MB; ++i) z[i] = Zr[lane * (MB + 1) + i];
+            wave_sync();
+        };
         auto mgs = [&]() {
             for (int k = 0; k < M; ++k) {
                 if ((cend >> k) & 1ull) {            // last of its cluster: only normalised
-                    if (lane == k) {
-                        weak |= dot(z, z) < 0.5;
-                        normalise(z);
+                    if (jq == k) {
+                        const double n2 = quad_sum(fma(zq[0], zq[0], fma(zq[1], zq[1], fma(zq[2], zq[2], zq[3] * zq[3]))));
+                        weak |= n2 < 0.5;
+                        const double rn = n2 > 0.0 ? rsq_full(n2) : 0.0;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) zq[t] *= rn;
                     }
                     continue;
                 }
                 const int ce = k + 2 + __builtin_ctzll(cend >> (k + 1));   // cluster end, exclusive
-                double zk[MB];
+                if (jq == k) {
 #pragma unroll
-                for (int i = 0; i < MB; ++i) zk[i] = readlane_f64(z[i], k);
-                const double lk = readlane_f64(lam, k);
-                weak |= dot(zk, zk) < 0.5;
-                normalise(zk);
-                if (lane == k) {
-#pragma unroll
-                    for (int i = 0; i < MB; ++i) z[i] = zk[i];
-                } else if (lane > k && lane < ce) {
-                    const double dt = dot(zk, z);
-                    mix = fmax(mix, fabs(dt) * fabs(lam - lk));
-#pragma unroll
-                    for (int i = 0; i < MB; ++i) z[i] = fma(-dt, zk[i], z[i]);
+                    for (int t = 0; t < 4; ++t) bk[4 * g + t] = zq[t];
                 }
+                wave_sync();
+                double zk[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zk[t] = bk[4 * g + t];
+                const double n2 = quad_sum(fma(zk[0], zk[0], fma(zk[1], zk[1], fma(zk[2], zk[2], zk[3] * zk[3]))));
+                const double lk = readlane_f64(lam, k);
+                weak |= n2 < 0.5;
+                const double rn = n2 > 0.0 ? rsq_full(n2) : 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zk[t] *= rn;
+                if (jq == k) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) zq[t] = zk[t];
+                } else if (jq > k && jq < ce) {
+                    const double dt = quad_sum(fma(zk[0], zq[0], fma(zk[1], zq[1], fma(zk[2], zq[2], zk[3] * zq[3]))));
+                    mix = fmax(mix, fabs(dt) * fabs(lamq - lk));
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) zq[t] = fma(-dt, zk[t], zq[t]);
+                }
+                wave_sync();
             }
         };
+        if (!finish) {
+            if (lane < M) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i) z[i] = i < M ? ii_start(i, lane) : 0.0;
+                solve(z);
+                solve(z);
+                normalise(z);
+#pragma unroll
+                for (int i = 0; i < MB; ++i) Zr[lane * (MB + 1) + i] = z[i];
+            }
+            if (lane < MB) cid[lane] = __builtin_popcountll(cend & ((1ull << lane) - 1ull));
+            return;
+        }
         if (lane < M) {
 #pragma unroll
-            for (int i = 0; i < MB; ++i) z[i] = i < M ? ii_start(i, lane) : 0.0;
-            solve(z);
-            solve(z);
-            normalise(z);
+            for (int i = 0; i < MB; ++i) z[i] = Zr[lane * (MB + 1) + i];
         }
+        to_quads();
         mgs();
-        if (__ballot(lane < M && (weak || mix > 16.0 * epsp))) {
+        if (__ballot(jq < M && (weak || mix > 16.0 * epsp))) {
+            from_quads();
             if (lane < M) {
                 solve(z);
                 normalise(z);
             }
+            to_quads();
             mgs();
         }
-    }
-    if (lane < M) {
+        // Z[i][j] = component i of vector j
+        if (jq < M) {
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (i < M) Zs[i * MB + lane] = z[i];
+            for (int t = 0; t < 4; ++t)
+                if (4 * g + t < M) Zs[(4 * g + t) * MB + jq] = zq[t];
+        }
+    } else if (lane < MB) {
+        // T = 0: the unit vectors, one cluster
+        if (!finish) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i) Zr[lane * (MB + 1) + i] = z[i];
+            cid[lane] = 0;
+        } else if (lane < M) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i < M) Zs[i * MB + lane] = z[i];
+        }
     }
 }
 
@@ -639,6 +730,7 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
     double2* evecs = reinterpret_cast<double2*>(ws + fr.ws_evecs);
     double2* Bout = reinterpret_cast<double2*>(ws + fr.ws_B);
     double* qref = reinterpret_cast<double*>(ws + fr.ws_qref);
+    double bmax = 0.0;                        // largest |Re|, |Im| of B (0 when bad: B is zero)
     if (bad) {
         st |= NSSDOA_ST_NONFINITE_INPUT;
         const double nan = __longlong_as_double(0x7ff8000000000000LL);
@@ -700,9 +792,13 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
             }
         }
         __syncthreads();
-        double q = 0.0;
-        for (int e = tid; e < M * K; e += bd) q += Bs[e].x * Bs[e].x + Bs[e].y * Bs[e].y;
-        q = block_sum(q, red);
+        double q = 0.0, mx = 0.0;
+        for (int e = tid; e < M * K; e += bd) {
+            q += Bs[e].x * Bs[e].x + Bs[e].y * Bs[e].y;
+            mx = fmax(mx, fmax(fabs(Bs[e].x), fabs(Bs[e].y)));
+        }
+        block_sum_max(q, mx, red);
+        bmax = mx;
         if (tid == 0) {
             *qref = q;
             // 16-bit scans: the Q below which a point is re-evaluated in FP64 at the least
@@ -730,9 +826,7 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
         const int rows = fr.emb_rows, inner = 2 * M;
         double bscale = 1.0;
         if (prm.write_emb >= 4) {
-            double mx = 0.0;
-            for (int e = tid; e < M * K; e += bd) mx = fmax(mx, fmax(fabs(Bs[e].x), fabs(Bs[e].y)));
-            mx = block_max(mx, red);
+            const double mx = bmax;
             if (mx > 0.0 && isfinite(mx)) bscale = ldexp(1.0, 12 - ilogb(mx));
             if (tid == 0) {
                 const double sab = (double)kSplitSteerScale * bscale;
@@ -1215,8 +1309,11 @@ __global__ __launch_bounds__(kSmallThreads) void evd_small_kernel(const int32_t*
     __shared__ double2 As[MB * ld];
     __shared__ double2 Bs[MB * MB];
     __shared__ double Zs[MB * MB];
+    __shared__ double Zr[MB * (MB + 1)];
+    __shared__ double Es[MB * MB];
+    __shared__ int cid[MB];
     __shared__ double2 ubuf[MB], ybuf[MB], sc[2];
-    __shared__ double dq[MB], eq[MB], lamv[MB], gpart[4];
+    __shared__ double dq[MB], eq[MB], lamv[MB], gpart[4], bk[MB];
     __shared__ int first[64];
     __shared__ int perm[64];
     __shared__ double red[32];
@@ -1248,7 +1345,37 @@ __global__ __launch_bounds__(kSmallThreads) void evd_small_kernel(const int32_t*
         }
         const double tnorm = eigvals_block(M, d, e, lamv, first);
         __syncthreads();
-        if (tid < 64) tridiag_eigvecs(M, d, e, tid < M ? lamv[tid] : 0.0, tnorm, Zs);
+        const double lj = tid < M ? lamv[tid] : 0.0;
+        if (tid < 64) tridiag_eigvecs(M, d, e, lj, tnorm, Zr, Zs, bk, cid, false);
+        __syncthreads();
+        // Orthonormalisation within clusters in one symmetric step: with the Gram matrix
+        // G = I + E of a cluster's vectors, z_j <- z_j - 1/2 sum_k E_jk z_k is Z (I + E)^(-1/2) up
+        // to O(|E|^2), taken when every |E_jk| <= 1e-10 and |E_jk| |lambda_j - lambda_k| <=
+        // 16 eps ||T|| (the change of the eigen-residuals); otherwise the wave runs Gram-Schmidt.
+        {
+            const int j = r, k = c;
+            double ejk = 0.0;
+            bool far = false;
+            if (j < M && k < M && cid[j] == cid[k]) {
+                double gjk = 0.0;
+#pragma unroll
+                for (int i = 0; i < MB; ++i) gjk = fma(Zr[j * (MB + 1) + i], Zr[k * (MB + 1) + i], gjk);
+                ejk = (j == k) ? gjk - 1.0 : gjk;
+                if (j != k)
+                    far = !(fabs(ejk) <= 1e-10) ||
+                          !(fabs(ejk) * fabs(lamv[j] - lamv[k]) <= 16.0 * 0x1p-52 * tnorm);
+            }
+            Es[j * MB + k] = ejk;
+            if (__syncthreads_or(far)) {
+                if (tid < 64) tridiag_eigvecs(M, d, e, lj, tnorm, Zr, Zs, bk, cid, true);
+            } else if (j < M && k < M) {
+                // thread (j, i = c): component i of the corrected vector j
+                double zv = Zr[j * (MB + 1) + k];
+                double corr = 0.0;
+                for (int kk = 0; kk < M; ++kk) corr = fma(Es[j * MB + kk], Zr[kk * (MB + 1) + k], corr);
+                Zs[k * MB + j] = fma(-0.5, corr, zv);
+            }
+        }
         __syncthreads();
         // V = Q Z (Z real), over Q
         double2 v = make_double2(0.0, 0.0);
