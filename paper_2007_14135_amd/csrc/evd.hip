@@ -742,7 +742,17 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
             if (prm.write_emb == 2 || prm.write_emb == 3) qref[1] = nan;
         }
     } else {
-        if (tid < M) {
+        if (M <= 16 && bd >= 256) {
+            // thread (i, j) = (tid / 16, tid % 16) compares eigenvalues i and j; the rank of i is
+            // the count over its row of 16 lanes
+            const int i = tid >> 4, j = tid & 15;
+            const double li = i < M ? lamv[i * lstride] : 0.0, lj = j < M ? lamv[j * lstride] : 0.0;
+            const unsigned long long bal = __ballot(i < M && j < M && (lj > li || (lj == li && j < i)));
+            if (tid < 256 && i < M && j == 0) {
+                perm[__builtin_popcount((uint32_t)(bal >> (tid & 48)) & 0xFFFFu)] = i;
+                lam[i] = li;
+            }
+        } else if (tid < M) {
             const double li = lamv[tid * lstride];
             int r = 0;
             for (int j = 0; j < M; ++j) {
@@ -839,12 +849,16 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
             typedef _Float16 halfx8v __attribute__((ext_vector_type(8)));
             halfx8v* o8 = reinterpret_cast<halfx8v*>(ws + g.ws_emb);
             const int P = prm.write_emb == 5 ? 3 : 2;
-            for (int u = tid; u < rows * (inner / 8); u += bd) {
+            // half of a lane's operand (four inner indices) per thread
+            typedef _Float16 halfx4v __attribute__((ext_vector_type(4)));
+            halfx4v* o4 = reinterpret_cast<halfx4v*>(o8);
+            for (int u2 = tid; u2 < rows * (inner / 4); u2 += bd) {
+                const int u = u2 >> 1, hf = u2 & 1;
                 const int rl = u / (inner / 8), kk0 = (u - rl * (inner / 8)) * 8;
-                const int col = rl >> 1, re = kk0 < M, m0 = re ? kk0 : kk0 - M;
-                halfx8v part8[3];
+                const int col = rl >> 1, re = kk0 < M, m0 = (re ? kk0 : kk0 - M) + 4 * hf;
+                halfx4v part4[3];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
+                for (int t = 0; t < 4; ++t) {
                     double vd = 0.0;
                     if (col < K) {
                         const double2 bv = Bs[col * M + m0 + t];
@@ -854,13 +868,13 @@ __device__ void finish_frame(const FrameDev& fr, int fidx, const EvdParams& prm,
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         const _Float16 x = f64_to_f16(vd);
-                        part8[q][t] = x;
+                        part4[q][t] = x;
                         vd -= (double)x;
                     }
                 }
                 const int r = fr.emb_row0 + rl, tile = r >> 5, i = r & 31;
                 const size_t o0 = ((size_t)tile * P * (M / 8) + (kk0 >> 4)) * 64 + ((kk0 >> 3) & 1) * 32 + i;
-                for (int q = 0; q < P; ++q) o8[o0 + (size_t)q * (M / 8) * 64] = part8[q];
+                for (int q = 0; q < P; ++q) o4[2 * (o0 + (size_t)q * (M / 8) * 64) + hf] = part4[q];
             }
         } else
         for (int e = tid; e < rows * inner; e += bd) {
