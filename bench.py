@@ -39,7 +39,9 @@ PEAK_FP16_MFMA_TFLOPS = 2516.6
 PEAK_HBM_GBS = 8000.0
 METRIC = "MUSIC spectrum points/s & frames/s at ≤0.01° peak err, learned vs full scan"
 WEIGHTS = os.path.join(ROOT, "paper_2007_14135_amd", "weights", "proposal_ula16.npy")
-SCAN_SRC = os.path.join(ROOT, "paper_2007_14135_amd", "csrc", "scan_f32.hip")
+# the scan kernels and the host code that orders their work items (the counter summary holds a
+# digest of both)
+SCAN_SRC = [os.path.join(ROOT, "paper_2007_14135_amd", "csrc", f) for f in ("scan_f32.hip", "api.hip")]
 PMC_SUMMARY = {"split16": os.path.join(ROOT, "profiles", "scan_split16_c2_music_pmc.txt"),
                "fp32": os.path.join(ROOT, "profiles", "scan_f32_c2_music_pmc.txt"),
                "split3": os.path.join(ROOT, "profiles", "scan_split3_c2_music_pmc.txt")}
@@ -140,8 +142,11 @@ def scan_traffic(scan_rows, kernel):
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        with open(SCAN_SRC, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in SCAN_SRC:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+        sha = h.hexdigest()
         if kv.get("source_sha256") != sha or int(kv.get("scan_rows", -1)) != scan_rows:
             return None
         return float(kv["traffic_bytes_per_launch"])

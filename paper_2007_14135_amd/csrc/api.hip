@@ -107,6 +107,45 @@ struct StageEvents {
     hipEvent_t a, b;
 };
 
+// Work-item order of one scan launch for the eight XCDs of the MI355X, which take workgroups
+// round-robin (workgroup i runs on XCD i mod 8 up to a fixed offset) and each have their own L2:
+// the angle tiles are split into eight contiguous ranges of about equal work, range x goes to
+// the items at positions x, x + 8, x + 16, ..., and within a range the row chunks of one angle
+// tile follow each other.  Each XCD then reads its eighth of the steering table once and keeps
+// the B tiles of all chunks in its L2, instead of every chunk pass re-reading the whole table.
+constexpr int kXcds = 8;
+static void xcd_order(std::vector<ScanItem>& items, size_t i, size_t j) {
+    if (j - i < 2 * (size_t)kXcds) return;
+    std::vector<ScanItem> its(items.begin() + i, items.begin() + j);
+    std::stable_sort(its.begin(), its.end(), [](const ScanItem& x, const ScanItem& y) {
+        return x.group != y.group ? x.group < y.group : x.angle_tile < y.angle_tile;
+    });
+    const size_t total = its.size();
+    std::vector<std::vector<ScanItem>> q(kXcds);
+    size_t k = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        const size_t end = total * (size_t)(x + 1) / kXcds;
+        // keep an angle tile's chunks together: extend the range to the end of its tile
+        size_t e = std::max(end, k);
+        while (e < total && e > k && its[e].group == its[e - 1].group && its[e].angle_tile == its[e - 1].angle_tile) ++e;
+        if (x == kXcds - 1) e = total;
+        for (; k < e; ++k) q[x].push_back(its[k]);
+    }
+    std::vector<size_t> pos(kXcds, 0);
+    size_t out = i;
+    while (out < j) {
+        for (int x = 0; x < kXcds && out < j; ++x) {
+            int y = x;
+            if (pos[y] >= q[y].size()) {          // this range is done: take from the fullest one
+                y = 0;
+                for (int z = 1; z < kXcds; ++z)
+                    if (q[z].size() - pos[z] > q[y].size() - pos[y]) y = z;
+            }
+            items[out++] = q[y][pos[y]++];
+        }
+    }
+}
+
 struct nssdoa_batch_s {
     nssdoa_plan plan = nullptr;
     nssdoa_alg alg;
@@ -512,6 +551,7 @@ nssdoa_status nssdoa_batch_create(nssdoa_batch* out, nssdoa_plan plan, nssdoa_al
             const int M = b->groups[b->scan_items[i].group].M;
             size_t j = i;
             while (j < b->scan_items.size() && b->groups[b->scan_items[j].group].M == M) ++j;
+            xcd_order(b->scan_items, i, j);
             b->scan_ranges.push_back({M, {(int)i, (int)j}});
             int mt = 0;
             for (size_t k = i; k < j; ++k) mt = std::max(mt, b->scan_items[k].t1 - b->scan_items[k].t0);
