@@ -209,6 +209,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 // Products of the parts that the split keeps: with P = 2, hi hi + hi lo + lo hi; with P = 3,
 // every pair of parts whose orders add up to at most 2 (hi hi, hi mid, mid hi, hi lo, lo hi,
 // mid mid), so the dropped products are below 2^-33 of |a b| (their orders add up to 3 or more).
+// Word 3 of a raw (untyped) buffer resource on gfx9-family GPUs: 32-bit data format, no swizzle.
+constexpr int kRawBufferFlags = 0x00020000;
+
 template <int P>
 __device__ __forceinline__ void split_mfma(const halfx8* bp, const halfx8* s0, const halfx8* s1, floatx16& a0,
                                            floatx16& a1) {
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     __shared__ float bqs[kScanMaxBlocks];
     __shared__ int64_t bso[kScanMaxBlocks];
     __shared__ int* bflag[kScanMaxBlocks];
+    __shared__ int bovf[kScanMaxBlocks];          // a frame's low-Q entries did not fit in lq
     constexpr int kTile8 = P * S * 64;                       // halfx8 per 32-row tile (all parts)
     const int nblk = (it.t1 - it.t0) * 4;
     // B tiles: each wave reads them from global memory (L2) itself, one tile ahead
@@ -277,6 +281,7 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
             const int f = blkframe[g.blk_off + it.t0 * 4 + i];
             bfr[i] = f;
+            bovf[i] = 0;
             if (f >= 0) {
                 const FrameDev& fd = frames[f];
                 const double* qr = reinterpret_cast<const double*>(ws + fd.ws_qref);
@@ -289,14 +294,35 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     }
     __syncthreads();
     float q0 = 0.0f, q1 = 0.0f;
-    int cur = -1, curf = -1;                     // a block and the frame being summed (-1: padding)
+    int curf = -1;                               // the frame being summed (-1: none yet)
+    // the frame's output offset, Q scale, low-Q threshold and flag, read from LDS when the frame
+    // starts so that the reads complete behind its matrix work
+    int64_t c_so = 0;
+    float c_qs = 0.0f, c_thr = 0.0f;
+    int c_blk = 0;
 
-    auto flush = [&](int bi) {
-        const float v = halves_sum(q0, q1) * bqs[bi];
-        const int l = base + lane;          // col tile lane/32, angle lane%32
-        const bool in = l < gL;
-        if (in) spec[bso[bi] + l] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
-        scan_lowq_collect(in && v < bthr[bi], bfr[bi], wave * kScanAnglesPerWave + lane, lq, bflag[bi]);
+    // Spectrum writes are software-pipelined: a tile's finished frames (at most one per 8-row
+    // block) are held in registers and stored in the next iteration, after its matrix
+    // instructions are issued and before its B prefetch, with a buffer store per block (a
+    // zero-length record where no frame ends, angles past the grid outside the record).  A wait
+    // for the prefetched operands then never waits for stores issued just before it.
+    const int l = base + lane;               // col tile lane/32, angle lane%32
+    float pv[4];
+    __amdgpu_buffer_rsrc_t prs[4];
+    const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(spec, (short)0, 0, kRawBufferFlags);
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+        pv[gq] = 0.0f;
+        prs[gq] = none;
+    }
+    auto finish = [&](int gq) {               // the frame summed so far ends before block gq
+        const float v = halves_sum(q0, q1) * c_qs;
+        scan_lowq_collect(l < gL && v < c_thr, curf, wave * kScanAnglesPerWave + lane, lq, &bovf[c_blk]);
+        const uint64_t addr = reinterpret_cast<uint64_t>(spec + c_so);
+        float* rowp = reinterpret_cast<float*>(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32)) << 32) |
+                                               (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)addr));
+        pv[gq] = __builtin_amdgcn_rcpf(fmaxf(v, FLT_MIN));
+        prs[gq] = __builtin_amdgcn_make_buffer_rsrc(rowp, (short)0, 4 * gL, kRawBufferFlags);
     };
 
     for (int t = it.t0; t < it.t1; ++t) {
@@ -305,15 +331,26 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int q = 0; q < P; ++q) bp[s][q] = nb[s][q];
-        if (t + 1 < it.t1) {
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-#pragma unroll
-                for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)(t + 1) * kTile8 + (q * S + s) * 64];
-        }
         floatx16 a0 = {0.0f}, a1 = {0.0f};
 #pragma unroll
         for (int s = 0; s < S; ++s) split_mfma<P>(bp[s], st0[s], st1[s], a0, a1);
+        __builtin_amdgcn_sched_barrier(0);
+        // the previous tile's frames
+#pragma unroll
+        for (int gq = 0; gq < 4; ++gq) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pv[gq]), prs[gq], 4 * l, 0, 0);
+            prs[gq] = none;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            // the next tile (the last one reloads itself: a fixed number of loads per tile)
+            const int tn = min(t + 1, it.t1 - 1);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)tn * kTile8 + (q * S + s) * 64];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         const int b0 = (t - it.t0) * 4;
         const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
         const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
@@ -321,11 +358,16 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         for (int gq = 0; gq < 4; ++gq) {
             const int f = fbk[gq];
             if (f != curf) {
-                if (curf >= 0) flush(cur);
-                cur = b0 + gq;
+                if (curf >= 0) finish(gq);
                 curf = f;
                 q0 = 0.0f;
                 q1 = 0.0f;
+                if (f >= 0) {
+                    c_so = bso[b0 + gq];
+                    c_qs = bqs[b0 + gq];
+                    c_thr = bthr[b0 + gq];
+                    c_blk = b0 + gq;
+                }
             }
             q0 += a0[4 * gq] * a0[4 * gq] + a0[4 * gq + 1] * a0[4 * gq + 1] +
                   a0[4 * gq + 2] * a0[4 * gq + 2] + a0[4 * gq + 3] * a0[4 * gq + 3];
@@ -333,8 +375,18 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
                   a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
         }
     }
-    if (curf >= 0) flush(cur);
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pv[gq]), prs[gq], 4 * l, 0, 0);
+        prs[gq] = none;
+    }
+    if (curf >= 0) {                          // the last frame of the work item
+        finish(0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pv[0]), prs[0], 4 * l, 0, 0);
+    }
     __syncthreads();
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+        if (bovf[i]) *bflag[i] = 1;
     scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
