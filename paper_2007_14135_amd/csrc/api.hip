@@ -88,7 +88,7 @@ constexpr int kChunkRows = 384;      // rows of stacked B per FP32 scan work ite
 constexpr int kChunkRowsLP = 4096;   // rows per 16-bit scan work item (128 tiles)
 constexpr int kCovTargetItems = 2048;
 constexpr int64_t kLowqListMax = 1 << 22;     // entries of a batch's low-Q list
-constexpr int kLowqRefineGrid = 2048;         // workgroups of the low-Q re-evaluation (one round for 32768 points)
+constexpr int kLowqRefineGrid = 1024;         // workgroups of the low-Q re-evaluation
 constexpr double kPlateauRelScan = 1e-4;   // > the FP32 scan's relative error above the low-Q cut
 
 

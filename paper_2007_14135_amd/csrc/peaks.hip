@@ -51,34 +51,22 @@ __device__ inline bool in_windows(const int32_t* W, int l) {
     return in;
 }
 
-// FP64 re-evaluation of the batch's low-Q list (published by the matrix-core scans), sixteen
-// lanes per point (q64_group) over a fixed grid, so that the list, whose length is known only
-// on the device, spreads over the whole GPU.
+// FP64 re-evaluation of the batch's low-Q list (published by the matrix-core scans), one point
+// per thread over a fixed grid: the list's length is known only on the device.
 template <int MB>
 __global__ __launch_bounds__(256) void lowq_refine_kernel(LowqList lq, const FrameDev* __restrict__ frames,
                                                           const double* __restrict__ pos,
                                                           const double2* __restrict__ cis,
                                                           const char* __restrict__ ws, float* __restrict__ spec,
                                                           int use_user) {
-    __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
     const int n = min(*lq.count, lq.cap);
-    const int g = threadIdx.x >> 4, j = threadIdx.x & 15;
-    double2* a = asteer + (threadIdx.x >> 6) * 4 * MB;
-    const int groups = gridDim.x * (blockDim.x >> 4);
-    // the wave's four groups take entries base .. base + 3 together, so every lane of a wave runs
-    // the same rounds (q64_group needs the whole wave)
-    const int wave_base = (blockIdx.x * blockDim.x + (threadIdx.x & ~63)) >> 4;
-    for (int base = wave_base; base < n; base += groups) {
-        const int i = base + (g & 3);
-        const bool live = i < n;
-        const int2 e = live ? lq.list[i] : make_int2(lq.list[0].x, 0);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int2 e = lq.list[i];
         const FrameDev& fr = frames[e.x];
-        const double Q = q64_group<MB>(pos + fr.pos_off, fr.M, fr.K, reinterpret_cast<const double2*>(ws + fr.ws_B),
-                                       grid_dir(fr, e.y), cis, a);
-        if (live && j == 0) {
-            float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
-            out[e.y] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
-        }
+        const double Q = q64_eval<MB>(pos + fr.pos_off, fr.M, fr.K, reinterpret_cast<const double2*>(ws + fr.ws_B),
+                                      grid_dir(fr, e.y), cis);
+        float* out = spec + (use_user ? fr.spec_off_user : fr.spec_off_ws);
+        out[e.y] = (float)(1.0 / fmax(Q, (double)FLT_MIN));
     }
 }
 
@@ -264,13 +252,8 @@ __global__ __launch_bounds__(kLmThreads, 4) void localmax_kernel(const PointItem
     chunk_candidates(n, lval, lidx, flag, &rcount, prm.plateau_rel, val, slots, C);
 }
 
-// Threads of a selection workgroup: sixteen lanes per FP64 point, so 64 points per pass for
-// arrays of up to 16 elements (whose q64_group scratch then still fits), fewer beyond.
 template <int MB>
-constexpr int sel_threads() { return MB <= 16 ? 1024 : MB <= 32 ? 512 : 256; }
-
-template <int MB>
-__global__ __launch_bounds__(sel_threads<MB>()) void select_kernel(const int32_t* __restrict__ flist,
+__global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__ flist,
                                                      const FrameDev* __restrict__ frames,
                                                      const double* __restrict__ pos,
                                                      const double2* __restrict__ cis,
@@ -292,10 +275,7 @@ __global__ __launch_bounds__(sel_threads<MB>()) void select_kernel(const int32_t
     __shared__ int rankpos[kMaxSel];
     __shared__ int ccount, fcount, nuniq, nproc, nbatch, done;
     __shared__ double dth;
-    constexpr int kWaves = sel_threads<MB>() / 64;
-    __shared__ double2 asteer[kWaves * 4 * MB];  // q64_group scratch: 4 groups x MB per wave
-    // B of the frame (M x K, column-major) for the FP64 evaluations, in LDS up to 32 elements
-    __shared__ double2 Bl[MB <= 32 ? MB * MB : 1];
+    __shared__ double2 asteer[4 * 4 * MB];      // q64_group scratch: 4 waves x 4 groups x MB
 
     const int f = flist[blockIdx.x];
     if (f < 0) return;                          // a frame with nothing to select (uniform)
@@ -359,14 +339,8 @@ __global__ __launch_bounds__(sel_threads<MB>()) void select_kernel(const int32_t
     //    (a plateau's FP64 values exceed its candidate's value by less than plateau_rel)
     const double* ps = pos + fr.pos_off;
     const double2* B = reinterpret_cast<const double2*>(ws + fr.ws_B);
-    if (MB <= 32) {
-        for (int e = tid; e < fr.M * fr.K; e += blockDim.x) Bl[e] = B[e];
-        __syncthreads();
-        B = Bl;
-    }
     const int w = prm.halfwidth;
     const int grp = tid >> 4, j = tid & 15;
-    const int ngrp = blockDim.x >> 4;
     double2* a = asteer + (tid >> 6) * 4 * MB;
     const int32_t* W = prm.windows ? prm.windows + (size_t)f * kWinStride : nullptr;
     for (;;) {
@@ -404,8 +378,8 @@ __global__ __launch_bounds__(sel_threads<MB>()) void select_kernel(const int32_t
         __syncthreads();
         if (done) break;
         const int nb = nbatch, tot = sp_off[nb];
-        // 16 lanes per point: blockDim.x / 16 points per pass
-        for (int e0 = 0; e0 < tot; e0 += ngrp) {
+        // 16 lanes per point: 16 points per pass of the 256-thread workgroup
+        for (int e0 = 0; e0 < tot; e0 += 16) {
             const int e = e0 + grp;
             const bool valid = e < tot;
             int b = 0;
@@ -526,8 +500,8 @@ hipError_t launch_mb(bool f64, const PointItem* items, int n_items, const int32_
     if (n_frames > 0) {
         if (p.sel_cap < 1 || p.sel_cap > kSelCap) return hipErrorInvalidValue;
         const size_t lds = (size_t)p.sel_cap * (sizeof(double) + 3 * sizeof(int));
-        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(sel_threads<MB>()), lds, s, flist, frames, pos,
-                           cis, ws, p, peaks, npeaks, status);
+        hipLaunchKernelGGL((select_kernel<MB>), dim3(n_frames), dim3(256), lds, s, flist, frames, pos, cis, ws, p,
+                           peaks, npeaks, status);
     }
     return hipGetLastError();
 }
