@@ -11,6 +11,7 @@ from __future__ import annotations
 import concurrent.futures
 import glob
 import os
+import shlex
 import subprocess
 import sys
 
@@ -31,9 +32,19 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+# Host AddressSanitizer copy of the library and its C ABI driver (tests/asan): host code
+# instrumented, device code as in the product build.
+ASAN_DIR = os.path.join(ROOT, "tests", "asan", "_build")
+ASAN_LIB = os.path.join(ASAN_DIR, "libnssdoa_asan.so")
+ASAN_DRIVER = os.path.join(ASAN_DIR, "abi_driver")
+ASAN_HOST_FLAGS = shlex.split("-Xarch_host -fsanitize=address -Xarch_host -fno-omit-frame-pointer -Xarch_host -g")
+CLANGXX = os.environ.get("NSSDOA_CLANGXX", "/opt/rocm/llvm/bin/clang++")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def _compile(src: str, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
@@ -57,6 +68,36 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def _run(cmd, what):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("%s failed:\n%s\n%s" % (what, " ".join(cmd), r.stderr))
+
+
+def build_asan(verbose: bool = False) -> str:
+    """Host-ASan libnssdoa_asan.so and the driver tests/asan/abi_driver.cpp linked against it
+    (with the ASan runtime in the executable); returns the driver's path."""
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, ASAN_DIR, ASAN_HOST_FLAGS), srcs))
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", ASAN_LIB] + objs, "ASan library link")
+    drv = os.path.join(ROOT, "tests", "asan", "abi_driver.cpp")
+    dobj = os.path.join(ASAN_DIR, "abi_driver.o")
+    san = shlex.split("-fsanitize=address -fno-omit-frame-pointer -g")
+    _run([CLANGXX, "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
+          "-I", INCLUDE] + san + ["-c", drv, "-o", dobj], "ASan driver compile")
+    _run([CLANGXX] + san + [dobj, "-o", ASAN_DRIVER, "-L", ASAN_DIR, "-lnssdoa_asan",
+                            "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+                            "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib")],
+         "ASan driver link")
+    if verbose:
+        print("built", ASAN_DRIVER)
+    return ASAN_DRIVER
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "asan":
+        build_asan(verbose=True)
     sys.exit(0)
