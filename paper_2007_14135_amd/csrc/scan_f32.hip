@@ -211,6 +211,9 @@ __global__ __launch_bounds__(256) void scan_f32_kernel(const ScanItem* __restric
 // mid mid), so the dropped products are below 2^-33 of |a b| (their orders add up to 3 or more).
 // Word 3 of a raw (untyped) buffer resource on gfx9-family GPUs: 32-bit data format, no swizzle.
 constexpr int kRawBufferFlags = 0x00020000;
+// s_waitcnt operand on gfx9-family GPUs waiting for vmcnt = 0 only (expcnt 7, lgkmcnt 15 left
+// unconstrained, vmcnt bits [3:0] and [15:14] zero).
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 template <int P>
 __device__ __forceinline__ void split_mfma(const halfx8* bp, const halfx8* s0, const halfx8* s1, floatx16& a0,
@@ -302,10 +305,11 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     int c_blk = 0;
 
     // Spectrum writes are software-pipelined: a tile's finished frames (at most one per 8-row
-    // block) are held in registers and stored in the next iteration, after its matrix
-    // instructions are issued and before its B prefetch, with a buffer store per block (a
-    // zero-length record where no frame ends, angles past the grid outside the record).  A wait
-    // for the prefetched operands then never waits for stores issued just before it.
+    // block) are held in registers and stored at the start of the next iteration, before the B
+    // prefetch and the matrix instructions, with a buffer store per block (a zero-length record
+    // where no frame ends, angles past the grid outside the record).  Each iteration begins
+    // with one wait for everything issued in the previous one (its operands and stores), so the
+    // loads and stores it issues stay in flight behind its matrix and epilogue work.
     const int l = base + lane;               // col tile lane/32, angle lane%32
     float pv[4];
     __amdgpu_buffer_rsrc_t prs[4];
@@ -326,14 +330,13 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     };
 
     for (int t = it.t0; t < it.t1; ++t) {
+        // this tile's operands and the previous tile's stores, all issued one iteration ago
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         halfx8 bp[S][P];
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int q = 0; q < P; ++q) bp[s][q] = nb[s][q];
-        floatx16 a0 = {0.0f}, a1 = {0.0f};
-#pragma unroll
-        for (int s = 0; s < S; ++s) split_mfma<P>(bp[s], st0[s], st1[s], a0, a1);
         __builtin_amdgcn_sched_barrier(0);
         // the previous tile's frames
 #pragma unroll
@@ -343,13 +346,18 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         }
         __builtin_amdgcn_sched_barrier(0);
         {
-            // the next tile (the last one reloads itself: a fixed number of loads per tile)
+            // the next tile (the last one reloads itself: a fixed number of loads per tile), in
+            // flight during this tile's matrix instructions and epilogue
             const int tn = min(t + 1, it.t1 - 1);
 #pragma unroll
             for (int s = 0; s < S; ++s)
 #pragma unroll
                 for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)tn * kTile8 + (q * S + s) * 64];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        floatx16 a0 = {0.0f}, a1 = {0.0f};
+#pragma unroll
+        for (int s = 0; s < S; ++s) split_mfma<P>(bp[s], st0[s], st1[s], a0, a1);
         __builtin_amdgcn_sched_barrier(0);
         const int b0 = (t - it.t0) * 4;
         const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
