@@ -32,6 +32,10 @@ CFLAGS = [
 ]
 
 
+# Per-source flags.  The scans keep their matrix-core accumulators in ordinary VGPRs (the
+# epilogue reads them with plain vector instructions instead of accvgpr copies).
+SOURCE_FLAGS = {"scan_f32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 # Host AddressSanitizer copy of the library and its C ABI driver (tests/asan): host code
 # instrumented, device code as in the product build.
 ASAN_DIR = os.path.join(ROOT, "tests", "asan", "_build")
@@ -44,7 +48,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 def _compile(src: str, out_dir: str = BUILD, extra=()) -> str:
     obj = os.path.join(out_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + SOURCE_FLAGS.get(os.path.basename(src), []) + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))

@@ -262,44 +262,63 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
     }
 
     __shared__ ScanLowq lq;
-    __shared__ __align__(16) int bfr[kScanMaxBlocks];
-    __shared__ float bthr[kScanMaxBlocks];
-    __shared__ float bqs[kScanMaxBlocks];
-    __shared__ int64_t bso[kScanMaxBlocks];
-    __shared__ int* bflag[kScanMaxBlocks];
     __shared__ int bovf[kScanMaxBlocks];          // a frame's low-Q entries did not fit in lq
     constexpr int kTile8 = P * S * 64;                       // halfx8 per 32-row tile (all parts)
     const int nblk = (it.t1 - it.t0) * 4;
-    // B tiles: each wave reads them from global memory (L2) itself, one tile ahead
+    // B tiles: each wave reads them from global memory (L2) itself, one tile ahead, into two
+    // operand buffers used in turn
     const halfx8* emb = reinterpret_cast<const halfx8*>(ws + g.ws_emb) + lane;
-    halfx8 nb[S][P];
+    halfx8 opA[S][P], opB[S][P];
     if (it.t0 < it.t1) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)it.t0 * kTile8 + (q * S + s) * 64];
+            for (int q = 0; q < P; ++q) opA[s][q] = emb[(size_t)it.t0 * kTile8 + (q * S + s) * 64];
     }
+    // LDS state behind a barrier that waits for no global load
     if (threadIdx.x == 0) lq.n = 0;
-    {
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) bovf[i] = 0;
+    __syncthreads();
+    // Per-block parameters in registers, block i of the item in lane i % 64 of set i / 64 (at
+    // most kScanMaxBlocks = 128 blocks), read with readlane: its frame, output offset, Q scale and
+    // low-Q threshold.  Every wave loads its own copy; nothing waits for them before the first
+    // tile's epilogue.
+    static_assert(kScanMaxBlocks <= 128, "two lane sets of block parameters");
+    int pf[2];
+    int64_t pso[2];
+    float pqs[2], pthr[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = lane + 64 * k;
+        pf[k] = -1;
+        pso[k] = 0;
+        pqs[k] = 0.0f;
+        pthr[k] = 0.0f;
+        if (i < nblk) {
             const int f = blkframe[g.blk_off + it.t0 * 4 + i];
-            bfr[i] = f;
-            bovf[i] = 0;
+            pf[k] = f;
             if (f >= 0) {
                 const FrameDev& fd = frames[f];
                 const double* qr = reinterpret_cast<const double*>(ws + fd.ws_qref);
-                bso[i] = use_user ? fd.spec_off_user : fd.spec_off_ws;
-                bthr[i] = lowq_tau * (float)qr[0];
-                bqs[i] = (float)qr[1];
-                bflag[i] = reinterpret_cast<int*>(ws + fd.ws_lowq);
+                pso[k] = use_user ? fd.spec_off_user : fd.spec_off_ws;
+                pthr[k] = lowq_tau * (float)qr[0];
+                pqs[k] = (float)qr[1];
             }
         }
     }
-    __syncthreads();
+    auto lane_i32 = [&](const int (&x)[2], int b) { return __builtin_amdgcn_readlane(b < 64 ? x[0] : x[1], b & 63); };
+    auto lane_f32 = [&](const float (&x)[2], int b) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b < 64 ? x[0] : x[1]), b & 63));
+    };
+    auto lane_i64 = [&](const int64_t (&x)[2], int b) {
+        const int64_t v = b < 64 ? x[0] : x[1];
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, b & 63);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), b & 63);
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
     float q0 = 0.0f, q1 = 0.0f;
     int curf = -1;                               // the frame being summed (-1: none yet)
-    // the frame's output offset, Q scale, low-Q threshold and flag, read from LDS when the frame
-    // starts so that the reads complete behind its matrix work
+    // the frame's output offset, Q scale and low-Q threshold, read when the frame starts
     int64_t c_so = 0;
     float c_qs = 0.0f, c_thr = 0.0f;
     int c_blk = 0;
@@ -329,14 +348,10 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         prs[gq] = __builtin_amdgcn_make_buffer_rsrc(rowp, (short)0, 4 * gL, kRawBufferFlags);
     };
 
-    for (int t = it.t0; t < it.t1; ++t) {
+    // One tile: its operands are in `cur`, the next tile's go to `nxt`.
+    auto tile = [&](int t, halfx8 (&cur)[S][P], halfx8 (&nxt)[S][P]) {
         // this tile's operands and the previous tile's stores, all issued one iteration ago
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        halfx8 bp[S][P];
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-            for (int q = 0; q < P; ++q) bp[s][q] = nb[s][q];
         __builtin_amdgcn_sched_barrier(0);
         // the previous tile's frames
 #pragma unroll
@@ -352,28 +367,26 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
 #pragma unroll
             for (int s = 0; s < S; ++s)
 #pragma unroll
-                for (int q = 0; q < P; ++q) nb[s][q] = emb[(size_t)tn * kTile8 + (q * S + s) * 64];
+                for (int q = 0; q < P; ++q) nxt[s][q] = emb[(size_t)tn * kTile8 + (q * S + s) * 64];
         }
         __builtin_amdgcn_sched_barrier(0);
         floatx16 a0 = {0.0f}, a1 = {0.0f};
 #pragma unroll
-        for (int s = 0; s < S; ++s) split_mfma<P>(bp[s], st0[s], st1[s], a0, a1);
+        for (int s = 0; s < S; ++s) split_mfma<P>(cur[s], st0[s], st1[s], a0, a1);
         __builtin_amdgcn_sched_barrier(0);
         const int b0 = (t - it.t0) * 4;
-        const int4 fb = *reinterpret_cast<const int4*>(bfr + b0);
-        const int fbk[4] = {fb.x, fb.y, fb.z, fb.w};
 #pragma unroll
         for (int gq = 0; gq < 4; ++gq) {
-            const int f = fbk[gq];
+            const int f = lane_i32(pf, b0 + gq);
             if (f != curf) {
                 if (curf >= 0) finish(gq);
                 curf = f;
                 q0 = 0.0f;
                 q1 = 0.0f;
                 if (f >= 0) {
-                    c_so = bso[b0 + gq];
-                    c_qs = bqs[b0 + gq];
-                    c_thr = bthr[b0 + gq];
+                    c_so = lane_i64(pso, b0 + gq);
+                    c_qs = lane_f32(pqs, b0 + gq);
+                    c_thr = lane_f32(pthr, b0 + gq);
                     c_blk = b0 + gq;
                 }
             }
@@ -382,6 +395,11 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
             q1 += a1[4 * gq] * a1[4 * gq] + a1[4 * gq + 1] * a1[4 * gq + 1] +
                   a1[4 * gq + 2] * a1[4 * gq + 2] + a1[4 * gq + 3] * a1[4 * gq + 3];
         }
+    };
+    for (int t = it.t0; t < it.t1; t += 2) {
+        tile(t, opA, opB);
+        if (t + 1 >= it.t1) break;
+        tile(t + 1, opB, opA);
     }
 #pragma unroll
     for (int gq = 0; gq < 4; ++gq) {
@@ -393,8 +411,13 @@ __global__ __launch_bounds__(256) void scan_split16_kernel(const ScanItem* __res
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pv[0]), prs[0], 4 * l, 0, 0);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
-        if (bovf[i]) *bflag[i] = 1;
+    if (wave == 0) {                          // low-Q overflow flags of the item's frames
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = lane + 64 * k;
+            if (i < nblk && bovf[i] && pf[k] >= 0) *reinterpret_cast<int*>(ws + frames[pf[k]].ws_lowq) = 1;
+        }
+    }
     scan_lowq_publish(lq, it.angle_tile * kScanAnglesPerWG, lql.count, lql.list, lql.cap, frames, ws);
 }
 
