@@ -328,16 +328,23 @@ def test_repeat_runs_bit_identical():
 
 
 def test_c2_full_batch_bench_configuration():
-    # The benchmark's workload and launch configuration: 256 frames, N=4096, L=18000, MUSIC.
-    # Every 16th frame is compared point by point with the oracle; every frame must report D
-    # peaks with status 0 and a finite positive spectrum.
+    # The benchmark's workload in the benchmark's launch configuration: 256 frames, N=4096,
+    # L=18000, MUSIC, with the scan work-item size bench.py takes from the committed autotuner
+    # cache for this batch.  Every frame is compared point by point with the oracle and must
+    # report D peaks with status 0.
+    import os
+    from paper_2007_14135_amd import autotune
+    from paper_2007_14135_amd.api import Options
+    _need_gpu()
     fs = make_frames("c2")
-    db, res = _run(fs, "music", "c64")
+    arrays, grids, frames, _ = frameset_inputs(fs)
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2007_14135_amd", "tuning",
+                         "autotune_cache.json")
+    rows = autotune.Cache(cache).get(autotune.device_name(), autotune.signature(arrays, grids, frames, "music", "c64"))
+    print("bench configuration: scan_rows %s" % rows, flush=True)
+    db, res = _run(fs, "music", "c64", options=Options(scan_rows=rows or 0))
     assert np.all(res["status"] == 0)
     assert np.all(res["npeaks"] == 4)
     for s in res["spectra"]:
         assert np.all(np.isfinite(s)) and np.all(s > 0)
-    sub = FrameSet([fs.frames[i] for i in range(0, 256, 16)], None, None, None)
-    sub_res = dict(spectra=[res["spectra"][i] for i in range(0, 256, 16)],
-                   npeaks=res["npeaks"][::16], peaks=res["peaks"][::16])
-    _check_frames(sub, sub_res, "music", 1e-4, 1e-8, "c2-full-sampled")
+    _check_frames(fs, res, "music", 1e-4, 1e-8, "c2-full-bench-configuration")
