@@ -20,8 +20,12 @@ the source directions only; it is part of the data model, not of the estimator.
 
 from __future__ import annotations
 
+import ast
 import dataclasses
+import json
 import math
+import operator
+import os
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -109,6 +113,8 @@ class Config:
     dtype: type
     draw: callable             # rng -> dict of per-frame parameters
     description: str
+    readings: List[str] = dataclasses.field(default_factory=list)
+    recipe: Optional[dict] = None
 
 
 def _grid_for_step(step: float):
@@ -116,78 +122,111 @@ def _grid_for_step(step: float):
     return (-90.0, float(step), L)
 
 
-def _c1(rng):
-    M = 8
-    return dict(M=M, geometry="ula", pos=ula_positions(M), D=2, N=1024, snr_db=10.0,
-                angle_lo=-60.0, angle_hi=60.0, gap=10.0, grid=_grid_for_step(0.1))
+# ---------------------------------------------------------------------------------------------
+# Workload recipes: one JSON file per configuration under configs/.  "draws" lists the per-frame
+# parameters in the order they are drawn from the frame's random stream; a value is
+#   a literal (number, string, list)                      no draw
+#   {"uniform": [lo, hi]}                                 float(rng.uniform(lo, hi))
+#   {"choice": [v0, v1, ...]}                             rng.choice(values)
+#   {"coin": [a, b]}                                      a if rng.uniform() < 0.5 else b
+#   {"integers": [lo, hi]}                                int(rng.integers(lo, hi + 1)), inclusive
+#   {"log_uniform_int": [lo, hi]}                         round(exp(rng.uniform(log lo, log hi)))
+#   {"expr": "0.5 * M / pi"}                              arithmetic over earlier parameters
+# and bounds may themselves be {"expr": ...}.  Derived: "pos" from "geometry", "M" and
+# "uca_radius"; "grid" from "grid_step" unless given.
+# ---------------------------------------------------------------------------------------------
+
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+_BINOPS = {ast.Add: operator.add, ast.Sub: operator.sub, ast.Mult: operator.mul,
+           ast.Div: operator.truediv, ast.FloorDiv: operator.floordiv}
 
 
-def _c2(rng):
-    M = 16
-    snr = float(rng.uniform(0.0, 20.0))
-    return dict(M=M, geometry="ula", pos=ula_positions(M), D=4, N=4096, snr_db=snr,
-                angle_lo=-70.0, angle_hi=70.0, gap=5.0, grid=_grid_for_step(0.01))
+def _eval_expr(text: str, env: dict):
+    """Evaluate +, -, *, /, // over numbers, ``pi`` and earlier parameters (nothing else)."""
+    def ev(node):
+        if isinstance(node, ast.Expression):
+            return ev(node.body)
+        if isinstance(node, ast.Constant) and isinstance(node.value, (int, float)):
+            return node.value
+        if isinstance(node, ast.Name):
+            if node.id == "pi":
+                return math.pi
+            if node.id in env and isinstance(env[node.id], (int, float)):
+                return env[node.id]
+            raise ValueError(f"unknown name {node.id!r} in {text!r}")
+        if isinstance(node, ast.BinOp) and type(node.op) in _BINOPS:
+            return _BINOPS[type(node.op)](ev(node.left), ev(node.right))
+        if isinstance(node, ast.UnaryOp) and isinstance(node.op, ast.USub):
+            return -ev(node.operand)
+        raise ValueError(f"unsupported expression {text!r}")
+    return ev(ast.parse(text, mode="eval"))
 
 
-def _c3(rng):
-    M = int(rng.choice([8, 16, 32, 64]))
-    geometry = "ula" if rng.uniform() < 0.5 else "uca"
-    pos = ula_positions(M) if geometry == "ula" else uca_positions(M, 0.5 * M / np.pi)
-    D = int(rng.integers(1, M // 4 + 1))
-    N = int(round(math.exp(rng.uniform(math.log(256.0), math.log(8192.0)))))
-    snr = float(rng.uniform(-5.0, 20.0))
-    step = float(rng.choice([0.1, 0.01, 0.002]))
-    return dict(M=M, geometry=geometry, pos=pos, D=D, N=N, snr_db=snr,
-                angle_lo=-70.0, angle_hi=70.0, gap=5.0, grid=_grid_for_step(step))
+def _value(spec, env: dict, rng: np.random.Generator):
+    if not isinstance(spec, dict):
+        return spec
+    if len(spec) != 1:
+        raise ValueError(f"draw spec {spec!r} must have one key")
+    (kind, arg), = spec.items()
+    if kind == "expr":
+        return _eval_expr(arg, env)
+    bounds = [_value(b, env, rng) for b in arg] if kind != "choice" else arg
+    if kind == "uniform":
+        return float(rng.uniform(bounds[0], bounds[1]))
+    if kind == "choice":
+        v = rng.choice(arg)
+        return int(v) if all(isinstance(x, int) for x in arg) else float(v)
+    if kind == "coin":
+        return bounds[0] if rng.uniform() < 0.5 else bounds[1]
+    if kind == "integers":
+        return int(rng.integers(int(bounds[0]), int(bounds[1]) + 1))
+    if kind == "log_uniform_int":
+        return int(round(math.exp(rng.uniform(math.log(bounds[0]), math.log(bounds[1])))))
+    raise ValueError(f"unknown draw kind {kind!r}")
 
 
-def _c4(rng):
-    M = 64
-    return dict(M=M, geometry="ula", pos=ula_positions(M), D=8, N=16384, snr_db=5.0,
-                angle_lo=-60.0, angle_hi=60.0, gap=1.0, grid=_grid_for_step(0.001))
+def _positions(p: dict) -> np.ndarray:
+    if p["geometry"] == "ula":
+        return ula_positions(p["M"])
+    if p["geometry"] == "uca":
+        return uca_positions(p["M"], p["uca_radius"])
+    raise ValueError(f"unknown geometry {p['geometry']!r}")
 
 
-def _c5(rng):
-    M = 16
-    D = int(rng.integers(1, 5))
-    snr = float(rng.uniform(-5.0, 20.0))
-    N = int(round(math.exp(rng.uniform(math.log(256.0), math.log(4096.0)))))
-    return dict(M=M, geometry="ula", pos=ula_positions(M), D=D, N=N, snr_db=snr,
-                angle_lo=-70.0, angle_hi=70.0, gap=5.0, grid=_grid_for_step(0.001))
+def _recipe_draw(recipe: dict):
+    def draw(rng: np.random.Generator) -> dict:
+        p: dict = {}
+        for name, spec in recipe["draws"]:
+            p[name] = _value(spec, p, rng)
+        p["pos"] = _positions(p)
+        if "grid" in p:
+            p["grid"] = (float(p["grid"][0]), float(p["grid"][1]), int(p["grid"][2]))
+        else:
+            p["grid"] = _grid_for_step(p["grid_step"])
+        if "polar" in p:
+            p["polar"] = tuple(p["polar"])
+        return p
+    return draw
 
 
-def _c6(rng):
-    # the paper's test scenario (Section 5): 8-element UCA of radius 10 m at 15 MHz (0.5 lambda),
-    # two uncorrelated sources at 15 dB; snapshot count and directions are not given (readings:
-    # N = 1024, azimuths uniform in [0, 330] deg at least 30 deg apart, so also 30 deg apart across
-    # 0/360, polar angles uniform in [60, 90] deg); scanned over 0:1:359 deg of azimuth
-    M = 8
-    return dict(M=M, geometry="uca", pos=uca_positions(M, 0.5), D=2, N=1024, snr_db=15.0,
-                angle_lo=0.0, angle_hi=330.0, gap=30.0, polar=(60.0, 90.0), grid=(0.0, 1.0, 360))
+def load_config(path: str) -> Config:
+    """A workload configuration from its JSON recipe."""
+    with open(path) as f:
+        r = json.load(f)
+    return Config(r["name"], int(r["index"]), int(r["frames"]), np.dtype(r["dtype"]).type,
+                  _recipe_draw(r), r["description"], list(r.get("readings", [])), r)
 
 
 CONFIGS: Dict[str, Config] = {
-    "c1": Config("c1", 0, 1, np.complex128, _c1,
-                 "ULA M=8, D=2, N=1024, 10 dB, one frame, complex128, 0.1 deg grid"),
-    "c2": Config("c2", 1, 256, np.complex64, _c2,
-                 "ULA M=16, D=4, N=4096, SNR U[0,20] dB, 256 frames, complex64, 0.01 deg grid"),
-    "c3": Config("c3", 2, 4096, np.complex64, _c3,
-                 "uneven batch: M in {8,16,32,64}, ULA/UCA, D U{1..M/4}, N log-U[256,8192], "
-                 "SNR U[-5,20] dB, step in {0.1,0.01,0.002} deg, 4096 frames, complex64"),
-    "c4": Config("c4", 3, 64, np.complex64, _c4,
-                 "ULA M=64, D=8 (gap 1 deg), N=16384, 5 dB, 64 frames, complex64, 0.001 deg grid"),
-    "c5": Config("c5", 4, 8192, np.complex64, _c5,
-                 "ULA M=16, D U{1..4}, SNR U[-5,20] dB, N log-U[256,4096], 0.001 deg grid"),
-    "c6": Config("c6", 5, 1, np.complex64, _c6,
-                 "UCA M=8 radius 0.5 lambda, D=2 at polar angles U[60,90] deg, N=1024, 15 dB, complex64, "
-                 "azimuth 0:1:359 deg (2-D grids add polar angles)"),
+    c.name: c for c in (load_config(os.path.join(CONFIG_DIR, fn))
+                        for fn in sorted(os.listdir(CONFIG_DIR)) if fn.endswith(".json"))
 }
 
 # Polar-angle ranges of the 2-D scans of the paper's scenario (azimuth 0:1:359 x these), keyed by
-# their point count: 360 x 1 is the horizontal plane; the larger ranges extend it away from the
-# plane at 1 deg (reading: the paper names only the counts 1, 30, 60 and 90, and phi = 1..90 for
-# the largest).
-EL_GRIDS_2D = {1: (90.0, 1.0, 1), 30: (61.0, 1.0, 30), 60: (31.0, 1.0, 60), 90: (1.0, 1.0, 90)}
+# their point count (the readings are stated in the scenario's recipe).
+EL_GRIDS_2D = {int(k): (float(v[0]), float(v[1]), int(v[2]))
+               for k, v in CONFIGS["c6"].recipe["polar_grids_2d"].items()}
 
 
 def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
@@ -203,7 +242,12 @@ def make_frame(config: str, frame_index: int, *, N: Optional[int] = None,
     p = cfg.draw(rng)
     if M is not None and M != p["M"]:
         p["M"] = M
-        p["pos"] = ula_positions(M) if p["geometry"] == "ula" else uca_positions(M, 0.5 * M / np.pi)
+        if p["geometry"] == "uca":
+            # the radius follows M when the recipe gives it as an expression (never a new draw)
+            spec = dict(cfg.recipe["draws"]).get("uca_radius")
+            if isinstance(spec, dict) and "expr" in spec:
+                p["uca_radius"] = _eval_expr(spec["expr"], p)
+        p["pos"] = _positions(p)
     if D is not None:
         p["D"] = D
     if N is not None:
