@@ -1,14 +1,18 @@
 // Step-1 (Eq. 3): partial sample covariances  sum_n x_i[n] conj(x_j[n])  over snapshot chunks.
 //
-// Two kernels compute the same partial sums; both accumulate in FP64.  For complex64 input
-// every product of two FP32 values is exact in FP64, so the only rounding is the accumulation.
+// Two kernels compute the same partial sums; both accumulate in FP64.
 //
-// cov_mfma_kernel (M <= 32): the real-embedded Gram on the FP64 matrix cores.  With
-// Y = [Re X; Im X], Re R = Xr Xr^T + Xi Xi^T and Im R = Xi Xr^T - (Xi Xr^T)^T, so per 16-row
-// block pair three 16x16x4 products are accumulated.  Lane l holds element l%16 of snapshot
-// group l/16: that one register is both the A operand (A[i][k], i = l%16, k = l/16) and the
-// B operand (B[k][j], j = l%16) of v_mfma_f64_16x16x4f64, whose result register r of lane l is
-// D[l/16 + 4r][l%16].  Each wave owns every fourth 16-snapshot block of the chunk and keeps
+// cov_mfma_kernel (M <= 32): the real-embedded Gram on the FP64 matrix cores, from two real
+// products instead of three.  With P = Xi Xr^T and Z = Xr + Xi, Im R = P - P^T and
+// Re R = Xr Xr^T + Xi Xi^T = Z Z^T - P - P^T, so per 16-row block pair two 16x16x4 products are
+// accumulated (Z Z^T over I <= J, P over all pairs).  Products of two FP32 values (P) are exact
+// in FP64; z = xr + xi rounds by at most u|z| (u = 2^-53; exact unless the exponents of xr and
+// xi differ by more than 29) and z_i z_j by at most u|z_i z_j|, so with |z| <= sqrt(2)|x| and
+// Cauchy-Schwarz over the snapshots the real part of R gains at most 6u sqrt(R_ii R_jj) beyond
+// the FP64 accumulation's own rounding; integer-valued data stays exact.  Lane l holds element
+// l%16 of snapshot group l/16: that one register is both the A operand (A[i][k], i = l%16,
+// k = l/16) and the B operand (B[k][j], j = l%16) of v_mfma_f64_16x16x4f64, whose result
+// register r of lane l is D[l/16 + 4r][l%16].  Each wave owns every fourth 16-snapshot block of the chunk and keeps
 // three blocks of loads in flight (raw complex64 read as aligned float4 when the layout allows)
 // while the matrix cores run; the four waves are reduced in LDS in fixed order.
 //
@@ -164,9 +168,9 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int mi = lane & 15, q = lane >> 4;       // element in a row block, snapshot group
 
-    doublex4 drr[NP], dii[NP], dir[NX];
+    doublex4 dzz[NP], dir[NX];
 #pragma unroll
-    for (int t = 0; t < NP; ++t) { drr[t] = doublex4{0, 0, 0, 0}; dii[t] = doublex4{0, 0, 0, 0}; }
+    for (int t = 0; t < NP; ++t) dzz[t] = doublex4{0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < NX; ++t) dir[t] = doublex4{0, 0, 0, 0};
 
@@ -180,16 +184,17 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
         rowok[b] = m < M;
         rowp[b] = xf + (size_t)(rowok[b] ? m : 0) * fr.ldx;
     }
-    // one 16-snapshot step of the three products from lane (mi, q)'s four snapshots n + 4q + u
+    // one 16-snapshot step of the two products from lane (mi, q)'s four snapshots n + 4q + u
     auto mfma_step = [&](const double (&xr)[RB], const double (&xi)[RB]) {
+        double z[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) z[b] = xr[b] + xi[b];
         int t = 0;
 #pragma unroll
         for (int I = 0; I < RB; ++I)
 #pragma unroll
-            for (int J = I; J < RB; ++J, ++t) {
-                drr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[I], xr[J], drr[t], 0, 0, 0);
-                dii[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[I], xi[J], dii[t], 0, 0, 0);
-            }
+            for (int J = I; J < RB; ++J, ++t)
+                dzz[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(z[I], z[J], dzz[t], 0, 0, 0);
 #pragma unroll
         for (int I = 0; I < RB; ++I)
 #pragma unroll
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
         }
     }
 
-    // scatter this wave's sums to LDS: Re R over I <= J, Xi Xr^T over all block pairs
+    // scatter this wave's sums to LDS: Z Z^T over I <= J, P = Xi Xr^T over all block pairs
     {
         int t = 0;
 #pragma unroll
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
             for (int J = I; J < RB; ++J, ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    sre[wave][I * 16 + q + 4 * r][J * 16 + mi] = drr[t][r] + dii[t][r];
+                    sre[wave][I * 16 + q + 4 * r][J * 16 + mi] = dzz[t][r];
 #pragma unroll
         for (int I = 0; I < RB; ++I)
 #pragma unroll
@@ -302,8 +307,9 @@ __global__ __launch_bounds__(256) void cov_mfma_kernel(const CovItem* __restrict
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            re += sre[w][i][j];
-            im += sim[w][i][j] - sim[w][j][i];   // Im R_ij = sum xi_i xr_j - xr_i xi_j
+            const double pij = sim[w][i][j], pji = sim[w][j][i];
+            re += sre[w][i][j] - (pij + pji);    // Re R_ij = (Z Z^T - P - P^T)_ij
+            im += pij - pji;                     // Im R_ij = sum xi_i xr_j - xr_i xi_j
         }
         out[i * M + j] = make_double2(re, im);
     }
