@@ -133,6 +133,42 @@ def _custom_frame(X):
                  angles_deg=np.zeros(1), grid_start=-90.0, grid_step=1.0, grid_L=180, X=X)
 
 
+@pytest.mark.parametrize("M", [16, 32])
+def test_covariance_matrix_core_bound_per_entry(M):
+    # The matrix-core covariance forms Re R from Z Z^T - P - P^T (Z = Re x + Im x in FP64), whose
+    # products can round: each entry may deviate from the FP64 oracle by at most 6u sqrt(R_ii R_jj)
+    # beyond the accumulation's own rounding.  Checked per entry, normalised by sqrt(R_ii R_jj),
+    # on ordinary frames, on rows 2^-8 .. 2^7 apart in scale, and on imaginary parts 2^-20 below
+    # the real parts (where Z's sums round); a one-row-block and a two-row-block batch.
+    from paper_2007_14135_amd import WS_COV
+    rng = np.random.default_rng(21)
+    frames = []
+    for i in range(3):
+        base = make_frame("c2", 40 + i, N=2048).X.astype(np.complex128)
+        X = np.vstack([base, base[::-1] * np.exp(0.3j)])[:M] if M > 16 else base
+        if i == 1:
+            X = X * (2.0 ** (np.arange(M) % 16 - 8.0))[:, None]
+        if i == 2:
+            X = X.real + 1j * X.imag * 2.0 ** -20
+        frames.append(_custom_frame(X.astype(np.complex64)))
+    frames.append(_custom_frame((rng.standard_normal((M, 777)) + 1j * rng.standard_normal((M, 777))).astype(np.complex64)))
+    fs = pack_frames(frames, dtype=np.complex64)
+    db, res = _run(fs, "music", "c64")
+    worst = 0.0
+    for f, fr in enumerate(frames):
+        R = db.workspace_array(WS_COV, f, M * M, np.complex128).reshape(M, M)
+        Ro = oracle.covariance(fr.X)
+        d = np.sqrt(np.outer(Ro.diagonal().real, Ro.diagonal().real))
+        err = np.abs(R - Ro) / d
+        worst = max(worst, float(err.max()))
+        # 6u from Z's products plus the FP64 accumulation's rounding (observed 7.8e-16): 1e-14
+        assert err.max() <= 1e-14, (f, float(err.max()))
+        # the imaginary part comes from exact products alone: relative to its own scale
+        im_scale = np.abs(Ro.imag).max()
+        assert np.abs(R.imag - Ro.imag).max() <= 1e-13 * im_scale, f
+    print("covariance M=%d: worst per-entry error %.2e of sqrt(R_ii R_jj)" % (M, worst), flush=True)
+
+
 @pytest.mark.parametrize("method", ["auto", "ql", "jacobi"])
 def test_eigensolvers_across_sizes_and_structures(method):
     # Both solvers against the oracle's LAPACK eigensolve for M = 2 .. 64 (odd, even, the
